@@ -1,0 +1,149 @@
+"""ctypes binding of the FP64 C oracle (``lb_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The oracle state is the post-streaming population n_i(r, t) of the paper's
+Eq. (lbupdate), stored as ``n[9, ny, nx]``, plus the previous stress trace
+``P[ny, nx]`` that Eq. (rhoplus) differences against.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+FIELDS = ["utx", "uty", "kxx", "kxy", "kyx", "kyy", "sxx", "sxy", "syy",
+          "trT", "r", "rho_e", "ux", "uy", "s", "mx", "my", "tauM"]
+
+CX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+CY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+WEIGHTS = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+class OrcParams(C.Structure):
+    _fields_ = [("g", C.c_double), ("tau_eff", C.c_double), ("G", C.c_double),
+                ("tau", C.c_double), ("gamma_c", C.c_double), ("lam", C.c_double),
+                ("t_startup", C.c_longlong), ("nn_pressure", C.c_int)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.ensure_built()
+        L = C.CDLL(path)
+        dp = C.POINTER(C.c_double)
+        L.orc_resolve.argtypes = [C.c_double] * 6 + [C.c_double, C.c_longlong, C.c_int, C.POINTER(OrcParams)]
+        L.orc_resolve.restype = C.c_int
+        L.orc_equilibrium.argtypes = [C.c_double] * 3 + [dp]
+        L.orc_forcing.argtypes = [C.c_double, dp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, dp]
+        L.orc_stress_series.argtypes = [dp, C.c_double, C.c_double, dp]
+        L.orc_stress_series.restype = C.c_int
+        L.orc_tau_M.argtypes = [dp, C.c_double, C.c_double]
+        L.orc_tau_M.restype = C.c_double
+        L.orc_step.argtypes = [C.POINTER(OrcParams), C.c_int, C.c_int, dp, dp, C.c_longlong, dp, dp, dp]
+        L.orc_step.restype = C.c_int
+        L.orc_run.argtypes = [C.POINTER(OrcParams), C.c_int, C.c_int, dp, dp, C.c_longlong, C.c_longlong]
+        L.orc_run.restype = C.c_longlong
+        L.orc_init_rest.argtypes = [C.c_int, C.c_int, dp, dp]
+        L.orc_wall_drag.argtypes = [C.c_int, C.c_int, dp]
+        L.orc_wall_drag.restype = C.c_double
+        L.orc_num_fields.restype = C.c_int
+        assert L.orc_num_fields() == len(FIELDS)
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def equilibrium(rho, ux, uy):
+    out = np.zeros(9)
+    lib().orc_equilibrium(rho, ux, uy, _p(out))
+    return out
+
+
+def forcing(tau, sbar, r, fx, fy, ux, uy):
+    out = np.zeros(9)
+    sb = np.ascontiguousarray(sbar, dtype=np.float64)
+    lib().orc_forcing(tau, _p(sb), r, fx, fy, ux, uy, _p(out))
+    return out
+
+
+def stress_series(kappa, G, tauM):
+    """sigma (xx, xy, yy) of Eq. (sigtsum) and the number of terms (-1: diverged)."""
+    k = np.ascontiguousarray(kappa, dtype=np.float64).reshape(2, 2)
+    out = np.zeros(3)
+    nt = lib().orc_stress_series(_p(k), G, tauM, _p(out))
+    return out, nt
+
+
+def tau_M(kappa, tau, gamma_c):
+    k = np.ascontiguousarray(kappa, dtype=np.float64).reshape(2, 2)
+    return lib().orc_tau_M(_p(k), tau, gamma_c)
+
+
+def resolve(tau_lb, G, tau0, gamma_c, eps=0.0, visc_split=0.0, force=0.0,
+            t_startup=2 ** 62, nn_pressure=True):
+    p = OrcParams()
+    rc = lib().orc_resolve(tau_lb, G, tau0, gamma_c, eps, visc_split, force,
+                           int(t_startup), int(bool(nn_pressure)), C.byref(p))
+    if rc != 0:
+        raise ValueError("invalid channel parameters")
+    return p
+
+
+class Channel:
+    """One channel advanced by the oracle. Time ``t`` counts completed steps."""
+
+    def __init__(self, nx, ny, force, tau_lb=1.0, G=1e-4, tau0=1e4, gamma_c=0.1,
+                 eps=0.0, visc_split=0.0, t_startup=2 ** 62, nn_pressure=True):
+        self.nx, self.ny = int(nx), int(ny)
+        self.params = resolve(tau_lb, G, tau0, gamma_c, eps, visc_split, force,
+                              t_startup, nn_pressure)
+        self.n = np.empty((9, self.ny, self.nx))
+        self.P = np.empty((self.ny, self.nx))
+        lib().orc_init_rest(self.nx, self.ny, _p(self.n), _p(self.P))
+        self.t = 0
+
+    def set_state(self, n, P, t=None):
+        self.n[...] = n
+        self.P[...] = P
+        if t is not None:
+            self.t = int(t)
+
+    def run(self, steps):
+        bad = lib().orc_run(C.byref(self.params), self.nx, self.ny, _p(self.n), _p(self.P),
+                            self.t, int(steps))
+        if bad != 0:
+            raise RuntimeError(f"oracle: stress series failed at {bad} node-steps")
+        self.t += int(steps)
+
+    def fields(self):
+        """Per-node observables of the current step, dict name -> [ny, nx]."""
+        f = np.empty((len(FIELDS), self.ny, self.nx))
+        bad = lib().orc_step(C.byref(self.params), self.nx, self.ny, _p(self.n), _p(self.P),
+                             self.t, None, None, _p(f))
+        if bad != 0:
+            raise RuntimeError("oracle: stress series failed")
+        return {name: f[q] for q, name in enumerate(FIELDS)}
+
+    def profiles(self):
+        """x-averaged rows of every field."""
+        return {k: v.mean(axis=1) for k, v in self.fields().items()}
+
+    def mass(self):
+        """sum over nodes of (sum_i n_i - delta rho_prev), delta rho_prev = -(3/2) P."""
+        return float(self.n.sum() + 1.5 * self.P.sum()) if self.params.nn_pressure else float(self.n.sum())
+
+    def momentum_x(self):
+        return float((CX[:, None, None] * self.n).sum())
+
+    def wall_drag(self):
+        return float(lib().orc_wall_drag(self.nx, self.ny, _p(self.n)))
+
+    def force_now(self):
+        return self.params.g if self.t < self.params.t_startup else 0.0

@@ -1,0 +1,367 @@
+/*
+ * Plain FP64 CPU oracle of the modified D2Q9 lattice-Boltzmann scheme for a
+ * fluid obeying the instantaneous nonlinear generalised Maxwell (inlM) model,
+ * in a 2D channel: x periodic, bounce-back walls in y, driven by a body force.
+ *
+ * TEST INFRASTRUCTURE. This file is the independent reference the GPU path is
+ * checked against. Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it; the product library never does. It shares
+ * no code, header or table with the GPU path.
+ *
+ * It is written to be read against the paper (Papenkort & Voigtmann,
+ * arXiv:1310.7450), one step per passage, with no blocking, fusion or
+ * reordering:
+ *   - collide and stream, n_i(r + c_i, t + 1) = n_i + Delta_i + F_i:
+ *     Sec. II.A, Eq. (lbupdate);
+ *   - density and current from the half-way average of pre- and
+ *     post-collision populations: Sec. II.A, Eq. (rhoj);
+ *   - D2Q9 velocities, weights a = 4/9, 1/9, 1/36 and the second-order
+ *     equilibrium: Sec. II.A (equilibrium distribution and the D2Q9 model);
+ *   - BGK collision, Delta_i = -(n_i - n_i^eq)/tau: Sec. II.A;
+ *   - forcing term F_i carrying the traceless non-Newtonian stress, the body
+ *     force and the flow-induced density change: Sec. II.A, Eq. (bodyforce);
+ *   - normal-stress advection, dt d(delta rho)/dt from the change of the stress
+ *     trace between two steps: Sec. II.A, Eq. (rhoplus);
+ *   - bounce-back walls: Sec. II.B;
+ *   - velocity gradient kappa_ab = d_b u_a by three-point central differences:
+ *     Sec. II.C;
+ *   - steady-state stress as the series sigma = sum_{n>=1} G tau_M^n d^n with
+ *     d^1 = D and d^{n+1} = kappa d^n + d^n kappa^T: Sec. III.A,
+ *     Eqs. (sigtsum), (smalld);
+ *   - shear-dependent relaxation 1/tau_M = 1/tau + sqrt(II_D)/gamma_c with
+ *     II_D = tr(D^2)/2: Sec. III.A, Eq. (nlmaxwell);
+ *   - the instantaneous model (kappa, tau_M taken at the current step):
+ *     Sec. III.A, closing paragraph;
+ *   - the viscosity split (tau_LB carrying part of G tau): Sec. IV, opening.
+ *
+ * Readings where the paper is silent or ambiguous (each is also listed in the
+ * design notes):
+ *   R1 the equilibrium density is rho_e = sum (n* + n)/2 (no -delta rho
+ *      subtraction), so that sum_nodes (sum_i n_i - delta rho_prev) is
+ *      conserved exactly;
+ *   R2 kappa is taken from u~ = j / sum_i n_i (j = m + f/2), the equilibrium and
+ *      the forcing use u = j / rho_e;
+ *   R3 body force density f = rho0 g with rho0 = 1;
+ *   R4 half-way bounce-back, walls at y = -1/2 and y = ny - 1/2;
+ *   R5 at the wall rows the finite difference uses the ghost velocity
+ *      u(-1) = -u(0), u(ny) = -u(ny-1) (no slip on the half link);
+ *   R6 the stress series is summed until a term is below 1e-18 of the running
+ *      sum; a node where it does not converge is counted and reported;
+ *   R7 separation eps: tau = tau0 * 10^(min(eps,0)/0.05),
+ *      G_inf = G (1 + sqrt(max(eps,0))); gamma_c fixed;
+ *   R8 viscosity split lambda: the collision relaxes with
+ *      tau_eff = 1/2 + 3 (eta_s + lambda G tau), eta_s = (tau_LB - 1/2)/3,
+ *      and Sigma^nN = sigma - lambda G tau D.
+ *
+ * Lattice units: dx = dt = 1, rho0 = 1, c_s^2 = 1/3, d = 2.
+ * Storage: populations n[i][y][x] (nine planes, x fastest), the previous
+ * stress trace P[y][x] = tr Sigma^nN at the previous step. The state held here
+ * is the post-streaming (pre-collision) population n_i(r, t).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* D2Q9 velocities in the order (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),
+ * (-1,-1),(1,-1) and their weights. */
+static const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                            1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+static const double CS2 = 1.0 / 3.0;
+
+static int opposite(int i) {
+  for (int k = 0; k < 9; ++k)
+    if (CX[k] == -CX[i] && CY[k] == -CY[i]) return k;
+  return -1;
+}
+
+typedef struct {
+  double g;         /* body-force density along +x while t < t_startup       */
+  double tau_eff;   /* BGK relaxation time of the collision                   */
+  double G;         /* plateau modulus after the eps closure                  */
+  double tau;       /* Maxwell relaxation time after the eps closure (or inf) */
+  double gamma_c;   /* critical strain                                        */
+  double lam;       /* viscosity split lambda in [0, 1]                       */
+  long long t_startup;
+  int nn_pressure;  /* 1: keep the delta-rho terms of the forcing            */
+} orc_params;
+
+/* Parameter resolution (readings R7, R8). Returns 0, or -1 for invalid input. */
+int orc_resolve(double tau_lb, double G, double tau0, double gamma_c, double eps,
+                double lam, double g, long long t_startup, int nn_pressure,
+                orc_params *out) {
+  if (!(tau_lb > 0.5) || !(G >= 0) || !(tau0 > 0) || !(gamma_c > 0) ||
+      !(lam >= 0 && lam <= 1) || !isfinite(g) || !isfinite(eps))
+    return -1;
+  double eta_s = (tau_lb - 0.5) / 3.0;
+  double tau = tau0 * pow(10.0, fmin(eps, 0.0) / 0.05);
+  double Ginf = G * (1.0 + sqrt(fmax(eps, 0.0)));
+  if (lam > 0 && isinf(tau)) return -1;
+  out->g = g;
+  out->tau_eff = 0.5 + 3.0 * (eta_s + (lam > 0 ? lam * Ginf * tau : 0.0));
+  out->G = Ginf;
+  out->tau = tau;
+  out->gamma_c = gamma_c;
+  out->lam = lam;
+  out->t_startup = t_startup;
+  out->nn_pressure = nn_pressure;
+  return 0;
+}
+
+/* Second-order equilibrium n_i^eq(rho, u) = a_i rho [1 + c.u/cs2 +
+ * (c_a c_b - cs2 delta_ab) u_a u_b / (2 cs2^2)]. */
+void orc_equilibrium(double rho, double ux, double uy, double neq[9]) {
+  for (int i = 0; i < 9; ++i) {
+    double cu = CX[i] * ux + CY[i] * uy;
+    double quad = 0.0;
+    double c[2] = {CX[i], CY[i]}, u[2] = {ux, uy};
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        quad += (c[a] * c[b] - CS2 * (a == b)) * u[a] * u[b];
+    neq[i] = W[i] * rho * (1.0 + cu / CS2 + quad / (2.0 * CS2 * CS2));
+  }
+}
+
+/* Forcing term of Eq. (bodyforce). sbar = traceless non-Newtonian stress
+ * (xx, xy, yy), r = dt d(delta rho)/dt, f = body-force density, u = velocity. */
+void orc_forcing(double tau, const double sbar[3], double r, double fx, double fy,
+                 double ux, double uy, double F[9]) {
+  double S[2][2] = {{sbar[0], sbar[1]}, {sbar[1], sbar[2]}};
+  double f[2] = {fx, fy}, u[2] = {ux, uy};
+  for (int i = 0; i < 9; ++i) {
+    double c[2] = {CX[i], CY[i]};
+    double stress = 0.0, second = 0.0, cf = 0.0;
+    for (int a = 0; a < 2; ++a) {
+      cf += f[a] * c[a];
+      for (int b = 0; b < 2; ++b) {
+        double q = c[a] * c[b] - CS2 * (a == b);
+        stress += S[a][b] * q;
+        second += q * (-r * u[a] * u[b] + (u[b] * f[a] + u[a] * f[b]));
+      }
+    }
+    F[i] = W[i] * (-stress / (2.0 * CS2 * CS2 * tau) +
+                   (1.0 - 1.0 / (2.0 * tau)) *
+                       (r + cf / CS2 + second / (2.0 * CS2 * CS2)));
+  }
+}
+
+/* Steady-state stress of Eq. (sigtsum) for velocity gradient k[a][b] =
+ * d_b u_a, relaxation time tau_M and modulus G: sigma = sum_{n>=1} G tau_M^n
+ * d^n, summed term by term. Writes (xx, xy, yy). Returns the number of terms
+ * used, or -1 if the series has not converged after 1000 terms. */
+int orc_stress_series(const double k[2][2], double G, double tauM, double sig[3]) {
+  double e[2][2]; /* e = tau_M^n d^n, starting from n = 1: tau_M D */
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) e[a][b] = tauM * (k[a][b] + k[b][a]);
+  double s[2][2];
+  memcpy(s, e, sizeof s);
+  for (int n = 2; n <= 1000; ++n) {
+    double nx[2][2];
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        double v = 0.0;
+        for (int c = 0; c < 2; ++c) v += k[a][c] * e[c][b] + e[a][c] * k[b][c];
+        nx[a][b] = tauM * v;
+      }
+    double tmax = 0.0, smax = 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        e[a][b] = nx[a][b];
+        s[a][b] += e[a][b];
+        if (fabs(e[a][b]) > tmax) tmax = fabs(e[a][b]);
+        if (fabs(s[a][b]) > smax) smax = fabs(s[a][b]);
+      }
+    if (!isfinite(tmax)) break;
+    if (tmax <= 1e-18 * smax || tmax == 0.0) {
+      sig[0] = G * s[0][0];
+      sig[1] = G * s[0][1];
+      sig[2] = G * s[1][1];
+      return n;
+    }
+  }
+  sig[0] = sig[1] = sig[2] = NAN;
+  return -1;
+}
+
+/* Shear-dependent Maxwell time of Eq. (nlmaxwell); +inf when both rates vanish. */
+double orc_tau_M(const double k[2][2], double tau, double gamma_c) {
+  double D[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) D[a][b] = k[a][b] + k[b][a];
+  double trD2 = 0.0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) trD2 += D[a][b] * D[b][a];
+  double II = 0.5 * trD2;
+  double rate = 1.0 / tau + sqrt(II) / gamma_c;
+  return 1.0 / rate;
+}
+
+/* Per-node observables written by orc_step / orc_observe, field-major
+ * [field][y][x]. */
+enum {
+  OF_UTX, OF_UTY, OF_KXX, OF_KXY, OF_KYX, OF_KYY, OF_SXX, OF_SXY, OF_SYY,
+  OF_TRT, OF_R, OF_RHOE, OF_UX, OF_UY, OF_S, OF_MX, OF_MY, OF_TAUM, OF_COUNT
+};
+int orc_num_fields(void) { return OF_COUNT; }
+
+/* One time step t -> t+1 of one channel. n: 9 planes of nx*ny post-streaming
+ * populations at time t; P: stress trace of step t-1. Writes the state at
+ * t+1 to n_out, P_out (which must not alias n, P). If fields != NULL the
+ * per-node observables of step t are stored there. If n_out == NULL nothing is
+ * advanced (observation only). Returns the number of nodes at which the
+ * stress series did not converge (0 on success). */
+int orc_step(const orc_params *p, int nx, int ny, const double *n, const double *P,
+             long long t, double *n_out, double *P_out, double *fields) {
+  const size_t N = (size_t)nx * ny;
+  double fx = (t < p->t_startup) ? p->g : 0.0, fy = 0.0;
+  double *utx = malloc(N * sizeof(double)), *uty = malloc(N * sizeof(double));
+  int bad = 0;
+
+  /* Moments and the provisional velocity u~ = j / sum_i n_i of every node,
+   * with j = m + f/2 (Eq. (rhoj), reading R2). */
+#pragma omp parallel for
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      size_t id = (size_t)y * nx + x;
+      double s = 0, mx = 0, my = 0;
+      for (int i = 0; i < 9; ++i) {
+        double v = n[i * N + id];
+        s += v;
+        mx += CX[i] * v;
+        my += CY[i] * v;
+      }
+      utx[id] = (mx + 0.5 * fx) / s;
+      uty[id] = (my + 0.5 * fy) / s;
+    }
+
+#pragma omp parallel for reduction(+ : bad)
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      size_t id = (size_t)y * nx + x;
+      double nn[9];
+      double s = 0, mx = 0, my = 0;
+      for (int i = 0; i < 9; ++i) {
+        nn[i] = n[i * N + id];
+        s += nn[i];
+        mx += CX[i] * nn[i];
+        my += CY[i] * nn[i];
+      }
+      double jx = mx + 0.5 * fx, jy = my + 0.5 * fy;
+
+      /* kappa_ab = d_b u_a by central differences; x periodic, wall ghosts
+       * u(-1) = -u(0), u(ny) = -u(ny-1) (readings R4, R5). */
+      int xm = (x - 1 + nx) % nx, xp = (x + 1) % nx;
+      double uxm = utx[(size_t)y * nx + xm], uxp = utx[(size_t)y * nx + xp];
+      double uym = uty[(size_t)y * nx + xm], uyp = uty[(size_t)y * nx + xp];
+      double uxd, uyd, uxu, uyu;
+      if (y > 0) { uxd = utx[id - nx]; uyd = uty[id - nx]; }
+      else       { uxd = -utx[id];     uyd = -uty[id]; }
+      if (y < ny - 1) { uxu = utx[id + nx]; uyu = uty[id + nx]; }
+      else            { uxu = -utx[id];     uyu = -uty[id]; }
+      double k[2][2];
+      k[0][0] = 0.5 * (uxp - uxm);  /* d_x u_x */
+      k[0][1] = 0.5 * (uxu - uxd);  /* d_y u_x */
+      k[1][0] = 0.5 * (uyp - uym);  /* d_x u_y */
+      k[1][1] = 0.5 * (uyu - uyd);  /* d_y u_y */
+
+      /* inlM stress: Maxwell time of Eq. (nlmaxwell), then Eq. (sigtsum). */
+      double sig[3] = {0, 0, 0};
+      double tauM = orc_tau_M(k, p->tau, p->gamma_c);
+      if (p->G > 0 && isfinite(tauM)) {
+        if (orc_stress_series(k, p->G, tauM, sig) < 0) bad++;
+      }
+      /* tau_M infinite means tau = inf and D = 0: the series is zero. */
+
+      /* Non-Newtonian stress carried by the forcing (viscosity split). */
+      double D[2][2] = {{2 * k[0][0], k[0][1] + k[1][0]}, {k[0][1] + k[1][0], 2 * k[1][1]}};
+      double lgt = (p->lam > 0) ? p->lam * p->G * p->tau : 0.0;
+      double T[3] = {sig[0] - lgt * D[0][0], sig[1] - lgt * D[0][1], sig[2] - lgt * D[1][1]};
+      double trT = T[0] + T[2];
+      double sbar[3] = {T[0] - 0.5 * trT, T[1], T[2] - 0.5 * trT};
+
+      /* Eq. (rhoplus): delta rho = -tr Sigma^nN / (cs2 d), and
+       * r = dt d(delta rho)/dt is its change since the last step. */
+      double r = 0.0;
+      if (p->nn_pressure) {
+        double drho_now = -trT / (CS2 * 2.0);
+        double drho_prev = -P[id] / (CS2 * 2.0);
+        r = drho_now - drho_prev;
+      }
+
+      /* Eq. (rhoj) with reading R1: rho_e = sum (n* + n)/2 = s + r/2. */
+      double rho_e = s + 0.5 * r;
+      double ux = jx / rho_e, uy = jy / rho_e;
+
+      double neq[9], F[9];
+      orc_equilibrium(rho_e, ux, uy, neq);
+      orc_forcing(p->tau_eff, sbar, r, fx, fy, ux, uy, F);
+
+      if (fields) {
+        double vals[OF_COUNT] = {utx[id], uty[id], k[0][0], k[0][1], k[1][0], k[1][1],
+                                 sig[0], sig[1], sig[2], trT, r, rho_e, ux, uy, s, mx, my,
+                                 tauM};
+        for (int q = 0; q < OF_COUNT; ++q) fields[q * N + id] = vals[q];
+      }
+      if (!n_out) continue;
+
+      /* Collide (BGK + forcing) and stream; links leaving through a wall are
+       * reflected back to the same node (half-way bounce-back). */
+      for (int i = 0; i < 9; ++i) {
+        double post = nn[i] - (nn[i] - neq[i]) / p->tau_eff + F[i];
+        int xd = (x + CX[i] + nx) % nx, yd = y + CY[i];
+        if (yd >= 0 && yd < ny)
+          n_out[i * N + (size_t)yd * nx + xd] = post;
+        else
+          n_out[opposite(i) * N + id] = post;
+      }
+      P_out[id] = trT;
+    }
+  free(utx);
+  free(uty);
+  return bad;
+}
+
+/* Rest state: n_i = a_i, P = 0. */
+void orc_init_rest(int nx, int ny, double *n, double *P) {
+  const size_t N = (size_t)nx * ny;
+  for (int i = 0; i < 9; ++i)
+    for (size_t id = 0; id < N; ++id) n[i * N + id] = W[i];
+  for (size_t id = 0; id < N; ++id) P[id] = 0.0;
+}
+
+/* Advances (n, P) in place from step t0 by nsteps. Returns the total count of
+ * non-converged stress evaluations, or -1 on allocation failure. */
+long long orc_run(const orc_params *p, int nx, int ny, double *n, double *P,
+                  long long t0, long long nsteps) {
+  const size_t N = (size_t)nx * ny;
+  double *n2 = malloc(9 * N * sizeof(double)), *P2 = malloc(N * sizeof(double));
+  if (!n2 || !P2) { free(n2); free(P2); return -1; }
+  long long bad = 0;
+  for (long long s = 0; s < nsteps; ++s) {
+    bad += orc_step(p, nx, ny, n, P, t0 + s, n2, P2, NULL);
+    memcpy(n, n2, 9 * N * sizeof(double));
+    memcpy(P, P2, N * sizeof(double));
+  }
+  free(n2);
+  free(P2);
+  return bad;
+}
+
+/* Momentum handed to the walls by the bounce-back links during the step that
+ * produced the current state: the populations that were reflected are the
+ * ones now travelling away from the wall in the wall rows. */
+double orc_wall_drag(int nx, int ny, const double *n) {
+  const size_t N = (size_t)nx * ny;
+  double w = 0.0;
+  for (int x = 0; x < nx; ++x) {
+    size_t b = (size_t)x, t = (size_t)(ny - 1) * nx + x;
+    for (int i = 0; i < 9; ++i) {
+      /* bottom wall: populations now moving up (cy = +1) came from links
+       * that pointed down, with x velocity -cx */
+      if (CY[i] == 1) w += 2.0 * (-CX[i]) * n[i * N + b];
+      if (CY[i] == -1) w += 2.0 * (-CX[i]) * n[i * N + t];
+    }
+  }
+  return w;
+}

@@ -1,0 +1,387 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage it follows. None of them retypes the oracle's
+arithmetic: they check moments, closed forms, limits, conservation laws and
+analytic channel solutions, chosen so that a dropped term, a wrong sign or a
+transposed operand in the oracle fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import analytic
+
+CS2 = 1.0 / 3.0
+CX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=float)
+CY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=float)
+ETA_S = 1.0 / 6.0  # tau_LB = 1
+
+
+def moments(f):
+    m0 = f.sum()
+    m1 = np.array([(CX * f).sum(), (CY * f).sum()])
+    m2 = np.array([[(CX * CX * f).sum(), (CX * CY * f).sum()],
+                   [(CY * CX * f).sum(), (CY * CY * f).sum()]])
+    return m0, m1, m2
+
+
+# ----------------------------------------------- Sec. II.A: n^eq and F_i --
+
+def test_equilibrium_moments(orc):
+    """Sec. II.A, Eqs. (rhoj), (pieq): sum n^eq = rho, sum c n^eq = rho u,
+    sum cc n^eq = rho cs2 1 + rho u u (D2Q9 reproduces them exactly)."""
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        rho = 1 + 0.1 * rng.standard_normal()
+        u = 0.05 * rng.standard_normal(2)
+        m0, m1, m2 = moments(orc.equilibrium(rho, *u))
+        assert abs(m0 - rho) < 1e-15
+        assert np.allclose(m1, rho * u, atol=1e-16, rtol=0)
+        assert np.allclose(m2, rho * CS2 * np.eye(2) + rho * np.outer(u, u), atol=1e-16, rtol=0)
+
+
+def test_forcing_moments(orc):
+    """Sec. II.A, moment conditions under Eq. (lbfab) and Eq. (lbfab) itself:
+    sum F = (1 - 1/2tau) r, sum c F = (1 - 1/2tau) f,
+    sum cc F = (1 - 1/2tau)(u f + f u) + (1 - 1/2tau)(cs2 1 - u u) r - Sbar/tau."""
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        tau = 0.6 + rng.random()
+        a, b = 1e-4 * rng.standard_normal(2)
+        sbar = np.array([a, b, -a])           # traceless
+        r = 1e-6 * rng.standard_normal()
+        f = 1e-5 * rng.standard_normal(2)
+        u = 0.05 * rng.standard_normal(2)
+        F = orc.forcing(tau, sbar, r, f[0], f[1], u[0], u[1])
+        m0, m1, m2 = moments(F)
+        k = 1 - 1 / (2 * tau)
+        S = np.array([[a, b], [b, -a]])
+        want2 = k * (np.outer(u, f) + np.outer(f, u)) + k * (CS2 * np.eye(2) - np.outer(u, u)) * r - S / tau
+        scale = abs(r) + np.abs(f).max() + np.abs(S).max()
+        assert abs(m0 - k * r) < 1e-15 * scale
+        assert np.allclose(m1, k * f, atol=1e-15 * scale, rtol=0)
+        assert np.allclose(m2, want2, atol=1e-15 * scale, rtol=0)
+
+
+def test_forcing_newtonian_crosscheck(orc):
+    """Sec. II.A, cross-check after Eq. (bodyforce): a stress of Newtonian form
+    Sigma^nN = Delta_eta D added through F gives Delta_i + F_i = -n^neq_i/tau'
+    with tau' the BGK time of eta + Delta_eta, for the non-equilibrium part
+    n^neq that carries the second moment pi^neq = -tau' cs2 D of Eq.
+    (pineqkappa) (rest, no force)."""
+    tau, deta = 0.9, 0.05
+    taup = tau + deta / CS2
+    D = np.array([[2e-4, 3e-4], [3e-4, -2e-4]])
+    pi_neq = -taup * CS2 * D
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    nneq = np.array([w[i] / (2 * CS2 * CS2) *
+                     (CX[i] * CX[i] * pi_neq[0, 0] + 2 * CX[i] * CY[i] * pi_neq[0, 1] + CY[i] * CY[i] * pi_neq[1, 1])
+                     for i in range(9)])
+    sbar = deta * D
+    F = orc.forcing(tau, np.array([sbar[0, 0], sbar[0, 1], sbar[1, 1]]), 0.0, 0, 0, 0, 0)
+    assert np.allclose(-nneq / tau + F, -nneq / taup, rtol=0, atol=1e-18)
+    # and a wrong split (deta with the opposite sign) does not
+    Fw = orc.forcing(tau, -np.array([sbar[0, 0], sbar[0, 1], sbar[1, 1]]), 0.0, 0, 0, 0, 0)
+    assert not np.allclose(-nneq / tau + Fw, -nneq / taup, rtol=0, atol=1e-10)
+
+
+# ------------------------------------------- Sec. III.A: the nlM stress --
+
+def test_tau_M_invariant(orc):
+    """Eq. (nlmaxwell): II_D = gdot^2 in simple shear, (2 edot)^2 in planar
+    extension."""
+    tau, gc = 1e4, 0.1
+    for gd in [1e-6, 1e-4, 1e-2]:
+        got = orc.tau_M([[0, gd], [0, 0]], tau, gc)
+        assert got == pytest.approx(1 / (1 / tau + math.sqrt(analytic.II_D_shear(gd)) / gc), rel=1e-14)
+        got = orc.tau_M([[gd, 0], [0, -gd]], tau, gc)
+        assert got == pytest.approx(1 / (1 / tau + math.sqrt(analytic.II_D_extension(gd)) / gc), rel=1e-14)
+
+
+def test_stress_simple_shear(orc):
+    """Sec. III.A, simple shear: sigma_xy = G gdot tau_M, N1 = 2 G gdot^2 tau_M^2,
+    sigma_yy = 0, and G N1 / sigma_xy^2 = 2; the series stops after n = 2."""
+    G, tau, gc = 1e-4, 1e4, 0.1
+    for gd in [-3e-5, 1e-6, 2e-4, 5e-2]:
+        kap = [[0, gd], [0, 0]]
+        tM = orc.tau_M(kap, tau, gc)
+        sig, nt = orc.stress_series(kap, G, tM)
+        want = analytic.simple_shear(gd, G, tau, gc)
+        assert nt >= 2
+        assert sig[1] == pytest.approx(want["sxy"], rel=1e-14)
+        assert sig[0] == pytest.approx(want["N1"], rel=1e-14)
+        assert sig[2] == 0.0
+        assert G * sig[0] / sig[1] ** 2 == pytest.approx(2.0, rel=1e-13)
+
+
+def test_stress_shear_in_y(orc):
+    """Same shear with the roles of x and y swapped (kappa_yx = gdot): the
+    normal stress moves to sigma_yy. Catches a transposed kappa in the series."""
+    G, tM = 1e-4, 300.0
+    gd = 1e-3
+    sig, _ = orc.stress_series([[0, 0], [gd, 0]], G, tM)
+    assert sig[0] == 0.0
+    assert sig[1] == pytest.approx(G * gd * tM, rel=1e-14)
+    assert sig[2] == pytest.approx(2 * G * gd ** 2 * tM ** 2, rel=1e-14)
+
+
+def test_stress_planar_extension(orc):
+    """Sec. III.A, planar extension at fixed tau_M (the UCM example):
+    sigma_xx = 2 G edot tau/(1 - 2 edot tau); the series diverges at
+    edot tau >= 1/2."""
+    G, tM = 2.0, 1.0
+    for et in [0.05, 0.2, 0.4, 0.45]:
+        sig, nt = orc.stress_series([[et, 0], [0, -et]], G, tM)
+        assert nt > 2
+        assert sig[0] == pytest.approx(analytic.planar_extension_sxx(et, G, tM), rel=1e-12)
+        assert sig[2] == pytest.approx(analytic.planar_extension_sxx(-et, G, tM), rel=1e-12)
+        assert sig[1] == 0.0
+    _, nt = orc.stress_series([[0.55, 0], [0, -0.55]], G, tM)
+    assert nt == -1
+
+
+def test_stress_series_fixed_point(orc):
+    """Eqs. (sigtsum), (smalld): since kappa d^n + d^n kappa^T = d^{n+1}, the
+    sum obeys sigma - tau_M (kappa sigma + sigma kappa^T) = G tau_M D for any
+    kappa where it converges (here with rotation, extension and shear mixed)."""
+    rng = np.random.default_rng(3)
+    G, gc, tau = 1e-4, 0.1, 1e3
+    for _ in range(50):
+        k = 1e-3 * rng.standard_normal((2, 2))
+        tM = orc.tau_M(k, tau, gc)
+        sig, nt = orc.stress_series(k, G, tM)
+        assert nt > 0
+        S = np.array([[sig[0], sig[1]], [sig[1], sig[2]]])
+        lhs = S - tM * (k @ S + S @ k.T)
+        assert np.allclose(lhs, G * tM * (k + k.T), rtol=0, atol=1e-14 * np.abs(S).max())
+
+
+def test_yield_stress_limit(orc):
+    """Eq. (yieldstress): for tau -> inf the shear stress is G gamma_c for any
+    shear rate (a Bingham fluid)."""
+    G, gc = 1e-4, 0.1
+    for gd in [1e-8, 1e-5, 1e-2]:
+        kap = [[0, gd], [0, 0]]
+        tM = orc.tau_M(kap, math.inf, gc)
+        sig, _ = orc.stress_series(kap, G, tM)
+        assert sig[1] == pytest.approx(G * gc, rel=1e-14)
+        assert sig[0] == pytest.approx(2 * G * gc * gc, rel=1e-14)
+
+
+# --------------------------------------------- Sec. III.B analytic forms --
+
+def test_lattice_profile_matches_paper_formula():
+    """Eq. (maxwellpoiseuille) in the paper's variables equals the lattice-unit
+    root used by the analytic profile, under tau_0 = eta_s/G, theta = tau/tau_0,
+    wp H = g H / G, v = u tau_0 / H, d = y/H."""
+    for (G, tau, g, H) in [(1e-4, 1e4, 1e-6, 32.0), (3e-5, 1e5, 2e-7, 100.0), (1e-4, 2e3, 1e-5, 16.0)]:
+        dl = analytic.dimensionless(2 * H, g, ETA_S, G, tau, 0.1)
+        d = np.linspace(0.01, 1, 50)
+        paper = analytic.paper_dvdd(d, dl["wpH"], dl["theta"], 0.1)
+        lattice = -dl["tau_0"] * analytic.shear_rate(g * d * H, ETA_S, G, tau, 0.1)
+        assert np.allclose(paper, lattice, rtol=1e-9, atol=0)
+
+
+def test_plug_asymptote():
+    """Eq. (plug): for theta -> inf the rate vanishes below d_c = gamma_c/(wp H)
+    and approaches -(wp H d) + gamma_c above it."""
+    G, g, H = 1e-4, 1e-6, 32.0
+    dl = analytic.dimensionless(2 * H, g, ETA_S, G, 1e12, 0.1)
+    dc = 0.1 / dl["wpH"]
+    d = np.array([0.5 * dc, 0.9 * dc, 1.1 * dc, 2 * dc, 0.99])
+    v = analytic.paper_dvdd(d, dl["wpH"], dl["theta"], 0.1)
+    assert np.all(np.abs(v[:2]) < 1e-6)
+    assert np.allclose(v[2:], -dl["wpH"] * d[2:] + 0.1, rtol=1e-4)
+
+
+def test_newtonian_startup_series_limits():
+    """The Fourier start-up series tends to the parabola and is zero at t = 0."""
+    u_inf = analytic.newtonian_startup(64, 1e-6, ETA_S, 1e9)
+    assert np.allclose(u_inf, analytic.newtonian_parabola(64, 1e-6, ETA_S), rtol=1e-9)
+    assert np.abs(analytic.newtonian_startup(64, 1e-6, ETA_S, 0.0)).max() == 0.0
+
+
+# ------------------------------------------------ the oracle on channels --
+
+def test_newtonian_magic_tau_exact_parabola(orc):
+    """With G = 0 the scheme is plain BGK with a body force; half-way
+    bounce-back has zero slip at tau = 1/2 + sqrt(3/16), where the steady
+    profile is the exact parabola g (H^2 - xi^2)/(2 eta) at the nodes."""
+    tau = 0.5 + math.sqrt(3 / 16)
+    ch = orc.Channel(1, 16, 1e-6, tau_lb=tau, G=0.0)
+    ch.run(20000)
+    want = analytic.newtonian_parabola(16, 1e-6, (tau - 0.5) / 3)
+    assert np.abs(ch.profiles()["ux"] - want).max() / want.max() < 1e-10
+
+
+def test_newtonian_second_difference(orc):
+    """G = 0, tau = 1: the bulk profile is exactly quadratic, second
+    difference -g/eta_s on every interior row."""
+    ch = orc.Channel(1, 24, 1e-6, tau_lb=1.0, G=0.0)
+    ch.run(30000)
+    u = ch.profiles()["ux"]
+    d2 = u[2:] - 2 * u[1:-1] + u[:-2]
+    assert np.allclose(d2, -1e-6 / ETA_S, rtol=1e-9)
+
+
+def test_newtonian_startup_transient(orc):
+    """Start-up from rest of a Newtonian channel follows the Fourier series
+    (Sec. IV.B: the Newtonian start-up has an explicit solution)."""
+    tau = 0.5 + math.sqrt(3 / 16)
+    eta = (tau - 0.5) / 3
+    ch = orc.Channel(1, 32, 1e-6, tau_lb=tau, G=0.0)
+    for t in [200, 1000, 3000]:
+        ch.run(t - ch.t)
+        want = analytic.newtonian_startup(32, 1e-6, eta, t)
+        got = ch.profiles()["ux"]
+        assert np.abs(got - want).max() / want.max() < 3e-3
+
+
+@pytest.mark.parametrize("ny,lam,tau0", [(64, 0.0, 2e3), (64, 0.25, 1e4), (32, 0.0, 1e3)])
+def test_nlm_steady_profile(orc, ny, lam, tau0):
+    """Sec. III.B, Eq. (maxwellpoiseuille) and Sec. IV.A: the steady LB profile
+    of the nlM fluid agrees with the analytic one within the paper's 1% (at
+    parameters inside the explicit-stress stability region)."""
+    g = 1e-6 * 64 / ny
+    ch = orc.Channel(1, ny, g, tau_lb=1.0, G=1e-4, tau0=tau0, gamma_c=0.1, visc_split=lam)
+    ch.run(40000)
+    want = analytic.steady_profile(ny, g, ETA_S, 1e-4, tau0, 0.1)
+    got = ch.profiles()["ux"]
+    assert np.abs(got - want).max() / want.max() < 1e-2
+
+
+def test_constitutive_identities_on_rows(orc):
+    """Sec. III.A/IV.A: on every row of an x-uniform steady channel
+    sigma_yy = 0, sigma_xy = G tau_M kappa_xy, N1 = 2 G tau_M^2 kappa_xy^2
+    (given the LB's own kappa and tau_M)."""
+    G = 1e-4
+    ch = orc.Channel(1, 32, 2e-6, tau_lb=1.0, G=G, tau0=1e3, gamma_c=0.1)
+    ch.run(20000)
+    f = ch.fields()
+    k, tM = f["kxy"][:, 0], f["tauM"][:, 0]
+    assert np.abs(f["kyy"]).max() < 1e-14 and np.abs(f["kyx"]).max() == 0.0
+    assert np.abs(f["syy"]).max() < 1e-16
+    sxy, n1 = f["sxy"][:, 0], f["sxx"][:, 0] - f["syy"][:, 0]
+    assert np.allclose(sxy, G * tM * k, rtol=1e-10, atol=1e-12 * np.abs(sxy).max())
+    # sigma_yy carries G tau_M kappa_yy with kappa_yy at round-off level, hence rtol 1e-8
+    assert np.allclose(n1, 2 * G * tM ** 2 * k ** 2, rtol=1e-8, atol=1e-12 * np.abs(n1).max())
+
+
+def test_mass_conservation(orc):
+    """Eq. (rhoj) with the continuity argument of Sec. II.A: the hydrodynamic
+    mass sum_nodes (sum_i n_i - delta rho_prev), delta rho_prev = -(3/2) P, is
+    conserved; the only drift is round-off (about 1e-16 per node and step).
+    A reading that subtracted delta rho inside the equilibrium would leak
+    about delta rho / tau per step and fail this by orders of magnitude."""
+    ch = orc.Channel(4, 32, 2e-6, tau_lb=1.0, G=1e-4, tau0=2e3, gamma_c=0.1)
+    n = ch.nx * ch.ny
+    q0 = ch.mass()
+    ch.run(5000)
+    assert abs(ch.P).max() > 1e-8          # normal stresses are present
+    assert abs(ch.mass() - q0) / n < 5e-16 * 5000
+    ch2 = orc.Channel(4, 32, 2e-6, tau_lb=1.0, G=1e-4, tau0=2e3, gamma_c=0.1, nn_pressure=False)
+    ch2.run(5000)
+    assert abs(ch2.n.sum() - q0) / n < 5e-16 * 5000
+
+
+def test_momentum_budget(orc):
+    """Collision conserves momentum up to the body force and streaming moves
+    it, so M_x(t+1) = M_x(t) + N f - W(t), W the momentum handed to the
+    walls by bounce-back; in the steady state W = N g."""
+    g = 2e-6
+    ch = orc.Channel(2, 32, g, tau_lb=1.0, G=1e-4, tau0=1e3, gamma_c=0.1)
+    N = ch.nx * ch.ny
+    for _ in range(30):
+        m0 = ch.momentum_x()
+        ch.run(1)
+        assert ch.momentum_x() - m0 - N * g + ch.wall_drag() == pytest.approx(0, abs=1e-13)
+    ch.run(20000)
+    assert ch.wall_drag() == pytest.approx(N * g, rel=1e-9)
+
+
+def test_transverse_pressure_balance(orc):
+    """Sec. III.B / IV.A: the normal stress difference raises the pressure in
+    the plug; in the steady state cs2 rho_e + N1/2 is uniform across the
+    channel (up to the lattice error), while cs2 rho_e itself varies."""
+    ch = orc.Channel(1, 32, 2e-6, tau_lb=1.0, G=1e-4, tau0=2e3, gamma_c=0.1)
+    ch.run(20000)
+    pr = ch.profiles()
+    p = CS2 * pr["rho_e"]
+    n1 = pr["sxx"] - pr["syy"]
+    tot = p + n1 / 2
+    assert p.max() - p.min() > 0.5 * (n1.max() - n1.min()) / 2
+    assert (tot.max() - tot.min()) < 0.05 * (p.max() - p.min())
+    assert p[16] > p[0]   # higher pressure at the centre than at the wall
+
+
+def test_symmetry_and_x_uniformity(orc):
+    """x-uniform runs stay bitwise uniform in x (kappa_xx = 0 exactly) and the
+    profile is mirror symmetric about the centre line."""
+    ch = orc.Channel(4, 30, 2e-6, tau_lb=1.0, G=1e-4, tau0=1e3, gamma_c=0.1)
+    ch.run(3000)
+    assert np.all(ch.n == ch.n[:, :, :1])
+    f = ch.fields()
+    assert np.abs(f["kxx"]).max() == 0.0
+    u = f["ux"][:, 0]
+    assert np.allclose(u, u[::-1], rtol=1e-12, atol=0)
+
+
+def test_ucm_limit_is_newtonian_in_shear(orc):
+    """gamma_c -> inf gives the UCM, a Newtonian shear viscosity eta_s + G tau
+    (Sec. III.A); the channel profile is the parabola with that viscosity,
+    up to the O(1/ny^2) lattice error, and the error falls with ny."""
+    errs = []
+    for ny in [16, 32]:
+        ch = orc.Channel(1, ny, 1e-6, tau_lb=1.0, G=1e-4, tau0=1e3, gamma_c=1e30)
+        ch.run(40000)
+        want = analytic.newtonian_parabola(ny, 1e-6, ETA_S + 0.1)
+        errs.append(np.abs(ch.profiles()["ux"] - want).max() / want.max())
+    assert errs[0] < 6e-3 and errs[1] < 1.5e-3 and errs[1] < errs[0] / 3
+
+
+def test_nn_pressure_same_steady_state(orc):
+    """Sec. II.B: with or without the delta-rho terms the steady velocity is
+    the same (Eq. (rhoplus) vanishes in a steady state)."""
+    out = []
+    for nnp in [True, False]:
+        ch = orc.Channel(1, 32, 2e-6, tau_lb=1.0, G=1e-4, tau0=1e3, gamma_c=0.1, nn_pressure=nnp)
+        ch.run(20000)
+        out.append(ch.profiles()["ux"])
+    assert np.abs(out[0] - out[1]).max() < 1e-6 * np.abs(out[0]).max()
+
+
+def test_newtonian_and_zero_modulus_identical(orc):
+    """G = 0 turns the forcing into the plain Guo body force: the nlM code path
+    with G = 0 equals a run with an infinite gamma_c and G = 0 bitwise."""
+    a = orc.Channel(1, 16, 1e-6, tau_lb=1.0, G=0.0, tau0=1e4, gamma_c=0.1)
+    b = orc.Channel(1, 16, 1e-6, tau_lb=1.0, G=0.0, tau0=5.0, gamma_c=1e30)
+    a.run(500)
+    b.run(500)
+    assert np.array_equal(a.n, b.n)
+
+
+def test_cessation_below_bingham_bound(orc):
+    """Sec. III.B / IV.B: after the force is removed a (nearly) yield-stress
+    fluid stops in finite time. The velocity falls to 1% of its start value
+    before the Bingham energy bound with plastic viscosity eta_s and yield
+    stress G gamma_c (large theta, Pe >> 1; paper-like split with tau_LB
+    matched to the low-shear viscosity)."""
+    eta_s = 1.32e-3
+    tau_lb = 0.5 + 3 * eta_s
+    G, gc, ny = 1e-5, 0.1, 32
+    tau = 0.132 / G
+    g = 2 * G * gc / (ny / 2)        # wp H = 2 gamma_c
+    T_s = 60000
+    ch = orc.Channel(1, ny, g, tau_lb=tau_lb, G=G, tau0=tau, gamma_c=gc, visc_split=1.0, t_startup=T_s)
+    ch.run(T_s)
+    u0 = ch.profiles()["ux"]
+    bound = analytic.bingham_stop_bound(u0, eta_s, G * gc, ny)
+    umid0 = u0[ny // 2]
+    t_stop = None
+    while ch.t < T_s + 2 * bound:
+        ch.run(10)
+        if ch.profiles()["ux"][ny // 2] < 1e-2 * umid0:
+            t_stop = ch.t - T_s
+            break
+    assert t_stop is not None and t_stop < bound
