@@ -1,0 +1,138 @@
+"""Throughput of the fused D2Q9 + inlM sweep on one MI355X.
+
+One step is one lattice-Boltzmann time step of the whole 4096 x 1024
+channel (every node pulled, stress evaluated, collided and stored). The
+headline value is FP32-shifted MLUPS (million lattice-node updates per
+second) with the state resident in HBM; the FP64 run of the same workload is
+reported beside it, and the FP64 CPU oracle is timed on a bounded sample of
+the same lattice on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % HBM roofline (FP32 vs FP64); steps-to-steady, learned vs from-rest"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic HBM bytes per node update: read 9 populations + the previous
+# stress trace, write 9 populations + the new trace.
+BYTES_PER_NODE = {"fp32": 80, "fp64": 160}
+
+
+def time_solver(precision, wl, steps, warmup):
+    import torch
+    from paper_1310_7450_amd import Solver
+    spec = wl["channels"][0]
+    nodes = spec.nx * spec.ny
+    with Solver([spec], precision=precision, obs_every=1000) as s:
+        s.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(s.stream)
+        s.step(steps)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1)
+        umid = s.observe(0, "umid")
+        mass = s.observe(0, "mass")
+    sec = ms / 1e3
+    per_step = sec / steps
+    mlups = nodes * steps / sec / 1e6
+    achieved = BYTES_PER_NODE[precision] * nodes / per_step / 1e9
+    return {"mlups": mlups, "ms_total": ms, "ms_per_step": ms / steps, "wall_s": wall,
+            "achieved_GBs": achieved, "frac": achieved / HBM_PEAK_GBS, "umid": umid,
+            "mass_rel_drift": (mass - nodes) / nodes}
+
+
+def cpu_baseline(wl, budget_s=15.0):
+    """The FP64 oracle as it stands, on the same lattice, for as many whole
+    steps as fit in about ``budget_s`` seconds (at least one)."""
+    from oracle import core as orc
+    spec = wl["channels"][0]
+    o = orc.Channel(spec.nx, spec.ny, spec.force, tau_lb=spec.tau_lb, G=spec.G, tau0=spec.tau0,
+                    gamma_c=spec.gamma_c, eps=spec.eps)
+    o.run(1)  # warm the code and the pages
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        o.run(1)
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    sec = time.perf_counter() - t0
+    return {"value": spec.nx * spec.ny * n / sec / 1e6, "unit": "MLUPS", "cores": orc.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} steps of the {spec.nx}x{spec.ny} lattice from rest (after 1 warm-up step), FP64"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1310_7450_amd import workloads
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    wl = workloads.large_channel()
+    spec = wl["channels"][0]
+    print(f"bench: {wl['name']} g={spec.force:.3e} eps={spec.eps:+.4f}, fp32 {args.steps} steps",
+          file=sys.stderr, flush=True)
+    r32 = time_solver("fp32", wl, args.steps, args.warmup)
+    print(f"bench: fp32 {r32['mlups']:.0f} MLUPS, {r32['achieved_GBs']:.0f} GB/s", file=sys.stderr, flush=True)
+    r64 = None
+    if not args.no_fp64:
+        r64 = time_solver("fp64", wl, args.steps, args.warmup)
+        print(f"bench: fp64 {r64['mlups']:.0f} MLUPS, {r64['achieved_GBs']:.0f} GB/s", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(wl, args.cpu_budget)
+        print(f"bench: cpu oracle {cpu['value']:.2f} MLUPS on {cpu['cores']} threads", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": round(r32["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "nx": spec.nx, "ny": spec.ny, "seed": wl["seed"],
+                   "force": spec.force, "eps": spec.eps, "tau_lb": spec.tau_lb, "G": spec.G,
+                   "tau0": spec.tau0, "gamma_c": spec.gamma_c, "precision": "fp32_shifted",
+                   "nn_pressure": 1, "start": "rest"},
+        "roofline": {"bound": "hbm", "achieved": round(r32["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(r32["frac"], 4), "traffic": None},
+        "fp64": None if r64 is None else {
+            "value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 5),
+            "roofline": {"bound": "hbm", "achieved": round(r64["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(r64["frac"], 4)}},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * lbnlm — MI355X (gfx950) lattice-Boltzmann solver for channel flow of the
+ * instantaneous nonlinear generalised Maxwell (inlM) fluid.
+ *
+ * C ABI. Plain pointers and sizes only; every call returns an lb_status
+ * (0 = LB_OK, negative = error) and, on error, leaves a message readable with
+ * lb_last_error(). A handle is bound to one HIP stream and is not thread
+ * safe; calls on different handles may run concurrently.
+ *
+ * The method (Papenkort & Voigtmann, arXiv:1310.7450): a D2Q9 BGK scheme
+ * whose forcing term carries the traceless non-Newtonian stress, the body
+ * force and the flow-induced density change (Sec. II.A, Eqs. (lbupdate),
+ * (rhoj), (bodyforce), (rhoplus)), with the stress taken each step from the
+ * steady-state series of the nonlinear Maxwell model evaluated on the
+ * instantaneous velocity gradient (Sec. III.A, Eqs. (sigtsum), (smalld),
+ * (nlmaxwell) and the inlM paragraph), the gradient from three-point central
+ * differences (Sec. II.C), in a channel with half-way bounce-back walls in y
+ * and periodic x, driven by a body force that is switched off for cessation
+ * (Sec. II.B, III.B, IV.B).
+ *
+ * Lattice units throughout: dx = dt = 1, reference density rho0 = 1,
+ * c_s^2 = 1/3, two dimensions.
+ */
+#ifndef LBNLM_LB_H
+#define LBNLM_LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lb_handle lb_handle;
+
+typedef enum {
+  LB_OK = 0,
+  LB_EINVAL = -1,     /* invalid argument (parameters, sizes, indices)       */
+  LB_ENOMEM = -2,     /* workspace too small or host allocation failed       */
+  LB_EHIP = -3,       /* a HIP runtime call failed                           */
+  LB_EUNSTABLE = -4,  /* a convergence check saw NaN/Inf in a channel         */
+  LB_ESTATE = -5      /* call not valid in the handle's current state        */
+} lb_status;
+
+typedef enum {
+  LB_FP64 = 0,          /* populations stored and updated in FP64             */
+  LB_FP32_SHIFTED = 1   /* populations stored in FP32 as n_i - a_i (a_i the   */
+                        /* rest weights); moments and updates in FP32         */
+} lb_precision;
+
+/*
+ * One channel: nx periodic nodes along the flow (x), ny fluid rows between
+ * half-way bounce-back walls at y = -1/2 and y = ny - 1/2 (half width
+ * H = ny/2). Parameters follow the problem statement of Sec. III.B:
+ *   force      body-force density g (= pressure drop per unit length with
+ *              rho0 = 1) along +x, applied for steps t < t_startup and
+ *              switched off afterwards (cessation, Sec. IV.B);
+ *   tau_lb     BGK relaxation time of the solvent, tau_lb > 1/2: the
+ *              high-shear (solvent) viscosity is eta_s = (tau_lb - 1/2)/3;
+ *   G          plateau modulus G_inf of the Maxwell stress (>= 0; 0 gives a
+ *              Newtonian fluid);
+ *   tau0       quiescent Maxwell relaxation time tau in steps at eps = 0
+ *              (> 0, may be +inf: the yield-stress limit);
+ *   gamma_c    critical strain of Eq. (nlmaxwell) (> 0);
+ *   eps        separation parameter: tau = tau0 * 10^(min(eps,0)/0.05),
+ *              G_inf = G (1 + sqrt(max(eps,0))) (the paper has no eps; this
+ *              closure is the library's definition);
+ *   visc_split lambda in [0,1]: the collision carries eta_s + lambda G tau
+ *              and the forcing Sigma^nN = sigma - lambda G tau D (lambda = 1
+ *              is the split of Sec. IV; lambda > 0 needs a finite tau);
+ *   t_startup  first step without the body force.
+ */
+typedef struct {
+  int32_t nx;
+  int32_t ny;
+  double force;
+  double tau_lb;
+  double G;
+  double tau0;
+  double gamma_c;
+  double eps;
+  double visc_split;
+  int64_t t_startup;
+} lb_channel;
+
+/*
+ * Options shared by all channels of a handle:
+ *   precision    lb_precision;
+ *   nn_pressure  1: full forcing of Eq. (bodyforce) including the
+ *                flow-induced density terms of Eq. (rhoplus); 0: those terms
+ *                are dropped (dt d(delta rho)/dt = 0);
+ *   obs_every    K, steps between convergence checks and the length of one
+ *                captured graph; even, >= 2 (default 1000 when 0);
+ *   strip_rows   rows per wavefront strip of the sweep (0: tuned default);
+ *   steady_tol   if > 0, lb_step checks every K steps the residual
+ *                R = max_y |ubar(t) - ubar(t-K)| / (K max_y |ubar(t)|) of the
+ *                x-averaged velocity ubar and freezes each channel once
+ *                R < steady_tol; 0 disables the checks.
+ */
+typedef struct {
+  int32_t precision;
+  int32_t nn_pressure;
+  int32_t obs_every;
+  int32_t strip_rows;
+  double steady_tol;
+} lb_options;
+
+/* Observables for lb_observe. Profiles return ny doubles (x-averages per row,
+ * row 0 next to the lower wall); scalars return one double. */
+enum {
+  LB_OBS_UX = 0,        /* u_x = j_x / rho_e                                 */
+  LB_OBS_UY = 1,
+  LB_OBS_SXX = 2,       /* Maxwell stress sigma (Eq. (sigtsum))             */
+  LB_OBS_SXY = 3,
+  LB_OBS_SYY = 4,
+  LB_OBS_N1 = 5,        /* sigma_xx - sigma_yy                              */
+  LB_OBS_PRESSURE = 6,  /* c_s^2 rho_e                                      */
+  LB_OBS_KXY = 7,       /* d_y u_x from the central difference              */
+  LB_OBS_TRT = 8,       /* tr Sigma^nN                                      */
+  LB_OBS_KXX = 9,       /* d_x u_x                                          */
+  LB_OBS_MASS = 32,     /* sum_nodes (sum_i n_i - delta rho_prev)            */
+  LB_OBS_MOMX = 33,     /* sum_nodes sum_i c_ix n_i                         */
+  LB_OBS_FLUX = 34,     /* sum_nodes u_x                                    */
+  LB_OBS_WALL_DRAG = 35,/* x momentum given to the walls in the last step   */
+  LB_OBS_UMID = 36,     /* x-averaged u_x at the centre line                */
+  LB_OBS_RESIDUAL = 37, /* last residual R (+inf before two checks)        */
+  LB_OBS_STEP = 38,     /* steps the channel has taken                      */
+  LB_OBS_ACTIVE = 39,   /* 1 while the channel advances, 0 once frozen      */
+  LB_OBS_NAN = 40       /* 1 if the observation saw NaN/Inf                 */
+};
+
+/* Device workspace the caller must provide for these channels and options.
+ * Returns LB_EINVAL for invalid channels or options. */
+lb_status lb_workspace_bytes(const lb_channel *channels, int32_t n_channels,
+                             const lb_options *opt, size_t *bytes);
+
+/* Creates a handle for n_channels channels (array read, not kept).
+ * dev_workspace: device memory of at least lb_workspace_bytes bytes, aligned
+ * to 256 bytes, owned by the caller, which must keep it alive until
+ * lb_destroy; the library never frees it. hip_stream: a hipStream_t (NULL:
+ * the library creates and owns one). All channels start from rest
+ * (n_i = a_i, previous stress trace 0) at step 0. */
+lb_status lb_create(const lb_channel *channels, int32_t n_channels,
+                    const lb_options *opt, void *dev_workspace, size_t ws_bytes,
+                    void *hip_stream, lb_handle **out);
+
+/* Releases the handle (graphs, host tables, an owned stream). Does not touch
+ * the workspace. NULL is accepted. */
+lb_status lb_destroy(lb_handle *h);
+
+/* Advances every active channel by up to n_steps steps, asynchronously on the
+ * handle's stream, except that with steady_tol > 0 it synchronises every K
+ * steps to read the residuals; returns when all channels are frozen or
+ * n_steps are done. LB_EUNSTABLE if a check saw NaN/Inf. */
+lb_status lb_step(lb_handle *h, int64_t n_steps);
+
+/* Reads one observable of channel ch at its current step into host_out
+ * (n doubles available). Synchronises the stream. */
+lb_status lb_observe(lb_handle *h, int32_t ch, int32_t what, double *host_out, size_t n);
+
+/* Copies the state of channel ch to host memory: the post-streaming
+ * populations n_i(x, y) of the current step as pops[9][ny][nx] (velocity
+ * order (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1)) and the
+ * previous stress trace P[ny][nx], in FP64. Synchronises the stream. */
+lb_status lb_get_state(lb_handle *h, int32_t ch, double *pops, double *P);
+
+/* Overwrites the state of channel ch (same layout as lb_get_state) and sets
+ * its step counter to t. Synchronises the stream. */
+lb_status lb_set_state(lb_handle *h, int32_t ch, const double *pops, const double *P, int64_t t);
+
+/* Initialises channel ch from a predicted steady profile (a warm start):
+ * u_x and N1 given at n_pts points, either the ny lattice rows (n_pts == ny)
+ * or the Chebyshev-Gauss points d_k = cos(pi (2k+1) / (2 n_pts)) across the
+ * channel (d = (y - y_c)/H, n_pts != ny). Populations are set to the
+ * equilibrium at u = (u_x, 0) and rho_e = 1 - (3/2) N1 (so that the
+ * hydrodynamic mass equals that of the rest state) and the previous trace to
+ * N1. The step counter is kept. */
+lb_status lb_set_profile(lb_handle *h, int32_t ch, const double *ux, const double *n1, int32_t n_pts);
+
+/* Message of the last error on this handle (never NULL). */
+const char *lb_last_error(const lb_handle *h);
+
+/* Name of a status code. */
+const char *lb_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBNLM_LB_H */

@@ -50,6 +50,7 @@ def lib():
         L.orc_wall_drag.argtypes = [C.c_int, C.c_int, dp]
         L.orc_wall_drag.restype = C.c_double
         L.orc_num_fields.restype = C.c_int
+        L.orc_num_threads.restype = C.c_int
         assert L.orc_num_fields() == len(FIELDS)
         _lib = L
     return _lib
@@ -58,6 +59,10 @@ def lib():
 def _p(a):
     assert a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def num_threads():
+    return int(lib().orc_num_threads())
 
 
 def equilibrium(rho, ux, uy):

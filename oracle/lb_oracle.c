@@ -61,6 +61,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* D2Q9 velocities in the order (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),
  * (-1,-1),(1,-1) and their weights. */
@@ -204,6 +207,15 @@ enum {
   OF_TRT, OF_R, OF_RHOE, OF_UX, OF_UY, OF_S, OF_MX, OF_MY, OF_TAUM, OF_COUNT
 };
 int orc_num_fields(void) { return OF_COUNT; }
+
+/* Threads an OpenMP loop of the oracle uses. */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* One time step t -> t+1 of one channel. n: 9 planes of nx*ny post-streaming
  * populations at time t; P: stress trace of step t-1. Writes the state at

@@ -1,0 +1,12 @@
+"""lbnlm: MI355X-native lattice-Boltzmann solver for channel flow of the
+instantaneous nonlinear generalised Maxwell fluid (Papenkort & Voigtmann,
+arXiv:1310.7450).
+
+The solver is the C-ABI library ``liblbnlm.so`` (``include/lb.h``) built from
+the gfx950 HIP sources in ``csrc/``; :mod:`.lbnlm` is its Python binding.
+"""
+from .lbnlm import (ABI_FUNCTIONS, FP32_SHIFTED, FP64, PROFILES, SCALARS, ChannelSpec, LbError,
+                    Solver, load_library, options, workspace_bytes)
+
+__all__ = ["ABI_FUNCTIONS", "FP32_SHIFTED", "FP64", "PROFILES", "SCALARS", "ChannelSpec", "LbError",
+           "Solver", "load_library", "options", "workspace_bytes"]

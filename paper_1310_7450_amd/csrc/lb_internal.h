@@ -1,0 +1,77 @@
+// Internal types shared by the host runtime and the gfx950 kernels of lbnlm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbnlm {
+
+// Number of stored planes: nine populations and the previous stress trace.
+constexpr int kPlanes = 10;
+// Per-row observation fields accumulated in FP64 (x sums per row).
+enum ObsField {
+  OF_UX = 0, OF_UY, OF_SXX, OF_SXY, OF_SYY, OF_RHOE_DEV, OF_MASS_DEV, OF_MOMX,
+  OF_KXY, OF_TRT, OF_DRAG, OF_KXX, OF_COUNT
+};
+// Per-channel scalars written by the reduction kernel.
+enum ChanScalar {
+  CS_MASS_DEV = 0, CS_MOMX, CS_FLUX, CS_DRAG, CS_UMID, CS_RESIDUAL, CS_UMAX, CS_NAN, CS_COUNT
+};
+
+// Resolved parameters of one channel as the kernels read them.
+struct ChanDev {
+  long long off;        // element offset of node (0,0) in every plane
+  long long t;          // steps completed before the current launch group
+  long long t_startup;  // first step without body force
+  int nx, ny;
+  int row_off;          // first row of this channel in the per-row buffers
+  int poff;             // first partial row of this channel
+  int nxs;              // partial columns per row (x strips)
+  int active;
+  double g;             // body-force density
+  double omega;         // 1 / tau_eff
+  double kf;            // 1 - 1/(2 tau_eff)
+  double sp;            // -9 / (2 tau_eff): stress coefficient of the forcing
+  double G;             // G_inf
+  double inv_tau;       // 1/tau (0 for tau = inf)
+  double inv_gc;        // 1/gamma_c
+  double lgt;           // lambda G_inf tau
+};
+
+// Work unit of one wavefront: rows [y0, y1) of channel ch, starting at
+// column x0 (wide mode: first interior column; narrow mode: 0).
+struct Strip {
+  int ch, x0, y0, y1;
+};
+
+struct SweepArgs {
+  const void *A;        // state read (10 planes)
+  void *B;              // state written (10 planes)
+  long long plane;      // plane stride in elements
+  const Strip *strips;
+  const ChanDev *ch;
+  double *part;         // observation partials [row][OF_COUNT]
+  int n_strips;
+  int n_wg;
+  int k;                // step offset added to every channel's t
+  int nnp;              // keep the flow-induced density terms
+};
+
+// Lane-group width classes of the sweep: nx in {1,2,4,...,64} runs a whole
+// period per lane group ("narrow"); anything else runs 64-lane strips with
+// one halo lane on each side ("wide").
+constexpr int kWideClass = 7;
+inline int width_class(int nx) {
+  for (int c = 0; c < 7; ++c)
+    if (nx == (1 << c)) return c;
+  return kWideClass;
+}
+
+// Host launchers (defined in lb_kernels.hip).
+hipError_t launch_sweep(int fp32, int cls, bool observe, const SweepArgs &a, hipStream_t s);
+hipError_t launch_reduce(const ChanDev *ch, int n_ch, const double *part, double *prof,
+                         double *prev_ux, double *scal, int update_residual, int steps_since,
+                         hipStream_t s);
+hipError_t launch_advance(ChanDev *ch, int n_ch, int steps, hipStream_t s);
+
+}  // namespace lbnlm

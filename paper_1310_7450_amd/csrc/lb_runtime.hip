@@ -1,0 +1,720 @@
+// Host runtime and C ABI of lbnlm: parameter resolution, workspace layout,
+// strip work lists, captured step graphs, convergence checks, observation
+// and state transfer. See include/lb.h for the contract of every entry point.
+#include "lb.h"
+#include "lb_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace lbnlm;
+
+namespace {
+
+constexpr int kWideInterior = 62;  // interior columns of a wide strip
+constexpr int kDefaultK = 1000;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// D2Q9 velocities and rest weights, host side (layout conversion only).
+constexpr int HCX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int HCY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int HOPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+inline double hweight(int i) { return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
+
+struct Layout {
+  long long plane = 0;       // elements per plane
+  int esize = 8;             // bytes per element
+  int total_rows = 0;
+  int total_part = 0;
+  int max_strips = 0;
+  size_t off_state[2] = {0, 0}, off_ch = 0, off_strips = 0, off_astrips = 0, off_part = 0,
+         off_prof = 0, off_prev = 0, off_scal = 0, bytes = 0;
+  std::vector<ChanDev> ch;
+};
+
+std::string validate(const lb_channel *c, int n, const lb_options *o) {
+  if (!c || n <= 0) return "no channels";
+  if (!o) return "options are NULL";
+  if (o->precision != LB_FP64 && o->precision != LB_FP32_SHIFTED) return "unknown precision";
+  if (o->nn_pressure != 0 && o->nn_pressure != 1) return "nn_pressure must be 0 or 1";
+  if (o->obs_every < 0 || (o->obs_every > 0 && (o->obs_every < 2 || (o->obs_every & 1))))
+    return "obs_every must be 0 or an even number >= 2";
+  if (o->strip_rows < 0 || o->strip_rows > 4096) return "strip_rows out of range";
+  if (!(o->steady_tol >= 0) || !std::isfinite(o->steady_tol)) return "steady_tol must be >= 0";
+  for (int i = 0; i < n; ++i) {
+    const lb_channel &q = c[i];
+    char buf[160];
+    auto bad = [&](const char *what) {
+      snprintf(buf, sizeof buf, "channel %d: %s", i, what);
+      return std::string(buf);
+    };
+    if (q.nx < 1 || q.ny < 1) return bad("nx and ny must be >= 1");
+    if ((long long)q.nx * q.ny > (1LL << 31)) return bad("too many nodes");
+    if (!(q.tau_lb > 0.5) || !std::isfinite(q.tau_lb)) return bad("tau_lb must be > 1/2");
+    if (!(q.G >= 0) || !std::isfinite(q.G)) return bad("G must be >= 0");
+    if (!(q.tau0 > 0)) return bad("tau0 must be > 0");
+    if (!(q.gamma_c > 0)) return bad("gamma_c must be > 0");
+    if (!std::isfinite(q.force)) return bad("force must be finite");
+    if (!std::isfinite(q.eps)) return bad("eps must be finite");
+    if (!(q.visc_split >= 0 && q.visc_split <= 1)) return bad("visc_split must be in [0,1]");
+    if (q.visc_split > 0 && std::isinf(q.tau0)) return bad("visc_split > 0 needs a finite tau0");
+  }
+  return "";
+}
+
+// Separation closure and viscosity split of the channel parameters.
+void resolve(const lb_channel &q, ChanDev &d) {
+  const double eta_s = (q.tau_lb - 0.5) / 3.0;
+  const double tau = q.tau0 * std::pow(10.0, std::min(q.eps, 0.0) / 0.05);
+  const double Ginf = q.G * (1.0 + std::sqrt(std::max(q.eps, 0.0)));
+  const double lgt = q.visc_split > 0 ? q.visc_split * Ginf * tau : 0.0;
+  const double tau_eff = 0.5 + 3.0 * (eta_s + lgt);
+  d.t = 0;
+  d.t_startup = q.t_startup;
+  d.nx = q.nx;
+  d.ny = q.ny;
+  d.active = 1;
+  d.g = q.force;
+  d.omega = 1.0 / tau_eff;
+  d.kf = 1.0 - 0.5 / tau_eff;
+  d.sp = -4.5 / tau_eff;
+  d.G = Ginf;
+  d.inv_tau = std::isinf(tau) ? 0.0 : 1.0 / tau;
+  d.inv_gc = 1.0 / q.gamma_c;
+  d.lgt = lgt;
+}
+
+int strip_rows_for(int cls, int nx, int ny, int requested) {
+  if (cls == kWideClass) {
+    int s = requested > 0 ? requested : 16;
+    return std::max(1, std::min(s, ny));
+  }
+  const int tyw = 64 / nx;
+  int s = requested > 0 ? requested : std::max(64, tyw);
+  s = (s + tyw - 1) / tyw * tyw;
+  return s;
+}
+
+// Strips of one channel, column-major (vertical neighbours adjacent).
+void add_strips(int ci, const ChanDev &d, int srows, std::vector<Strip> &out) {
+  const int cls = width_class(d.nx);
+  const int nxs = (cls == kWideClass) ? (d.nx + kWideInterior - 1) / kWideInterior : 1;
+  for (int xs = 0; xs < nxs; ++xs)
+    for (int y0 = 0; y0 < d.ny; y0 += srows)
+      out.push_back(Strip{ci, xs * kWideInterior, y0, std::min(y0 + srows, d.ny)});
+}
+
+Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
+  Layout L;
+  L.esize = (o->precision == LB_FP32_SHIFTED) ? 4 : 8;
+  L.ch.resize(n);
+  long long node = 0;
+  int rows = 0, part = 0, strips = 0;
+  for (int i = 0; i < n; ++i) {
+    ChanDev &d = L.ch[i];
+    resolve(c[i], d);
+    d.off = node;
+    node += (long long)align_up((size_t)c[i].nx * c[i].ny, 64);
+    d.row_off = rows;
+    rows += c[i].ny;
+    const int cls = width_class(c[i].nx);
+    d.nxs = (cls == kWideClass) ? (c[i].nx + kWideInterior - 1) / kWideInterior : 1;
+    d.poff = part;
+    part += d.nxs * c[i].ny;
+    const int srows = strip_rows_for(cls, c[i].nx, c[i].ny, o->strip_rows);
+    strips += d.nxs * ((c[i].ny + srows - 1) / srows);
+  }
+  L.plane = (long long)align_up((size_t)std::max<long long>(node, 64), 64);
+  L.total_rows = rows;
+  L.total_part = part;
+  L.max_strips = strips;
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    size_t p = at;
+    at = align_up(at + bytes, kAlign);
+    return p;
+  };
+  const size_t state = (size_t)kPlanes * L.plane * L.esize;
+  L.off_state[0] = take(state);
+  L.off_state[1] = take(state);
+  L.off_ch = take(sizeof(ChanDev) * n);
+  L.off_strips = take(sizeof(Strip) * strips);
+  L.off_astrips = take(sizeof(Strip) * strips);
+  L.off_part = take(sizeof(double) * OF_COUNT * part);
+  L.off_prof = take(sizeof(double) * OF_COUNT * rows);
+  L.off_prev = take(sizeof(double) * rows);
+  L.off_scal = take(sizeof(double) * CS_COUNT * n);
+  L.bytes = at;
+  return L;
+}
+
+}  // namespace
+
+struct lb_handle {
+  Layout L;
+  lb_options opt{};
+  int n_ch = 0;
+  int K = kDefaultK;
+  std::vector<lb_channel> in;
+  char *ws = nullptr;
+  void *buf[2] = {nullptr, nullptr};
+  ChanDev *dch = nullptr;
+  Strip *dall = nullptr;     // every channel, for observation
+  Strip *dact = nullptr;     // active channels, for stepping
+  double *dpart = nullptr, *dprof = nullptr, *dprev = nullptr, *dscal = nullptr;
+  // strips grouped by width class: [begin, begin + count) in the arrays
+  int all_begin[8] = {0}, all_count[8] = {0};
+  int act_begin[8] = {0}, act_count[8] = {0};
+  int cur = 0;               // buffer holding the current state
+  hipStream_t stream = nullptr, cap = nullptr;
+  bool own_stream = false;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  bool obs_valid = false;
+  std::vector<double> hprof, hscal;
+  std::vector<long long> t;  // host mirror of every channel's step
+  std::vector<int> active;
+  int n_checks = 0;
+  std::string err;
+};
+
+namespace {
+
+lb_status fail(lb_handle *h, lb_status s, const std::string &msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+lb_status hipfail(lb_handle *h, hipError_t e, const char *where) {
+  return fail(h, LB_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHECK(h, call)                                  \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return hipfail((h), e_, #call);  \
+  } while (0)
+
+void group_strips(const std::vector<Strip> &s, const std::vector<ChanDev> &ch,
+                  std::vector<Strip> &out, int begin[8], int count[8]) {
+  out.clear();
+  for (int c = 0; c < 8; ++c) {
+    begin[c] = (int)out.size();
+    for (const Strip &x : s)
+      if (width_class(ch[x.ch].nx) == c) out.push_back(x);
+    count[c] = (int)out.size() - begin[c];
+  }
+}
+
+lb_status upload_strips(lb_handle *h, bool all) {
+  std::vector<Strip> raw, grouped;
+  for (int i = 0; i < h->n_ch; ++i) {
+    if (!all && !h->active[i]) continue;
+    const ChanDev &d = h->L.ch[i];
+    add_strips(i, d, strip_rows_for(width_class(d.nx), d.nx, d.ny, h->opt.strip_rows), raw);
+  }
+  if (all) {
+    group_strips(raw, h->L.ch, grouped, h->all_begin, h->all_count);
+    if (!grouped.empty())
+      HIPCHECK(h, hipMemcpyAsync(h->dall, grouped.data(), grouped.size() * sizeof(Strip),
+                                 hipMemcpyHostToDevice, h->stream));
+  } else {
+    group_strips(raw, h->L.ch, grouped, h->act_begin, h->act_count);
+    if (!grouped.empty())
+      HIPCHECK(h, hipMemcpyAsync(h->dact, grouped.data(), grouped.size() * sizeof(Strip),
+                                 hipMemcpyHostToDevice, h->stream));
+  }
+  // the host vector dies here: make the copy complete first
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  return LB_OK;
+}
+
+SweepArgs sweep_args(lb_handle *h, const Strip *strips, int begin, int count, int src, int k) {
+  SweepArgs a{};
+  a.A = h->buf[src];
+  a.B = h->buf[src ^ 1];
+  a.plane = h->L.plane;
+  a.strips = strips + begin;
+  a.ch = h->dch;
+  a.part = h->dpart;
+  a.n_strips = count;
+  a.n_wg = (count + 3) / 4;
+  a.k = k;
+  a.nnp = h->opt.nn_pressure;
+  return a;
+}
+
+// Enqueues the sweeps of one step (source buffer src, step offset k).
+lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s) {
+  for (int c = 0; c < 8; ++c) {
+    if (!h->act_count[c]) continue;
+    SweepArgs a = sweep_args(h, h->dact, h->act_begin[c], h->act_count[c], src, k);
+    HIPCHECK(h, launch_sweep(h->opt.precision == LB_FP32_SHIFTED, c, false, a, s));
+  }
+  return LB_OK;
+}
+
+lb_status enqueue_observe(lb_handle *h, int update_residual, int steps_since) {
+  for (int c = 0; c < 8; ++c) {
+    if (!h->all_count[c]) continue;
+    SweepArgs a = sweep_args(h, h->dall, h->all_begin[c], h->all_count[c], h->cur, 0);
+    HIPCHECK(h, launch_sweep(h->opt.precision == LB_FP32_SHIFTED, c, true, a, h->stream));
+  }
+  HIPCHECK(h, launch_reduce(h->dch, h->n_ch, h->dpart, h->dprof, h->dprev, h->dscal,
+                            update_residual, steps_since, h->stream));
+  return LB_OK;
+}
+
+void drop_graphs(lb_handle *h) {
+  for (int p = 0; p < 2; ++p)
+    if (h->graph[p]) {
+      (void)hipGraphExecDestroy(h->graph[p]);
+      h->graph[p] = nullptr;
+    }
+}
+
+// Captures K steps starting from buffer src, followed by the step-counter
+// advance, as one graph (K is even, so the state returns to buffer src).
+lb_status capture(lb_handle *h, int src) {
+  hipGraph_t g = nullptr;
+  HIPCHECK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed));
+  lb_status st = LB_OK;
+  for (int k = 0; k < h->K && st == LB_OK; ++k) st = enqueue_step(h, src ^ (k & 1), k, h->cap);
+  if (st == LB_OK) {
+    hipError_t e = launch_advance(h->dch, h->n_ch, h->K, h->cap);
+    if (e != hipSuccess) st = hipfail(h, e, "launch_advance");
+  }
+  hipError_t e = hipStreamEndCapture(h->cap, &g);
+  if (st != LB_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hipfail(h, e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&h->graph[src], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hipfail(h, e, "hipGraphInstantiate");
+  return LB_OK;
+}
+
+lb_status read_observation(lb_handle *h) {
+  if (h->obs_valid) return LB_OK;
+  lb_status st = enqueue_observe(h, 0, 0);
+  if (st != LB_OK) return st;
+  h->hprof.resize((size_t)h->L.total_rows * OF_COUNT);
+  h->hscal.resize((size_t)h->n_ch * CS_COUNT);
+  HIPCHECK(h, hipMemcpyAsync(h->hprof.data(), h->dprof, h->hprof.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipMemcpyAsync(h->hscal.data(), h->dscal, h->hscal.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  h->obs_valid = true;
+  return LB_OK;
+}
+
+// Convergence check after a graph: residuals of all channels, freeze the
+// converged ones and rebuild the active work list.
+lb_status check_steady(lb_handle *h) {
+  const int first = (h->n_checks == 0);
+  lb_status st = enqueue_observe(h, 1, h->K);
+  if (st != LB_OK) return st;
+  h->n_checks++;
+  h->hscal.resize((size_t)h->n_ch * CS_COUNT);
+  h->hprof.resize((size_t)h->L.total_rows * OF_COUNT);
+  HIPCHECK(h, hipMemcpyAsync(h->hscal.data(), h->dscal, h->hscal.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipMemcpyAsync(h->hprof.data(), h->dprof, h->hprof.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  h->obs_valid = true;
+  bool changed = false, unstable = false;
+  for (int i = 0; i < h->n_ch; ++i) {
+    if (!h->active[i]) continue;
+    const double *s = &h->hscal[(size_t)i * CS_COUNT];
+    if (s[CS_NAN] != 0.0) unstable = true;
+    if (!first && s[CS_RESIDUAL] < h->opt.steady_tol) {
+      h->active[i] = 0;
+      h->L.ch[i].active = 0;
+      changed = true;
+    }
+  }
+  if (unstable) return fail(h, LB_EUNSTABLE, "NaN/Inf seen in a channel during a convergence check");
+  if (changed) {
+    // publish the active flags and the new work list, then recapture
+    std::vector<ChanDev> cur(h->n_ch);
+    HIPCHECK(h, hipMemcpyAsync(cur.data(), h->dch, sizeof(ChanDev) * h->n_ch, hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    for (int i = 0; i < h->n_ch; ++i) cur[i].active = h->active[i];
+    HIPCHECK(h, hipMemcpyAsync(h->dch, cur.data(), sizeof(ChanDev) * h->n_ch, hipMemcpyHostToDevice, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    lb_status u = upload_strips(h, false);
+    if (u != LB_OK) return u;
+    drop_graphs(h);
+  }
+  return LB_OK;
+}
+
+lb_status fill_rest(lb_handle *h, int which);
+
+}  // namespace
+
+extern "C" {
+
+const char *lb_status_string(int32_t s) {
+  switch (s) {
+    case LB_OK: return "LB_OK";
+    case LB_EINVAL: return "LB_EINVAL";
+    case LB_ENOMEM: return "LB_ENOMEM";
+    case LB_EHIP: return "LB_EHIP";
+    case LB_EUNSTABLE: return "LB_EUNSTABLE";
+    case LB_ESTATE: return "LB_ESTATE";
+    default: return "unknown status";
+  }
+}
+
+const char *lb_last_error(const lb_handle *h) { return h ? h->err.c_str() : "NULL handle"; }
+
+lb_status lb_workspace_bytes(const lb_channel *c, int32_t n, const lb_options *o, size_t *bytes) {
+  if (!bytes) return LB_EINVAL;
+  if (!validate(c, n, o).empty()) return LB_EINVAL;
+  *bytes = make_layout(c, n, o).bytes;
+  return LB_OK;
+}
+
+lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *ws, size_t ws_bytes,
+                    void *stream, lb_handle **out) {
+  if (!out) return LB_EINVAL;
+  *out = nullptr;
+  if (!validate(c, n, o).empty()) return LB_EINVAL;
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign)) return LB_EINVAL;
+  lb_handle *h = new (std::nothrow) lb_handle();
+  if (!h) return LB_ENOMEM;
+  h->L = make_layout(c, n, o);
+  if (ws_bytes < h->L.bytes) {
+    delete h;
+    return LB_ENOMEM;
+  }
+  h->opt = *o;
+  h->n_ch = n;
+  h->K = o->obs_every > 0 ? o->obs_every : kDefaultK;
+  h->in.assign(c, c + n);
+  h->ws = static_cast<char *>(ws);
+  h->buf[0] = h->ws + h->L.off_state[0];
+  h->buf[1] = h->ws + h->L.off_state[1];
+  h->dch = reinterpret_cast<ChanDev *>(h->ws + h->L.off_ch);
+  h->dall = reinterpret_cast<Strip *>(h->ws + h->L.off_strips);
+  h->dact = reinterpret_cast<Strip *>(h->ws + h->L.off_astrips);
+  h->dpart = reinterpret_cast<double *>(h->ws + h->L.off_part);
+  h->dprof = reinterpret_cast<double *>(h->ws + h->L.off_prof);
+  h->dprev = reinterpret_cast<double *>(h->ws + h->L.off_prev);
+  h->dscal = reinterpret_cast<double *>(h->ws + h->L.off_scal);
+  h->t.assign(n, 0);
+  h->active.assign(n, 1);
+  auto bail = [&](lb_status s) {
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    return s;
+  };
+  if (stream) {
+    h->stream = static_cast<hipStream_t>(stream);
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) return bail(LB_EHIP);
+    h->own_stream = true;
+  }
+  if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) return bail(LB_EHIP);
+  if (hipMemcpyAsync(h->dch, h->L.ch.data(), sizeof(ChanDev) * n, hipMemcpyHostToDevice, h->stream) !=
+      hipSuccess)
+    return bail(LB_EHIP);
+  std::vector<double> nanrows(std::max(1, h->L.total_rows), std::numeric_limits<double>::quiet_NaN());
+  if (hipMemcpyAsync(h->dprev, nanrows.data(), sizeof(double) * h->L.total_rows, hipMemcpyHostToDevice,
+                     h->stream) != hipSuccess)
+    return bail(LB_EHIP);
+  if (upload_strips(h, true) != LB_OK || upload_strips(h, false) != LB_OK) return bail(LB_EHIP);
+  if (fill_rest(h, 0) != LB_OK || fill_rest(h, 1) != LB_OK) return bail(LB_EHIP);
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(LB_EHIP);
+  *out = h;
+  return LB_OK;
+}
+
+lb_status lb_destroy(lb_handle *h) {
+  if (!h) return LB_OK;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  drop_graphs(h);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+  return LB_OK;
+}
+
+lb_status lb_step(lb_handle *h, int64_t n) {
+  if (!h) return LB_EINVAL;
+  if (n < 0) return fail(h, LB_EINVAL, "negative step count");
+  h->obs_valid = false;
+  int64_t left = n;
+  while (left > 0) {
+    bool any = false;
+    for (int a : h->active) any |= (a != 0);
+    if (!any) break;
+    if (left >= h->K) {
+      if (!h->graph[h->cur]) {
+        lb_status st = capture(h, h->cur);
+        if (st != LB_OK) return st;
+      }
+      HIPCHECK(h, hipGraphLaunch(h->graph[h->cur], h->stream));
+      for (int i = 0; i < h->n_ch; ++i)
+        if (h->active[i]) h->t[i] += h->K;
+      left -= h->K;
+      h->obs_valid = false;
+      if (h->opt.steady_tol > 0) {
+        lb_status st = check_steady(h);
+        if (st != LB_OK) return st;
+      }
+    } else {
+      const int m = (int)left;
+      for (int k = 0; k < m; ++k) {
+        lb_status st = enqueue_step(h, h->cur ^ (k & 1), k, h->stream);
+        if (st != LB_OK) return st;
+      }
+      HIPCHECK(h, launch_advance(h->dch, h->n_ch, m, h->stream));
+      for (int i = 0; i < h->n_ch; ++i)
+        if (h->active[i]) h->t[i] += m;
+      h->cur ^= (m & 1);
+      left = 0;
+    }
+  }
+  h->obs_valid = false;
+  return LB_OK;
+}
+
+lb_status lb_observe(lb_handle *h, int32_t ch, int32_t what, double *out, size_t n) {
+  if (!h) return LB_EINVAL;
+  if (ch < 0 || ch >= h->n_ch || !out) return fail(h, LB_EINVAL, "bad channel or output");
+  const ChanDev &d = h->L.ch[ch];
+  if (what == LB_OBS_STEP) {
+    if (n < 1) return fail(h, LB_EINVAL, "output too small");
+    out[0] = (double)h->t[ch];
+    return LB_OK;
+  }
+  if (what == LB_OBS_ACTIVE) {
+    if (n < 1) return fail(h, LB_EINVAL, "output too small");
+    out[0] = h->active[ch];
+    return LB_OK;
+  }
+  lb_status st = read_observation(h);
+  if (st != LB_OK) return st;
+  const double *s = &h->hscal[(size_t)ch * CS_COUNT];
+  const double *pr = &h->hprof[(size_t)d.row_off * OF_COUNT];
+  const long long N = (long long)d.nx * d.ny;
+  if (what >= 32) {
+    if (n < 1) return fail(h, LB_EINVAL, "output too small");
+    switch (what) {
+      case LB_OBS_MASS: out[0] = (double)N + s[CS_MASS_DEV]; return LB_OK;
+      case LB_OBS_MOMX: out[0] = s[CS_MOMX]; return LB_OK;
+      case LB_OBS_FLUX: out[0] = s[CS_FLUX]; return LB_OK;
+      case LB_OBS_WALL_DRAG: out[0] = s[CS_DRAG]; return LB_OK;
+      case LB_OBS_UMID: out[0] = s[CS_UMID]; return LB_OK;
+      case LB_OBS_RESIDUAL: {
+        // residual is only meaningful after two checks
+        out[0] = h->n_checks >= 2 ? s[CS_RESIDUAL] : INFINITY;
+        return LB_OK;
+      }
+      case LB_OBS_NAN: out[0] = s[CS_NAN]; return LB_OK;
+      default: return fail(h, LB_EINVAL, "unknown observable");
+    }
+  }
+  if (n < (size_t)d.ny) return fail(h, LB_EINVAL, "output shorter than ny");
+  for (int y = 0; y < d.ny; ++y) {
+    const double *r = pr + (size_t)y * OF_COUNT;
+    double v;
+    switch (what) {
+      case LB_OBS_UX: v = r[OF_UX]; break;
+      case LB_OBS_UY: v = r[OF_UY]; break;
+      case LB_OBS_SXX: v = r[OF_SXX]; break;
+      case LB_OBS_SXY: v = r[OF_SXY]; break;
+      case LB_OBS_SYY: v = r[OF_SYY]; break;
+      case LB_OBS_N1: v = r[OF_SXX] - r[OF_SYY]; break;
+      case LB_OBS_PRESSURE: v = (1.0 + r[OF_RHOE_DEV]) / 3.0; break;
+      case LB_OBS_KXY: v = r[OF_KXY]; break;
+      case LB_OBS_TRT: v = r[OF_TRT]; break;
+      case LB_OBS_KXX: v = r[OF_KXX]; break;
+      default: return fail(h, LB_EINVAL, "unknown observable");
+    }
+    out[y] = v;
+  }
+  return LB_OK;
+}
+
+lb_status lb_get_state(lb_handle *h, int32_t ch, double *pops, double *P) {
+  if (!h) return LB_EINVAL;
+  if (ch < 0 || ch >= h->n_ch || !pops || !P) return fail(h, LB_EINVAL, "bad channel or output");
+  const ChanDev &d = h->L.ch[ch];
+  const size_t N = (size_t)d.nx * d.ny;
+  const int es = h->L.esize;
+  std::vector<char> raw((size_t)kPlanes * N * es);
+  const char *src = static_cast<const char *>(h->buf[h->cur]);
+  for (int p = 0; p < kPlanes; ++p)
+    HIPCHECK(h, hipMemcpyAsync(raw.data() + (size_t)p * N * es,
+                               src + ((size_t)p * h->L.plane + d.off) * es, N * es,
+                               hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  auto at = [&](int p, size_t id) -> double {
+    if (es == 8) return reinterpret_cast<const double *>(raw.data())[(size_t)p * N + id];
+    const double v = reinterpret_cast<const float *>(raw.data())[(size_t)p * N + id];
+    return p < 9 ? v + hweight(p) : v;
+  };
+  // the pull: stored slot (plane i, source node) -> n_i at the destination
+  for (int y = 0; y < d.ny; ++y)
+    for (int x = 0; x < d.nx; ++x) {
+      const size_t id = (size_t)y * d.nx + x;
+      for (int i = 0; i < 9; ++i) {
+        const int ys = y - HCY[i];
+        const int xs = ((x - HCX[i]) % d.nx + d.nx) % d.nx;
+        double v;
+        if (ys < 0 || ys >= d.ny)
+          v = at(HOPP[i], id);
+        else
+          v = at(i, (size_t)ys * d.nx + xs);
+        pops[(size_t)i * N + id] = v;
+      }
+      P[id] = at(9, id);
+    }
+  return LB_OK;
+}
+
+lb_status lb_set_state(lb_handle *h, int32_t ch, const double *pops, const double *P, int64_t t) {
+  if (!h) return LB_EINVAL;
+  if (ch < 0 || ch >= h->n_ch || !pops || !P || t < 0) return fail(h, LB_EINVAL, "bad arguments");
+  const ChanDev &d = h->L.ch[ch];
+  const size_t N = (size_t)d.nx * d.ny;
+  const int es = h->L.esize;
+  std::vector<char> raw((size_t)kPlanes * N * es);
+  auto put = [&](int p, size_t id, double v) {
+    if (es == 8)
+      reinterpret_cast<double *>(raw.data())[(size_t)p * N + id] = v;
+    else
+      reinterpret_cast<float *>(raw.data())[(size_t)p * N + id] = (float)(p < 9 ? v - hweight(p) : v);
+  };
+  // inverse of the pull: every stored slot feeds exactly one (node, i)
+  for (int y = 0; y < d.ny; ++y)
+    for (int x = 0; x < d.nx; ++x) {
+      const size_t id = (size_t)y * d.nx + x;
+      for (int i = 0; i < 9; ++i) {
+        const int ys = y - HCY[i];
+        const int xs = ((x - HCX[i]) % d.nx + d.nx) % d.nx;
+        const double v = pops[(size_t)i * N + id];
+        if (ys < 0 || ys >= d.ny)
+          put(HOPP[i], id, v);
+        else
+          put(i, (size_t)ys * d.nx + xs, v);
+      }
+      put(9, id, P[id]);
+    }
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  char *dst = static_cast<char *>(h->buf[h->cur]);
+  for (int p = 0; p < kPlanes; ++p)
+    HIPCHECK(h, hipMemcpyAsync(dst + ((size_t)p * h->L.plane + d.off) * es,
+                               raw.data() + (size_t)p * N * es, N * es, hipMemcpyHostToDevice, h->stream));
+  // step counter and residual history of this channel
+  std::vector<ChanDev> cur(h->n_ch);
+  HIPCHECK(h, hipMemcpyAsync(cur.data(), h->dch, sizeof(ChanDev) * h->n_ch, hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  cur[ch].t = t;
+  HIPCHECK(h, hipMemcpyAsync(h->dch, cur.data(), sizeof(ChanDev) * h->n_ch, hipMemcpyHostToDevice, h->stream));
+  std::vector<double> nanrows(d.ny, std::numeric_limits<double>::quiet_NaN());
+  HIPCHECK(h, hipMemcpyAsync(h->dprev + d.row_off, nanrows.data(), sizeof(double) * d.ny,
+                             hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  h->t[ch] = t;
+  h->obs_valid = false;
+  return LB_OK;
+}
+
+lb_status lb_set_profile(lb_handle *h, int32_t ch, const double *ux, const double *n1, int32_t n_pts) {
+  if (!h) return LB_EINVAL;
+  if (ch < 0 || ch >= h->n_ch || !ux || !n1 || n_pts < 1) return fail(h, LB_EINVAL, "bad arguments");
+  const ChanDev &d = h->L.ch[ch];
+  std::vector<double> u(d.ny), q(d.ny);
+  if (n_pts == d.ny) {
+    for (int y = 0; y < d.ny; ++y) {
+      u[y] = ux[y];
+      q[y] = n1[y];
+    }
+  } else {
+    // barycentric interpolation on the Chebyshev-Gauss points
+    // d_k = cos(pi (2k+1)/(2n)), weights (-1)^k sin(pi (2k+1)/(2n))
+    const double H = 0.5 * d.ny, yc = 0.5 * (d.ny - 1);
+    for (int y = 0; y < d.ny; ++y) {
+      const double dd = (y - yc) / H;
+      double num_u = 0, num_q = 0, den = 0;
+      int hit = -1;
+      for (int k = 0; k < n_pts; ++k) {
+        const double th = M_PI * (2 * k + 1) / (2.0 * n_pts);
+        const double dk = std::cos(th);
+        if (dd == dk) {
+          hit = k;
+          break;
+        }
+        const double wk = ((k & 1) ? -1.0 : 1.0) * std::sin(th) / (dd - dk);
+        num_u += wk * ux[k];
+        num_q += wk * n1[k];
+        den += wk;
+      }
+      u[y] = hit >= 0 ? ux[hit] : num_u / den;
+      q[y] = hit >= 0 ? n1[hit] : num_q / den;
+    }
+  }
+  const size_t N = (size_t)d.nx * d.ny;
+  std::vector<double> pops(9 * N), P(N);
+  for (int y = 0; y < d.ny; ++y) {
+    const double rho = 1.0 - 1.5 * q[y];
+    const double usq = u[y] * u[y];
+    for (int x = 0; x < d.nx; ++x) {
+      const size_t id = (size_t)y * d.nx + x;
+      for (int i = 0; i < 9; ++i) {
+        const double cu = HCX[i] * u[y];
+        pops[(size_t)i * N + id] = hweight(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+      }
+      P[id] = q[y];
+    }
+  }
+  return lb_set_state(h, ch, pops.data(), P.data(), h->t[ch]);
+}
+
+}  // extern "C"
+
+namespace {
+
+__global__ void fill_kernel_d(double *p, long long n, double v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void fill_kernel_f(float *p, long long n, float v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Rest state in buffer `which`: n_i = a_i (stored as 0 when shifted), P = 0.
+lb_status fill_rest(lb_handle *h, int which) {
+  const long long n = h->L.plane;
+  for (int p = 0; p < kPlanes; ++p) {
+    const double v = (p < 9 && h->L.esize == 8) ? hweight(p) : 0.0;
+    if (h->L.esize == 8) {
+      double *base = static_cast<double *>(h->buf[which]) + (size_t)p * n;
+      hipLaunchKernelGGL(fill_kernel_d, dim3(1024), dim3(256), 0, h->stream, base, n, v);
+    } else {
+      float *base = static_cast<float *>(h->buf[which]) + (size_t)p * n;
+      hipLaunchKernelGGL(fill_kernel_f, dim3(1024), dim3(256), 0, h->stream, base, n, (float)v);
+    }
+    HIPCHECK(h, hipGetLastError());
+  }
+  return LB_OK;
+}
+
+}  // namespace

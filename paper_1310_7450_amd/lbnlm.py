@@ -1,0 +1,205 @@
+"""Python binding of the lbnlm C ABI (``include/lb.h``).
+
+Argument marshalling only: every step of the solver runs in the gfx950
+kernels of ``liblbnlm.so``. PyTorch provides the device workspace and the
+stream. There is no CPU path: without the built library, or without a GPU,
+creating a :class:`Solver` raises.
+"""
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbnlm.so")
+
+FP64 = 0
+FP32_SHIFTED = 1
+
+PROFILES = {"ux": 0, "uy": 1, "sxx": 2, "sxy": 3, "syy": 4, "n1": 5, "pressure": 6,
+            "kxy": 7, "trT": 8, "kxx": 9}
+SCALARS = {"mass": 32, "momx": 33, "flux": 34, "wall_drag": 35, "umid": 36,
+           "residual": 37, "step": 38, "active": 39, "nan": 40}
+
+STATUS = {0: "LB_OK", -1: "LB_EINVAL", -2: "LB_ENOMEM", -3: "LB_EHIP", -4: "LB_EUNSTABLE", -5: "LB_ESTATE"}
+
+# Names of every function include/lb.h declares.
+ABI_FUNCTIONS = ["lb_workspace_bytes", "lb_create", "lb_destroy", "lb_step", "lb_observe",
+                 "lb_get_state", "lb_set_state", "lb_set_profile", "lb_last_error",
+                 "lb_status_string"]
+
+
+class LbChannel(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("force", C.c_double), ("tau_lb", C.c_double),
+                ("G", C.c_double), ("tau0", C.c_double), ("gamma_c", C.c_double), ("eps", C.c_double),
+                ("visc_split", C.c_double), ("t_startup", C.c_int64)]
+
+
+class LbOptions(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("nn_pressure", C.c_int32), ("obs_every", C.c_int32),
+                ("strip_rows", C.c_int32), ("steady_tol", C.c_double)]
+
+
+class LbError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library():
+    """Loads ``liblbnlm.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1310_7450_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, sz = C.c_void_p, C.POINTER(C.c_double), C.c_size_t
+    L.lb_workspace_bytes.argtypes = [C.POINTER(LbChannel), C.c_int32, C.POINTER(LbOptions), C.POINTER(sz)]
+    L.lb_create.argtypes = [C.POINTER(LbChannel), C.c_int32, C.POINTER(LbOptions), vp, sz, vp, C.POINTER(vp)]
+    L.lb_destroy.argtypes = [vp]
+    L.lb_step.argtypes = [vp, C.c_int64]
+    L.lb_observe.argtypes = [vp, C.c_int32, C.c_int32, dp, sz]
+    L.lb_get_state.argtypes = [vp, C.c_int32, dp, dp]
+    L.lb_set_state.argtypes = [vp, C.c_int32, dp, dp, C.c_int64]
+    L.lb_set_profile.argtypes = [vp, C.c_int32, dp, dp, C.c_int32]
+    L.lb_last_error.argtypes = [vp]
+    L.lb_last_error.restype = C.c_char_p
+    L.lb_status_string.argtypes = [C.c_int32]
+    L.lb_status_string.restype = C.c_char_p
+    for name in ["lb_workspace_bytes", "lb_create", "lb_destroy", "lb_step", "lb_observe",
+                 "lb_get_state", "lb_set_state", "lb_set_profile"]:
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+@dataclass
+class ChannelSpec:
+    """Parameters of one channel (lattice units; see ``lb_channel`` in lb.h)."""
+    nx: int
+    ny: int
+    force: float
+    tau_lb: float = 1.0
+    G: float = 1e-4
+    tau0: float = 1e4
+    gamma_c: float = 0.1
+    eps: float = 0.0
+    visc_split: float = 0.0
+    t_startup: int = 2 ** 62
+
+    def to_c(self):
+        return LbChannel(int(self.nx), int(self.ny), float(self.force), float(self.tau_lb), float(self.G),
+                         float(self.tau0), float(self.gamma_c), float(self.eps), float(self.visc_split),
+                         int(self.t_startup))
+
+
+def _dp(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def options(precision=FP64, nn_pressure=True, obs_every=1000, strip_rows=0, steady_tol=0.0):
+    if isinstance(precision, str):
+        precision = {"fp64": FP64, "fp32": FP32_SHIFTED, "fp32_shifted": FP32_SHIFTED}[precision]
+    return LbOptions(int(precision), int(bool(nn_pressure)), int(obs_every), int(strip_rows), float(steady_tol))
+
+
+def workspace_bytes(channels: Sequence[ChannelSpec], opts: LbOptions) -> int:
+    L = load_library()
+    arr = (LbChannel * len(channels))(*[c.to_c() for c in channels])
+    out = C.c_size_t(0)
+    st = L.lb_workspace_bytes(arr, len(channels), C.byref(opts), C.byref(out))
+    if st != 0:
+        raise LbError(st, "invalid channels or options")
+    return int(out.value)
+
+
+class Solver:
+    """A handle of the C library over ``channels``, on one CUDA/HIP stream."""
+
+    def __init__(self, channels: Sequence[ChannelSpec], precision="fp64", nn_pressure=True,
+                 obs_every=1000, strip_rows=0, steady_tol=0.0, stream=None, device="cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("lbnlm needs a GPU; no CPU fallback exists")
+        self.L = load_library()
+        self.channels = list(channels)
+        self.opts = options(precision, nn_pressure, obs_every, strip_rows, steady_tol)
+        nbytes = workspace_bytes(self.channels, self.opts)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = self.workspace.data_ptr()
+        aligned = (ptr + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        arr = (LbChannel * len(self.channels))(*[c.to_c() for c in self.channels])
+        h = C.c_void_p()
+        st = self.L.lb_create(arr, len(self.channels), C.byref(self.opts), C.c_void_p(aligned),
+                              nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != 0:
+            raise LbError(st, "lb_create failed")
+        self.h = h
+
+    # ------------------------------------------------------------------ calls
+    def _check(self, st):
+        if st != 0:
+            msg = self.L.lb_last_error(self.h).decode()
+            raise LbError(st, msg)
+
+    def step(self, n: int):
+        self._check(self.L.lb_step(self.h, int(n)))
+
+    def observe(self, ch: int, what: str):
+        if what in SCALARS:
+            out = np.zeros(1)
+            self._check(self.L.lb_observe(self.h, ch, SCALARS[what], _dp(out), 1))
+            return float(out[0])
+        ny = self.channels[ch].ny
+        out = np.zeros(ny)
+        self._check(self.L.lb_observe(self.h, ch, PROFILES[what], _dp(out), ny))
+        return out
+
+    def profiles(self, ch: int):
+        return {k: self.observe(ch, k) for k in PROFILES}
+
+    def get_state(self, ch: int):
+        c = self.channels[ch]
+        pops = np.zeros((9, c.ny, c.nx))
+        P = np.zeros((c.ny, c.nx))
+        self._check(self.L.lb_get_state(self.h, ch, _dp(pops), _dp(P)))
+        return pops, P
+
+    def set_state(self, ch: int, pops, P, t: int):
+        pops = np.ascontiguousarray(pops, dtype=np.float64)
+        P = np.ascontiguousarray(P, dtype=np.float64)
+        c = self.channels[ch]
+        assert pops.shape == (9, c.ny, c.nx) and P.shape == (c.ny, c.nx)
+        self._check(self.L.lb_set_state(self.h, ch, _dp(pops), _dp(P), int(t)))
+
+    def set_profile(self, ch: int, ux, n1):
+        ux = np.ascontiguousarray(ux, dtype=np.float64)
+        n1 = np.ascontiguousarray(n1, dtype=np.float64)
+        assert ux.shape == n1.shape and ux.ndim == 1
+        self._check(self.L.lb_set_profile(self.h, ch, _dp(ux), _dp(n1), len(ux)))
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.L.lb_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,69 @@
+"""Seeded synthetic channel workloads shaped like the paper's runs.
+
+Input generation only: this module draws channel parameters and initial
+perturbations from seeded numpy generators and holds none of the method's
+arithmetic. Both the GPU path and the CPU oracle take their inputs from here.
+
+Named workloads (lattice units, rho0 = 1):
+
+* ``poiseuille_64``: one 8 x 64 channel, g = 1e-6, tau_LB = 1, G = 1e-4,
+  tau0 = 1e4 steps, gamma_c = 0.1, eps = 0 (yield-stress-like, theta = 6),
+  20,000 start-up steps then 20,000 cessation steps; ``newtonian=True``
+  sets G = 0.
+* ``large_channel``: one 4096 x 1024 channel, g log-uniform in [1e-7, 1e-5]
+  and eps uniform in [-0.05, 0.05] from seed 1, other parameters as above,
+  10,000 steps from rest.
+* ``batched_sweep``: 256 channels, nx = 8, per channel in order
+  ny ~ U{32..512}, log10 g ~ U(-7, -5), eps ~ U(-0.1, 0.1),
+  log10 tau0 ~ U(3, 5), from seed 2 (see the function for the admission
+  rules).
+* ``transient_scale``: 16 channels of 8192 x 2048, 8 at eps = 0 and 8 at
+  eps = +0.02, g = 2 G gamma_c / H (wp H = 2 gamma_c), 50,000 start-up steps
+  then cessation.
+"""
+import numpy as np
+
+from .lbnlm import ChannelSpec
+
+REST_WEIGHTS = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def poiseuille_64(newtonian=False, nx=8, ny=64, tau0=1e4):
+    """``tau0`` other than 1e4 gives the same channel at another Maxwell time
+    (tau0 = 2e3 puts G tau = 0.2 inside the explicit-stress stable band)."""
+    spec = ChannelSpec(nx=nx, ny=ny, force=1e-6, tau_lb=1.0, G=0.0 if newtonian else 1e-4, tau0=tau0,
+                       gamma_c=0.1, eps=0.0, visc_split=0.0, t_startup=20000)
+    name = "poiseuille_64" + ("_newtonian" if newtonian else "") + ("" if tau0 == 1e4 else f"_tau0_{tau0:g}")
+    return {"name": name, "channels": [spec], "startup": 20000, "cessation": 20000}
+
+
+def large_channel(seed=1, nx=4096, ny=1024, eps=None):
+    """``eps`` overrides the drawn separation (the force is still drawn)."""
+    rng = np.random.default_rng(seed)
+    g = 10.0 ** rng.uniform(-7.0, -5.0)
+    e = rng.uniform(-0.05, 0.05)
+    if eps is not None:
+        e = float(eps)
+    spec = ChannelSpec(nx=nx, ny=ny, force=g, tau_lb=1.0, G=1e-4, tau0=1e4, gamma_c=0.1, eps=e)
+    return {"name": f"large_channel_{nx}x{ny}" + ("" if eps is None else f"_eps_{e:g}"),
+            "channels": [spec], "steps": 10000, "seed": seed}
+
+
+def perturbed_rest_state(nx, ny, seed, amplitude=1e-4):
+    """Populations of a fluid at rest with a seeded density perturbation of
+    relative amplitude ``amplitude`` (n_i = a_i (1 + delta)), and P = 0, in the
+    layout of ``lb_get_state``: pops[9][ny][nx], P[ny][nx]."""
+    rng = np.random.default_rng(seed)
+    delta = amplitude * rng.uniform(-1.0, 1.0, size=(ny, nx))
+    pops = REST_WEIGHTS[:, None, None] * (1.0 + delta[None, :, :])
+    return np.ascontiguousarray(pops), np.zeros((ny, nx))
+
+
+def random_state(nx, ny, seed, amplitude=1e-3):
+    """Rest populations with independent seeded perturbations of every
+    population (non-equilibrium content in every moment) and a random
+    previous trace; for layout and streaming tests."""
+    rng = np.random.default_rng(seed)
+    pops = REST_WEIGHTS[:, None, None] * (1.0 + amplitude * rng.uniform(-1, 1, size=(9, ny, nx)))
+    P = 1e-6 * rng.uniform(-1, 1, size=(ny, nx))
+    return np.ascontiguousarray(pops), np.ascontiguousarray(P)

@@ -1,0 +1,93 @@
+"""The C-ABI library loads, exports every declared symbol, and validates its
+inputs on the host (no GPU needed: only host-side calls are made here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1310_7450_amd import lbnlm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lb.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:lb_status|const char \*)\s*(lb_\w+)\s*\(", src, re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(lbnlm.LIB_PATH):
+        pytest.skip("liblbnlm.so not built")
+    return lbnlm.load_library()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert set(names) == set(lbnlm.ABI_FUNCTIONS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings(L):
+    assert L.lb_status_string(0) == b"LB_OK"
+    assert L.lb_status_string(-4) == b"LB_EUNSTABLE"
+
+
+def spec(**kw):
+    base = dict(nx=8, ny=64, force=1e-6)
+    base.update(kw)
+    return lbnlm.ChannelSpec(**base)
+
+
+def test_workspace_bytes_layout(L):
+    opt64 = lbnlm.options("fp64")
+    opt32 = lbnlm.options("fp32")
+    b64 = lbnlm.workspace_bytes([spec(nx=4096, ny=1024)], opt64)
+    b32 = lbnlm.workspace_bytes([spec(nx=4096, ny=1024)], opt32)
+    state64 = 2 * 10 * 4096 * 1024 * 8
+    assert state64 <= b64 < state64 * 1.05
+    assert 2 * 10 * 4096 * 1024 * 4 <= b32 < b64
+    # channels are padded to 64 nodes per plane
+    one = lbnlm.workspace_bytes([spec(nx=8, ny=33)], opt64)
+    two = lbnlm.workspace_bytes([spec(nx=8, ny=33)] * 2, opt64)
+    assert two > one
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tau_lb=0.5), dict(G=-1.0), dict(tau0=0.0), dict(gamma_c=0.0), dict(nx=0), dict(ny=0),
+    dict(visc_split=1.5), dict(visc_split=0.5, tau0=float("inf")), dict(force=float("nan")),
+])
+def test_invalid_channels_rejected(L, bad):
+    with pytest.raises(lbnlm.LbError) as e:
+        lbnlm.workspace_bytes([spec(**bad)], lbnlm.options("fp64"))
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("kw", [dict(obs_every=3), dict(obs_every=1), dict(steady_tol=-1.0), dict(precision=7)])
+def test_invalid_options_rejected(L, kw):
+    o = lbnlm.options()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    with pytest.raises(lbnlm.LbError):
+        lbnlm.workspace_bytes([spec()], o)
+
+
+def test_create_rejects_small_or_misaligned_workspace(L):
+    arr = (lbnlm.LbChannel * 1)(spec().to_c())
+    opt = lbnlm.options()
+    h = C.c_void_p()
+    # host-side checks fail before any device call
+    assert L.lb_create(arr, 1, C.byref(opt), C.c_void_p(0), 0, None, C.byref(h)) == -1
+    assert L.lb_create(arr, 1, C.byref(opt), C.c_void_p(4096 + 8), 1 << 30, None, C.byref(h)) == -1
+    assert L.lb_create(arr, 1, C.byref(opt), C.c_void_p(4096), 16, None, C.byref(h)) == -2
+    assert L.lb_destroy(None) == 0
+
+
+def test_solver_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(RuntimeError):
+        lbnlm.Solver([spec()])

@@ -1,0 +1,282 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances: FP64 storage within 1e-5 relative L-infinity on u_x and sigma_xy
+(expected ~1e-12: the two sides differ only in rounding order; the stress
+comes from a closed-form solve on the GPU and from summing the series in the
+oracle), FP32 shifted storage within 1e-3. L-infinity relative means
+max|a - b| / max|b| over the field.
+
+Element-wise parity needs a well-conditioned run. With the explicit stress,
+the scheme amplifies round-off without bound once G tau (lattice units)
+exceeds about 0.3 at visc_split 0: the 8 x 64, G tau = 1 channel turns a
+1e-15 perturbation of the oracle into a 27% change of its own state within
+500 steps. Long parity runs therefore use G tau <= 0.2; the G tau = 1
+workload is compared exactly over its first steps and statistically after.
+"""
+import numpy as np
+import pytest
+
+from paper_1310_7450_amd import workloads
+from paper_1310_7450_amd.lbnlm import ChannelSpec
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-5
+FP32_TOL = 1e-3
+
+
+def solver(channels, **kw):
+    from paper_1310_7450_amd import Solver
+    return Solver(channels, **kw)
+
+
+def linf(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def oracle_channel(orc, spec, nn_pressure=True):
+    return orc.Channel(spec.nx, spec.ny, spec.force, tau_lb=spec.tau_lb, G=spec.G, tau0=spec.tau0,
+                       gamma_c=spec.gamma_c, eps=spec.eps, visc_split=spec.visc_split,
+                       t_startup=spec.t_startup, nn_pressure=nn_pressure)
+
+
+def compare_fields(s, ch, o, tol, label):
+    f = o.fields()
+    ux_o, sxy_o = f["ux"].mean(axis=1), f["sxy"].mean(axis=1)
+    ux_g, sxy_g = s.observe(ch, "ux"), s.observe(ch, "sxy")
+    e_u, e_s = linf(ux_g, ux_o), linf(sxy_g, sxy_o)
+    print(f"{label}: Linf rel u_x {e_u:.3e}  sigma_xy {e_s:.3e}", flush=True)
+    assert e_u <= tol, (label, e_u)
+    if np.abs(sxy_o).max() > 0:
+        assert e_s <= tol, (label, e_s)
+    return e_u, e_s
+
+
+def test_poiseuille_fp64_state_parity(orc):
+    """The 8 x 64 start-up/cessation channel at G tau = 0.2, FP64: full
+    population state and previous trace equal the oracle's during start-up,
+    at the switch-off and during cessation."""
+    wl = workloads.poiseuille_64(tau0=2e3)
+    spec = wl["channels"][0]
+    o = oracle_channel(orc, spec)
+    dev = pdev = 0.0
+    with solver([spec], precision="fp64", obs_every=1000) as s:
+        for n in [3000, 17000, 20000]:
+            s.step(n)
+            o.run(n)
+            pops, P = s.get_state(0)
+            # normalise by the largest deviation from rest seen so far (the
+            # fluid is nearly at rest again after the cessation)
+            dev = max(dev, np.abs(o.n - workloads.REST_WEIGHTS[:, None, None]).max())
+            err = np.abs(pops - o.n).max() / dev
+            print(f"t={o.t}: state rel err {err:.3e}  P err {np.abs(P - o.P).max():.3e}", flush=True)
+            assert err < 1e-9
+            pdev = max(pdev, np.abs(o.P).max())
+            assert np.abs(P - o.P).max() <= 1e-9 * pdev
+            if o.t <= 20000:
+                compare_fields(s, 0, o, FP64_TOL, f"fp64 t={o.t}")
+
+
+def test_poiseuille_newtonian_fp64(orc):
+    spec = workloads.poiseuille_64(newtonian=True)["channels"][0]
+    o = oracle_channel(orc, spec)
+    with solver([spec], precision="fp64") as s:
+        s.step(25000)
+        o.run(25000)
+        compare_fields(s, 0, o, FP64_TOL, "newtonian")
+
+
+def test_poiseuille_fp32_shifted(orc):
+    """FP32 shifted storage through start-up and into cessation; during the
+    cessation the error is measured against the largest velocity and stress
+    of the run (the fields decay towards zero)."""
+    spec = workloads.poiseuille_64(tau0=2e3)["channels"][0]
+    o = oracle_channel(orc, spec)
+    umax = smax = 0.0
+    with solver([spec], precision="fp32") as s:
+        for n in [5000, 15000, 2000, 18000]:
+            s.step(n)
+            o.run(n)
+            pr = o.profiles()
+            umax = max(umax, np.abs(pr["ux"]).max())
+            smax = max(smax, np.abs(pr["sxy"]).max())
+            eu = np.abs(s.observe(0, "ux") - pr["ux"]).max() / umax
+            es = np.abs(s.observe(0, "sxy") - pr["sxy"]).max() / smax
+            print(f"fp32 t={o.t}: u_x err {eu:.3e} sigma_xy err {es:.3e} (of run max)", flush=True)
+            assert eu < FP32_TOL and es < FP32_TOL
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 16), (2, 9), (4, 33), (16, 20), (64, 7), (3, 12), (100, 37), (130, 5), (63, 2), (8, 1)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_perturbed_state_parity(orc, nx, ny, precision):
+    """Seeded random populations (every moment non-zero, x gradients present)
+    on narrow, wide and ragged lattices: one and several steps match the
+    oracle node by node; covers the lane-group wrap, the halo lanes of wide
+    strips, partial last strips, and single/double-row channels."""
+    spec = ChannelSpec(nx=nx, ny=ny, force=3e-6, tau_lb=0.8, G=2e-4, tau0=500.0, gamma_c=0.1,
+                       eps=0.01, visc_split=0.3, t_startup=40)
+    pops, P = workloads.random_state(nx, ny, seed=nx * 1000 + ny)
+    o = oracle_channel(orc, spec)
+    o.set_state(pops, P, t=0)
+    tol = 1e-12 if precision == "fp64" else 2e-6
+    with solver([spec], precision=precision, obs_every=16, strip_rows=4) as s:
+        s.set_state(0, pops, P, 0)
+        g_pops, g_P = s.get_state(0)
+        assert np.abs(g_pops - pops).max() <= (0 if precision == "fp64" else 1e-7)
+        for n in [1, 2, 57]:
+            s.step(n)
+            o.run(n)
+            g_pops, g_P = s.get_state(0)
+            err = np.abs(g_pops - o.n).max() / np.abs(o.n - workloads.REST_WEIGHTS[:, None, None]).max()
+            perr = np.abs(g_P - o.P).max() / max(np.abs(o.P).max(), 1e-30)
+            print(f"{precision} {nx}x{ny} t={o.t}: state {err:.2e} P {perr:.2e}", flush=True)
+            assert err < tol * 50 and perr < (1e-9 if precision == "fp64" else 1e-3)
+
+
+def test_batched_channels_match_individual_oracles(orc):
+    """Channels of different shapes and parameters in one handle advance
+    exactly as separate oracle runs (no cross-talk between channels)."""
+    specs = [
+        ChannelSpec(8, 48, 1e-6, 1.0, 1e-4, 1e3, 0.1, 0.0, 0.0),
+        ChannelSpec(8, 33, 2e-6, 0.9, 5e-5, 2e3, 0.1, -0.03, 0.0, t_startup=700),
+        ChannelSpec(100, 20, 1e-6, 1.0, 1e-4, 1e3, 0.1, 0.02, 0.25),
+        ChannelSpec(4, 64, 5e-7, 1.0, 0.0, 1e4, 0.1),
+        ChannelSpec(64, 12, 1e-6, 1.2, 1e-4, 1.5e3, 0.2, 0.0, 0.5),
+    ]
+    oracles = [oracle_channel(orc, sp) for sp in specs]
+    with solver(specs, precision="fp64", obs_every=200) as s:
+        s.step(1500)
+        for i, o in enumerate(oracles):
+            o.run(1500)
+            pops, P = s.get_state(i)
+            err = np.abs(pops - o.n).max() / np.abs(o.n - workloads.REST_WEIGHTS[:, None, None]).max()
+            print(f"channel {i}: state rel err {err:.2e}", flush=True)
+            assert err < 1e-9
+            compare_fields(s, i, o, FP64_TOL, f"batched ch{i}")
+
+
+def test_observables_match_oracle(orc):
+    """Profiles and channel totals (pressure, N1, kappa_xy, mass, momentum,
+    wall drag, centre velocity) agree with the oracle's."""
+    spec = ChannelSpec(8, 40, 2e-6, 1.0, 1e-4, 1e3, 0.1)
+    o = oracle_channel(orc, spec)
+    with solver([spec], precision="fp64") as s:
+        s.step(3001)
+        o.run(3001)
+        f = o.fields()
+        pr = {k: v.mean(axis=1) for k, v in f.items()}
+        assert linf(s.observe(0, "n1"), pr["sxx"] - pr["syy"]) < 1e-9
+        assert linf(s.observe(0, "pressure"), pr["rho_e"] / 3) < 1e-14
+        assert linf(s.observe(0, "kxy"), pr["kxy"]) < 1e-9
+        assert linf(s.observe(0, "trT"), pr["trT"]) < 1e-9
+        assert s.observe(0, "mass") == pytest.approx(o.mass(), rel=1e-14)
+        assert s.observe(0, "momx") == pytest.approx(o.momentum_x(), rel=1e-10)
+        assert s.observe(0, "wall_drag") == pytest.approx(o.wall_drag(), rel=1e-9)
+        ux = pr["ux"]
+        assert s.observe(0, "umid") == pytest.approx(0.5 * (ux[19] + ux[20]), rel=1e-10)
+        assert s.observe(0, "step") == 3001
+
+
+def test_bitwise_repeat_and_step_splitting():
+    """Two handles give identical states; N steps equal k + (N - k) steps in
+    any split across graph boundaries (bitwise)."""
+    spec = ChannelSpec(200, 50, 1e-6, 1.0, 1e-4, 1e3, 0.1)
+    pops0, P0 = workloads.perturbed_rest_state(200, 50, seed=7)
+    states = []
+    for split in [[2500], [1000, 1500], [999, 1, 1337, 163], [2500]]:
+        with solver([spec], precision="fp32", obs_every=500) as s:
+            s.set_state(0, pops0, P0, 0)
+            for n in split:
+                s.step(n)
+            states.append(s.get_state(0))
+    for pops, P in states[1:]:
+        assert np.array_equal(pops, states[0][0]) and np.array_equal(P, states[0][1])
+
+
+def test_x_uniform_stays_bitwise_uniform():
+    """A wide x-periodic channel started from rest stays exactly x-uniform:
+    every halo lane and wrapped column computes the same values."""
+    spec = ChannelSpec(300, 40, 1e-6, 1.0, 1e-4, 1e3, 0.1)
+    with solver([spec], precision="fp64", obs_every=100) as s:
+        s.step(777)
+        pops, P = s.get_state(0)
+        assert np.array_equal(pops, np.broadcast_to(pops[:, :, :1], pops.shape))
+        assert np.abs(s.observe(0, "kxx")).max() == 0.0
+
+
+def test_mass_conservation_fp64():
+    """Hydrodynamic mass conserved to round-off on the GPU (FP64)."""
+    spec = ChannelSpec(8, 64, 2e-6, 1.0, 1e-4, 2e3, 0.1)
+    with solver([spec], precision="fp64", obs_every=1000) as s:
+        m0 = s.observe(0, "mass")
+        s.step(10000)
+        assert abs(s.observe(0, "mass") - m0) / 512 < 1e-15 * 10000
+
+
+def test_convergence_freezes_channels(orc):
+    """With steady_tol, channels stop once the residual falls below it and
+    their final profile matches the oracle run for the same number of steps."""
+    specs = [ChannelSpec(8, 16, 2e-6, 1.0, 1e-4, 1e3, 0.1), ChannelSpec(8, 48, 1e-6, 1.0, 1e-4, 1e3, 0.1)]
+    with solver(specs, precision="fp64", obs_every=200, steady_tol=1e-7) as s:
+        s.step(200000)
+        steps = [int(s.observe(i, "step")) for i in range(2)]
+        assert all(s.observe(i, "active") == 0 for i in range(2))
+        assert steps[0] < steps[1] < 200000
+        for i, sp in enumerate(specs):
+            o = oracle_channel(orc, sp)
+            o.run(steps[i])
+            compare_fields(s, i, o, FP64_TOL, f"frozen ch{i} at {steps[i]}")
+
+
+def test_warm_start_profile_state():
+    """lb_set_profile writes equilibrium populations at the given u_x with
+    rho_e = 1 - (3/2) N1 and P = N1, keeping the rest-state mass."""
+    spec = ChannelSpec(4, 24, 1e-6, 1.0, 1e-4, 1e3, 0.1)
+    ux = 1e-3 * np.sin(np.linspace(0.1, 3.0, 24))
+    n1 = 1e-6 * np.cos(np.linspace(0, 2, 24))
+    with solver([spec], precision="fp64") as s:
+        s.set_profile(0, ux, n1)
+        pops, P = s.get_state(0)
+        assert np.allclose(P, n1[:, None], rtol=0, atol=1e-20)
+        rho = pops.sum(axis=0)
+        assert np.allclose(rho, (1 - 1.5 * n1)[:, None], rtol=1e-14)
+        mx = (pops[[1, 5, 8]].sum(axis=0) - pops[[3, 6, 7]].sum(axis=0))
+        assert np.allclose(mx / rho, ux[:, None], rtol=1e-12, atol=1e-18)
+        assert s.observe(0, "mass") == pytest.approx(96.0, rel=1e-14)
+
+
+def test_large_channel_sampled_rows(orc):
+    """The 4096 x 1024 lattice in FP32 at full size, in the launch
+    configuration the benchmark times, with eps = -0.05 (G tau = 0.1; the
+    drawn eps = 0.045 gives G tau = 1.2, outside the well-conditioned band):
+    the x-uniform run equals an nx = 1 oracle run row for row (an x-periodic
+    uniform state has no x dependence), within the FP32 tolerance."""
+    wl = workloads.large_channel(eps=-0.05)
+    spec = wl["channels"][0]
+    with solver([spec], precision="fp32", obs_every=1000) as s:
+        s.step(wl["steps"])
+        import dataclasses
+        o = oracle_channel(orc, dataclasses.replace(spec, nx=1))
+        o.run(wl["steps"])
+        compare_fields(s, 0, o, FP32_TOL, "large_channel fp32")
+        assert np.abs(s.observe(0, "kxx")).max() == 0.0
+
+
+def test_poiseuille_gtau1_short_exact_long_statistical(orc):
+    """The G tau = 1 workload as specified: exact over the first 5 steps
+    (round-off has not been amplified yet), then after 20,000 steps the
+    x-averaged velocity within 1% of the oracle's (two oracle runs that differ
+    by 1e-15 already differ by 0.13% there) and mass conserved."""
+    spec = workloads.poiseuille_64()["channels"][0]
+    o = oracle_channel(orc, spec)
+    with solver([spec], precision="fp64") as s:
+        s.step(5)
+        o.run(5)
+        pops, _ = s.get_state(0)
+        assert np.abs(pops - o.n).max() / np.abs(o.n - workloads.REST_WEIGHTS[:, None, None]).max() < 1e-9
+        s.step(19995)
+        o.run(19995)
+        e = linf(s.observe(0, "ux"), o.profiles()["ux"])
+        print(f"G tau = 1 at t=20000: u_x Linf rel {e:.3e}", flush=True)
+        assert e < 1e-2
+        assert abs(s.observe(0, "mass") - 512) < 1e-9
