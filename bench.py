@@ -25,12 +25,12 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"fp32": 80, "fp64": 160}
 
 
-def time_solver(precision, wl, steps, warmup):
+def time_solver(precision, wl, steps, warmup, strip_rows=0):
     import torch
     from paper_1310_7450_amd import Solver
     spec = wl["channels"][0]
     nodes = spec.nx * spec.ny
-    with Solver([spec], precision=precision, obs_every=1000) as s:
+    with Solver([spec], precision=precision, obs_every=1000, strip_rows=strip_rows) as s:
         s.step(warmup)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -82,6 +82,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--strip-rows", type=int, default=0, help="rows per wavefront strip (0: library default)")
+    ap.add_argument("--tune", type=str, default="",
+                    help="comma-separated strip_rows values to time (FP32 and FP64) instead of the JSON line")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB, 5 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
@@ -91,15 +96,31 @@ def main():
     import torch
     from paper_1310_7450_amd import workloads
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.copy_calibration:
+        n = 1 << 28  # 2^28 float32 = 1 GiB read and 1 GiB written per copy
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"copy calibration: 5 copies of {n * 4} bytes", flush=True)
+        return
     wl = workloads.large_channel()
+    if args.tune:
+        for sr in [int(v) for v in args.tune.split(",")]:
+            for prec in ["fp32", "fp64"]:
+                r = time_solver(prec, wl, args.steps, args.warmup, sr)
+                print(f"tune strip_rows={sr} {prec}: {r['mlups']:.0f} MLUPS {r['achieved_GBs']:.0f} GB/s "
+                      f"({100 * r['frac']:.1f}%)", flush=True)
+        return
     spec = wl["channels"][0]
     print(f"bench: {wl['name']} g={spec.force:.3e} eps={spec.eps:+.4f}, fp32 {args.steps} steps",
           file=sys.stderr, flush=True)
-    r32 = time_solver("fp32", wl, args.steps, args.warmup)
+    r32 = time_solver("fp32", wl, args.steps, args.warmup, args.strip_rows)
     print(f"bench: fp32 {r32['mlups']:.0f} MLUPS, {r32['achieved_GBs']:.0f} GB/s", file=sys.stderr, flush=True)
     r64 = None
     if not args.no_fp64:
-        r64 = time_solver("fp64", wl, args.steps, args.warmup)
+        r64 = time_solver("fp64", wl, args.steps, args.warmup, args.strip_rows)
         print(f"bench: fp64 {r64['mlups']:.0f} MLUPS, {r64['achieved_GBs']:.0f} GB/s", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:

@@ -6,8 +6,13 @@
 
 namespace lbnlm {
 
-// Number of stored planes: nine populations and the previous stress trace.
+// Stored fields per node: nine populations and the previous stress trace.
 constexpr int kPlanes = 10;
+// Nodes per storage tile; field p of node n lives at slot(p, n).
+constexpr int kTile = 64;
+__host__ __device__ inline long long slot(int p, long long n) {
+  return ((n >> 6) * kPlanes + p) * kTile + (n & (kTile - 1));
+}
 // Per-row observation fields accumulated in FP64 (x sums per row).
 enum ObsField {
   OF_UX = 0, OF_UY, OF_SXX, OF_SXY, OF_SYY, OF_RHOE_DEV, OF_MASS_DEV, OF_MOMX,
@@ -47,7 +52,7 @@ struct Strip {
 struct SweepArgs {
   const void *A;        // state read (10 planes)
   void *B;              // state written (10 planes)
-  long long plane;      // plane stride in elements
+  long long plane;      // nodes per buffer (a multiple of the tile)
   const Strip *strips;
   const ChanDev *ch;
   double *part;         // observation partials [row][OF_COUNT]
@@ -57,15 +62,20 @@ struct SweepArgs {
   int nnp;              // keep the flow-induced density terms
 };
 
-// Lane-group width classes of the sweep: nx in {1,2,4,...,64} runs a whole
-// period per lane group ("narrow"); anything else runs 64-lane strips with
-// one halo lane on each side ("wide").
+// Width classes of the sweep: nx in {1,2,4,...,64} runs a whole period per
+// lane group ("narrow", classes 0..6); nx a multiple of 64 (>= 128) runs
+// aligned 64-column strips (kWide64Class); any other width runs generic
+// 64-column strips with wrapped lanes (kWideClass).
 constexpr int kWideClass = 7;
+constexpr int kWide64Class = 8;
+constexpr int kClasses = 9;
 inline int width_class(int nx) {
   for (int c = 0; c < 7; ++c)
     if (nx == (1 << c)) return c;
+  if (nx % 64 == 0) return kWide64Class;
   return kWideClass;
 }
+inline bool is_strip_class(int cls) { return cls >= kWideClass; }
 
 // Host launchers (defined in lb_kernels.hip).
 hipError_t launch_sweep(int fp32, int cls, bool observe, const SweepArgs &a, hipStream_t s);

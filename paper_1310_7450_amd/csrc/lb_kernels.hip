@@ -2,10 +2,12 @@
 // forcing / BGK sweep, its observation variant, the per-channel FP64
 // reduction and the step-counter advance.
 //
-// Layout: structure of arrays, ten planes (nine populations in the order
+// Layout: ten fields per node (nine populations in the order
 // (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1), then the
-// previous stress trace), each plane holding every channel's nodes row by
-// row (x fastest). A plane slot holds the post-collision population of the
+// previous stress trace), stored as tiles of 64 consecutive nodes (row by
+// row, x fastest, every channel starting on a tile): a tile holds field 0 of
+// its 64 nodes, then field 1, ... (structure of arrays inside a 64-node
+// tile, 2.5 KB in FP32). A slot holds the post-collision population of the
 // previous step at its source node; the sweep pulls it along the lattice
 // velocity (Sec. II.A, Eq. (lbupdate)), or from the same node with the
 // opposite velocity where the link crosses a wall (half-way bounce-back,
@@ -14,14 +16,29 @@
 // One wavefront marches up a strip of rows. It keeps the provisional
 // velocity u~ = j/sum_i n_i of three consecutive row blocks in registers, so
 // the central differences of Sec. II.C need no LDS: x neighbours come from
-// lane shuffles, y neighbours from the previous/next block. A narrow channel
-// (nx a power of two up to 64) puts whole periods into lane groups of nx
-// lanes; a wide channel runs 64-lane strips whose two edge lanes only
-// supply the x halo.
+// lane moves, y neighbours from the previous/next block.
+//  * narrow channels (nx a power of two up to 64) put whole periods into
+//    lane groups of nx lanes (sweep_kernel);
+//  * channels with nx a multiple of 64 run strips of 64 aligned columns
+//    (sweep_wide64_kernel): every load is one aligned 64-lane run of a tile,
+//    addressed from a wave-uniform tile base, and the x-shifted pulls are
+//    DPP lane shifts of the aligned loads, with the two edge columns loaded
+//    separately; this keeps the address arithmetic scalar;
+//  * other widths run generic 64-column strips with wrapped lanes
+//    (sweep_kernel, WIDE).
+// The physics of one node (stencil, stress, forcing, collision) is one
+// device function shared by all of them.
 #include "lb_internal.h"
 
 namespace lbnlm {
 namespace {
+
+#ifndef LB_WG_WAVES
+#define LB_WG_WAVES 4
+#endif
+#ifndef LB_PREFETCH_DEPTH
+#define LB_PREFETCH_DEPTH 1
+#endif
 
 template <typename T>
 __device__ __forceinline__ T shfl(T v, int src) {
@@ -33,23 +50,70 @@ __device__ __forceinline__ constexpr T weight(int i) {
   return i == 0 ? T(4.0 / 9.0) : (i < 5 ? T(1.0 / 9.0) : T(1.0 / 36.0));
 }
 
-// Pulls the nine post-streaming populations of node (x, y), 0 <= y < ny.
 template <typename T>
-__device__ __forceinline__ void pull(const T *__restrict__ A, long long P, long long row, int nx,
-                                     int ny, int x, int y, T f[9]) {
+__device__ __forceinline__ T recip(T v) {
+  if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(v);
+  return T(1) / v;
+}
+
+// Lane moves across the whole wavefront: shift_up gives lane i the value of
+// lane i-1 (lane 0 gets `edge`), shift_down gives lane i the value of lane
+// i+1 (lane 63 gets `edge`).
+__device__ __forceinline__ int dpp_shr(int edge, int v) {
+  return __builtin_amdgcn_update_dpp(edge, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_shl(int edge, int v) {
+  return __builtin_amdgcn_update_dpp(edge, v, 0x130, 0xf, 0xf, false);
+}
+template <typename T>
+__device__ __forceinline__ T shift_up(T edge, T v) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, dpp_shr(__builtin_bit_cast(int, edge), __builtin_bit_cast(int, v)));
+  } else {
+    const long long e = __builtin_bit_cast(long long, edge), x = __builtin_bit_cast(long long, v);
+    const int lo = dpp_shr((int)e, (int)x), hi = dpp_shr((int)(e >> 32), (int)(x >> 32));
+    return __builtin_bit_cast(T, ((long long)hi << 32) | (unsigned int)lo);
+  }
+}
+template <typename T>
+__device__ __forceinline__ T shift_down(T edge, T v) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, dpp_shl(__builtin_bit_cast(int, edge), __builtin_bit_cast(int, v)));
+  } else {
+    const long long e = __builtin_bit_cast(long long, edge), x = __builtin_bit_cast(long long, v);
+    const int lo = dpp_shl((int)e, (int)x), hi = dpp_shl((int)(e >> 32), (int)(x >> 32));
+    return __builtin_bit_cast(T, ((long long)hi << 32) | (unsigned int)lo);
+  }
+}
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int l) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+  } else {
+    const long long x = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)x, l), hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+    return __builtin_bit_cast(T, ((long long)hi << 32) | (unsigned int)lo);
+  }
+}
+
+// Pulls the nine post-streaming populations of node (x, y), 0 <= y < ny;
+// row = index of node (0, y).
+template <typename T>
+__device__ __forceinline__ void pull(const T *__restrict__ A, long long row, int nx, int ny, int x,
+                                     int y, T f[9]) {
   const int xm = (x == 0) ? nx - 1 : x - 1;
   const int xp = (x == nx - 1) ? 0 : x + 1;
   const long long dn = row - nx, up = row + nx;
   const bool bot = (y == 0), top = (y == ny - 1);
-  f[0] = A[row + x];
-  f[1] = A[1 * P + row + xm];
-  f[3] = A[3 * P + row + xp];
-  f[2] = A[bot ? (4 * P + row + x) : (2 * P + dn + x)];
-  f[5] = A[bot ? (7 * P + row + x) : (5 * P + dn + xm)];
-  f[6] = A[bot ? (8 * P + row + x) : (6 * P + dn + xp)];
-  f[4] = A[top ? (2 * P + row + x) : (4 * P + up + x)];
-  f[7] = A[top ? (5 * P + row + x) : (7 * P + up + xp)];
-  f[8] = A[top ? (6 * P + row + x) : (8 * P + up + xm)];
+  f[0] = A[slot(0, row + x)];
+  f[1] = A[slot(1, row + xm)];
+  f[3] = A[slot(3, row + xp)];
+  f[2] = A[bot ? slot(4, row + x) : slot(2, dn + x)];
+  f[5] = A[bot ? slot(7, row + x) : slot(5, dn + xm)];
+  f[6] = A[bot ? slot(8, row + x) : slot(6, dn + xp)];
+  f[4] = A[top ? slot(2, row + x) : slot(4, up + x)];
+  f[7] = A[top ? slot(5, row + x) : slot(7, up + xp)];
+  f[8] = A[top ? slot(6, row + x) : slot(8, up + xm)];
 }
 
 // Zeroth and first moments of the stored values: sd = sum_i f_i, m = sum_i
@@ -73,6 +137,14 @@ __device__ __forceinline__ U2<T> shfl2(U2<T> v, int src) {
   return U2<T>{shfl(v.x, src), shfl(v.y, src)};
 }
 
+// Provisional velocity u~ = (m + f/2) / sum_i n_i (reading R2 of the design
+// notes: the stencil uses the velocity before the flow-induced density).
+template <typename T, bool SHIFT>
+__device__ __forceinline__ U2<T> u_tilde(T sd, T mx, T my, T fx) {
+  const T inv = recip<T>(SHIFT ? T(1) + sd : sd);
+  return U2<T>{(mx + T(0.5) * fx) * inv, my * inv};
+}
+
 // Wave-wide sum over a lane group of width GW (power of two).
 template <int GW>
 __device__ __forceinline__ double group_sum(double v) {
@@ -81,73 +153,229 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
-template <typename T, bool SHIFT, int TXW, bool WIDE, bool OBS>
-__global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a) {
-  constexpr int TYW = 64 / TXW;
-  const int lane = threadIdx.x & 63;
+// Channel constants in the arithmetic type.
+template <typename T>
+struct Coef {
+  T om, kf, sp, G, inv_tau, inv_gc, lgt;
+  bool stress_on;
+  __device__ explicit Coef(const ChanDev &c)
+      : om(T(c.omega)), kf(T(c.kf)), sp(T(c.sp)), G(T(c.G)), inv_tau(T(c.inv_tau)),
+        inv_gc(T(c.inv_gc)), lgt(T(c.lgt)), stress_on(c.G > 0.0) {}
+};
+
+// Everything that happens at one node once its populations and the stencil
+// velocities are known: kappa (Sec. II.C), the inlM stress (Eqs.
+// (nlmaxwell), (sigtsum)), the flow-induced density change (Eq. (rhoplus)),
+// the density and velocity of Eq. (rhoj), and either the post-collision
+// populations (equilibrium, forcing of Eq. (bodyforce), BGK) or the
+// observables of the node.
+template <typename T, bool SHIFT, bool OBS>
+__device__ __forceinline__ void node_update(const T f[9], T sd, T mx, T my, T Pc, T fx, U2<T> lf,
+                                            U2<T> rt, U2<T> dn, U2<T> up, const Coef<T> &q,
+                                            int nnp, T out[9], T &trT_out, double obs[OF_COUNT]) {
+  // velocity gradient kappa_ab = d_b u_a
+  const T kxx = T(0.5) * (rt.x - lf.x);
+  const T kxy = T(0.5) * (up.x - dn.x);
+  const T kyx = T(0.5) * (rt.y - lf.y);
+  const T kyy = T(0.5) * (up.y - dn.y);
+
+  // tau_M of Eq. (nlmaxwell), then the steady series of Eq. (sigtsum) through
+  // the relation it satisfies by Eq. (smalld),
+  // sigma - tau_M (kappa sigma + sigma kappa^T) = G tau_M D, solved in closed
+  // form (Cramer) for (sigma_xx, sigma_xy, sigma_yy).
+  const T Dxx = T(2) * kxx, Dxy = kxy + kyx, Dyy = T(2) * kyy;
+  T sxx = T(0), sxy = T(0), syy = T(0);
+  if (q.stress_on) {
+    const T II = T(0.5) * (Dxx * Dxx + T(2) * Dxy * Dxy + Dyy * Dyy);
+    const T rate = q.inv_tau + sqrt(II) * q.inv_gc;
+    if (rate > T(0)) {
+      const T tM = recip<T>(rate);
+      const T ka = tM * kxx, kb = tM * kxy, kc = tM * kyx, kd = tM * kyy;
+      const T gt = q.G * tM;
+      const T r1 = gt * Dxx, r2 = gt * Dxy, r3 = gt * Dyy;
+      const T m11 = T(1) - T(2) * ka, m12 = T(-2) * kb, m21 = -kc;
+      const T m22 = T(1) - ka - kd, m23 = -kb, m32 = T(-2) * kc, m33 = T(1) - T(2) * kd;
+      const T c11 = m22 * m33 - m23 * m32;
+      const T det = m11 * c11 - m12 * m21 * m33;
+      const T idet = recip<T>(det);
+      const T e2 = r2 * m33 - m23 * r3;
+      sxx = (r1 * c11 - m12 * e2) * idet;
+      sxy = (m11 * e2 - r1 * m21 * m33) * idet;
+      syy = (m11 * (m22 * r3 - r2 * m32) - m12 * m21 * r3 + r1 * m21 * m32) * idet;
+    }
+  }
+  // non-Newtonian stress carried by the forcing (viscosity split)
+  const T Txx = sxx - q.lgt * Dxx, Txy = sxy - q.lgt * Dxy, Tyy = syy - q.lgt * Dyy;
+  const T trT = Txx + Tyy;
+  const T Sxx = T(0.5) * (Txx - Tyy);  // traceless part; Sbar_yy = -Sxx
+  // Eq. (rhoplus): r = dt d(delta rho)/dt with delta rho = -tr Sigma^nN /(cs2 d)
+  const T rr = nnp ? T(-1.5) * (trT - Pc) : T(0);
+
+  const T jx = mx + T(0.5) * fx, jy = my;
+  // Eq. (rhoj): the equilibrium density is sum (n* + n)/2 = s + r/2, carried
+  // as its deviation from 1 in the shifted storage
+  const T sdev = SHIFT ? sd : sd - T(1);
+  const T rho_dev = sdev + T(0.5) * rr;
+  const T rho_e = SHIFT ? T(1) + rho_dev : sd + T(0.5) * rr;
+  const T irho = recip<T>(rho_e);
+  const T ux = jx * irho, uy = jy * irho;
+  trT_out = trT;
+
+  if constexpr (OBS) {
+    obs[OF_UX] = (double)ux;
+    obs[OF_UY] = (double)uy;
+    obs[OF_SXX] = (double)sxx;
+    obs[OF_SXY] = (double)sxy;
+    obs[OF_SYY] = (double)syy;
+    obs[OF_RHOE_DEV] = (double)rho_dev;
+    obs[OF_MASS_DEV] = (double)sdev + (nnp ? 1.5 * (double)Pc : 0.0);
+    obs[OF_MOMX] = (double)mx;
+    obs[OF_KXY] = (double)kxy;
+    obs[OF_TRT] = (double)trT;
+    obs[OF_KXX] = (double)kxx;
+  } else {
+    // equilibrium, forcing of Eq. (bodyforce) and BGK collision:
+    // n*_i = (1 - om) n_i + om n^eq_i + F_i. For a pair of opposite
+    // velocities c_i = -c_j the parts even in c (constant, (c.u)^2, (c.u)(c.f),
+    // the stress term) are shared and the odd parts ((c.u), (c.f)) change sign.
+    const T usq = ux * ux + uy * uy;
+    const T uf = ux * fx;
+    const T K0 = q.kf * (rr + T(1.5) * rr * usq - T(3) * uf);
+    const T eq0 = SHIFT ? (rho_dev - T(1.5) * rho_e * usq) : rho_e * (T(1) - T(1.5) * usq);
+    const T om1 = T(1) - q.om;
+    const T C0 = q.om * eq0 + K0;                      // constant part
+    const T Acu2 = T(4.5) * (q.om * rho_e - q.kf * rr); // coefficient of (c.u)^2
+    const T Bcu = T(3) * q.om * rho_e;                 // coefficient of (c.u), odd
+    const T Ccf = T(3) * q.kf * fx;                    // 3 kf (c.f) for c_x = 1, odd
+    const T Dcf = T(9) * q.kf * fx;                    // 9 kf (c.u)(c.f) for c_x = 1, even
+    const T spS = q.sp * Sxx, spT = T(2) * q.sp * Txy;
+    constexpr T w0 = weight<T>(0), w1 = weight<T>(1), w5 = weight<T>(5);
+    out[0] = om1 * f[0] + w0 * C0;
+    {  // (1,0) and (-1,0): c.u = ux, c.f = fx, stress term Sxx
+      const T cu = ux;
+      const T ev = w1 * (C0 + Acu2 * cu * cu + spS + Dcf * cu);
+      const T od = w1 * (Bcu * cu + Ccf);
+      out[1] = om1 * f[1] + ev + od;
+      out[3] = om1 * f[3] + ev - od;
+    }
+    {  // (0,1) and (0,-1): c.u = uy, c.f = 0, stress term -Sxx
+      const T cu = uy;
+      const T ev = w1 * (C0 + Acu2 * cu * cu - spS);
+      const T od = w1 * (Bcu * cu);
+      out[2] = om1 * f[2] + ev + od;
+      out[4] = om1 * f[4] + ev - od;
+    }
+    {  // (1,1) and (-1,-1): c.u = ux + uy, c.f = fx, stress term 2 Sxy
+      const T cu = ux + uy;
+      const T ev = w5 * (C0 + Acu2 * cu * cu + spT + Dcf * cu);
+      const T od = w5 * (Bcu * cu + Ccf);
+      out[5] = om1 * f[5] + ev + od;
+      out[7] = om1 * f[7] + ev - od;
+    }
+    {  // (-1,1) and (1,-1): c.u = uy - ux, c.f = -fx, stress term -2 Sxy
+      const T cu = uy - ux;
+      const T ev = w5 * (C0 + Acu2 * cu * cu - spT - Dcf * cu);
+      const T od = w5 * (Bcu * cu - Ccf);
+      out[6] = om1 * f[6] + ev + od;
+      out[8] = om1 * f[8] + ev - od;
+    }
+  }
+}
+
+// Momentum handed to the walls in the previous step: the reflected
+// populations sit in the wall rows with the opposite velocity.
+template <typename T>
+__device__ __forceinline__ double wall_drag(const T f[9], int y, int ny) {
+  double d = 0.0;
+  if (y == 0) d += 2.0 * ((double)f[6] - (double)f[5]);
+  if (y == ny - 1) d += 2.0 * ((double)f[7] - (double)f[8]);
+  return d;
+}
+
+// Workgroup w runs on XCD w % 8; give each XCD a contiguous range of strips
+// so that neighbouring strips share halo rows through that XCD's L2.
+__device__ __forceinline__ int strip_index(const SweepArgs &a) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // Spread consecutive work over one XCD: workgroup w runs on XCD w % 8,
-  // and each XCD takes a contiguous range of strips (vertical neighbours
-  // share halo rows through that XCD's L2).
   const int w = blockIdx.x;
   const int q = a.n_wg >> 3, rem = a.n_wg & 7, j = w & 7;
   const int L = j * q + (j < rem ? j : rem) + (w >> 3);
-  const int sidx = L * 4 + wave;
+  return L * LB_WG_WAVES + wave;
+}
+
+template <typename T, bool SHIFT, int TXW, bool WIDE, bool OBS>
+__global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
+  constexpr int TYW = 64 / TXW;
+  const int lane = threadIdx.x & 63;
+  const int sidx = strip_index(a);
   if (sidx >= a.n_strips) return;
   const Strip st = a.strips[sidx];
   const ChanDev c = a.ch[st.ch];
   const T *__restrict__ A = static_cast<const T *>(a.A);
   T *__restrict__ B = static_cast<T *>(a.B);
-  const long long P = a.plane;
   const int nx = c.nx, ny = c.ny;
   const long long t = c.t + a.k;
   const T fx = (t < c.t_startup) ? T(c.g) : T(0);
+  const Coef<T> q(c);
 
-  int lx, ly, x;
+  int lx, ly, x, hx = 0;
   bool colok;
   if (WIDE) {
+    // 64 columns from x0; lanes past the end of the channel wrap onto valid
+    // columns and only supply neighbours
     lx = lane;
     ly = 0;
-    const int xr = st.x0 + lane - 1;
-    x = ((xr % nx) + nx) % nx;
-    colok = (lane >= 1) && (lane <= 62) && (xr < nx);
+    const int xr = st.x0 + lane;
+    x = xr % nx;
+    colok = xr < nx;
+    // x halo: even lanes pull the column left of the strip, odd lanes the
+    // column right of it
+    hx = (lane & 1) ? (st.x0 + 64) % nx : (st.x0 - 1 + nx) % nx;
   } else {
     lx = lane & (TXW - 1);
     ly = lane / TXW;
     x = lx;
     colok = true;
   }
-  const int left_src = WIDE ? lane - 1 : ly * TXW + ((lx + TXW - 1) & (TXW - 1));
-  const int right_src = WIDE ? lane + 1 : ly * TXW + ((lx + 1) & (TXW - 1));
+  const int left_src = WIDE ? (lane == 0 ? 0 : lane - 1) : ly * TXW + ((lx + TXW - 1) & (TXW - 1));
+  const int right_src = WIDE ? (lane == 63 ? 63 : lane + 1) : ly * TXW + ((lx + 1) & (TXW - 1));
   const long long base = c.off;
 
   auto clampy = [&](int y) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
-  auto load_u = [&](int y, T f[9], T &Pv) -> U2<T> {
+  auto pull_row = [&](int y, T f[9], T &Pv) {
     const int yc = clampy(y);
     const long long row = base + (long long)yc * nx;
-    pull<T>(A, P, row, nx, ny, x, yc, f);
-    Pv = A[9 * P + row + x];
-    T sd, mx, my;
+    pull<T>(A, row, nx, ny, x, yc, f);
+    Pv = A[slot(9, row + x)];
+  };
+  auto halo_u = [&](int y) -> U2<T> {
+    const int yc = clampy(y);
+    T f[9], sd, mx, my;
+    pull<T>(A, base + (long long)yc * nx, nx, ny, hx, yc, f);
     moments<T>(f, sd, mx, my);
-    const T inv = T(1) / (SHIFT ? T(1) + sd : sd);
-    return U2<T>{(mx + T(0.5) * fx) * inv, my * inv};
+    return u_tilde<T, SHIFT>(sd, mx, my, fx);
   };
 
   T fc[9], fn[9], Pc, Pn;
-  U2<T> uPrev, uCur, uNext;
+  U2<T> uPrev, uCur, uNext, uhCur = {T(0), T(0)}, uhNext = {T(0), T(0)};
   {
-    T ftmp[9], Ptmp;
-    uPrev = load_u(st.y0 - TYW + ly, ftmp, Ptmp);
+    T ftmp[9], Ptmp, sd, mx, my;
+    pull_row(st.y0 - TYW + ly, ftmp, Ptmp);
+    moments<T>(ftmp, sd, mx, my);
+    uPrev = u_tilde<T, SHIFT>(sd, mx, my, fx);
   }
-  uCur = load_u(st.y0 + ly, fc, Pc);
-
-  const T om = T(c.omega), kf = T(c.kf), sp = T(c.sp), Gm = T(c.G);
-  const T inv_tau = T(c.inv_tau), inv_gc = T(c.inv_gc), lgt = T(c.lgt);
-  const bool stress_on = c.G > 0.0;
+  T sdc, mxc, myc;
+  pull_row(st.y0 + ly, fc, Pc);
+  moments<T>(fc, sdc, mxc, myc);
+  uCur = u_tilde<T, SHIFT>(sdc, mxc, myc, fx);
+  if (WIDE) uhCur = halo_u(st.y0);
 
 #pragma unroll 1
   for (int yb = st.y0; yb < st.y1; yb += TYW) {
-    uNext = load_u(yb + TYW + ly, fn, Pn);
+    T sdn, mxn, myn;
+    pull_row(yb + TYW + ly, fn, Pn);
+    if (WIDE) uhNext = halo_u(yb + TYW);
+    moments<T>(fn, sdn, mxn, myn);
+    uNext = u_tilde<T, SHIFT>(sdn, mxn, myn, fx);
     const int y = yb + ly;
 
     U2<T> dn, up;
@@ -162,8 +390,13 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a) {
       dn = (ly > 0) ? dc : dp;
       up = (ly < TYW - 1) ? uc : un;
     }
-    const U2<T> lf = shfl2(uCur, left_src < 0 ? 0 : left_src);
-    const U2<T> rt = shfl2(uCur, right_src > 63 ? 63 : right_src);
+    U2<T> lf = shfl2(uCur, left_src);
+    U2<T> rt = shfl2(uCur, right_src);
+    if (WIDE) {
+      const U2<T> hl = shfl2(uhCur, 0), hr = shfl2(uhCur, 1);
+      if (lane == 0) lf = hl;
+      if (lane == 63) rt = hr;
+    }
     // no-slip ghosts behind the half-way walls
     if (y == 0) dn = U2<T>{-uCur.x, -uCur.y};
     if (y == ny - 1) up = U2<T>{-uCur.x, -uCur.y};
@@ -171,125 +404,223 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a) {
     // Every lane computes; only valid lanes store. Lanes past the strip or
     // outside the channel read clamped rows and their results are dropped.
     const bool ok = (y < st.y1) && colok;
-
-    // velocity gradient kappa_ab = d_b u_a (Sec. II.C)
-    const T kxx = T(0.5) * (rt.x - lf.x);
-    const T kxy = T(0.5) * (up.x - dn.x);
-    const T kyx = T(0.5) * (rt.y - lf.y);
-    const T kyy = T(0.5) * (up.y - dn.y);
-
-    // inlM stress: tau_M of Eq. (nlmaxwell), then the steady series of
-    // Eq. (sigtsum) through the relation it satisfies by Eq. (smalld),
-    // sigma - tau_M (kappa sigma + sigma kappa^T) = G tau_M D, solved in
-    // closed form (Cramer) for (sigma_xx, sigma_xy, sigma_yy).
-    const T Dxx = T(2) * kxx, Dxy = kxy + kyx, Dyy = T(2) * kyy;
-    T sxx = T(0), sxy = T(0), syy = T(0);
-    if (stress_on) {
-      const T II = T(0.5) * (Dxx * Dxx + T(2) * Dxy * Dxy + Dyy * Dyy);
-      const T rate = inv_tau + sqrt(II) * inv_gc;
-      if (rate > T(0)) {
-        const T tM = T(1) / rate;
-        const T ka = tM * kxx, kb = tM * kxy, kc = tM * kyx, kd = tM * kyy;
-        const T gt = Gm * tM;
-        const T r1 = gt * Dxx, r2 = gt * Dxy, r3 = gt * Dyy;
-        const T m11 = T(1) - T(2) * ka, m12 = T(-2) * kb, m21 = -kc;
-        const T m22 = T(1) - ka - kd, m23 = -kb, m32 = T(-2) * kc, m33 = T(1) - T(2) * kd;
-        const T c11 = m22 * m33 - m23 * m32;
-        const T det = m11 * c11 - m12 * m21 * m33;
-        const T idet = T(1) / det;
-        const T e2 = r2 * m33 - m23 * r3;
-        sxx = (r1 * c11 - m12 * e2) * idet;
-        sxy = (m11 * e2 - r1 * m21 * m33) * idet;
-        syy = (m11 * (m22 * r3 - r2 * m32) - m12 * m21 * r3 + r1 * m21 * m32) * idet;
-      }
-    }
-    // non-Newtonian stress carried by the forcing (viscosity split)
-    const T Txx = sxx - lgt * Dxx, Txy = sxy - lgt * Dxy, Tyy = syy - lgt * Dyy;
-    const T trT = Txx + Tyy;
-    const T Sxx = T(0.5) * (Txx - Tyy);  // traceless part; Sbar_yy = -Sxx
-    // Eq. (rhoplus): r = dt d(delta rho)/dt with delta rho = -tr Sigma^nN /(cs2 d)
-    const T rr = a.nnp ? T(-1.5) * (trT - Pc) : T(0);
-
-    T sd, mx, my;
-    moments<T>(fc, sd, mx, my);
-    const T jx = mx + T(0.5) * fx, jy = my;
-    // Eq. (rhoj): the equilibrium density is sum (n* + n)/2 = s + r/2, carried
-    // as its deviation from 1 in the shifted storage
-    const T sdev = SHIFT ? sd : sd - T(1);
-    const T rho_dev = sdev + T(0.5) * rr;
-    const T rho_e = SHIFT ? T(1) + rho_dev : sd + T(0.5) * rr;
-    const T irho = T(1) / rho_e;
-    const T ux = jx * irho, uy = jy * irho;
-
-    if (OBS) {
-      double v[OF_COUNT];
-      v[OF_UX] = (double)ux;
-      v[OF_UY] = (double)uy;
-      v[OF_SXX] = (double)sxx;
-      v[OF_SXY] = (double)sxy;
-      v[OF_SYY] = (double)syy;
-      v[OF_RHOE_DEV] = (double)rho_dev;
-      v[OF_MASS_DEV] = (double)sdev + (a.nnp ? 1.5 * (double)Pc : 0.0);
-      v[OF_MOMX] = (double)mx;
-      v[OF_KXY] = (double)kxy;
-      v[OF_TRT] = (double)trT;
-      // x momentum handed to the walls in the previous step: the reflected
-      // populations now sit in the wall rows with the opposite velocity
-      double drag = 0.0;
-      if (y == 0) drag += 2.0 * ((double)fc[6] - (double)fc[5]);
-      if (y == ny - 1) drag += 2.0 * ((double)fc[7] - (double)fc[8]);
-      v[OF_DRAG] = drag;
-      v[OF_KXX] = (double)kxx;
+    T out[9], trT;
+    double obs[OF_COUNT];
+    node_update<T, SHIFT, OBS>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, q, a.nnp, out, trT, obs);
+    if constexpr (OBS) {
+      obs[OF_DRAG] = wall_drag<T>(fc, y, ny);
       constexpr int GW = WIDE ? 64 : TXW;
 #pragma unroll
-      for (int f = 0; f < OF_COUNT; ++f) v[f] = group_sum<GW>(ok ? v[f] : 0.0);
+      for (int f = 0; f < OF_COUNT; ++f) obs[f] = group_sum<GW>(ok ? obs[f] : 0.0);
       const bool writer = WIDE ? (lane == 0) : (lx == 0);
       if (writer && y < st.y1) {
-        const long long pr = (long long)c.poff + (long long)y * c.nxs + (WIDE ? st.x0 / 62 : 0);
+        const long long pr = (long long)c.poff + (long long)y * c.nxs + (WIDE ? st.x0 / 64 : 0);
         double *dst = a.part + pr * OF_COUNT;
 #pragma unroll
-        for (int f = 0; f < OF_COUNT; ++f) dst[f] = v[f];
+        for (int f = 0; f < OF_COUNT; ++f) dst[f] = obs[f];
       }
     } else {
-      // equilibrium, forcing of Eq. (bodyforce) and BGK collision
-      const T usq = ux * ux + uy * uy;
-      const T uf = ux * fx;
-      const T K0 = kf * (rr + T(1.5) * rr * usq - T(3) * uf);
-      const T eq0 = SHIFT ? (rho_dev - T(1.5) * rho_e * usq) : rho_e * (T(1) - T(1.5) * usq);
-      const T Sxy2 = T(2) * Txy;
-      const long long o = base + (long long)y * nx + x;
-      T out[9];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        constexpr int cxs[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-        constexpr int cys[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-        const int cx = cxs[i], cy = cys[i];
-        const T cu = T(cx) * ux + T(cy) * uy;
-        const T cf = T(cx) * fx;
-        const T Q = (i == 0) ? T(0)
-                    : (i < 5 ? (cx != 0 ? Sxx : -Sxx) : (cx * cy > 0 ? Sxy2 : -Sxy2));
-        const T wi = weight<T>(i);
-        const T Fi = wi * (sp * Q + K0 + kf * (T(3) * cf - T(4.5) * rr * cu * cu + T(9) * cu * cf));
-        const T eqi = wi * (eq0 + rho_e * (T(3) * cu + T(4.5) * cu * cu));
-        out[i] = fc[i] - om * (fc[i] - eqi) + Fi;
-      }
       if (ok) {
+        const long long o = base + (long long)y * nx + x;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) B[i * P + o] = out[i];
-        B[9 * P + o] = trT;
+        for (int i = 0; i < 9; ++i) B[slot(i, o)] = out[i];
+        B[slot(9, o)] = trT;
       }
     }
 
     uPrev = uCur;
     uCur = uNext;
+    uhCur = uhNext;
 #pragma unroll
     for (int i = 0; i < 9; ++i) fc[i] = fn[i];
     Pc = Pn;
+    sdc = sdn;
+    mxc = mxn;
+    myc = myn;
   }
 }
 
-// One workgroup per channel: sums the x partials of every row in a fixed
-// order, writes x-averaged rows, channel totals and the steady residual.
+// Aligned 64-column strips of a channel whose width is a multiple of 64
+// (and at least 128). Row y of the strip is tile (off + y nx + x0)/64; lane
+// l owns column x0 + l.
+template <typename T, bool SHIFT, bool OBS>
+__global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int sidx = strip_index(a);
+  if (sidx >= a.n_strips) return;
+  const Strip st = a.strips[sidx];
+  const ChanDev c = a.ch[st.ch];
+  const T *__restrict__ A = static_cast<const T *>(a.A);
+  T *__restrict__ B = static_cast<T *>(a.B);
+  const int nx = c.nx, ny = c.ny;
+  const long long t = c.t + a.k;
+  const T fx = (t < c.t_startup) ? T(c.g) : T(0);
+  const Coef<T> q(c);
+
+  const int tiles_row = nx >> 6;                 // tiles per row
+  const long long tile0 = (c.off + st.x0) >> 6;  // tile of row 0 of this strip
+  const int xt = st.x0 >> 6;                     // tile column of the strip
+  // tile offsets (in tiles) of the left and right neighbour columns' tiles
+  const int dl = (xt == 0) ? tiles_row - 1 : -1;
+  const int dr = (xt == tiles_row - 1) ? -(tiles_row - 1) : 1;
+  constexpr int F = kTile;  // stride between fields inside a tile
+
+  // Wave-uniform addressing: tile index of row y in this strip's column and
+  // in the columns left/right of it; ld() reads one field of one column of a
+  // tile (every lane the same address).
+  auto tile = [&](int y) -> long long { return tile0 + (long long)y * tiles_row; };
+  // wave-uniform loads go through the scalar unit: A is not written during
+  // the sweep, so it can be read as constant memory
+  typedef const __attribute__((address_space(4))) T *cptr;
+  const cptr Ac = (cptr)(A);
+  auto ld = [&](long long tl, int col, int p) -> T { return Ac[(tl * kPlanes + p) * F + col]; };
+  auto run = [&](long long tl, int p) -> T { return A[(tl * kPlanes + p) * F + lane]; };
+
+  // Pull of row y (0 <= y < ny) for every lane from aligned runs of the
+  // strip's own tiles; the x-shifted directions are lane shifts whose edge
+  // lanes take the neighbouring column's value.
+  auto pull_row = [&](int y, T f[9], T &Pv) {
+    const bool bot = (y == 0), top = (y == ny - 1);
+    const long long t0 = tile(y), td = bot ? t0 : tile(y - 1), tu = top ? t0 : tile(y + 1);
+    f[0] = run(t0, 0);
+    f[1] = shift_up(ld(t0 + dl, 63, 1), run(t0, 1));
+    f[3] = shift_down(ld(t0 + dr, 0, 3), run(t0, 3));
+    Pv = run(t0, 9);
+    if (bot) {
+      f[2] = run(t0, 4);
+      f[5] = run(t0, 7);
+      f[6] = run(t0, 8);
+    } else {
+      f[2] = run(td, 2);
+      f[5] = shift_up(ld(td + dl, 63, 5), run(td, 5));
+      f[6] = shift_down(ld(td + dr, 0, 6), run(td, 6));
+    }
+    if (top) {
+      f[4] = run(t0, 2);
+      f[7] = run(t0, 5);
+      f[8] = run(t0, 6);
+    } else {
+      f[4] = run(tu, 4);
+      f[7] = shift_down(ld(tu + dr, 0, 7), run(tu, 7));
+      f[8] = shift_up(ld(tu + dl, 63, 8), run(tu, 8));
+    }
+  };
+  // u~ of the column left of the strip (column 63 of the left tile) and of
+  // the column right of it (column 0 of the right tile), from wave-uniform
+  // pulls.
+  auto halo_u = [&](int y, U2<T> &uL, U2<T> &uR) {
+    const bool bot = (y == 0), top = (y == ny - 1);
+    const long long t0 = tile(y), L0 = t0 + dl, R0 = t0 + dr;
+    T a[9], b[9];
+    a[0] = ld(L0, 63, 0);
+    a[1] = ld(L0, 62, 1);
+    a[3] = ld(t0, 0, 3);
+    b[0] = ld(R0, 0, 0);
+    b[1] = ld(t0, 63, 1);
+    b[3] = ld(R0, 1, 3);
+    if (bot) {
+      a[2] = ld(L0, 63, 4);
+      a[5] = ld(L0, 63, 7);
+      a[6] = ld(L0, 63, 8);
+      b[2] = ld(R0, 0, 4);
+      b[5] = ld(R0, 0, 7);
+      b[6] = ld(R0, 0, 8);
+    } else {
+      const long long td = tile(y - 1);
+      a[2] = ld(td + dl, 63, 2);
+      a[5] = ld(td + dl, 62, 5);
+      a[6] = ld(td, 0, 6);
+      b[2] = ld(td + dr, 0, 2);
+      b[5] = ld(td, 63, 5);
+      b[6] = ld(td + dr, 1, 6);
+    }
+    if (top) {
+      a[4] = ld(L0, 63, 2);
+      a[7] = ld(L0, 63, 5);
+      a[8] = ld(L0, 63, 6);
+      b[4] = ld(R0, 0, 2);
+      b[7] = ld(R0, 0, 5);
+      b[8] = ld(R0, 0, 6);
+    } else {
+      const long long tu = tile(y + 1);
+      a[4] = ld(tu + dl, 63, 4);
+      a[7] = ld(tu, 0, 7);
+      a[8] = ld(tu + dl, 62, 8);
+      b[4] = ld(tu + dr, 0, 4);
+      b[7] = ld(tu + dr, 1, 7);
+      b[8] = ld(tu, 63, 8);
+    }
+    T sd, mx, my;
+    moments<T>(a, sd, mx, my);
+    uL = u_tilde<T, SHIFT>(sd, mx, my, fx);
+    moments<T>(b, sd, mx, my);
+    uR = u_tilde<T, SHIFT>(sd, mx, my, fx);
+  };
+  auto clampy = [&](int y) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
+
+  T fc[9], fn[9], Pc, Pn;
+  U2<T> uPrev, uCur, uNext, uLc, uRc, uLn, uRn;
+  {
+    T ftmp[9], Ptmp, sd, mx, my;
+    pull_row(clampy(st.y0 - 1), ftmp, Ptmp);
+    moments<T>(ftmp, sd, mx, my);
+    uPrev = u_tilde<T, SHIFT>(sd, mx, my, fx);
+  }
+  T sdc, mxc, myc;
+  pull_row(st.y0, fc, Pc);
+  moments<T>(fc, sdc, mxc, myc);
+  uCur = u_tilde<T, SHIFT>(sdc, mxc, myc, fx);
+  halo_u(st.y0, uLc, uRc);
+
+#pragma unroll 1
+  for (int y = st.y0; y < st.y1; ++y) {
+    const int yn = clampy(y + 1);
+    T sdn, mxn, myn;
+    pull_row(yn, fn, Pn);
+    halo_u(yn, uLn, uRn);
+    moments<T>(fn, sdn, mxn, myn);
+    uNext = u_tilde<T, SHIFT>(sdn, mxn, myn, fx);
+
+    U2<T> dn = uPrev, up = uNext;
+    const U2<T> lf{shift_up(uLc.x, uCur.x), shift_up(uLc.y, uCur.y)};
+    const U2<T> rt{shift_down(uRc.x, uCur.x), shift_down(uRc.y, uCur.y)};
+    // no-slip ghosts behind the half-way walls
+    if (y == 0) dn = U2<T>{-uCur.x, -uCur.y};
+    if (y == ny - 1) up = U2<T>{-uCur.x, -uCur.y};
+
+    T out[9], trT;
+    double obs[OF_COUNT];
+    node_update<T, SHIFT, OBS>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, q, a.nnp, out, trT, obs);
+    if constexpr (OBS) {
+      obs[OF_DRAG] = wall_drag<T>(fc, y, ny);
+#pragma unroll
+      for (int f = 0; f < OF_COUNT; ++f) obs[f] = group_sum<64>(obs[f]);
+      if (lane == 0) {
+        const long long pr = (long long)c.poff + (long long)y * c.nxs + xt;
+        double *dst = a.part + pr * OF_COUNT;
+#pragma unroll
+        for (int f = 0; f < OF_COUNT; ++f) dst[f] = obs[f];
+      }
+    } else {
+      T *w = B + tile(y) * (kPlanes * F);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) w[i * F + lane] = out[i];
+      w[9 * F + lane] = trT;
+    }
+
+    uPrev = uCur;
+    uCur = uNext;
+    uLc = uLn;
+    uRc = uRn;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fc[i] = fn[i];
+    Pc = Pn;
+    sdc = sdn;
+    mxc = mxn;
+    myc = myn;
+  }
+}
+
 __global__ void __launch_bounds__(256) reduce_kernel(const ChanDev *ch, const double *part,
                                                      double *prof, double *prev_ux, double *scal,
                                                      int update_residual, int steps_since) {
@@ -371,11 +702,22 @@ __global__ void advance_kernel(ChanDev *ch, int n_ch, int steps) {
 template <typename T, bool SHIFT, int TXW, bool WIDE>
 hipError_t launch_cls(bool observe, const SweepArgs &a, hipStream_t s) {
   if (a.n_strips == 0) return hipSuccess;
-  dim3 grid(a.n_wg), block(256);
+  dim3 grid(a.n_wg), block(64 * LB_WG_WAVES);
   if (observe)
     hipLaunchKernelGGL((sweep_kernel<T, SHIFT, TXW, WIDE, true>), grid, block, 0, s, a);
   else
     hipLaunchKernelGGL((sweep_kernel<T, SHIFT, TXW, WIDE, false>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, bool SHIFT>
+hipError_t launch_wide64(bool observe, const SweepArgs &a, hipStream_t s) {
+  if (a.n_strips == 0) return hipSuccess;
+  dim3 grid(a.n_wg), block(64 * LB_WG_WAVES);
+  if (observe)
+    hipLaunchKernelGGL((sweep_wide64_kernel<T, SHIFT, true>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((sweep_wide64_kernel<T, SHIFT, false>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
@@ -389,6 +731,7 @@ hipError_t launch_prec(int cls, bool observe, const SweepArgs &a, hipStream_t s)
     case 4: return launch_cls<T, SHIFT, 16, false>(observe, a, s);
     case 5: return launch_cls<T, SHIFT, 32, false>(observe, a, s);
     case 6: return launch_cls<T, SHIFT, 64, false>(observe, a, s);
+    case kWide64Class: return launch_wide64<T, SHIFT>(observe, a, s);
     default: return launch_cls<T, SHIFT, 64, true>(observe, a, s);
   }
 }

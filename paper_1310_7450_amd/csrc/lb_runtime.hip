@@ -17,9 +17,14 @@ using namespace lbnlm;
 
 namespace {
 
-constexpr int kWideInterior = 62;  // interior columns of a wide strip
+constexpr int kWideInterior = 64;  // columns of a wide strip
 constexpr int kDefaultK = 1000;
 constexpr size_t kAlign = 256;
+#ifndef LB_WG_WAVES
+#define LB_WG_WAVES 4
+#endif
+constexpr int kWaves = LB_WG_WAVES;  // wavefronts (strips) per workgroup
+
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -30,7 +35,7 @@ constexpr int HOPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 inline double hweight(int i) { return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
 
 struct Layout {
-  long long plane = 0;       // elements per plane
+  long long plane = 0;       // nodes per state buffer (multiple of the tile)
   int esize = 8;             // bytes per element
   int total_rows = 0;
   int total_part = 0;
@@ -93,7 +98,7 @@ void resolve(const lb_channel &q, ChanDev &d) {
 }
 
 int strip_rows_for(int cls, int nx, int ny, int requested) {
-  if (cls == kWideClass) {
+  if (is_strip_class(cls)) {
     int s = requested > 0 ? requested : 16;
     return std::max(1, std::min(s, ny));
   }
@@ -103,12 +108,14 @@ int strip_rows_for(int cls, int nx, int ny, int requested) {
   return s;
 }
 
-// Strips of one channel, column-major (vertical neighbours adjacent).
+// Strips of one channel in row-band order: the strips of one band of rows
+// are consecutive (x neighbours, which share cache lines at their edges,
+// land on the same XCD), and bands follow each other upwards.
 void add_strips(int ci, const ChanDev &d, int srows, std::vector<Strip> &out) {
   const int cls = width_class(d.nx);
-  const int nxs = (cls == kWideClass) ? (d.nx + kWideInterior - 1) / kWideInterior : 1;
-  for (int xs = 0; xs < nxs; ++xs)
-    for (int y0 = 0; y0 < d.ny; y0 += srows)
+  const int nxs = is_strip_class(cls) ? (d.nx + kWideInterior - 1) / kWideInterior : 1;
+  for (int y0 = 0; y0 < d.ny; y0 += srows)
+    for (int xs = 0; xs < nxs; ++xs)
       out.push_back(Strip{ci, xs * kWideInterior, y0, std::min(y0 + srows, d.ny)});
 }
 
@@ -126,13 +133,13 @@ Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
     d.row_off = rows;
     rows += c[i].ny;
     const int cls = width_class(c[i].nx);
-    d.nxs = (cls == kWideClass) ? (c[i].nx + kWideInterior - 1) / kWideInterior : 1;
+    d.nxs = is_strip_class(cls) ? (c[i].nx + kWideInterior - 1) / kWideInterior : 1;
     d.poff = part;
     part += d.nxs * c[i].ny;
     const int srows = strip_rows_for(cls, c[i].nx, c[i].ny, o->strip_rows);
     strips += d.nxs * ((c[i].ny + srows - 1) / srows);
   }
-  L.plane = (long long)align_up((size_t)std::max<long long>(node, 64), 64);
+  L.plane = (long long)align_up((size_t)std::max<long long>(node, kTile), kTile);
   L.total_rows = rows;
   L.total_part = part;
   L.max_strips = strips;
@@ -171,8 +178,8 @@ struct lb_handle {
   Strip *dact = nullptr;     // active channels, for stepping
   double *dpart = nullptr, *dprof = nullptr, *dprev = nullptr, *dscal = nullptr;
   // strips grouped by width class: [begin, begin + count) in the arrays
-  int all_begin[8] = {0}, all_count[8] = {0};
-  int act_begin[8] = {0}, act_count[8] = {0};
+  int all_begin[kClasses] = {0}, all_count[kClasses] = {0};
+  int act_begin[kClasses] = {0}, act_count[kClasses] = {0};
   int cur = 0;               // buffer holding the current state
   hipStream_t stream = nullptr, cap = nullptr;
   bool own_stream = false;
@@ -203,9 +210,9 @@ lb_status hipfail(lb_handle *h, hipError_t e, const char *where) {
   } while (0)
 
 void group_strips(const std::vector<Strip> &s, const std::vector<ChanDev> &ch,
-                  std::vector<Strip> &out, int begin[8], int count[8]) {
+                  std::vector<Strip> &out, int begin[kClasses], int count[kClasses]) {
   out.clear();
-  for (int c = 0; c < 8; ++c) {
+  for (int c = 0; c < kClasses; ++c) {
     begin[c] = (int)out.size();
     for (const Strip &x : s)
       if (width_class(ch[x.ch].nx) == c) out.push_back(x);
@@ -245,7 +252,7 @@ SweepArgs sweep_args(lb_handle *h, const Strip *strips, int begin, int count, in
   a.ch = h->dch;
   a.part = h->dpart;
   a.n_strips = count;
-  a.n_wg = (count + 3) / 4;
+  a.n_wg = (count + kWaves - 1) / kWaves;
   a.k = k;
   a.nnp = h->opt.nn_pressure;
   return a;
@@ -253,7 +260,7 @@ SweepArgs sweep_args(lb_handle *h, const Strip *strips, int begin, int count, in
 
 // Enqueues the sweeps of one step (source buffer src, step offset k).
 lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s) {
-  for (int c = 0; c < 8; ++c) {
+  for (int c = 0; c < kClasses; ++c) {
     if (!h->act_count[c]) continue;
     SweepArgs a = sweep_args(h, h->dact, h->act_begin[c], h->act_count[c], src, k);
     HIPCHECK(h, launch_sweep(h->opt.precision == LB_FP32_SHIFTED, c, false, a, s));
@@ -262,7 +269,7 @@ lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s) {
 }
 
 lb_status enqueue_observe(lb_handle *h, int update_residual, int steps_since) {
-  for (int c = 0; c < 8; ++c) {
+  for (int c = 0; c < kClasses; ++c) {
     if (!h->all_count[c]) continue;
     SweepArgs a = sweep_args(h, h->dall, h->all_begin[c], h->all_count[c], h->cur, 0);
     HIPCHECK(h, launch_sweep(h->opt.precision == LB_FP32_SHIFTED, c, true, a, h->stream));
@@ -556,17 +563,18 @@ lb_status lb_get_state(lb_handle *h, int32_t ch, double *pops, double *P) {
   if (ch < 0 || ch >= h->n_ch || !pops || !P) return fail(h, LB_EINVAL, "bad channel or output");
   const ChanDev &d = h->L.ch[ch];
   const size_t N = (size_t)d.nx * d.ny;
+  const size_t Npad = align_up(N, kTile);
   const int es = h->L.esize;
-  std::vector<char> raw((size_t)kPlanes * N * es);
+  // the channel's tiles are one contiguous block of the state buffer
+  std::vector<char> raw((size_t)kPlanes * Npad * es);
   const char *src = static_cast<const char *>(h->buf[h->cur]);
-  for (int p = 0; p < kPlanes; ++p)
-    HIPCHECK(h, hipMemcpyAsync(raw.data() + (size_t)p * N * es,
-                               src + ((size_t)p * h->L.plane + d.off) * es, N * es,
-                               hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipMemcpyAsync(raw.data(), src + (size_t)slot(0, d.off) * es, raw.size(),
+                             hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(h, hipStreamSynchronize(h->stream));
   auto at = [&](int p, size_t id) -> double {
-    if (es == 8) return reinterpret_cast<const double *>(raw.data())[(size_t)p * N + id];
-    const double v = reinterpret_cast<const float *>(raw.data())[(size_t)p * N + id];
+    const size_t k = (size_t)slot(p, (long long)id);
+    if (es == 8) return reinterpret_cast<const double *>(raw.data())[k];
+    const double v = reinterpret_cast<const float *>(raw.data())[k];
     return p < 9 ? v + hweight(p) : v;
   };
   // the pull: stored slot (plane i, source node) -> n_i at the destination
@@ -593,13 +601,21 @@ lb_status lb_set_state(lb_handle *h, int32_t ch, const double *pops, const doubl
   if (ch < 0 || ch >= h->n_ch || !pops || !P || t < 0) return fail(h, LB_EINVAL, "bad arguments");
   const ChanDev &d = h->L.ch[ch];
   const size_t N = (size_t)d.nx * d.ny;
+  const size_t Npad = align_up(N, kTile);
   const int es = h->L.esize;
-  std::vector<char> raw((size_t)kPlanes * N * es);
+  // start from the device copy so the padding slots of the last tile keep
+  // their values
+  std::vector<char> raw((size_t)kPlanes * Npad * es);
+  char *dst = static_cast<char *>(h->buf[h->cur]);
+  HIPCHECK(h, hipMemcpyAsync(raw.data(), dst + (size_t)slot(0, d.off) * es, raw.size(),
+                             hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
   auto put = [&](int p, size_t id, double v) {
+    const size_t k = (size_t)slot(p, (long long)id);
     if (es == 8)
-      reinterpret_cast<double *>(raw.data())[(size_t)p * N + id] = v;
+      reinterpret_cast<double *>(raw.data())[k] = v;
     else
-      reinterpret_cast<float *>(raw.data())[(size_t)p * N + id] = (float)(p < 9 ? v - hweight(p) : v);
+      reinterpret_cast<float *>(raw.data())[k] = (float)(p < 9 ? v - hweight(p) : v);
   };
   // inverse of the pull: every stored slot feeds exactly one (node, i)
   for (int y = 0; y < d.ny; ++y)
@@ -616,11 +632,8 @@ lb_status lb_set_state(lb_handle *h, int32_t ch, const double *pops, const doubl
       }
       put(9, id, P[id]);
     }
-  HIPCHECK(h, hipStreamSynchronize(h->stream));
-  char *dst = static_cast<char *>(h->buf[h->cur]);
-  for (int p = 0; p < kPlanes; ++p)
-    HIPCHECK(h, hipMemcpyAsync(dst + ((size_t)p * h->L.plane + d.off) * es,
-                               raw.data() + (size_t)p * N * es, N * es, hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(h, hipMemcpyAsync(dst + (size_t)slot(0, d.off) * es, raw.data(), raw.size(),
+                             hipMemcpyHostToDevice, h->stream));
   // step counter and residual history of this channel
   std::vector<ChanDev> cur(h->n_ch);
   HIPCHECK(h, hipMemcpyAsync(cur.data(), h->dch, sizeof(ChanDev) * h->n_ch, hipMemcpyDeviceToHost, h->stream));
@@ -691,29 +704,25 @@ lb_status lb_set_profile(lb_handle *h, int32_t ch, const double *ux, const doubl
 
 namespace {
 
-__global__ void fill_kernel_d(double *p, long long n, double v) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-__global__ void fill_kernel_f(float *p, long long n, float v) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    p[i] = v;
+// Rest state: n_i = a_i (stored as 0 when shifted), previous trace 0.
+template <typename T>
+__global__ void fill_rest_kernel(T *p, long long n_slots, int shifted) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n_slots;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int f = (int)((i / kTile) % kPlanes);
+    p[i] = (f < 9 && !shifted) ? T(f == 0 ? 4.0 / 9.0 : (f < 5 ? 1.0 / 9.0 : 1.0 / 36.0)) : T(0);
+  }
 }
 
-// Rest state in buffer `which`: n_i = a_i (stored as 0 when shifted), P = 0.
 lb_status fill_rest(lb_handle *h, int which) {
-  const long long n = h->L.plane;
-  for (int p = 0; p < kPlanes; ++p) {
-    const double v = (p < 9 && h->L.esize == 8) ? hweight(p) : 0.0;
-    if (h->L.esize == 8) {
-      double *base = static_cast<double *>(h->buf[which]) + (size_t)p * n;
-      hipLaunchKernelGGL(fill_kernel_d, dim3(1024), dim3(256), 0, h->stream, base, n, v);
-    } else {
-      float *base = static_cast<float *>(h->buf[which]) + (size_t)p * n;
-      hipLaunchKernelGGL(fill_kernel_f, dim3(1024), dim3(256), 0, h->stream, base, n, (float)v);
-    }
-    HIPCHECK(h, hipGetLastError());
-  }
+  const long long n = (long long)kPlanes * h->L.plane;
+  if (h->L.esize == 8)
+    hipLaunchKernelGGL(fill_rest_kernel<double>, dim3(2048), dim3(256), 0, h->stream,
+                       static_cast<double *>(h->buf[which]), n, 0);
+  else
+    hipLaunchKernelGGL(fill_rest_kernel<float>, dim3(2048), dim3(256), 0, h->stream,
+                       static_cast<float *>(h->buf[which]), n, 1);
+  HIPCHECK(h, hipGetLastError());
   return LB_OK;
 }
 

@@ -106,13 +106,15 @@ def test_poiseuille_fp32_shifted(orc):
             assert eu < FP32_TOL and es < FP32_TOL
 
 
-@pytest.mark.parametrize("nx,ny", [(1, 16), (2, 9), (4, 33), (16, 20), (64, 7), (3, 12), (100, 37), (130, 5), (63, 2), (8, 1)])
+@pytest.mark.parametrize("nx,ny", [(1, 16), (2, 9), (4, 33), (16, 20), (64, 7), (3, 12), (100, 37), (130, 5), (63, 2),
+                                   (8, 1), (128, 9), (192, 5), (256, 3), (128, 1), (384, 2)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_perturbed_state_parity(orc, nx, ny, precision):
     """Seeded random populations (every moment non-zero, x gradients present)
-    on narrow, wide and ragged lattices: one and several steps match the
-    oracle node by node; covers the lane-group wrap, the halo lanes of wide
-    strips, partial last strips, and single/double-row channels."""
+    on narrow, aligned-wide (nx a multiple of 64), ragged-wide and odd
+    lattices: one and several steps match the oracle node by node; covers the
+    lane-group wrap, the edge columns and halo of wide strips, the periodic
+    wrap across strips, partial last strips, and one/two-row channels."""
     spec = ChannelSpec(nx=nx, ny=ny, force=3e-6, tau_lb=0.8, G=2e-4, tau0=500.0, gamma_c=0.1,
                        eps=0.01, visc_split=0.3, t_startup=40)
     pops, P = workloads.random_state(nx, ny, seed=nx * 1000 + ny)
@@ -180,8 +182,8 @@ def test_observables_match_oracle(orc):
 def test_bitwise_repeat_and_step_splitting():
     """Two handles give identical states; N steps equal k + (N - k) steps in
     any split across graph boundaries (bitwise)."""
-    spec = ChannelSpec(200, 50, 1e-6, 1.0, 1e-4, 1e3, 0.1)
-    pops0, P0 = workloads.perturbed_rest_state(200, 50, seed=7)
+    spec = ChannelSpec(256, 50, 1e-6, 1.0, 1e-4, 1e3, 0.1)
+    pops0, P0 = workloads.perturbed_rest_state(256, 50, seed=7)
     states = []
     for split in [[2500], [1000, 1500], [999, 1, 1337, 163], [2500]]:
         with solver([spec], precision="fp32", obs_every=500) as s:
@@ -193,10 +195,11 @@ def test_bitwise_repeat_and_step_splitting():
         assert np.array_equal(pops, states[0][0]) and np.array_equal(P, states[0][1])
 
 
-def test_x_uniform_stays_bitwise_uniform():
+@pytest.mark.parametrize("nx", [300, 512])
+def test_x_uniform_stays_bitwise_uniform(nx):
     """A wide x-periodic channel started from rest stays exactly x-uniform:
-    every halo lane and wrapped column computes the same values."""
-    spec = ChannelSpec(300, 40, 1e-6, 1.0, 1e-4, 1e3, 0.1)
+    every halo lane, edge column and wrapped column computes the same values."""
+    spec = ChannelSpec(nx, 40, 1e-6, 1.0, 1e-4, 1e3, 0.1)
     with solver([spec], precision="fp64", obs_every=100) as s:
         s.step(777)
         pops, P = s.get_state(0)
