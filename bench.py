@@ -10,6 +10,7 @@ the same lattice on the host.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +24,23 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic HBM bytes per node update: read 9 populations + the previous
 # stress trace, write 9 populations + the new trace.
 BYTES_PER_NODE = {"fp32": 80, "fp64": 160}
+
+
+def measured_traffic(precision):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size), or
+    None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_large_channel_4096x1024.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ["lb_kernels.hip", "lb_runtime.hip", "lb_internal.h"]:
+        h.update(open(os.path.join(ROOT, "paper_1310_7450_amd", "csrc", f), "rb").read())
+    if h.hexdigest()[:16] != rec.get("source_hash"):
+        return None
+    k = rec["kernels"].get(precision)
+    return None if k is None else round(k["traffic_bytes"])
 
 
 def time_solver(precision, wl, steps, warmup, strip_rows=0):
@@ -145,11 +163,12 @@ def main():
                    "tau0": spec.tau0, "gamma_c": spec.gamma_c, "precision": "fp32_shifted",
                    "nn_pressure": 1, "start": "rest"},
         "roofline": {"bound": "hbm", "achieved": round(r32["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(r32["frac"], 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(r32["frac"], 4), "traffic": measured_traffic("fp32"),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"},
         "fp64": None if r64 is None else {
             "value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 5),
             "roofline": {"bound": "hbm", "achieved": round(r64["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(r64["frac"], 4)}},
+                         "unit": "GB/s", "frac": round(r64["frac"], 4), "traffic": measured_traffic("fp64")}},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
