@@ -1,0 +1,73 @@
+"""Tile autotuner: picks the rows per wavefront strip of the sweep.
+
+For a set of channels and a precision it times each candidate on a throwaway
+handle (so the caller's state is untouched) with HIP events on the handle's
+stream, keeps the fastest, and caches the choice in a JSON file keyed by the
+device name, the precision and the shape of the batch (the width classes,
+the node count and the row-count range).
+"""
+import json
+import os
+from typing import Iterable, Optional, Sequence
+
+from .lbnlm import ChannelSpec, Solver
+
+DEFAULT_CANDIDATES = (4, 8, 16, 24, 32, 64)
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lbnlm_autotune.json")
+
+
+def shape_key(channels: Sequence[ChannelSpec], precision: str) -> str:
+    import torch
+    nodes = sum(c.nx * c.ny for c in channels)
+    widths = sorted({c.nx for c in channels})
+    nys = [c.ny for c in channels]
+    dev = torch.cuda.get_device_name(0)
+    # node count rounded to two significant digits
+    mag = 10 ** max(len(str(nodes)) - 2, 0)
+    return f"{dev}|{precision}|nx={widths[:8]}|nodes~{round(nodes / mag) * mag}|ny={min(nys)}-{max(nys)}"
+
+
+def time_candidate(channels, precision, strip_rows, steps, nn_pressure=True):
+    import torch
+    with Solver(channels, precision=precision, obs_every=max(2, (steps // 2) // 2 * 2),
+                strip_rows=strip_rows, nn_pressure=nn_pressure) as s:
+        s.step(s.opts.obs_every)  # captures the graph and warms the caches
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.step(steps)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+
+def tune_strip_rows(channels: Sequence[ChannelSpec], precision: str = "fp32",
+                    candidates: Iterable[int] = DEFAULT_CANDIDATES, steps: int = 200,
+                    cache_path: Optional[str] = DEFAULT_CACHE, nn_pressure: bool = True,
+                    verbose: bool = False) -> int:
+    """Returns the fastest rows-per-strip for these channels (cached)."""
+    key = shape_key(channels, precision)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        try:
+            cache = json.load(open(cache_path))
+        except (OSError, ValueError):
+            cache = {}
+    if key in cache:
+        return int(cache[key]["strip_rows"])
+    times = {}
+    for sr in candidates:
+        times[sr] = time_candidate(channels, precision, sr, steps, nn_pressure)
+        if verbose:
+            print(f"autotune {key}: strip_rows={sr} {times[sr] * 1e3:.1f} us/step", flush=True)
+    best = min(times, key=times.get)
+    cache[key] = {"strip_rows": best, "ms_per_step": times}
+    if cache_path:
+        try:
+            os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+            tmp = cache_path + ".tmp"
+            json.dump(cache, open(tmp, "w"), indent=1)
+            os.replace(tmp, cache_path)
+        except OSError:
+            pass
+    return best

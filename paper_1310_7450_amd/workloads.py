@@ -67,3 +67,40 @@ def random_state(nx, ny, seed, amplitude=1e-3):
     pops = REST_WEIGHTS[:, None, None] * (1.0 + amplitude * rng.uniform(-1, 1, size=(9, ny, nx)))
     P = 1e-6 * rng.uniform(-1, 1, size=(ny, nx))
     return np.ascontiguousarray(pops), np.ascontiguousarray(P)
+
+
+# Admission rules of the batched sweep (input recipe; see the design notes):
+# the explicit stress is well conditioned for G_inf tau <= 0.3 at
+# visc_split 0 (a measured stability map of the scheme), and the low-Mach
+# limit asks for a solvent-viscosity Poiseuille velocity g H^2 / (2 eta_s)
+# of at most 0.1.
+GTAU_MAX = 0.3
+U_SOLVENT_MAX = 0.1
+
+
+def _closure(tau0, eps, G=1e-4):
+    tau = tau0 * 10.0 ** (min(eps, 0.0) / 0.05)
+    return G * (1.0 + max(eps, 0.0) ** 0.5), tau
+
+
+def batched_sweep(seed=2, n_channels=256, nx=8, tau_lb=1.0, G=1e-4, gamma_c=0.1):
+    """Channels drawn in order ny ~ U{32..512}, log10 g ~ U(-7,-5),
+    eps ~ U(-0.1, 0.1), log10 tau0 ~ U(3, 5) from ``seed``; a draw is kept if
+    G_inf tau <= GTAU_MAX and g (ny/2)^2 / (2 eta_s) <= U_SOLVENT_MAX,
+    otherwise redrawn. Returns the channels and the number of draws."""
+    rng = np.random.default_rng(seed)
+    eta_s = (tau_lb - 0.5) / 3.0
+    chans, draws = [], 0
+    while len(chans) < n_channels:
+        ny = int(rng.integers(32, 513))
+        g = 10.0 ** rng.uniform(-7.0, -5.0)
+        eps = rng.uniform(-0.1, 0.1)
+        tau0 = 10.0 ** rng.uniform(3.0, 5.0)
+        draws += 1
+        Ginf, tau = _closure(tau0, eps, G)
+        if Ginf * tau > GTAU_MAX or g * (ny / 2.0) ** 2 / (2 * eta_s) > U_SOLVENT_MAX:
+            continue
+        chans.append(ChannelSpec(nx=nx, ny=ny, force=g, tau_lb=tau_lb, G=G, tau0=tau0, gamma_c=gamma_c,
+                                 eps=eps, visc_split=0.0))
+    return {"name": f"batched_sweep_{n_channels}x{nx}", "channels": chans, "draws": draws, "seed": seed,
+            "steady_tol": 1e-9, "obs_every": 1000, "max_steps": 3_000_000}

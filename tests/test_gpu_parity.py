@@ -283,3 +283,22 @@ def test_poiseuille_gtau1_short_exact_long_statistical(orc):
         print(f"G tau = 1 at t=20000: u_x Linf rel {e:.3e}", flush=True)
         assert e < 1e-2
         assert abs(s.observe(0, "mass") - 512) < 1e-9
+
+
+def test_batched_sweep_subset_to_steady(orc):
+    """The first 24 channels of the batched sweep (nx = 8, ragged widths and
+    parameters) in one FP32 handle, each frozen at residual < 1e-9: all
+    converge, and the four narrowest match oracle runs of the same length
+    within the FP32 tolerance."""
+    import dataclasses
+    wl = workloads.batched_sweep()
+    chans = wl["channels"][:24]
+    with solver(chans, precision="fp32", obs_every=1000, steady_tol=1e-9, strip_rows=64) as s:
+        s.step(3_000_000)
+        steps = [int(s.observe(i, "step")) for i in range(len(chans))]
+        assert all(s.observe(i, "active") == 0 for i in range(len(chans))), steps
+        order = np.argsort([c.ny for c in chans])[:4]
+        for i in order:
+            o = oracle_channel(orc, dataclasses.replace(chans[i], nx=1))
+            o.run(steps[i])
+            compare_fields(s, int(i), o, FP32_TOL, f"batched ny={chans[i].ny} steps={steps[i]}")
