@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbnlm.so")
-SOURCES = ["lb_kernels.hip", "lb_runtime.hip"]
+SOURCES = ["lb_kernels.hip", "lb_runtime.hip", "mlp_kernels.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
