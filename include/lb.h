@@ -168,14 +168,22 @@ lb_status lb_get_state(lb_handle *h, int32_t ch, double *pops, double *P);
  * its step counter to t. Synchronises the stream. */
 lb_status lb_set_state(lb_handle *h, int32_t ch, const double *pops, const double *P, int64_t t);
 
+/* Point sets of lb_set_profile. */
+enum {
+  LB_PROFILE_ROWS = 0,      /* n_pts == ny values at the lattice rows y = 0..ny-1 */
+  LB_PROFILE_CHEBYSHEV = 1  /* values at d_k = cos(pi (2k+1) / (2 n_pts)), k < n_pts,
+                               d = (y - y_c)/H across the channel; interpolated to
+                               the rows with the barycentric formula */
+};
+
 /* Initialises channel ch from a predicted steady profile (a warm start):
- * u_x and N1 given at n_pts points, either the ny lattice rows (n_pts == ny)
- * or the Chebyshev-Gauss points d_k = cos(pi (2k+1) / (2 n_pts)) across the
- * channel (d = (y - y_c)/H, n_pts != ny). Populations are set to the
- * equilibrium at u = (u_x, 0) and rho_e = 1 - (3/2) N1 (so that the
+ * u_x and N1 given at n_pts points of the set `points`. Populations are set
+ * to the equilibrium at u = (u_x, 0) and rho_e = 1 - (3/2) N1 (so that the
  * hydrodynamic mass equals that of the rest state) and the previous trace to
- * N1. The step counter is kept. */
-lb_status lb_set_profile(lb_handle *h, int32_t ch, const double *ux, const double *n1, int32_t n_pts);
+ * N1. The step counter is kept. LB_EINVAL for an unknown point set or
+ * n_pts != ny with LB_PROFILE_ROWS. */
+lb_status lb_set_profile(lb_handle *h, int32_t ch, const double *ux, const double *n1, int32_t n_pts,
+                         int32_t points);
 
 /* Message of the last error on this handle (never NULL). */
 const char *lb_last_error(const lb_handle *h);

@@ -41,7 +41,10 @@ lbml_status lbml_param_count(int32_t n_layers, const int32_t *dims, size_t *coun
 
 /* Creates a network in caller-owned device memory (aligned to 256 bytes,
  * kept alive until lbml_destroy). Parameters are zero until lbml_set_params;
- * the Adam moments start at zero. hip_stream NULL: the library owns a stream. */
+ * the Adam moments start at zero. hip_stream: the stream every call of this
+ * handle runs on; NULL is the default (null) stream. The caller orders its own
+ * producers and consumers of dev_ buffers with that stream (passing the
+ * stream those run on is the simple way). */
 lbml_status lbml_create(int32_t n_layers, const int32_t *dims, int32_t max_batch, void *dev_workspace,
                         size_t ws_bytes, void *hip_stream, lbml_net **out);
 lbml_status lbml_destroy(lbml_net *net);

@@ -649,12 +649,15 @@ lb_status lb_set_state(lb_handle *h, int32_t ch, const double *pops, const doubl
   return LB_OK;
 }
 
-lb_status lb_set_profile(lb_handle *h, int32_t ch, const double *ux, const double *n1, int32_t n_pts) {
+lb_status lb_set_profile(lb_handle *h, int32_t ch, const double *ux, const double *n1, int32_t n_pts,
+                         int32_t points) {
   if (!h) return LB_EINVAL;
   if (ch < 0 || ch >= h->n_ch || !ux || !n1 || n_pts < 1) return fail(h, LB_EINVAL, "bad arguments");
+  if (points != LB_PROFILE_ROWS && points != LB_PROFILE_CHEBYSHEV) return fail(h, LB_EINVAL, "unknown point set");
   const ChanDev &d = h->L.ch[ch];
+  if (points == LB_PROFILE_ROWS && n_pts != d.ny) return fail(h, LB_EINVAL, "row profile needs ny values");
   std::vector<double> u(d.ny), q(d.ny);
-  if (n_pts == d.ny) {
+  if (points == LB_PROFILE_ROWS) {
     for (int y = 0; y < d.ny; ++y) {
       u[y] = ux[y];
       q[y] = n1[y];

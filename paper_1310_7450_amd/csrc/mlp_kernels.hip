@@ -202,7 +202,6 @@ struct lbml_net {
   int nl = 0, max_batch = 0;
   char *ws = nullptr;
   hipStream_t stream = nullptr;
-  bool own_stream = false;
   const float *last_x = nullptr;
   int last_batch = 0;
   std::string err;
@@ -263,15 +262,7 @@ lbml_status lbml_create(int32_t nl, const int32_t *dims, int32_t max_batch, void
   h->nl = nl;
   h->max_batch = max_batch;
   h->ws = static_cast<char *>(ws);
-  if (stream) {
-    h->stream = static_cast<hipStream_t>(stream);
-  } else {
-    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
-      delete h;
-      return -3;
-    }
-    h->own_stream = true;
-  }
+  h->stream = static_cast<hipStream_t>(stream);  // NULL: the default stream
   // zero parameters, gradients and moments (a small fill, not a memset node)
   std::vector<float> zeros(P.params, 0.0f);
   for (size_t off : {P.off_p, P.off_g, P.off_m, P.off_v})
@@ -291,8 +282,7 @@ lbml_status lbml_create(int32_t nl, const int32_t *dims, int32_t max_batch, void
 
 lbml_status lbml_destroy(lbml_net *h) {
   if (!h) return 0;
-  if (h->stream) (void)hipStreamSynchronize(h->stream);
-  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  (void)hipStreamSynchronize(h->stream);
   delete h;
   return 0;
 }

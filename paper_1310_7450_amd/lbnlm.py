@@ -67,7 +67,7 @@ def load_library():
     L.lb_observe.argtypes = [vp, C.c_int32, C.c_int32, dp, sz]
     L.lb_get_state.argtypes = [vp, C.c_int32, dp, dp]
     L.lb_set_state.argtypes = [vp, C.c_int32, dp, dp, C.c_int64]
-    L.lb_set_profile.argtypes = [vp, C.c_int32, dp, dp, C.c_int32]
+    L.lb_set_profile.argtypes = [vp, C.c_int32, dp, dp, C.c_int32, C.c_int32]
     L.lb_last_error.argtypes = [vp]
     L.lb_last_error.restype = C.c_char_p
     L.lb_status_string.argtypes = [C.c_int32]
@@ -181,11 +181,14 @@ class Solver:
         assert pops.shape == (9, c.ny, c.nx) and P.shape == (c.ny, c.nx)
         self._check(self.L.lb_set_state(self.h, ch, _dp(pops), _dp(P), int(t)))
 
-    def set_profile(self, ch: int, ux, n1):
+    def set_profile(self, ch: int, ux, n1, points="rows"):
+        """Warm start of channel ch from u_x and N1 at the lattice rows
+        (points="rows") or at Chebyshev-Gauss points (points="chebyshev")."""
         ux = np.ascontiguousarray(ux, dtype=np.float64)
         n1 = np.ascontiguousarray(n1, dtype=np.float64)
         assert ux.shape == n1.shape and ux.ndim == 1
-        self._check(self.L.lb_set_profile(self.h, ch, _dp(ux), _dp(n1), len(ux)))
+        mode = {"rows": 0, "chebyshev": 1}[points]
+        self._check(self.L.lb_set_profile(self.h, ch, _dp(ux), _dp(n1), len(ux), mode))
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

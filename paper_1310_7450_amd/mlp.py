@@ -66,7 +66,12 @@ def init_params(dims: Sequence[int], seed: int = 0) -> np.ndarray:
 
 
 class Net:
-    """A network of widths ``dims`` for batches of up to ``max_batch`` rows."""
+    """A network of widths ``dims`` for batches of up to ``max_batch`` rows.
+
+    Its kernels run on ``stream`` (default: torch's current stream, which may
+    be the null stream), so that they are ordered with the torch operations
+    that produce its inputs and consume its outputs, and with the caching
+    allocator that recycles those tensors."""
 
     def __init__(self, dims: Sequence[int], max_batch: int, stream=None, device="cuda"):
         import torch
@@ -82,7 +87,7 @@ class Net:
         self.device = torch.device(device)
         self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
         ptr = (self.workspace.data_ptr() + 255) // 256 * 256
-        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = C.c_void_p()
         st = self.L.lbml_create(len(self.dims) - 1, d, self.max_batch, C.c_void_p(ptr), nb.value,
                                 C.c_void_p(self.stream.cuda_stream), C.byref(h))

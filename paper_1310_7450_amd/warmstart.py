@@ -1,0 +1,205 @@
+"""Learned warm start of steady channel runs.
+
+A network (``mlp.Net``: 5 -> 256 -> 256 -> 256 -> 192, SiLU, BF16 matrix-core
+GEMMs with FP32 accumulation) maps the channel parameters
+(log10 g, ny, eps, log10 tau0, G/eta_s) to the steady profiles of u_x,
+sigma_xy and N1 = sigma_xx - sigma_yy at the 64 Chebyshev-Gauss points
+d_k = cos(pi (2k+1)/128) across the channel (d = (y - y_c)/H). It is trained
+on steady states the lattice-Boltzmann solver itself produces; at inference
+the predicted u_x and N1 initialise new runs through ``lb_set_profile``. The
+solver stays the judge: a warm run is kept only if its converged profile
+agrees with a run from rest (else the rest run is the answer: fallback).
+
+Targets are scaled to O(1): u_x by g H^2 / (2 eta_s), sigma_xy by g H and N1 by
+G gamma_c^2 (lattice units, rho0 = 1).
+
+Run the whole experiment with ``python -m paper_1310_7450_amd.warmstart``.
+"""
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import workloads
+from .lbnlm import ChannelSpec, Solver
+from .mlp import Net, init_params
+
+DIMS = [5, 256, 256, 256, 192]
+N_PTS = 64
+CHEB = np.cos(np.pi * (2 * np.arange(N_PTS) + 1) / (2 * N_PTS))
+
+
+def eta_s(spec):
+    return (spec.tau_lb - 0.5) / 3.0
+
+
+def features(specs):
+    return np.array([[math.log10(c.force), c.ny, c.eps, math.log10(c.tau0), c.G / eta_s(c)] for c in specs])
+
+
+def scales(spec):
+    H = spec.ny / 2.0
+    return (spec.force * H * H / (2.0 * eta_s(spec)), spec.force * H, max(spec.G * spec.gamma_c ** 2, 1e-300))
+
+
+def sample_at_points(spec, ux, sxy, n1):
+    """Row profiles -> values at the Chebyshev points (linear interpolation;
+    u_x vanishes on the half-way walls, the stresses are extended linearly
+    to them)."""
+    ny = spec.ny
+    H, yc = ny / 2.0, (ny - 1) / 2.0
+    ys = yc + CHEB * H
+    rows = np.arange(ny, dtype=np.float64)
+    yw = np.concatenate([[-0.5], rows, [ny - 0.5]])
+
+    def ext_lin(v):
+        if ny == 1:
+            return np.concatenate([[v[0]], v, [v[0]]])
+        lo = v[0] - 0.5 * (v[1] - v[0])
+        hi = v[-1] + 0.5 * (v[-1] - v[-2])
+        return np.concatenate([[lo], v, [hi]])
+
+    u = np.interp(ys, yw, np.concatenate([[0.0], ux, [0.0]]))
+    s = np.interp(ys, yw, ext_lin(sxy))
+    n = np.interp(ys, yw, ext_lin(n1))
+    return u, s, n
+
+
+def targets(specs, profiles):
+    Y = np.zeros((len(specs), 3 * N_PTS))
+    for i, (c, (ux, sxy, n1)) in enumerate(zip(specs, profiles)):
+        u, s, n = sample_at_points(c, ux, sxy, n1)
+        su, ss, sn = scales(c)
+        Y[i] = np.concatenate([u / su, s / ss, n / sn])
+    return Y
+
+
+def solve_to_steady(specs, precision="fp32", max_steps=3_000_000, strip_rows=16, warm=None, tol=1e-9):
+    """Runs every channel to its steady state (residual < tol) in one handle.
+    ``warm`` optionally gives (u_x, N1) at the Chebyshev points per channel.
+    Returns the row profiles (u_x, sigma_xy, N1), the steps each channel took
+    and the wall time."""
+    t0 = time.perf_counter()
+    with Solver(specs, precision=precision, obs_every=1000, steady_tol=tol, strip_rows=strip_rows) as s:
+        if warm is not None:
+            for i, (u, n1) in enumerate(warm):
+                s.set_profile(i, u, n1, points="chebyshev")
+        s.step(max_steps)
+        steps = np.array([int(s.observe(i, "step")) for i in range(len(specs))])
+        frozen = np.array([s.observe(i, "active") == 0 for i in range(len(specs))])
+        prof = [(s.observe(i, "ux"), s.observe(i, "sxy"), s.observe(i, "n1")) for i in range(len(specs))]
+    return prof, steps, frozen, time.perf_counter() - t0
+
+
+def generate(seeds, n_per_seed=256, verbose=True):
+    specs = []
+    for sd in seeds:
+        specs += workloads.batched_sweep(seed=sd, n_channels=n_per_seed)["channels"]
+    prof, steps, frozen, wall = solve_to_steady(specs)
+    if verbose:
+        print(f"warmstart: {len(specs)} training states, {frozen.sum()} steady, {wall:.1f} s", file=sys.stderr,
+              flush=True)
+    keep = np.nonzero(frozen)[0]
+    specs = [specs[i] for i in keep]
+    prof = [prof[i] for i in keep]
+    return specs, features(specs), targets(specs, prof)
+
+
+class Normaliser:
+    def __init__(self, X):
+        self.mu = X.mean(axis=0)
+        sd = X.std(axis=0)
+        self.sd = np.where(sd > 0, sd, 1.0)
+
+    def __call__(self, X):
+        return ((X - self.mu) / self.sd).astype(np.float32)
+
+
+def train(X, Y, steps=4000, batch=256, lr=1e-3, seed=0, verbose=True):
+    import torch
+    norm = Normaliser(X)
+    Xn = torch.from_numpy(norm(X)).cuda()
+    Yd = torch.from_numpy(Y.astype(np.float32)).cuda()
+    net = Net(DIMS, max_batch=batch)
+    net.set_params(init_params(DIMS, seed=seed))
+    rng = np.random.default_rng(seed)
+    dy = torch.empty((batch, DIMS[-1]), dtype=torch.float32, device="cuda")
+    hist = []
+    n = X.shape[0]
+    for it in range(steps):
+        idx = torch.from_numpy(rng.choice(n, batch, replace=n < batch)).cuda()
+        xb = Xn.index_select(0, idx).contiguous()
+        yb = Yd.index_select(0, idx).contiguous()
+        y = net.forward(xb)
+        want = (it % 500 == 0) or it == steps - 1
+        loss = net.mse(y, yb, dy, want_loss=want)
+        net.backward(dy)
+        # cosine decay of the learning rate
+        net.adam_step(lr=lr * 0.5 * (1 + math.cos(math.pi * it / steps)) + 1e-5)
+        if want:
+            hist.append((it, loss))
+            if verbose:
+                print(f"warmstart: train step {it} loss {loss:.4e}", file=sys.stderr, flush=True)
+    return net, norm, hist
+
+
+def predict(net, norm, specs):
+    import torch
+    X = torch.from_numpy(norm(features(specs))).cuda()
+    out = []
+    for i0 in range(0, len(specs), net.max_batch):
+        xb = X[i0:i0 + net.max_batch].contiguous()
+        out.append(net.forward(xb).cpu().numpy())
+    Y = np.concatenate(out).astype(np.float64)
+    res = []
+    for c, y in zip(specs, Y):
+        su, ss, sn = scales(c)
+        res.append((y[:N_PTS] * su, y[N_PTS:2 * N_PTS] * ss, y[2 * N_PTS:] * sn))
+    return res
+
+
+def experiment(train_seeds=range(100, 116), test_seed=200, n_per_seed=256, train_steps=4000, agree_tol=5e-3,
+               verbose=True):
+    """Trains on steady states of ``train_seeds`` and warm-starts the held-out
+    ``test_seed`` batch; returns a report of steps to steady, warm vs rest."""
+    t0 = time.perf_counter()
+    specs, X, Y = generate(list(train_seeds), n_per_seed, verbose)
+    t_gen = time.perf_counter() - t0
+    net, norm, hist = train(X, Y, steps=train_steps, verbose=verbose)
+    t_train = time.perf_counter() - t0 - t_gen
+    test = workloads.batched_sweep(seed=test_seed, n_channels=n_per_seed)["channels"]
+    pred = predict(net, norm, test)
+    prof_w, steps_w, frozen_w, wall_w = solve_to_steady(test, warm=[(u, n1) for u, _, n1 in pred])
+    prof_r, steps_r, frozen_r, wall_r = solve_to_steady(test)
+    # the solver judges: warm and rest converged profiles must agree (a run
+    # stopped at residual R is up to about R / (slowest decay rate) from its
+    # fixed point, 1e-4..1e-3 of u_x for the widest channels)
+    err = np.array([np.abs(pw[0] - pr[0]).max() / np.abs(pr[0]).max() for pw, pr in zip(prof_w, prof_r)])
+    ok = (err <= agree_tol) & frozen_w
+    used = np.where(ok, steps_w, steps_r + steps_w)  # a fallback pays for both runs
+    pred_err = []
+    for c, p, pr in zip(test, pred, prof_r):
+        u, _, _ = sample_at_points(c, *pr)
+        pred_err.append(np.abs(p[0] - u).max() / np.abs(u).max())
+    ratio = steps_r / np.maximum(steps_w, 1)
+    rep = {
+        "train_states": int(X.shape[0]), "train_seeds": [int(s) for s in train_seeds], "test_seed": int(test_seed),
+        "test_channels": len(test), "final_train_loss": hist[-1][1],
+        "prediction_linf_rel_ux": {"median": float(np.median(pred_err)), "max": float(np.max(pred_err))},
+        "steps_rest": {"median": int(np.median(steps_r)), "total": int(steps_r.sum())},
+        "steps_warm": {"median": int(np.median(steps_w)), "total": int(steps_w.sum())},
+        "steps_ratio_rest_over_warm": {"median": float(np.median(ratio)),
+                                       "geomean": float(np.exp(np.mean(np.log(ratio))))},
+        "steps_with_fallback_total": int(used.sum()),
+        "fallbacks": int((~ok).sum()), "agree_tol": agree_tol,
+        "final_linf_rel_ux_warm_vs_rest": {"median": float(np.median(err)), "max": float(np.max(err))},
+        "seconds": {"generate": round(t_gen, 1), "train": round(t_train, 1), "warm_run": round(wall_w, 1),
+                    "rest_run": round(wall_r, 1)},
+    }
+    return rep
+
+
+if __name__ == "__main__":
+    print(json.dumps(experiment()), flush=True)
