@@ -107,6 +107,41 @@ def run_batched(max_steps=None, verbose=True):
             "precision": "fp32_shifted", "steady_tol": wl["steady_tol"]}
 
 
+def run_transient_scale(steps=200, warmup=50):
+    """Throughput of the start-up/cessation workload at full size: 16
+    channels of 8192 x 2048 (268M nodes), FP32 shifted, from rest with the
+    force on. The protocol itself (250,000 steps, stopping times) runs on the
+    x-reduced lattice in the tests."""
+    import torch
+    from paper_1310_7450_amd import Solver, workloads
+    wl = workloads.transient_scale()
+    chans = wl["channels"]
+    nodes = sum(c.nx * c.ny for c in chans)
+    with Solver(chans, precision="fp32", obs_every=1000) as s:
+        s.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.step(steps)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3
+    achieved = BYTES_PER_NODE["fp32"] * nodes * steps / sec / 1e9
+    return {"workload": wl["name"], "nodes": nodes, "steps": steps, "value": round(nodes * steps / sec / 1e6, 1),
+            "unit": "MLUPS", "ms_per_step": round(sec * 1e3 / steps, 4),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4)}}
+
+
+def run_warm_start(verbose=True):
+    """Steps to steady state, learned warm start vs from rest: the network is
+    trained on the GPU on 4096 solver steady states (seeds 100..115) and
+    initialises the 256 held-out channels of seed 200."""
+    from paper_1310_7450_amd import warmstart
+    return warmstart.experiment(verbose=verbose)
+
+
 def cpu_baseline(wl, budget_s=15.0):
     """The FP64 oracle as it stands, on the same lattice, for as many whole
     steps as fit in about ``budget_s`` seconds (at least one)."""
@@ -140,6 +175,8 @@ def main():
     ap.add_argument("--tune", type=str, default="",
                     help="comma-separated strip_rows values to time (FP32 and FP64) instead of the JSON line")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-channel sweep")
+    ap.add_argument("--no-transient", action="store_true", help="skip the 16 x 8192 x 2048 throughput leg")
+    ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start experiment")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB, 5 times (counter calibration)")
     args = ap.parse_args()
@@ -182,6 +219,16 @@ def main():
         batched = run_batched()
         print(f"bench: batched {batched['value']:.0f} MLUPS, {batched['converged']}/{batched['channels']} steady "
               f"in {batched['seconds']:.1f} s", file=sys.stderr, flush=True)
+    transient = None
+    if not args.no_transient:
+        transient = run_transient_scale()
+        print(f"bench: transient_scale {transient['value']:.0f} MLUPS "
+              f"({100 * transient['roofline']['frac']:.1f}% of HBM peak)", file=sys.stderr, flush=True)
+    warm = None
+    if not args.no_warm:
+        warm = run_warm_start()
+        print(f"bench: warm start cuts steps to steady by {warm['steps_ratio_rest_over_warm']['geomean']:.2f}x "
+              f"(geomean), {warm['fallbacks']} fallbacks", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(wl, args.cpu_budget)
@@ -212,6 +259,8 @@ def main():
             "roofline": {"bound": "hbm", "achieved": round(r64["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(r64["frac"], 4), "traffic": measured_traffic("fp64")}},
         "batched": batched,
+        "transient_scale": transient,
+        "warm_start": warm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -161,15 +161,19 @@ def predict(net, norm, specs):
 
 
 def experiment(train_seeds=range(100, 116), test_seed=200, n_per_seed=256, train_steps=4000, agree_tol=5e-3,
-               verbose=True):
+               n_test=None, verbose=True, details=False):
     """Trains on steady states of ``train_seeds`` and warm-starts the held-out
-    ``test_seed`` batch; returns a report of steps to steady, warm vs rest."""
+    ``test_seed`` batch (its first ``n_test`` channels, default all); returns
+    a report of steps to steady, warm vs rest, and with ``details`` also the
+    per-channel results."""
     t0 = time.perf_counter()
     specs, X, Y = generate(list(train_seeds), n_per_seed, verbose)
     t_gen = time.perf_counter() - t0
     net, norm, hist = train(X, Y, steps=train_steps, verbose=verbose)
     t_train = time.perf_counter() - t0 - t_gen
     test = workloads.batched_sweep(seed=test_seed, n_channels=n_per_seed)["channels"]
+    if n_test is not None:
+        test = test[:n_test]
     pred = predict(net, norm, test)
     prof_w, steps_w, frozen_w, wall_w = solve_to_steady(test, warm=[(u, n1) for u, _, n1 in pred])
     prof_r, steps_r, frozen_r, wall_r = solve_to_steady(test)
@@ -198,6 +202,10 @@ def experiment(train_seeds=range(100, 116), test_seed=200, n_per_seed=256, train
         "seconds": {"generate": round(t_gen, 1), "train": round(t_train, 1), "warm_run": round(wall_w, 1),
                     "rest_run": round(wall_r, 1)},
     }
+    if details:
+        return rep, {"test": test, "pred": pred, "prof_warm": prof_w, "prof_rest": prof_r, "steps_warm": steps_w,
+                     "steps_rest": steps_r, "frozen_warm": frozen_w, "frozen_rest": frozen_r, "ok": ok,
+                     "err_warm_vs_rest": err}
     return rep
 
 

@@ -104,3 +104,24 @@ def batched_sweep(seed=2, n_channels=256, nx=8, tau_lb=1.0, G=1e-4, gamma_c=0.1)
                                  eps=eps, visc_split=0.0))
     return {"name": f"batched_sweep_{n_channels}x{nx}", "channels": chans, "draws": draws, "seed": seed,
             "steady_tol": 1e-9, "obs_every": 1000, "max_steps": 3_000_000}
+
+
+def transient_scale(nx=8192, ny=2048, n_per_eps=8, eps_values=(0.0, 0.02), G=1e-4, tau0=1e4, gamma_c=0.1,
+                    tau_lb=1.0):
+    """Start-up and cessation at scale: ``n_per_eps`` channels of nx x ny at
+    each separation in ``eps_values`` (yield-stress case eps = 0, glass side
+    eps = +0.02), the nlM parameters of the 8 x 64 channel, and one force for
+    all of them, g = 2 G gamma_c / H (wp H = 2 gamma_c: the wall stress of the
+    steady flow is twice the yield stress G gamma_c at eps = 0). The force is
+    on for 50,000 steps; cessation runs until u_mid has fallen to 1e-3 of its
+    value at the switch-off, for at most 200,000 steps. No draws: every
+    channel of one eps is the same channel. ``nx`` = 64 gives the x-reduced
+    lattice, which evolves bitwise like the full one from rest (the flow
+    stays exactly x-uniform and every column runs the same arithmetic)."""
+    H = ny / 2.0
+    g = 2.0 * G * gamma_c / H
+    chans = [ChannelSpec(nx=nx, ny=ny, force=g, tau_lb=tau_lb, G=G, tau0=tau0, gamma_c=gamma_c, eps=float(e),
+                         visc_split=0.0, t_startup=50000)
+             for e in eps_values for _ in range(n_per_eps)]
+    return {"name": f"transient_scale_{len(chans)}x{nx}x{ny}", "channels": chans, "startup": 50000,
+            "cessation_cap": 200000, "stop_fraction": 1e-3, "thresholds": (1e-2, 1e-3, 1e-4)}

@@ -248,6 +248,27 @@ def test_warm_start_profile_state():
         assert s.observe(0, "mass") == pytest.approx(96.0, rel=1e-14)
 
 
+@pytest.mark.parametrize("ny", [24, 64, 97])
+def test_warm_start_chebyshev_points_exact_for_polynomials(ny):
+    """lb_set_profile from values at the 64 Chebyshev-Gauss points
+    d_k = cos(pi (2k+1)/128): barycentric interpolation reproduces any
+    polynomial of degree < 64 at the rows d = (y - y_c)/H, so a cubic u_x and
+    a quadratic N1 come back exactly (to round-off) in the state's moments."""
+    n = 64
+    dk = np.cos(np.pi * (2 * np.arange(n) + 1) / (2 * n))
+    u_of = lambda d: 1e-3 * (1 - d * d) * (1 + 0.3 * d)
+    n1_of = lambda d: 2e-6 * (1 - 0.5 * d * d)
+    spec = ChannelSpec(2, ny, 1e-6, 1.0, 1e-4, 1e3, 0.1)
+    d = (np.arange(ny) - (ny - 1) / 2) / (ny / 2)
+    with solver([spec], precision="fp64") as s:
+        s.set_profile(0, u_of(dk), n1_of(dk), points="chebyshev")
+        pops, P = s.get_state(0)
+        rho = pops.sum(axis=0)
+        mx = pops[[1, 5, 8]].sum(axis=0) - pops[[3, 6, 7]].sum(axis=0)
+        assert np.allclose(P, n1_of(d)[:, None], rtol=1e-11, atol=1e-18)
+        assert np.allclose(mx / rho, u_of(d)[:, None], rtol=1e-10, atol=1e-16)
+
+
 def test_large_channel_sampled_rows(orc):
     """The 4096 x 1024 lattice in FP32 at full size, in the launch
     configuration the benchmark times, with eps = -0.05 (G tau = 0.1; the
