@@ -63,19 +63,31 @@ struct SweepArgs {
 };
 
 // Width classes of the sweep: nx in {1,2,4,...,64} runs a whole period per
-// lane group ("narrow", classes 0..6); nx a multiple of 64 (>= 128) runs
-// aligned 64-column strips (kWide64Class); any other width runs generic
-// 64-column strips with wrapped lanes (kWideClass).
+// lane group ("narrow", classes 0..6); nx a multiple of 64 lanes times the
+// nodes one lane holds in a 16-byte access (4 in FP32, 2 in FP64) runs
+// aligned strips of that many columns with vector accesses (kVecClass); any
+// other multiple of 64 (>= 128) runs aligned 64-column strips
+// (kWide64Class); any other width runs generic 64-column strips with wrapped
+// lanes (kWideClass).
+#ifndef LB_VEC_SWEEP
+#define LB_VEC_SWEEP 1
+#endif
 constexpr int kWideClass = 7;
 constexpr int kWide64Class = 8;
-constexpr int kClasses = 9;
-inline int width_class(int nx) {
+constexpr int kVecClass = 9;
+constexpr int kClasses = 10;
+// nodes per lane of the vector sweep for an element size of esize bytes
+inline int vec_nodes(int esize) { return esize == 4 ? 4 : 2; }
+inline int width_class(int nx, int esize) {
   for (int c = 0; c < 7; ++c)
     if (nx == (1 << c)) return c;
+  if (LB_VEC_SWEEP && nx % (64 * vec_nodes(esize)) == 0) return kVecClass;
   if (nx % 64 == 0) return kWide64Class;
   return kWideClass;
 }
 inline bool is_strip_class(int cls) { return cls >= kWideClass; }
+// columns of one strip of a strip class
+inline int strip_cols(int cls, int esize) { return cls == kVecClass ? 64 * vec_nodes(esize) : 64; }
 
 // Host launchers (defined in lb_kernels.hip).
 hipError_t launch_sweep(int fp32, int cls, bool observe, const SweepArgs &a, hipStream_t s);

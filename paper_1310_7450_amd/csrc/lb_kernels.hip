@@ -621,6 +621,310 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
   }
 }
 
+// Vector accesses of NPL consecutive elements (16 bytes).
+template <typename T, int NPL>
+struct Vec;
+template <>
+struct Vec<float, 4> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Vec<double, 2> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+
+// Side values of a row of a vector strip (see sweep_vec_kernel), packed as
+// (dy + 1) | tile << 2 | column << 4 | field << 11 with tile 0: column left
+// of the strip's tiles, 1: right of them, 2: first tile, 3: last tile.
+#define SIDE(dy, t, col, p) ((dy) + 1 | (t) << 2 | (col) << 4 | (p) << 11)
+constexpr int kSideIn[25] = {
+    SIDE(0, 0, 63, 1),  SIDE(0, 1, 0, 3),   SIDE(-1, 0, 63, 5), SIDE(-1, 1, 0, 6),  SIDE(1, 1, 0, 7),
+    SIDE(1, 0, 63, 8),  SIDE(0, 0, 63, 0),  SIDE(0, 0, 62, 1),  SIDE(0, 2, 0, 3),   SIDE(-1, 0, 63, 2),
+    SIDE(-1, 0, 62, 5), SIDE(-1, 2, 0, 6),  SIDE(1, 0, 63, 4),  SIDE(1, 2, 0, 7),   SIDE(1, 0, 62, 8),
+    SIDE(0, 1, 0, 0),   SIDE(0, 3, 63, 1),  SIDE(0, 1, 1, 3),   SIDE(-1, 1, 0, 2),  SIDE(-1, 3, 63, 5),
+    SIDE(-1, 1, 1, 6),  SIDE(1, 1, 0, 4),   SIDE(1, 1, 1, 7),   SIDE(1, 3, 63, 8),  SIDE(0, 2, 0, 0)};
+// bottom wall row: entries reading row y-1 take the bounce-back source (-1: unchanged)
+constexpr int kSideBot[25] = {
+    -1, -1, SIDE(0, 2, 0, 0), SIDE(0, 2, 0, 0), -1, -1, -1, -1, -1, SIDE(0, 0, 63, 4), SIDE(0, 0, 63, 7),
+    SIDE(0, 0, 63, 8), -1, -1, -1, -1, -1, -1, SIDE(0, 1, 0, 4), SIDE(0, 1, 0, 7), SIDE(0, 1, 0, 8), -1, -1, -1, -1};
+// top wall row: entries reading row y+1 take the bounce-back source
+constexpr int kSideTop[25] = {
+    -1, -1, -1, -1, SIDE(0, 2, 0, 0), SIDE(0, 2, 0, 0), -1, -1, -1, -1, -1, -1, SIDE(0, 0, 63, 2),
+    SIDE(0, 0, 63, 5), SIDE(0, 0, 63, 6), -1, -1, -1, -1, -1, -1, SIDE(0, 1, 0, 2), SIDE(0, 1, 0, 5),
+    SIDE(0, 1, 0, 6), -1};
+#undef SIDE
+
+// Aligned strips of 64 NPL columns of a channel whose width is a multiple of
+// that: lane l owns the NPL consecutive columns x0 + NPL l + k, k < NPL, which
+// sit in one tile (tile x0/64 + l/(64/NPL), first column NPL (l % (64/NPL))),
+// so every field of a row is one 16-byte access per lane. A pull along +x
+// takes element k-1 of the same lane, and for k = 0 element NPL-1 of lane l-1
+// (a DPP lane shift; lane 0 takes the column left of the strip); a pull along
+// -x mirrors it.
+//
+// The march is software-pipelined two rows deep: while row y is computed,
+// the loads of row y+2 are in flight and row y+1 (loaded one iteration
+// earlier) is assembled for the stencil. The 24 values a row needs from the
+// columns beside the strip (the six edge populations of the shifted pulls and
+// the nine pulled populations of each neighbour column, for its u~) come in
+// one lane-indexed vector load, lane i holding value i, so that they complete
+// in order with the row's other loads; they are read out with readlane.
+template <typename T, bool SHIFT, bool OBS, int NPL>
+__global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a) {
+  typedef typename Vec<T, NPL>::type V;
+  constexpr int LPT = 64 / NPL;  // lanes per tile
+  const int lane = threadIdx.x & 63;
+  const int sidx = strip_index(a);
+  if (sidx >= a.n_strips) return;
+  const Strip st = a.strips[sidx];
+  const ChanDev c = a.ch[st.ch];
+  const T *__restrict__ A = static_cast<const T *>(a.A);
+  T *__restrict__ B = static_cast<T *>(a.B);
+  const int nx = c.nx, ny = c.ny;
+  const long long t = c.t + a.k;
+  const T fx = (t < c.t_startup) ? T(c.g) : T(0);
+  const Coef<T> q(c);
+
+  const int tiles_row = nx >> 6;        // tiles per row
+  const long long tile00 = c.off >> 6;  // tile of node (0, 0)
+  const int xt = st.x0 >> 6;            // first tile column of the strip
+  const int xe = xt + NPL - 1;          // last tile column of the strip
+  const int xl = (xt == 0) ? tiles_row - 1 : xt - 1;  // tile column left of the strip
+  const int xr = (xe == tiles_row - 1) ? 0 : xe + 1;  // tile column right of the strip
+  const int lt = lane / LPT;            // tile of this lane inside the strip
+  const int lo = NPL * (lane % LPT);    // first column of this lane inside its tile
+  constexpr int F = kTile;
+
+  auto tile = [&](int y, int tx) __attribute__((always_inline)) -> long long { return tile00 + (long long)y * tiles_row + tx; };
+  // one field of this lane's NPL columns of row y
+  auto vrun = [&](int y, int p) __attribute__((always_inline)) -> V {
+    return *reinterpret_cast<const V *>(A + (tile(y, xt + lt) * kPlanes + p) * F + lo);
+  };
+
+  // Side values of a row, by lane i < 24 (kSide* below): lanes 0..5 hold the
+  // edge populations of the shifted pulls, lanes 6..14 the pulled
+  // populations of the column left of the strip, lanes 15..23 those of the
+  // column right of it; wall rows take the bounce-back sources. Other lanes
+  // read node (x0, y). Each lane decodes its entry into an element offset
+  // relative to row 0: once per strip for interior rows, again on the wall
+  // rows (bottom, top, or both when ny = 1).
+  auto side_off = [&](int code) __attribute__((always_inline)) -> long long {
+    const int dy = (code & 3) - 1, tsel = (code >> 2) & 3, col = (code >> 4) & 127, p = code >> 11;
+    // a blend of values, not a choice between the captured variables (which
+    // the compiler would turn into a load through a chosen address and so
+    // keep those variables in scratch memory)
+    const int tc = (tsel == 0) * xl + (tsel == 1) * xr + (tsel == 2) * xt + (tsel == 3) * xe;
+    return ((tile00 + (long long)dy * tiles_row + tc) * kPlanes + p) * F + col;
+  };
+  const int li = lane < 24 ? lane : 24;
+  const int c_in = kSideIn[li];
+  const int c_bot = kSideBot[li] >= 0 ? kSideBot[li] : c_in;
+  const int c_top = kSideTop[li] >= 0 ? kSideTop[li] : c_in;
+  const int c_both = kSideBot[li] >= 0 ? kSideBot[li] : c_top;
+  const long long o_in = side_off(c_in);
+  const long long row_stride = (long long)tiles_row * kPlanes * F;  // elements per row
+
+  // Raw loads of row y: the ten runs (fields 0, 1, 3, 9 of row y; 2, 5, 6 of
+  // row y-1 or, at the bottom wall, 4, 7, 8 of row y; 4, 7, 8 of row y+1 or,
+  // at the top wall, 2, 5, 6 of row y) and the side values.
+  struct Raw {
+    V r[10];
+    T side;
+  };
+  auto load_raw = [&](int y, Raw &R) __attribute__((always_inline)) {
+    const bool bot = (y == 0), top = (y == ny - 1);
+    const int yd = bot ? y : y - 1, yu = top ? y : y + 1;
+    R.r[0] = vrun(y, 0);
+    R.r[1] = vrun(y, 1);
+    R.r[3] = vrun(y, 3);
+    R.r[9] = vrun(y, 9);
+    R.r[2] = vrun(yd, bot ? 4 : 2);
+    R.r[5] = vrun(yd, bot ? 7 : 5);
+    R.r[6] = vrun(yd, bot ? 8 : 6);
+    R.r[4] = vrun(yu, top ? 2 : 4);
+    R.r[7] = vrun(yu, top ? 5 : 7);
+    R.r[8] = vrun(yu, top ? 6 : 8);
+    long long o = o_in;
+    if (bot || top)  // wall rows only
+      o = side_off(bot * top * c_both + bot * (1 - top) * c_bot + (1 - bot) * c_top);
+    R.side = A[o + (long long)y * row_stride];
+  };
+  // Pulled populations, P, moments and u~ of the NPL columns of row y, and u~
+  // of the two columns beside the strip.
+  auto assemble = [&](int y, const Raw &R, T f[9][NPL], T P[NPL], T sd[NPL], T mx[NPL], T my[NPL],
+                      U2<T> u[NPL], U2<T> &uL, U2<T> &uR) __attribute__((always_inline)) {
+    const bool bot = (y == 0), top = (y == ny - 1);
+    auto from_left = [&](const V &r, T edge, T out[NPL]) __attribute__((always_inline)) {
+      out[0] = shift_up(edge, r[NPL - 1]);
+#pragma unroll
+      for (int k = 1; k < NPL; ++k) out[k] = r[k - 1];
+    };
+    auto from_right = [&](const V &r, T edge, T out[NPL]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int k = 0; k < NPL - 1; ++k) out[k] = r[k + 1];
+      out[NPL - 1] = shift_down(edge, r[0]);
+    };
+    auto split = [&](const V &r, T out[NPL]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) out[k] = r[k];
+    };
+    split(R.r[0], f[0]);
+    from_left(R.r[1], lane_value(R.side, 0), f[1]);
+    from_right(R.r[3], lane_value(R.side, 1), f[3]);
+    split(R.r[9], P);
+    split(R.r[2], f[2]);
+    split(R.r[4], f[4]);
+    if (bot) {
+      split(R.r[5], f[5]);
+      split(R.r[6], f[6]);
+    } else {
+      from_left(R.r[5], lane_value(R.side, 2), f[5]);
+      from_right(R.r[6], lane_value(R.side, 3), f[6]);
+    }
+    if (top) {
+      split(R.r[7], f[7]);
+      split(R.r[8], f[8]);
+    } else {
+      from_right(R.r[7], lane_value(R.side, 4), f[7]);
+      from_left(R.r[8], lane_value(R.side, 5), f[8]);
+    }
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      T g[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) g[i] = f[i][k];
+      moments<T>(g, sd[k], mx[k], my[k]);
+      u[k] = u_tilde<T, SHIFT>(sd[k], mx[k], my[k], fx);
+    }
+    // side lanes 6..14 / 15..23 hold populations 0,1,3,2,5,6,4,7,8
+    T l[9], r[9];
+    l[0] = lane_value(R.side, 6);
+    l[1] = lane_value(R.side, 7);
+    l[3] = lane_value(R.side, 8);
+    l[2] = lane_value(R.side, 9);
+    l[5] = lane_value(R.side, 10);
+    l[6] = lane_value(R.side, 11);
+    l[4] = lane_value(R.side, 12);
+    l[7] = lane_value(R.side, 13);
+    l[8] = lane_value(R.side, 14);
+    r[0] = lane_value(R.side, 15);
+    r[1] = lane_value(R.side, 16);
+    r[3] = lane_value(R.side, 17);
+    r[2] = lane_value(R.side, 18);
+    r[5] = lane_value(R.side, 19);
+    r[6] = lane_value(R.side, 20);
+    r[4] = lane_value(R.side, 21);
+    r[7] = lane_value(R.side, 22);
+    r[8] = lane_value(R.side, 23);
+    T s0, m0, n0;
+    moments<T>(l, s0, m0, n0);
+    uL = u_tilde<T, SHIFT>(s0, m0, n0, fx);
+    moments<T>(r, s0, m0, n0);
+    uR = u_tilde<T, SHIFT>(s0, m0, n0, fx);
+  };
+  auto clampy = [&](int y) __attribute__((always_inline)) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
+
+  T fc[9][NPL], Pc[NPL], sdc[NPL], mxc[NPL], myc[NPL];
+  U2<T> uPrev[NPL], uCur[NPL], uLc, uRc;
+  Raw R1, R2;  // raw loads of rows y+1 and y+2
+  {
+    Raw R0;
+    T ftmp[9][NPL], Ptmp[NPL], s0[NPL], m0[NPL], n0[NPL];
+    U2<T> hl, hr;
+    const int yp = clampy(st.y0 - 1);
+    load_raw(yp, R0);
+    assemble(yp, R0, ftmp, Ptmp, s0, m0, n0, uPrev, hl, hr);
+    load_raw(st.y0, R0);
+    assemble(st.y0, R0, fc, Pc, sdc, mxc, myc, uCur, uLc, uRc);
+  }
+  load_raw(clampy(st.y0 + 1), R1);
+
+#pragma unroll 1
+  for (int y = st.y0; y < st.y1; ++y) {
+    load_raw(clampy(y + 2), R2);
+    T fn[9][NPL], Pn[NPL], sdn[NPL], mxn[NPL], myn[NPL];
+    U2<T> uNext[NPL], uLn, uRn;
+    assemble(clampy(y + 1), R1, fn, Pn, sdn, mxn, myn, uNext, uLn, uRn);
+
+    T out[9][NPL], trT[NPL];
+    double obs[OF_COUNT];
+    if constexpr (OBS) {
+#pragma unroll
+      for (int f = 0; f < OF_COUNT; ++f) obs[f] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      U2<T> lf, rt;
+      if (k == 0) {
+        lf = U2<T>{shift_up(uLc.x, uCur[NPL - 1].x), shift_up(uLc.y, uCur[NPL - 1].y)};
+      } else {
+        lf = uCur[k - 1];
+      }
+      if (k == NPL - 1) {
+        rt = U2<T>{shift_down(uRc.x, uCur[0].x), shift_down(uRc.y, uCur[0].y)};
+      } else {
+        rt = uCur[k + 1];
+      }
+      U2<T> dn = uPrev[k], up = uNext[k];
+      // no-slip ghosts behind the half-way walls
+      if (y == 0) dn = U2<T>{-uCur[k].x, -uCur[k].y};
+      if (y == ny - 1) up = U2<T>{-uCur[k].x, -uCur[k].y};
+      T g[9], o[9], tr;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) g[i] = fc[i][k];
+      double ob[OF_COUNT];
+      node_update<T, SHIFT, OBS>(g, sdc[k], mxc[k], myc[k], Pc[k], fx, lf, rt, dn, up, q, a.nnp, o, tr, ob);
+      if constexpr (OBS) {
+        ob[OF_DRAG] = wall_drag<T>(g, y, ny);
+#pragma unroll
+        for (int f = 0; f < OF_COUNT; ++f) obs[f] += ob[f];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) out[i][k] = o[i];
+        trT[k] = tr;
+      }
+    }
+    if constexpr (OBS) {
+#pragma unroll
+      for (int f = 0; f < OF_COUNT; ++f) obs[f] = group_sum<64>(obs[f]);
+      if (lane == 0) {
+        const long long pr = (long long)c.poff + (long long)y * c.nxs + st.x0 / (64 * NPL);
+        double *dst = a.part + pr * OF_COUNT;
+#pragma unroll
+        for (int f = 0; f < OF_COUNT; ++f) dst[f] = obs[f];
+      }
+    } else {
+      T *w = B + tile(y, xt + lt) * (kPlanes * F) + lo;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        V v;
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) v[k] = out[i][k];
+        *reinterpret_cast<V *>(w + i * F) = v;
+      }
+      V v;
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) v[k] = trT[k];
+      *reinterpret_cast<V *>(w + 9 * F) = v;
+    }
+
+    uLc = uLn;
+    uRc = uRn;
+    R1 = R2;
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      uPrev[k] = uCur[k];
+      uCur[k] = uNext[k];
+      Pc[k] = Pn[k];
+      sdc[k] = sdn[k];
+      mxc[k] = mxn[k];
+      myc[k] = myn[k];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) fc[i][k] = fn[i][k];
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256) reduce_kernel(const ChanDev *ch, const double *part,
                                                      double *prof, double *prev_ux, double *scal,
                                                      int update_residual, int steps_since) {
@@ -722,6 +1026,18 @@ hipError_t launch_wide64(bool observe, const SweepArgs &a, hipStream_t s) {
 }
 
 template <typename T, bool SHIFT>
+hipError_t launch_vec(bool observe, const SweepArgs &a, hipStream_t s) {
+  if (a.n_strips == 0) return hipSuccess;
+  constexpr int NPL = sizeof(T) == 4 ? 4 : 2;
+  dim3 grid(a.n_wg), block(64 * LB_WG_WAVES);
+  if (observe)
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, true, NPL>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, bool SHIFT>
 hipError_t launch_prec(int cls, bool observe, const SweepArgs &a, hipStream_t s) {
   switch (cls) {
     case 0: return launch_cls<T, SHIFT, 1, false>(observe, a, s);
@@ -732,6 +1048,7 @@ hipError_t launch_prec(int cls, bool observe, const SweepArgs &a, hipStream_t s)
     case 5: return launch_cls<T, SHIFT, 32, false>(observe, a, s);
     case 6: return launch_cls<T, SHIFT, 64, false>(observe, a, s);
     case kWide64Class: return launch_wide64<T, SHIFT>(observe, a, s);
+    case kVecClass: return launch_vec<T, SHIFT>(observe, a, s);
     default: return launch_cls<T, SHIFT, 64, true>(observe, a, s);
   }
 }

@@ -17,7 +17,6 @@ using namespace lbnlm;
 
 namespace {
 
-constexpr int kWideInterior = 64;  // columns of a wide strip
 constexpr int kDefaultK = 1000;
 constexpr size_t kAlign = 256;
 #ifndef LB_WG_WAVES
@@ -111,12 +110,13 @@ int strip_rows_for(int cls, int nx, int ny, int requested) {
 // Strips of one channel in row-band order: the strips of one band of rows
 // are consecutive (x neighbours, which share cache lines at their edges,
 // land on the same XCD), and bands follow each other upwards.
-void add_strips(int ci, const ChanDev &d, int srows, std::vector<Strip> &out) {
-  const int cls = width_class(d.nx);
-  const int nxs = is_strip_class(cls) ? (d.nx + kWideInterior - 1) / kWideInterior : 1;
+void add_strips(int ci, const ChanDev &d, int esize, int srows, std::vector<Strip> &out) {
+  const int cls = width_class(d.nx, esize);
+  const int w = strip_cols(cls, esize);
+  const int nxs = is_strip_class(cls) ? (d.nx + w - 1) / w : 1;
   for (int y0 = 0; y0 < d.ny; y0 += srows)
     for (int xs = 0; xs < nxs; ++xs)
-      out.push_back(Strip{ci, xs * kWideInterior, y0, std::min(y0 + srows, d.ny)});
+      out.push_back(Strip{ci, xs * w, y0, std::min(y0 + srows, d.ny)});
 }
 
 Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
@@ -132,8 +132,9 @@ Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
     node += (long long)align_up((size_t)c[i].nx * c[i].ny, 64);
     d.row_off = rows;
     rows += c[i].ny;
-    const int cls = width_class(c[i].nx);
-    d.nxs = is_strip_class(cls) ? (c[i].nx + kWideInterior - 1) / kWideInterior : 1;
+    const int cls = width_class(c[i].nx, L.esize);
+    const int w = strip_cols(cls, L.esize);
+    d.nxs = is_strip_class(cls) ? (c[i].nx + w - 1) / w : 1;
     d.poff = part;
     part += d.nxs * c[i].ny;
     const int srows = strip_rows_for(cls, c[i].nx, c[i].ny, o->strip_rows);
@@ -209,13 +210,13 @@ lb_status hipfail(lb_handle *h, hipError_t e, const char *where) {
     if (e_ != hipSuccess) return hipfail((h), e_, #call);  \
   } while (0)
 
-void group_strips(const std::vector<Strip> &s, const std::vector<ChanDev> &ch,
+void group_strips(const std::vector<Strip> &s, const std::vector<ChanDev> &ch, int esize,
                   std::vector<Strip> &out, int begin[kClasses], int count[kClasses]) {
   out.clear();
   for (int c = 0; c < kClasses; ++c) {
     begin[c] = (int)out.size();
     for (const Strip &x : s)
-      if (width_class(ch[x.ch].nx) == c) out.push_back(x);
+      if (width_class(ch[x.ch].nx, esize) == c) out.push_back(x);
     count[c] = (int)out.size() - begin[c];
   }
 }
@@ -225,15 +226,16 @@ lb_status upload_strips(lb_handle *h, bool all) {
   for (int i = 0; i < h->n_ch; ++i) {
     if (!all && !h->active[i]) continue;
     const ChanDev &d = h->L.ch[i];
-    add_strips(i, d, strip_rows_for(width_class(d.nx), d.nx, d.ny, h->opt.strip_rows), raw);
+    add_strips(i, d, h->L.esize, strip_rows_for(width_class(d.nx, h->L.esize), d.nx, d.ny, h->opt.strip_rows),
+               raw);
   }
   if (all) {
-    group_strips(raw, h->L.ch, grouped, h->all_begin, h->all_count);
+    group_strips(raw, h->L.ch, h->L.esize, grouped, h->all_begin, h->all_count);
     if (!grouped.empty())
       HIPCHECK(h, hipMemcpyAsync(h->dall, grouped.data(), grouped.size() * sizeof(Strip),
                                  hipMemcpyHostToDevice, h->stream));
   } else {
-    group_strips(raw, h->L.ch, grouped, h->act_begin, h->act_count);
+    group_strips(raw, h->L.ch, h->L.esize, grouped, h->act_begin, h->act_count);
     if (!grouped.empty())
       HIPCHECK(h, hipMemcpyAsync(h->dact, grouped.data(), grouped.size() * sizeof(Strip),
                                  hipMemcpyHostToDevice, h->stream));
