@@ -60,15 +60,20 @@ struct SweepArgs {
   int n_wg;
   int k;                // step offset added to every channel's t
   int nnp;              // keep the flow-induced density terms
+  int nt;               // store the new state with nontemporal hints
+  int down;             // march the strips downwards (vector sweep)
 };
+// A state buffer larger than this is written with nontemporal stores: it
+// cannot stay in the 256 MB last-level cache (MALL) until the next step reads
+// it, so caching its lines only evicts the reads in flight.
+constexpr long long kNontemporalBytes = 256ll << 20;
 
 // Width classes of the sweep: nx in {1,2,4,...,64} runs a whole period per
 // lane group ("narrow", classes 0..6); nx a multiple of 64 lanes times the
-// nodes one lane holds in a 16-byte access (4 in FP32, 2 in FP64) runs
-// aligned strips of that many columns with vector accesses (kVecClass); any
-// other multiple of 64 (>= 128) runs aligned 64-column strips
-// (kWide64Class); any other width runs generic 64-column strips with wrapped
-// lanes (kWideClass).
+// nodes one lane holds (vec_nodes) runs aligned strips of that many columns
+// with vector accesses (kVecClass); any other multiple of 64 (>= 128) runs
+// aligned 64-column strips (kWide64Class); any other width runs generic
+// 64-column strips with wrapped lanes (kWideClass).
 #ifndef LB_VEC_SWEEP
 #define LB_VEC_SWEEP 1
 #endif
@@ -76,8 +81,16 @@ constexpr int kWideClass = 7;
 constexpr int kWide64Class = 8;
 constexpr int kVecClass = 9;
 constexpr int kClasses = 10;
-// nodes per lane of the vector sweep for an element size of esize bytes
-inline int vec_nodes(int esize) { return esize == 4 ? 4 : 2; }
+// nodes per lane of the vector sweep: four FP32 nodes (one 16-byte access)
+// or one FP64 node (measured: an 8-byte FP64 access over 64-column strips
+// beats a 16-byte one over 128-column strips on the 4096 x 1024 channel)
+#ifndef LB_VEC_NPL32
+#define LB_VEC_NPL32 4
+#endif
+#ifndef LB_VEC_NPL64
+#define LB_VEC_NPL64 1
+#endif
+inline int vec_nodes(int esize) { return esize == 4 ? LB_VEC_NPL32 : LB_VEC_NPL64; }
 inline int width_class(int nx, int esize) {
   for (int c = 0; c < 7; ++c)
     if (nx == (1 << c)) return c;

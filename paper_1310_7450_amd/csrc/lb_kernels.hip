@@ -36,8 +36,9 @@ namespace {
 #ifndef LB_WG_WAVES
 #define LB_WG_WAVES 4
 #endif
-#ifndef LB_PREFETCH_DEPTH
-#define LB_PREFETCH_DEPTH 1
+// rows of loads in flight per wavefront in the vector sweep
+#ifndef LB_VEC_DEPTH
+#define LB_VEC_DEPTH 3
 #endif
 
 template <typename T>
@@ -621,7 +622,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
   }
 }
 
-// Vector accesses of NPL consecutive elements (16 bytes).
+// Vector accesses of NPL consecutive elements.
 template <typename T, int NPL>
 struct Vec;
 template <>
@@ -631,6 +632,14 @@ struct Vec<float, 4> {
 template <>
 struct Vec<double, 2> {
   typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec<float, 2> {
+  typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec<double, 1> {
+  typedef double type __attribute__((ext_vector_type(1)));
 };
 
 // Side values of a row of a vector strip (see sweep_vec_kernel), packed as
@@ -657,7 +666,8 @@ constexpr int kSideTop[25] = {
 // Aligned strips of 64 NPL columns of a channel whose width is a multiple of
 // that: lane l owns the NPL consecutive columns x0 + NPL l + k, k < NPL, which
 // sit in one tile (tile x0/64 + l/(64/NPL), first column NPL (l % (64/NPL))),
-// so every field of a row is one 16-byte access per lane. A pull along +x
+// so every field of a row is one NPL-element access per lane (16 bytes for
+// four FP32 nodes). A pull along +x
 // takes element k-1 of the same lane, and for k = 0 element NPL-1 of lane l-1
 // (a DPP lane shift; lane 0 takes the column left of the strip); a pull along
 // -x mirrors it.
@@ -669,7 +679,7 @@ constexpr int kSideTop[25] = {
 // the nine pulled populations of each neighbour column, for its u~) come in
 // one lane-indexed vector load, lane i holding value i, so that they complete
 // in order with the row's other loads; they are read out with readlane.
-template <typename T, bool SHIFT, bool OBS, int NPL>
+template <typename T, bool SHIFT, bool OBS, int NPL, bool NT, bool DOWN>
 __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a) {
   typedef typename Vec<T, NPL>::type V;
   constexpr int LPT = 64 / NPL;  // lanes per tile
@@ -824,27 +834,36 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
   };
   auto clampy = [&](int y) __attribute__((always_inline)) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
 
+  // The march runs upwards from y0, or with DOWN downwards from y1 - 1; "prev"
+  // and "next" are the rows behind and ahead of the current one.
+  constexpr int dir = DOWN ? -1 : 1;
+  const int yfirst = DOWN ? st.y1 - 1 : st.y0;
+  const int nrows = st.y1 - st.y0;
   T fc[9][NPL], Pc[NPL], sdc[NPL], mxc[NPL], myc[NPL];
   U2<T> uPrev[NPL], uCur[NPL], uLc, uRc;
-  Raw R1, R2;  // raw loads of rows y+1 and y+2
   {
     Raw R0;
     T ftmp[9][NPL], Ptmp[NPL], s0[NPL], m0[NPL], n0[NPL];
     U2<T> hl, hr;
-    const int yp = clampy(st.y0 - 1);
+    const int yp = clampy(yfirst - dir);
     load_raw(yp, R0);
     assemble(yp, R0, ftmp, Ptmp, s0, m0, n0, uPrev, hl, hr);
-    load_raw(st.y0, R0);
-    assemble(st.y0, R0, fc, Pc, sdc, mxc, myc, uCur, uLc, uRc);
+    load_raw(yfirst, R0);
+    assemble(yfirst, R0, fc, Pc, sdc, mxc, myc, uCur, uLc, uRc);
   }
-  load_raw(clampy(st.y0 + 1), R1);
+  // ring of raw rows: the row i steps ahead of the first lives in slot i mod D
+  constexpr int D = LB_VEC_DEPTH;
+  Raw S[D];
+#pragma unroll
+  for (int k = 1; k < D; ++k) load_raw(clampy(yfirst + dir * k), S[k]);
 
-#pragma unroll 1
-  for (int y = st.y0; y < st.y1; ++y) {
-    load_raw(clampy(y + 2), R2);
+  // Row y: start the loads of the row D ahead, assemble the next row (loaded
+  // D - 1 rows earlier), update and store row y.
+  auto row_step = [&](int y, Raw &Rload, const Raw &Rasm) __attribute__((always_inline)) {
+    load_raw(clampy(y + dir * D), Rload);  // unconditional: a branch here costs more than the loads
     T fn[9][NPL], Pn[NPL], sdn[NPL], mxn[NPL], myn[NPL];
     U2<T> uNext[NPL], uLn, uRn;
-    assemble(clampy(y + 1), R1, fn, Pn, sdn, mxn, myn, uNext, uLn, uRn);
+    assemble(clampy(y + dir), Rasm, fn, Pn, sdn, mxn, myn, uNext, uLn, uRn);
 
     T out[9][NPL], trT[NPL];
     double obs[OF_COUNT];
@@ -865,7 +884,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
       } else {
         rt = uCur[k + 1];
       }
-      U2<T> dn = uPrev[k], up = uNext[k];
+      U2<T> dn = DOWN ? uNext[k] : uPrev[k], up = DOWN ? uPrev[k] : uNext[k];
       // no-slip ghosts behind the half-way walls
       if (y == 0) dn = U2<T>{-uCur[k].x, -uCur[k].y};
       if (y == ny - 1) up = U2<T>{-uCur[k].x, -uCur[k].y};
@@ -895,22 +914,24 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
       }
     } else {
       T *w = B + tile(y, xt + lt) * (kPlanes * F) + lo;
+      V v[kPlanes];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        V v;
+      for (int k = 0; k < NPL; ++k) {
 #pragma unroll
-        for (int k = 0; k < NPL; ++k) v[k] = out[i][k];
-        *reinterpret_cast<V *>(w + i * F) = v;
+        for (int i = 0; i < 9; ++i) v[i][k] = out[i][k];
+        v[9][k] = trT[k];
       }
-      V v;
+      if constexpr (NT) {
 #pragma unroll
-      for (int k = 0; k < NPL; ++k) v[k] = trT[k];
-      *reinterpret_cast<V *>(w + 9 * F) = v;
+        for (int i = 0; i < kPlanes; ++i) __builtin_nontemporal_store(v[i], reinterpret_cast<V *>(w + i * F));
+      } else {
+#pragma unroll
+        for (int i = 0; i < kPlanes; ++i) *reinterpret_cast<V *>(w + i * F) = v[i];
+      }
     }
 
     uLc = uLn;
     uRc = uRn;
-    R1 = R2;
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       uPrev[k] = uCur[k];
@@ -922,6 +943,14 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
 #pragma unroll
       for (int i = 0; i < 9; ++i) fc[i][k] = fn[i][k];
     }
+  };
+
+  // unrolled D times so that the ring slots are fixed registers
+#pragma unroll 1
+  for (int i = 0; i < nrows; i += D) {
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j == 0 || i + j < nrows) row_step(yfirst + dir * (i + j), S[j], S[(j + 1) % D]);
   }
 }
 
@@ -1028,12 +1057,16 @@ hipError_t launch_wide64(bool observe, const SweepArgs &a, hipStream_t s) {
 template <typename T, bool SHIFT>
 hipError_t launch_vec(bool observe, const SweepArgs &a, hipStream_t s) {
   if (a.n_strips == 0) return hipSuccess;
-  constexpr int NPL = sizeof(T) == 4 ? 4 : 2;
+  constexpr int NPL = sizeof(T) == 4 ? LB_VEC_NPL32 : LB_VEC_NPL64;
   dim3 grid(a.n_wg), block(64 * LB_WG_WAVES);
   if (observe)
-    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, true, NPL>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, true, NPL, false, false>), grid, block, 0, s, a);
+  else if (a.nt)
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, true, false>), grid, block, 0, s, a);
+  else if (a.down)
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, false, true>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, false, false>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 

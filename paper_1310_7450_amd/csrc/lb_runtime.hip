@@ -39,7 +39,7 @@ struct Layout {
   int total_rows = 0;
   int total_part = 0;
   int max_strips = 0;
-  size_t off_state[2] = {0, 0}, off_ch = 0, off_strips = 0, off_astrips = 0, off_part = 0,
+  size_t off_state[2] = {0, 0}, off_ch = 0, off_strips = 0, off_astrips = 0, off_rstrips = 0, off_part = 0,
          off_prof = 0, off_prev = 0, off_scal = 0, bytes = 0;
   std::vector<ChanDev> ch;
 };
@@ -156,6 +156,7 @@ Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
   L.off_ch = take(sizeof(ChanDev) * n);
   L.off_strips = take(sizeof(Strip) * strips);
   L.off_astrips = take(sizeof(Strip) * strips);
+  L.off_rstrips = take(sizeof(Strip) * strips);
   L.off_part = take(sizeof(double) * OF_COUNT * part);
   L.off_prof = take(sizeof(double) * OF_COUNT * rows);
   L.off_prev = take(sizeof(double) * rows);
@@ -177,6 +178,7 @@ struct lb_handle {
   ChanDev *dch = nullptr;
   Strip *dall = nullptr;     // every channel, for observation
   Strip *dact = nullptr;     // active channels, for stepping
+  Strip *dact_rev = nullptr; // the same, each class group in reverse order
   double *dpart = nullptr, *dprof = nullptr, *dprev = nullptr, *dscal = nullptr;
   // strips grouped by width class: [begin, begin + count) in the arrays
   int all_begin[kClasses] = {0}, all_count[kClasses] = {0};
@@ -236,9 +238,17 @@ lb_status upload_strips(lb_handle *h, bool all) {
                                  hipMemcpyHostToDevice, h->stream));
   } else {
     group_strips(raw, h->L.ch, h->L.esize, grouped, h->act_begin, h->act_count);
-    if (!grouped.empty())
+    std::vector<Strip> rev(grouped);
+    for (int c = 0; c < kClasses; ++c)
+      std::reverse(rev.begin() + h->act_begin[c], rev.begin() + h->act_begin[c] + h->act_count[c]);
+    if (!grouped.empty()) {
       HIPCHECK(h, hipMemcpyAsync(h->dact, grouped.data(), grouped.size() * sizeof(Strip),
                                  hipMemcpyHostToDevice, h->stream));
+      HIPCHECK(h, hipMemcpyAsync(h->dact_rev, rev.data(), rev.size() * sizeof(Strip), hipMemcpyHostToDevice,
+                                 h->stream));
+    }
+    // the host vectors die here: make the copies complete first
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
   }
   // the host vector dies here: make the copy complete first
   HIPCHECK(h, hipStreamSynchronize(h->stream));
@@ -257,6 +267,7 @@ SweepArgs sweep_args(lb_handle *h, const Strip *strips, int begin, int count, in
   a.n_wg = (count + kWaves - 1) / kWaves;
   a.k = k;
   a.nnp = h->opt.nn_pressure;
+  a.nt = (long long)kPlanes * h->L.plane * h->L.esize > kNontemporalBytes;
   return a;
 }
 
@@ -264,7 +275,13 @@ SweepArgs sweep_args(lb_handle *h, const Strip *strips, int begin, int count, in
 lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s) {
   for (int c = 0; c < kClasses; ++c) {
     if (!h->act_count[c]) continue;
-    SweepArgs a = sweep_args(h, h->dact, h->act_begin[c], h->act_count[c], src, k);
+    // Serpentine order: steps reading buffer 0 take the strips in order and
+    // march them upwards, steps reading buffer 1 take them in reverse and
+    // march downwards, so that every step starts on what the previous step
+    // wrote last, the likeliest to still sit in the last-level cache (MALL)
+    // when the state does not fit it whole.
+    SweepArgs a = sweep_args(h, src == 0 ? h->dact : h->dact_rev, h->act_begin[c], h->act_count[c], src, k);
+    a.down = (src == 1);
     HIPCHECK(h, launch_sweep(h->opt.precision == LB_FP32_SHIFTED, c, false, a, s));
   }
   return LB_OK;
@@ -419,6 +436,7 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
   h->dch = reinterpret_cast<ChanDev *>(h->ws + h->L.off_ch);
   h->dall = reinterpret_cast<Strip *>(h->ws + h->L.off_strips);
   h->dact = reinterpret_cast<Strip *>(h->ws + h->L.off_astrips);
+  h->dact_rev = reinterpret_cast<Strip *>(h->ws + h->L.off_rstrips);
   h->dpart = reinterpret_cast<double *>(h->ws + h->L.off_part);
   h->dprof = reinterpret_cast<double *>(h->ws + h->L.off_prof);
   h->dprev = reinterpret_cast<double *>(h->ws + h->L.off_prev);
