@@ -26,11 +26,12 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"fp32": 80, "fp64": 160}
 
 
-def measured_traffic(precision):
+def measured_traffic(key):
     """HBM bytes per sweep launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size), or
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size) for
+    'fp32', 'fp64' (4096 x 1024) or 'transient_fp32' (16 x 8192 x 2048), or
     None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_large_channel_4096x1024.json")
+    path = os.path.join(ROOT, "profiles", "traffic_sweep_vec.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -39,7 +40,7 @@ def measured_traffic(precision):
         h.update(open(os.path.join(ROOT, "paper_1310_7450_amd", "csrc", f), "rb").read())
     if h.hexdigest()[:16] != rec.get("source_hash"):
         return None
-    k = rec["kernels"].get(precision)
+    k = rec["kernels"].get(key)
     return None if k is None else round(k["traffic_bytes"])
 
 
@@ -131,7 +132,7 @@ def run_transient_scale(steps=200, warmup=50):
     return {"workload": wl["name"], "nodes": nodes, "steps": steps, "value": round(nodes * steps / sec / 1e6, 1),
             "unit": "MLUPS", "ms_per_step": round(sec * 1e3 / steps, 4),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4)}}
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("transient_fp32")}}
 
 
 def run_warm_start(verbose=True):
