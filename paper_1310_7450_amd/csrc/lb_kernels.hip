@@ -841,21 +841,23 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
   const int nrows = st.y1 - st.y0;
   T fc[9][NPL], Pc[NPL], sdc[NPL], mxc[NPL], myc[NPL];
   U2<T> uPrev[NPL], uCur[NPL], uLc, uRc;
-  {
-    Raw R0;
-    T ftmp[9][NPL], Ptmp[NPL], s0[NPL], m0[NPL], n0[NPL];
-    U2<T> hl, hr;
-    const int yp = clampy(yfirst - dir);
-    load_raw(yp, R0);
-    assemble(yp, R0, ftmp, Ptmp, s0, m0, n0, uPrev, hl, hr);
-    load_raw(yfirst, R0);
-    assemble(yfirst, R0, fc, Pc, sdc, mxc, myc, uCur, uLc, uRc);
-  }
   // ring of raw rows: the row i steps ahead of the first lives in slot i mod D
   constexpr int D = LB_VEC_DEPTH;
   Raw S[D];
+  {
+    // every load of the prologue is issued before the first is used, so the
+    // strip pays one memory latency before its first row, not three
+    Raw Rp, Rf;
+    const int yp = clampy(yfirst - dir);
+    load_raw(yp, Rp);
+    load_raw(yfirst, Rf);
 #pragma unroll
-  for (int k = 1; k < D; ++k) load_raw(clampy(yfirst + dir * k), S[k]);
+    for (int k = 1; k < D; ++k) load_raw(clampy(yfirst + dir * k), S[k]);
+    T ftmp[9][NPL], Ptmp[NPL], s0[NPL], m0[NPL], n0[NPL];
+    U2<T> hl, hr;
+    assemble(yp, Rp, ftmp, Ptmp, s0, m0, n0, uPrev, hl, hr);
+    assemble(yfirst, Rf, fc, Pc, sdc, mxc, myc, uCur, uLc, uRc);
+  }
 
   // Row y: start the loads of the row D ahead, assemble the next row (loaded
   // D - 1 rows earlier), update and store row y.
