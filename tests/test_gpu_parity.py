@@ -269,20 +269,22 @@ def test_warm_start_chebyshev_points_exact_for_polynomials(ny):
         assert np.allclose(mx / rho, u_of(d)[:, None], rtol=1e-10, atol=1e-16)
 
 
-def test_large_channel_sampled_rows(orc):
-    """The 4096 x 1024 lattice in FP32 at full size, in the launch
-    configuration the benchmark times, with eps = -0.05 (G tau = 0.1; the
-    drawn eps = 0.045 gives G tau = 1.2, outside the well-conditioned band):
-    the x-uniform run equals an nx = 1 oracle run row for row (an x-periodic
-    uniform state has no x dependence), within the FP32 tolerance."""
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_large_channel_sampled_rows(orc, precision):
+    """The 4096 x 1024 lattice at full size, in the launch configuration the
+    benchmark times (FP64: a 336 MB state, written with nontemporal stores),
+    with eps = -0.05 (G tau = 0.1; the drawn eps = 0.045 gives G tau = 1.2,
+    outside the well-conditioned band): the x-uniform run equals an nx = 1
+    oracle run row for row (an x-periodic uniform state has no x
+    dependence), within the tolerance of the precision."""
     wl = workloads.large_channel(eps=-0.05)
     spec = wl["channels"][0]
-    with solver([spec], precision="fp32", obs_every=1000) as s:
+    with solver([spec], precision=precision, obs_every=1000) as s:
         s.step(wl["steps"])
         import dataclasses
         o = oracle_channel(orc, dataclasses.replace(spec, nx=1))
         o.run(wl["steps"])
-        compare_fields(s, 0, o, FP32_TOL, "large_channel fp32")
+        compare_fields(s, 0, o, FP32_TOL if precision == "fp32" else FP64_TOL, f"large_channel {precision}")
         assert np.abs(s.observe(0, "kxx")).max() == 0.0
 
 
