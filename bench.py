@@ -143,25 +143,66 @@ def run_warm_start(verbose=True):
     return warmstart.experiment(verbose=verbose)
 
 
-def cpu_baseline(wl, budget_s=15.0):
-    """The FP64 oracle as it stands, on the same lattice, for as many whole
-    steps as fit in about ``budget_s`` seconds (at least one)."""
-    from oracle import core as orc
-    spec = wl["channels"][0]
-    o = orc.Channel(spec.nx, spec.ny, spec.force, tau_lb=spec.tau_lb, G=spec.G, tau0=spec.tau0,
-                    gamma_c=spec.gamma_c, eps=spec.eps)
-    o.run(1)  # warm the code and the pages
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _time_oracle(channel, budget_s):
+    """Whole oracle steps of one channel for about budget_s seconds (at
+    least one, after one warm-up step): (node updates, seconds, steps)."""
+    channel.run(1)
     n = 0
     t0 = time.perf_counter()
     while True:
-        o.run(1)
+        channel.run(1)
         n += 1
         if time.perf_counter() - t0 > budget_s:
             break
-    sec = time.perf_counter() - t0
-    return {"value": spec.nx * spec.ny * n / sec / 1e6, "unit": "MLUPS", "cores": orc.num_threads(),
-            "kind": "oracle",
-            "sample": f"{n} steps of the {spec.nx}x{spec.ny} lattice from rest (after 1 warm-up step), FP64"}
+    return channel.nx * channel.ny * n, time.perf_counter() - t0, n
+
+
+def cpu_baseline(wl, budget_s=15.0):
+    """The FP64 oracle as it stands, on the same lattice, for as many whole
+    steps as fit in about budget_s seconds with every host thread, then for
+    a fifth of that at one thread; and the batched sweep's channels, 1000
+    steps each, for a fifth of the budget."""
+    from oracle import core as orc
+    from paper_1310_7450_amd import workloads
+    spec = wl["channels"][0]
+
+    def channel(c):
+        return orc.Channel(c.nx, c.ny, c.force, tau_lb=c.tau_lb, G=c.G, tau0=c.tau0, gamma_c=c.gamma_c,
+                           eps=c.eps, visc_split=c.visc_split)
+
+    threads = orc.num_threads()
+    upd, sec, n = _time_oracle(channel(spec), budget_s)
+    orc.set_num_threads(1)
+    upd1, sec1, n1 = _time_oracle(channel(spec), budget_s / 5)
+    orc.set_num_threads(threads)
+    # batched sweep: whole channels of 1000 steps until a fifth of the budget is spent
+    b_upd, b_sec, b_ch = 0, 0.0, 0
+    for c in workloads.batched_sweep()["channels"]:
+        o = channel(c)
+        t0 = time.perf_counter()
+        o.run(1000)
+        b_sec += time.perf_counter() - t0
+        b_upd += c.nx * c.ny * 1000
+        b_ch += 1
+        if b_sec > budget_s / 5:
+            break
+    return {"value": upd / sec / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{n} steps of the {spec.nx}x{spec.ny} lattice from rest (after 1 warm-up step), FP64, "
+                      f"{threads} threads on {cpu_model()}",
+            "single_thread": {"value": upd1 / sec1 / 1e6, "unit": "MLUPS", "cores": 1,
+                              "sample": f"{n1} steps of the same lattice"},
+            "batched": {"value": b_upd / b_sec / 1e6, "unit": "MLUPS", "cores": threads,
+                        "sample": f"first {b_ch} channels of the batched sweep (nx = 8), 1000 steps each, FP64"}}
 
 
 def main():

@@ -51,6 +51,7 @@ def lib():
         L.orc_wall_drag.restype = C.c_double
         L.orc_num_fields.restype = C.c_int
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         assert L.orc_num_fields() == len(FIELDS)
         _lib = L
     return _lib
@@ -63,6 +64,10 @@ def _p(a):
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n):
+    lib().orc_set_num_threads(int(n))
 
 
 def equilibrium(rho, ux, uy):

@@ -217,6 +217,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Sets the threads later loops use (for timing at one thread and at all). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* One time step t -> t+1 of one channel. n: 9 planes of nx*ny post-streaming
  * populations at time t; P: stress trace of step t-1. Writes the state at
  * t+1 to n_out, P_out (which must not alias n, P). If fields != NULL the
