@@ -68,7 +68,14 @@ typedef enum {
  *   visc_split lambda in [0,1]: the collision carries eta_s + lambda G tau
  *              and the forcing Sigma^nN = sigma - lambda G tau D (lambda = 1
  *              is the split of Sec. IV; lambda > 0 needs a finite tau);
- *   t_startup  first step without the body force.
+ *   t_startup  first step without the body force (and without the wall
+ *              motion);
+ *   wall_velocity  x velocity of the top wall (y = ny - 1/2) for steps
+ *              t < t_startup, 0 afterwards: planar Couette flow driven by a
+ *              wall that is switched on and off (Sec. IV.B). The wall stays
+ *              on the half link and reflects with the wall-momentum term
+ *              -2 a_i (c_i . u_w) / c_s^2 (wall density rho0 = 1); |u_w| < 0.3
+ *              (low Mach number). 0 gives two fixed walls.
  */
 typedef struct {
   int32_t nx;
@@ -81,6 +88,7 @@ typedef struct {
   double eps;
   double visc_split;
   int64_t t_startup;
+  double wall_velocity;
 } lb_channel;
 
 /*

@@ -117,6 +117,21 @@ def newtonian_startup(ny, g, eta, t, kmax=2000):
     return (coef[None, :] * np.cos(np.outer(xi, mu)) * (1 - np.exp(-eta * mu[None, :] ** 2 * t))).sum(axis=1)
 
 
+def newtonian_couette_startup(ny, U, eta, t, kmax=2000, rho0=1.0):
+    """Start-up of planar Couette flow from rest (Sec. IV.B): walls at
+    y = -1/2 (at rest) and y = ny - 1/2 (moving with U from t = 0), H = ny,
+    s = (y + 1/2)/H. Steady part U s; the transient solves the diffusion
+    equation with zero wall values, starting from -U s, whose sine series has
+    coefficients -2U (-1)^(n+1) / (n pi): u = U s - (2U/pi) sum (-1)^(n+1)/n
+    sin(n pi s) exp(-(eta/rho0) (n pi/H)^2 t)."""
+    H = float(ny)
+    s = (np.arange(ny) + 0.5) / H
+    n = np.arange(1, kmax + 1)[:, None]
+    terms = ((-1.0) ** (n + 1) / n) * np.sin(n * math.pi * s[None, :]) * np.exp(
+        -(eta / rho0) * (n * math.pi / H) ** 2 * t)
+    return U * s - (2 * U / math.pi) * terms.sum(axis=0)
+
+
 def bingham_stop_bound(u_rows, eta, sigma_y, ny, rho0=1.0):
     """Upper bound on the stopping time of a Bingham fluid (yield stress
     sigma_y, plastic viscosity eta) released from the profile u_rows in a

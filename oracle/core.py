@@ -25,7 +25,7 @@ WEIGHTS = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
 class OrcParams(C.Structure):
     _fields_ = [("g", C.c_double), ("tau_eff", C.c_double), ("G", C.c_double),
                 ("tau", C.c_double), ("gamma_c", C.c_double), ("lam", C.c_double),
-                ("t_startup", C.c_longlong), ("nn_pressure", C.c_int)]
+                ("t_startup", C.c_longlong), ("nn_pressure", C.c_int), ("uw", C.c_double)]
 
 
 def lib():
@@ -34,7 +34,8 @@ def lib():
         path = _build.ensure_built()
         L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
-        L.orc_resolve.argtypes = [C.c_double] * 6 + [C.c_double, C.c_longlong, C.c_int, C.POINTER(OrcParams)]
+        L.orc_resolve.argtypes = [C.c_double] * 6 + [C.c_double, C.c_longlong, C.c_int, C.c_double,
+                                                     C.POINTER(OrcParams)]
         L.orc_resolve.restype = C.c_int
         L.orc_equilibrium.argtypes = [C.c_double] * 3 + [dp]
         L.orc_forcing.argtypes = [C.c_double, dp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, dp]
@@ -47,7 +48,7 @@ def lib():
         L.orc_run.argtypes = [C.POINTER(OrcParams), C.c_int, C.c_int, dp, dp, C.c_longlong, C.c_longlong]
         L.orc_run.restype = C.c_longlong
         L.orc_init_rest.argtypes = [C.c_int, C.c_int, dp, dp]
-        L.orc_wall_drag.argtypes = [C.c_int, C.c_int, dp]
+        L.orc_wall_drag.argtypes = [C.c_int, C.c_int, dp, C.c_double]
         L.orc_wall_drag.restype = C.c_double
         L.orc_num_fields.restype = C.c_int
         L.orc_num_threads.restype = C.c_int
@@ -97,10 +98,10 @@ def tau_M(kappa, tau, gamma_c):
 
 
 def resolve(tau_lb, G, tau0, gamma_c, eps=0.0, visc_split=0.0, force=0.0,
-            t_startup=2 ** 62, nn_pressure=True):
+            t_startup=2 ** 62, nn_pressure=True, wall_velocity=0.0):
     p = OrcParams()
     rc = lib().orc_resolve(tau_lb, G, tau0, gamma_c, eps, visc_split, force,
-                           int(t_startup), int(bool(nn_pressure)), C.byref(p))
+                           int(t_startup), int(bool(nn_pressure)), float(wall_velocity), C.byref(p))
     if rc != 0:
         raise ValueError("invalid channel parameters")
     return p
@@ -110,10 +111,12 @@ class Channel:
     """One channel advanced by the oracle. Time ``t`` counts completed steps."""
 
     def __init__(self, nx, ny, force, tau_lb=1.0, G=1e-4, tau0=1e4, gamma_c=0.1,
-                 eps=0.0, visc_split=0.0, t_startup=2 ** 62, nn_pressure=True):
+                 eps=0.0, visc_split=0.0, t_startup=2 ** 62, nn_pressure=True, wall_velocity=0.0):
+        """wall_velocity: x velocity of the top wall while t < t_startup
+        (planar Couette flow); 0 gives the channel with two fixed walls."""
         self.nx, self.ny = int(nx), int(ny)
         self.params = resolve(tau_lb, G, tau0, gamma_c, eps, visc_split, force,
-                              t_startup, nn_pressure)
+                              t_startup, nn_pressure, wall_velocity)
         self.n = np.empty((9, self.ny, self.nx))
         self.P = np.empty((self.ny, self.nx))
         lib().orc_init_rest(self.nx, self.ny, _p(self.n), _p(self.P))
@@ -153,7 +156,10 @@ class Channel:
         return float((CX[:, None, None] * self.n).sum())
 
     def wall_drag(self):
-        return float(lib().orc_wall_drag(self.nx, self.ny, _p(self.n)))
+        """Momentum handed to both walls by the step that produced the state
+        (the top wall moved during step t - 1 if t - 1 < t_startup)."""
+        uw = self.params.uw if 1 <= self.t and self.t - 1 < self.params.t_startup else 0.0
+        return float(lib().orc_wall_drag(self.nx, self.ny, _p(self.n), uw))
 
     def force_now(self):
         return self.params.g if self.t < self.params.t_startup else 0.0

@@ -52,6 +52,11 @@
  *   R8 viscosity split lambda: the collision relaxes with
  *      tau_eff = 1/2 + 3 (eta_s + lambda G tau), eta_s = (tau_LB - 1/2)/3,
  *      and Sigma^nN = sigma - lambda G tau D.
+ *   R9 planar Couette flow (Sec. IV.B): the top wall moves along x with u_w
+ *      while t < t_startup; it stays on the half link and reflects with the
+ *      wall-momentum term -2 a_i (c_i . u_w)/cs2 (rho_w = rho0 = 1), and the
+ *      stencil ghost behind it is 2 u_w - u(ny-1). The paper's Couette runs
+ *      used Zou and He's velocity boundary on a node row instead.
  *
  * Lattice units: dx = dt = 1, rho0 = 1, c_s^2 = 1/3, d = 2.
  * Storage: populations n[i][y][x] (nine planes, x fastest), the previous
@@ -88,14 +93,15 @@ typedef struct {
   double lam;       /* viscosity split lambda in [0, 1]                       */
   long long t_startup;
   int nn_pressure;  /* 1: keep the delta-rho terms of the forcing            */
+  double uw;        /* x velocity of the top wall while t < t_startup (R9)   */
 } orc_params;
 
 /* Parameter resolution (readings R7, R8). Returns 0, or -1 for invalid input. */
 int orc_resolve(double tau_lb, double G, double tau0, double gamma_c, double eps,
-                double lam, double g, long long t_startup, int nn_pressure,
+                double lam, double g, long long t_startup, int nn_pressure, double uw,
                 orc_params *out) {
   if (!(tau_lb > 0.5) || !(G >= 0) || !(tau0 > 0) || !(gamma_c > 0) ||
-      !(lam >= 0 && lam <= 1) || !isfinite(g) || !isfinite(eps))
+      !(lam >= 0 && lam <= 1) || !isfinite(g) || !isfinite(eps) || !isfinite(uw))
     return -1;
   double eta_s = (tau_lb - 0.5) / 3.0;
   double tau = tau0 * pow(10.0, fmin(eps, 0.0) / 0.05);
@@ -109,6 +115,7 @@ int orc_resolve(double tau_lb, double G, double tau0, double gamma_c, double eps
   out->lam = lam;
   out->t_startup = t_startup;
   out->nn_pressure = nn_pressure;
+  out->uw = uw;
   return 0;
 }
 
@@ -236,6 +243,7 @@ int orc_step(const orc_params *p, int nx, int ny, const double *n, const double 
              long long t, double *n_out, double *P_out, double *fields) {
   const size_t N = (size_t)nx * ny;
   double fx = (t < p->t_startup) ? p->g : 0.0, fy = 0.0;
+  double uw = (t < p->t_startup) ? p->uw : 0.0;  /* top wall velocity at step t */
   double *utx = malloc(N * sizeof(double)), *uty = malloc(N * sizeof(double));
   int bad = 0;
 
@@ -271,7 +279,7 @@ int orc_step(const orc_params *p, int nx, int ny, const double *n, const double 
       double jx = mx + 0.5 * fx, jy = my + 0.5 * fy;
 
       /* kappa_ab = d_b u_a by central differences; x periodic, wall ghosts
-       * u(-1) = -u(0), u(ny) = -u(ny-1) (readings R4, R5). */
+       * u(-1) = -u(0), u(ny) = 2 u_w - u(ny-1) (readings R4, R5, R9). */
       int xm = (x - 1 + nx) % nx, xp = (x + 1) % nx;
       double uxm = utx[(size_t)y * nx + xm], uxp = utx[(size_t)y * nx + xp];
       double uym = uty[(size_t)y * nx + xm], uyp = uty[(size_t)y * nx + xp];
@@ -279,7 +287,7 @@ int orc_step(const orc_params *p, int nx, int ny, const double *n, const double 
       if (y > 0) { uxd = utx[id - nx]; uyd = uty[id - nx]; }
       else       { uxd = -utx[id];     uyd = -uty[id]; }
       if (y < ny - 1) { uxu = utx[id + nx]; uyu = uty[id + nx]; }
-      else            { uxu = -utx[id];     uyu = -uty[id]; }
+      else            { uxu = 2.0 * uw - utx[id]; uyu = -uty[id]; }
       double k[2][2];
       k[0][0] = 0.5 * (uxp - uxm);  /* d_x u_x */
       k[0][1] = 0.5 * (uxu - uxd);  /* d_y u_x */
@@ -327,12 +335,16 @@ int orc_step(const orc_params *p, int nx, int ny, const double *n, const double 
       if (!n_out) continue;
 
       /* Collide (BGK + forcing) and stream; links leaving through a wall are
-       * reflected back to the same node (half-way bounce-back). */
+       * reflected back to the same node (half-way bounce-back); at the moving
+       * top wall the reflected population gains the wall's momentum,
+       * -2 a_i (c_i . u_w) / cs2 with the wall density rho0 = 1 (R9). */
       for (int i = 0; i < 9; ++i) {
         double post = nn[i] - (nn[i] - neq[i]) / p->tau_eff + F[i];
         int xd = (x + CX[i] + nx) % nx, yd = y + CY[i];
         if (yd >= 0 && yd < ny)
           n_out[i * N + (size_t)yd * nx + xd] = post;
+        else if (yd >= ny)
+          n_out[opposite(i) * N + id] = post - 2.0 * W[i] * (CX[i] * uw) / CS2;
         else
           n_out[opposite(i) * N + id] = post;
       }
@@ -371,8 +383,10 @@ long long orc_run(const orc_params *p, int nx, int ny, double *n, double *P,
 
 /* Momentum handed to the walls by the bounce-back links during the step that
  * produced the current state: the populations that were reflected are the
- * ones now travelling away from the wall in the wall rows. */
-double orc_wall_drag(int nx, int ny, const double *n) {
+ * ones now travelling away from the wall in the wall rows. uw is the top
+ * wall's velocity during that step: a reflected population n_i there left as
+ * n_i + 2 a_i (c_i . u_w)/cs2 in the opposite direction. */
+double orc_wall_drag(int nx, int ny, const double *n, double uw) {
   const size_t N = (size_t)nx * ny;
   double w = 0.0;
   for (int x = 0; x < nx; ++x) {
@@ -381,7 +395,7 @@ double orc_wall_drag(int nx, int ny, const double *n) {
       /* bottom wall: populations now moving up (cy = +1) came from links
        * that pointed down, with x velocity -cx */
       if (CY[i] == 1) w += 2.0 * (-CX[i]) * n[i * N + b];
-      if (CY[i] == -1) w += 2.0 * (-CX[i]) * n[i * N + t];
+      if (CY[i] == -1) w += -CX[i] * (2.0 * n[i * N + t] + 2.0 * W[i] * (-CX[i] * uw) / CS2);
     }
   }
   return w;

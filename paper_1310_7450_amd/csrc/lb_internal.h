@@ -41,6 +41,7 @@ struct ChanDev {
   double inv_tau;       // 1/tau (0 for tau = inf)
   double inv_gc;        // 1/gamma_c
   double lgt;           // lambda G_inf tau
+  double uw;            // top wall x velocity while t < t_startup
 };
 
 // Work unit of one wavefront: rows [y0, y1) of channel ch, starting at

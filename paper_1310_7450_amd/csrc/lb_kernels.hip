@@ -99,9 +99,11 @@ __device__ __forceinline__ T lane_value(T v, int l) {
 
 // Pulls the nine post-streaming populations of node (x, y), 0 <= y < ny;
 // row = index of node (0, y).
+// uw6 = u_w/6 of the top wall during the previous step: the populations
+// reflected there gained -/+ u_w/6 (a_i c_ix u_w / cs2 for the diagonals).
 template <typename T>
 __device__ __forceinline__ void pull(const T *__restrict__ A, long long row, int nx, int ny, int x,
-                                     int y, T f[9]) {
+                                     int y, T uw6, T f[9]) {
   const int xm = (x == 0) ? nx - 1 : x - 1;
   const int xp = (x == nx - 1) ? 0 : x + 1;
   const long long dn = row - nx, up = row + nx;
@@ -113,8 +115,8 @@ __device__ __forceinline__ void pull(const T *__restrict__ A, long long row, int
   f[5] = A[bot ? slot(7, row + x) : slot(5, dn + xm)];
   f[6] = A[bot ? slot(8, row + x) : slot(6, dn + xp)];
   f[4] = A[top ? slot(2, row + x) : slot(4, up + x)];
-  f[7] = A[top ? slot(5, row + x) : slot(7, up + xp)];
-  f[8] = A[top ? slot(6, row + x) : slot(8, up + xm)];
+  f[7] = A[top ? slot(5, row + x) : slot(7, up + xp)] - (top ? uw6 : T(0));
+  f[8] = A[top ? slot(6, row + x) : slot(8, up + xm)] + (top ? uw6 : T(0));
 }
 
 // Zeroth and first moments of the stored values: sd = sum_i f_i, m = sum_i
@@ -286,10 +288,11 @@ __device__ __forceinline__ void node_update(const T f[9], T sd, T mx, T my, T Pc
 // Momentum handed to the walls in the previous step: the reflected
 // populations sit in the wall rows with the opposite velocity.
 template <typename T>
-__device__ __forceinline__ double wall_drag(const T f[9], int y, int ny) {
+__device__ __forceinline__ double wall_drag(const T f[9], int y, int ny, T uw6) {
   double d = 0.0;
   if (y == 0) d += 2.0 * ((double)f[6] - (double)f[5]);
-  if (y == ny - 1) d += 2.0 * ((double)f[7] - (double)f[8]);
+  // a moving top wall also received the momentum its reflection added
+  if (y == ny - 1) d += 2.0 * ((double)f[7] - (double)f[8]) + 2.0 * (double)uw6;
   return d;
 }
 
@@ -316,6 +319,10 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
   const int nx = c.nx, ny = c.ny;
   const long long t = c.t + a.k;
   const T fx = (t < c.t_startup) ? T(c.g) : T(0);
+  // moving top wall: its velocity at step t (stencil ghost) and u_w/6 of step
+  // t - 1, whose reflected links step t pulls
+  const T uwg = (t < c.t_startup) ? T(c.uw) : T(0);
+  const T uw6 = (t >= 1 && t - 1 < c.t_startup) ? T(c.uw / 6.0) : T(0);
   const Coef<T> q(c);
 
   int lx, ly, x, hx = 0;
@@ -345,13 +352,13 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
   auto pull_row = [&](int y, T f[9], T &Pv) {
     const int yc = clampy(y);
     const long long row = base + (long long)yc * nx;
-    pull<T>(A, row, nx, ny, x, yc, f);
+    pull<T>(A, row, nx, ny, x, yc, uw6, f);
     Pv = A[slot(9, row + x)];
   };
   auto halo_u = [&](int y) -> U2<T> {
     const int yc = clampy(y);
     T f[9], sd, mx, my;
-    pull<T>(A, base + (long long)yc * nx, nx, ny, hx, yc, f);
+    pull<T>(A, base + (long long)yc * nx, nx, ny, hx, yc, uw6, f);
     moments<T>(f, sd, mx, my);
     return u_tilde<T, SHIFT>(sd, mx, my, fx);
   };
@@ -400,7 +407,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
     }
     // no-slip ghosts behind the half-way walls
     if (y == 0) dn = U2<T>{-uCur.x, -uCur.y};
-    if (y == ny - 1) up = U2<T>{-uCur.x, -uCur.y};
+    if (y == ny - 1) up = U2<T>{T(2) * uwg - uCur.x, -uCur.y};
 
     // Every lane computes; only valid lanes store. Lanes past the strip or
     // outside the channel read clamped rows and their results are dropped.
@@ -409,7 +416,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
     double obs[OF_COUNT];
     node_update<T, SHIFT, OBS>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, q, a.nnp, out, trT, obs);
     if constexpr (OBS) {
-      obs[OF_DRAG] = wall_drag<T>(fc, y, ny);
+      obs[OF_DRAG] = wall_drag<T>(fc, y, ny, uw6);
       constexpr int GW = WIDE ? 64 : TXW;
 #pragma unroll
       for (int f = 0; f < OF_COUNT; ++f) obs[f] = group_sum<GW>(ok ? obs[f] : 0.0);
@@ -456,6 +463,10 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
   const int nx = c.nx, ny = c.ny;
   const long long t = c.t + a.k;
   const T fx = (t < c.t_startup) ? T(c.g) : T(0);
+  // moving top wall: its velocity at step t (stencil ghost) and u_w/6 of step
+  // t - 1, whose reflected links step t pulls
+  const T uwg = (t < c.t_startup) ? T(c.uw) : T(0);
+  const T uw6 = (t >= 1 && t - 1 < c.t_startup) ? T(c.uw / 6.0) : T(0);
   const Coef<T> q(c);
 
   const int tiles_row = nx >> 6;                 // tiles per row
@@ -498,8 +509,8 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
     }
     if (top) {
       f[4] = run(t0, 2);
-      f[7] = run(t0, 5);
-      f[8] = run(t0, 6);
+      f[7] = run(t0, 5) - uw6;
+      f[8] = run(t0, 6) + uw6;
     } else {
       f[4] = run(tu, 4);
       f[7] = shift_down(ld(tu + dr, 0, 7), run(tu, 7));
@@ -537,11 +548,11 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
     }
     if (top) {
       a[4] = ld(L0, 63, 2);
-      a[7] = ld(L0, 63, 5);
-      a[8] = ld(L0, 63, 6);
+      a[7] = ld(L0, 63, 5) - uw6;
+      a[8] = ld(L0, 63, 6) + uw6;
       b[4] = ld(R0, 0, 2);
-      b[7] = ld(R0, 0, 5);
-      b[8] = ld(R0, 0, 6);
+      b[7] = ld(R0, 0, 5) - uw6;
+      b[8] = ld(R0, 0, 6) + uw6;
     } else {
       const long long tu = tile(y + 1);
       a[4] = ld(tu + dl, 63, 4);
@@ -587,13 +598,13 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
     const U2<T> rt{shift_down(uRc.x, uCur.x), shift_down(uRc.y, uCur.y)};
     // no-slip ghosts behind the half-way walls
     if (y == 0) dn = U2<T>{-uCur.x, -uCur.y};
-    if (y == ny - 1) up = U2<T>{-uCur.x, -uCur.y};
+    if (y == ny - 1) up = U2<T>{T(2) * uwg - uCur.x, -uCur.y};
 
     T out[9], trT;
     double obs[OF_COUNT];
     node_update<T, SHIFT, OBS>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, q, a.nnp, out, trT, obs);
     if constexpr (OBS) {
-      obs[OF_DRAG] = wall_drag<T>(fc, y, ny);
+      obs[OF_DRAG] = wall_drag<T>(fc, y, ny, uw6);
 #pragma unroll
       for (int f = 0; f < OF_COUNT; ++f) obs[f] = group_sum<64>(obs[f]);
       if (lane == 0) {
@@ -693,6 +704,10 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
   const int nx = c.nx, ny = c.ny;
   const long long t = c.t + a.k;
   const T fx = (t < c.t_startup) ? T(c.g) : T(0);
+  // moving top wall: its velocity at step t (stencil ghost) and u_w/6 of step
+  // t - 1, whose reflected links step t pulls
+  const T uwg = (t < c.t_startup) ? T(c.uw) : T(0);
+  const T uw6 = (t >= 1 && t - 1 < c.t_startup) ? T(c.uw / 6.0) : T(0);
   const Coef<T> q(c);
 
   const int tiles_row = nx >> 6;        // tiles per row
@@ -794,6 +809,11 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
     if (top) {
       split(R.r[7], f[7]);
       split(R.r[8], f[8]);
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        f[7][k] -= uw6;
+        f[8][k] += uw6;
+      }
     } else {
       from_right(R.r[7], lane_value(R.side, 4), f[7]);
       from_left(R.r[8], lane_value(R.side, 5), f[8]);
@@ -826,6 +846,11 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
     r[4] = lane_value(R.side, 21);
     r[7] = lane_value(R.side, 22);
     r[8] = lane_value(R.side, 23);
+    const T wc = top ? uw6 : T(0);  // a select: no branch in the row step
+    l[7] -= wc;
+    l[8] += wc;
+    r[7] -= wc;
+    r[8] += wc;
     T s0, m0, n0;
     moments<T>(l, s0, m0, n0);
     uL = u_tilde<T, SHIFT>(s0, m0, n0, fx);
@@ -889,14 +914,14 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
       U2<T> dn = DOWN ? uNext[k] : uPrev[k], up = DOWN ? uPrev[k] : uNext[k];
       // no-slip ghosts behind the half-way walls
       if (y == 0) dn = U2<T>{-uCur[k].x, -uCur[k].y};
-      if (y == ny - 1) up = U2<T>{-uCur[k].x, -uCur[k].y};
+      if (y == ny - 1) up = U2<T>{T(2) * uwg - uCur[k].x, -uCur[k].y};
       T g[9], o[9], tr;
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[i] = fc[i][k];
       double ob[OF_COUNT];
       node_update<T, SHIFT, OBS>(g, sdc[k], mxc[k], myc[k], Pc[k], fx, lf, rt, dn, up, q, a.nnp, o, tr, ob);
       if constexpr (OBS) {
-        ob[OF_DRAG] = wall_drag<T>(g, y, ny);
+        ob[OF_DRAG] = wall_drag<T>(g, y, ny, uw6);
 #pragma unroll
         for (int f = 0; f < OF_COUNT; ++f) obs[f] += ob[f];
       } else {

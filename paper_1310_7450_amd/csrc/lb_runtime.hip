@@ -70,6 +70,7 @@ std::string validate(const lb_channel *c, int n, const lb_options *o) {
     if (!std::isfinite(q.eps)) return bad("eps must be finite");
     if (!(q.visc_split >= 0 && q.visc_split <= 1)) return bad("visc_split must be in [0,1]");
     if (q.visc_split > 0 && std::isinf(q.tau0)) return bad("visc_split > 0 needs a finite tau0");
+    if (!(std::fabs(q.wall_velocity) < 0.3)) return bad("wall_velocity must be finite with |u_w| < 0.3");
   }
   return "";
 }
@@ -94,6 +95,16 @@ void resolve(const lb_channel &q, ChanDev &d) {
   d.inv_tau = std::isinf(tau) ? 0.0 : 1.0 / tau;
   d.inv_gc = 1.0 / q.gamma_c;
   d.lgt = lgt;
+  d.uw = q.wall_velocity;
+}
+
+// Term the pull adds to population i of a top-row node at step t: the link
+// reflected at the moving wall during step t - 1 gained -2 a c_x u_w / cs2
+// (a and c of the outgoing population opp(i)); only i = 7, 8 are affected.
+double wall_pull_term(const lb_channel &q, int i, long long t) {
+  const double uw = (t >= 1 && t - 1 < q.t_startup) ? q.wall_velocity : 0.0;
+  const int o = HOPP[i];
+  return -6.0 * hweight(o) * HCX[o] * uw;
 }
 
 int strip_rows_for(int cls, int nx, int ny, int requested) {
@@ -605,8 +616,10 @@ lb_status lb_get_state(lb_handle *h, int32_t ch, double *pops, double *P) {
         const int ys = y - HCY[i];
         const int xs = ((x - HCX[i]) % d.nx + d.nx) % d.nx;
         double v;
-        if (ys < 0 || ys >= d.ny)
+        if (ys < 0)
           v = at(HOPP[i], id);
+        else if (ys >= d.ny)
+          v = at(HOPP[i], id) + wall_pull_term(h->in[ch], i, h->t[ch]);
         else
           v = at(i, (size_t)ys * d.nx + xs);
         pops[(size_t)i * N + id] = v;
@@ -645,8 +658,10 @@ lb_status lb_set_state(lb_handle *h, int32_t ch, const double *pops, const doubl
         const int ys = y - HCY[i];
         const int xs = ((x - HCX[i]) % d.nx + d.nx) % d.nx;
         const double v = pops[(size_t)i * N + id];
-        if (ys < 0 || ys >= d.ny)
+        if (ys < 0)
           put(HOPP[i], id, v);
+        else if (ys >= d.ny)
+          put(HOPP[i], id, v - wall_pull_term(h->in[ch], i, t));
         else
           put(i, (size_t)ys * d.nx + xs, v);
       }

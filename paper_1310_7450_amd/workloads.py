@@ -20,6 +20,8 @@ Named workloads (lattice units, rho0 = 1):
 * ``transient_scale``: 16 channels of 8192 x 2048, 8 at eps = 0 and 8 at
   eps = +0.02, g = 2 G gamma_c / H (wp H = 2 gamma_c), 50,000 start-up steps
   then cessation.
+* ``couette_64``: planar Couette flow, 8 x 64, top wall at u0 switched on and
+  off, theta = 100 (the paper's Fig. stopshear parameters in lattice units).
 """
 import numpy as np
 
@@ -125,3 +127,24 @@ def transient_scale(nx=8192, ny=2048, n_per_eps=8, eps_values=(0.0, 0.02), G=1e-
              for e in eps_values for _ in range(n_per_eps)]
     return {"name": f"transient_scale_{len(chans)}x{nx}x{ny}", "channels": chans, "startup": 50000,
             "cessation_cap": 200000, "stop_fraction": 1e-3, "thresholds": (1e-2, 1e-3, 1e-4)}
+
+
+def couette_64(nx=8, ny=64, theta=100.0, tau_lb=0.6, G=1e-3, gamma_c=0.1, wall_u_scale=1e-2, startup=60000,
+               newtonian=False):
+    """Planar Couette flow switched on and off (Sec. IV.B, Fig. stopshear):
+    the top wall moves with u0 for ``startup`` steps, then stops. The
+    paper's parameters in lattice units: theta = G tau / eta_s = 100 and
+    u0 = 1e-2 H / tau_mu with tau_mu = eta_s / G and H = ny, i.e.
+    u0 = 1e-2 H G / eta_s (0.0192 here; the wall Peclet number
+    gdot tau / gamma_c = 10). tau_lb = 0.6 keeps G tau = 3.3; the viscosity
+    split 1/2 without the delta-rho terms (``nn_pressure = 0`` on the handle)
+    is the well-conditioned setting for it. ``newtonian=True`` gives the
+    solvent alone (G = 0) as a reference."""
+    eta_s = (tau_lb - 0.5) / 3.0
+    tau0 = theta * eta_s / G
+    u0 = wall_u_scale * ny * G / eta_s
+    spec = ChannelSpec(nx=nx, ny=ny, force=0.0, tau_lb=tau_lb, G=0.0 if newtonian else G, tau0=tau0,
+                       gamma_c=gamma_c, eps=0.0, visc_split=0.0 if newtonian else 0.5, t_startup=startup,
+                       wall_velocity=u0)
+    return {"name": f"couette_{nx}x{ny}" + ("_newtonian" if newtonian else ""), "channels": [spec],
+            "startup": startup, "cessation": 10000, "nn_pressure": False, "theta": theta}

@@ -1,0 +1,115 @@
+"""Planar Couette flow with the moving top wall (Sec. IV.B): GPU against the
+oracle, through the C ABI.
+
+The wall stays on the half link and reflects with the wall-momentum term
+(reading R9 of the oracle). The workload takes the paper's Fig. stopshear
+parameters (theta = 100, u0 = 1e-2 H / tau_mu) in the well-conditioned
+setting (viscosity split 1/2 without the delta-rho terms), where GPU and
+oracle agree to round-off."""
+import numpy as np
+import pytest
+
+from paper_1310_7450_amd import workloads
+from paper_1310_7450_amd.lbnlm import ChannelSpec
+from paper_1310_7450_amd.protocol import startup_cessation
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-5
+FP32_TOL = 1e-3
+
+
+def solver(channels, **kw):
+    from paper_1310_7450_amd import Solver
+    return Solver(channels, **kw)
+
+
+def oracle_channel(orc, spec, nx=None, nn_pressure=True):
+    return orc.Channel(spec.nx if nx is None else nx, spec.ny, spec.force, tau_lb=spec.tau_lb, G=spec.G,
+                       tau0=spec.tau0, gamma_c=spec.gamma_c, eps=spec.eps, visc_split=spec.visc_split,
+                       t_startup=spec.t_startup, nn_pressure=nn_pressure, wall_velocity=spec.wall_velocity)
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 16), (8, 9), (64, 7), (100, 13), (128, 9), (192, 5), (256, 6), (3, 1)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_couette_state_parity(orc, nx, ny, precision):
+    """Seeded random populations with the top wall moving (u_w = 0.02) and
+    stopping at t = 40, on narrow, aligned-wide and ragged-wide lattices and
+    a one-row channel: the state set at t0 = 5 (the reflected populations of
+    the top row carry the wall term of step 4) and advanced across the
+    switch matches the oracle node by node."""
+    spec = ChannelSpec(nx=nx, ny=ny, force=1e-6, tau_lb=0.8, G=2e-4, tau0=500.0, gamma_c=0.1, eps=0.01,
+                       visc_split=0.3, t_startup=40, wall_velocity=0.02)
+    pops, P = workloads.random_state(nx, ny, seed=7000 + nx * 100 + ny)
+    o = oracle_channel(orc, spec)
+    o.set_state(pops, P, t=5)
+    tol = 1e-12 if precision == "fp64" else 2e-6
+    with solver([spec], precision=precision, obs_every=16, strip_rows=4) as s:
+        s.set_state(0, pops, P, 5)
+        g_pops, _ = s.get_state(0)
+        assert np.abs(g_pops - pops).max() <= (1e-16 if precision == "fp64" else 1e-7)
+        for n in [1, 2, 57]:
+            s.step(n)
+            o.run(n)
+            g_pops, g_P = s.get_state(0)
+            err = np.abs(g_pops - o.n).max() / np.abs(o.n - workloads.REST_WEIGHTS[:, None, None]).max()
+            print(f"{precision} {nx}x{ny} t={o.t}: state {err:.2e}", flush=True)
+            assert err < tol * 50
+            if precision == "fp64":
+                drag = s.observe(0, "wall_drag")
+                assert drag == pytest.approx(o.wall_drag(), rel=1e-9, abs=1e-15)
+
+
+def plug_rows(u):
+    """Rows within 1% of the maximum velocity: the paper's indicator of the
+    plug width (Fig. stopprofiles)."""
+    return int((u >= 0.99 * u.max()).sum())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_couette_startup_cessation(orc, precision):
+    """The Couette workload (8 x 64, theta = 100, Pe = 10): the profile
+    through start-up and cessation equals an nx = 1 oracle run; the steady
+    start-up profile is the linear one; after the wall stops an intermediate
+    plug forms at the formerly moving wall and moves into the channel (its
+    1%-of-maximum width at least twice that of the solvent alone at the same
+    times, its maximum starting within 8 rows of the wall and moving down);
+    and u_mid falls below 1e-2 of its value at the switch-off within the
+    Bingham energy bound evaluated on the oracle's profile (Pe >= 10)."""
+    from oracle import analytic
+    wl = workloads.couette_64()
+    spec = wl["channels"][0]
+    ts = wl["startup"]
+    tol = FP64_TOL * 1e-4 if precision == "fp64" else FP32_TOL
+    o = oracle_channel(orc, spec, nx=1, nn_pressure=False)
+    newt = oracle_channel(orc, workloads.couette_64(newtonian=True)["channels"][0], nx=1, nn_pressure=False)
+    checkpoints = [ts // 2, ts, ts + 100, ts + 500, ts + 1000, ts + 2000]
+    with solver([spec], precision=precision, obs_every=100, nn_pressure=False) as s:
+        argmax = []
+        for t in checkpoints:
+            s.step(t - int(s.observe(0, "step")))
+            o.run(t - o.t)
+            newt.run(t - newt.t)
+            ug, uo = s.observe(0, "ux"), o.profiles()["ux"]
+            e = np.abs(ug - uo).max() / spec.wall_velocity
+            print(f"{precision} t={t}: u_x err {e:.2e} (of u0); plug rows {plug_rows(ug)} "
+                  f"(solvent alone {plug_rows(newt.profiles()['ux'])}); argmax {int(ug.argmax())}", flush=True)
+            assert e <= tol
+            if t == ts:
+                lin = spec.wall_velocity * (np.arange(spec.ny) + 0.5) / spec.ny
+                assert np.abs(ug - lin).max() / spec.wall_velocity < 1e-3
+                u_ts_oracle = uo.copy()
+            if t > ts:
+                argmax.append(int(ug.argmax()))
+            if t in (ts + 500, ts + 1000):
+                assert plug_rows(ug) >= 2 * plug_rows(newt.profiles()["ux"])
+        assert argmax[0] >= spec.ny - 8
+        assert all(a >= b for a, b in zip(argmax, argmax[1:]))
+    eta_s = (spec.tau_lb - 0.5) / 3.0
+    bound = analytic.bingham_stop_bound(u_ts_oracle, eta_s, spec.G * spec.gamma_c, spec.ny)
+    pe = (spec.wall_velocity / spec.ny) * spec.tau0 / spec.gamma_c
+    with solver([spec], precision=precision, obs_every=100, nn_pressure=False) as s:
+        res = startup_cessation(s, ts, wl["cessation"], every=100, thresholds=(1e-2, 1e-3))
+    t_stop = res[0]["t_stop"]
+    print(f"{precision}: t_stop {t_stop}, Bingham bound {bound:.0f}, Pe {pe:.1f}", flush=True)
+    assert pe >= 10 and t_stop[1e-2] is not None and t_stop[1e-2] <= bound

@@ -37,7 +37,7 @@ def linf(a, b):
 def oracle_channel(orc, spec, nn_pressure=True):
     return orc.Channel(spec.nx, spec.ny, spec.force, tau_lb=spec.tau_lb, G=spec.G, tau0=spec.tau0,
                        gamma_c=spec.gamma_c, eps=spec.eps, visc_split=spec.visc_split,
-                       t_startup=spec.t_startup, nn_pressure=nn_pressure)
+                       t_startup=spec.t_startup, nn_pressure=nn_pressure, wall_velocity=spec.wall_velocity)
 
 
 def compare_fields(s, ch, o, tol, label):

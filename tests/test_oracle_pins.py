@@ -385,3 +385,69 @@ def test_cessation_below_bingham_bound(orc):
             t_stop = ch.t - T_s
             break
     assert t_stop is not None and t_stop < bound
+
+
+# ---- planar Couette flow: the moving top wall (reading R9)
+
+def test_couette_newtonian_linear(orc):
+    """G = 0 with the top wall moving at U: the steady profile is exactly the
+    linear Couette profile U (y + 1/2)/ny for any relaxation time (the
+    half-way moving wall has no slip), u_y = 0."""
+    for tau in (0.6, 0.8, 1.3):
+        ch = orc.Channel(1, 16, 0.0, tau_lb=tau, G=0.0, wall_velocity=0.01)
+        ch.run(int(6000 / ((tau - 0.5) / 3 / (1 / 6))))
+        pr = ch.profiles()
+        want = 0.01 * (np.arange(16) + 0.5) / 16
+        assert np.abs(pr["ux"] - want).max() / 0.01 < 1e-10
+        assert np.abs(pr["uy"]).max() / 0.01 < 1e-10
+
+
+def test_couette_newtonian_startup(orc):
+    """Start-up of Newtonian Couette flow follows its Fourier series (the
+    moving wall switched on at t = 0, Sec. IV.B)."""
+    tau = 0.8
+    eta = (tau - 0.5) / 3
+    ch = orc.Channel(1, 32, 0.0, tau_lb=tau, G=0.0, wall_velocity=0.01)
+    for t in (100, 500, 2000):
+        ch.run(t - ch.t)
+        want = analytic.newtonian_couette_startup(32, 0.01, eta, t)
+        assert np.abs(ch.profiles()["ux"] - want).max() / 0.01 < 3e-3
+
+
+def test_couette_mass_and_momentum_budget(orc):
+    """With the wall moving and then stopped: mass is conserved to round-off
+    (the wall-momentum term has no zeroth moment) and M_x(t+1) = M_x(t) -
+    W(t+1) exactly, W including the momentum the moving wall imparts."""
+    ch = orc.Channel(2, 24, 0.0, tau_lb=0.7, G=1e-4, tau0=1e3, gamma_c=0.1, wall_velocity=0.02,
+                     t_startup=40)
+    q0 = ch.mass()
+    for _ in range(80):
+        m0 = ch.momentum_x()
+        ch.run(1)
+        assert ch.momentum_x() - m0 + ch.wall_drag() == pytest.approx(0, abs=1e-14)
+    assert abs(ch.mass() - q0) / (ch.nx * ch.ny) < 5e-16 * 80
+
+
+def test_couette_nlm_steady(orc):
+    """Sec. IV.B: in steady planar Couette flow the shear rate is the same
+    everywhere (no plug): the nlM profile is the linear one, kappa_xy = U/H
+    on every row, and the stress is the simple-shear one of Sec. III.A,
+    sigma_xy = G gdot tau_M, N1 = 2 G gdot^2 tau_M^2, 1/tau_M = 1/tau +
+    gdot/gamma_c. Parameters: theta = G tau / eta_s = 100, Pe = gdot tau /
+    gamma_c = 10, viscosity split 1/2 without the delta-rho terms (the
+    well-conditioned setting). Deviations decay with the differential
+    viscosity eta_s + G tau / (1 + Pe)^2, so 16 rows reach the steady state
+    to round-off within 30,000 steps."""
+    ny, U = 16, 0.0048
+    G, tau, gc = 1e-3, 10000.0 / 3.0, 0.1
+    ch = orc.Channel(1, ny, 0.0, tau_lb=0.6, G=G, tau0=tau, gamma_c=gc, visc_split=0.5,
+                     nn_pressure=False, wall_velocity=U)
+    ch.run(30000)
+    pr = ch.profiles()
+    gdot = U / ny
+    want = U * (np.arange(ny) + 0.5) / ny
+    assert np.abs(pr["ux"] - want).max() / U < 1e-9
+    assert np.abs(pr["kxy"] - gdot).max() / gdot < 1e-9
+    tauM = 1.0 / (1.0 / tau + gdot / gc)
+    assert np.abs(pr["sxy"] - G * gdot * tauM).max() / (G * gdot * tauM) < 1e-9
+    assert np.abs(pr["sxx"] - pr["syy"] - 2 * G * gdot ** 2 * tauM ** 2).max() / (2 * G * gdot ** 2 * tauM ** 2) < 1e-9
