@@ -57,6 +57,17 @@
  *      wall-momentum term -2 a_i (c_i . u_w)/cs2 (rho_w = rho0 = 1), and the
  *      stencil ghost behind it is 2 u_w - u(ny-1). The paper's Couette runs
  *      used Zou and He's velocity boundary on a node row instead.
+ *   R10 pressure drive by generalised periodic boundaries (Sec. II.B): the
+ *      inlet pressure p+ = cs2 + dp/2 belongs to the virtual node x = -1
+ *      before the inlet column, the outlet pressure p- = cs2 - dp/2 to the
+ *      virtual node x = nx after the outlet column (mean density rho0 = 1),
+ *      so dp spans nx + 1 spacings: a pressure gradient G_p is dp =
+ *      (nx + 1) G_p, equivalent to a body force G_p. A population streaming from
+ *      the outlet into the inlet becomes n^eq(p+/cs2 + rho - rho_bar_out, j)
+ *      + (n* - n^eq(rho, j)), (rho, j) the moments of its source node and
+ *      rho_bar_out the mean density of the outlet column; the reverse
+ *      direction likewise with p- and the inlet column. With this drive the
+ *      forcing keeps its first line only (no body force, no delta rho).
  *
  * Lattice units: dx = dt = 1, rho0 = 1, c_s^2 = 1/3, d = 2.
  * Storage: populations n[i][y][x] (nine planes, x fastest), the previous
@@ -94,15 +105,18 @@ typedef struct {
   long long t_startup;
   int nn_pressure;  /* 1: keep the delta-rho terms of the forcing            */
   double uw;        /* x velocity of the top wall while t < t_startup (R9)   */
+  double dp;        /* pressure drop p+ - p- across the period (R10), 0: off */
 } orc_params;
 
 /* Parameter resolution (readings R7, R8). Returns 0, or -1 for invalid input. */
 int orc_resolve(double tau_lb, double G, double tau0, double gamma_c, double eps,
                 double lam, double g, long long t_startup, int nn_pressure, double uw,
-                orc_params *out) {
+                double dp, orc_params *out) {
   if (!(tau_lb > 0.5) || !(G >= 0) || !(tau0 > 0) || !(gamma_c > 0) ||
-      !(lam >= 0 && lam <= 1) || !isfinite(g) || !isfinite(eps) || !isfinite(uw))
+      !(lam >= 0 && lam <= 1) || !isfinite(g) || !isfinite(eps) || !isfinite(uw) || !isfinite(dp))
     return -1;
+  /* the pressure drive keeps the first line of Eq. (bodyforce) only */
+  if (dp != 0 && (g != 0 || nn_pressure || uw != 0)) return -1;
   double eta_s = (tau_lb - 0.5) / 3.0;
   double tau = tau0 * pow(10.0, fmin(eps, 0.0) / 0.05);
   double Ginf = G * (1.0 + sqrt(fmax(eps, 0.0)));
@@ -116,6 +130,7 @@ int orc_resolve(double tau_lb, double G, double tau0, double gamma_c, double eps
   out->t_startup = t_startup;
   out->nn_pressure = nn_pressure;
   out->uw = uw;
+  out->dp = dp;
   return 0;
 }
 
@@ -246,6 +261,18 @@ int orc_step(const orc_params *p, int nx, int ny, const double *n, const double 
   double uw = (t < p->t_startup) ? p->uw : 0.0;  /* top wall velocity at step t */
   double *utx = malloc(N * sizeof(double)), *uty = malloc(N * sizeof(double));
   int bad = 0;
+  /* pressure drive: mean density of the inlet (x = 0) and outlet (x = nx-1)
+   * columns; the collision keeps every node's density and momentum then */
+  double rbar_in = 0, rbar_out = 0;
+  if (p->dp != 0) {
+    for (int y = 0; y < ny; ++y)
+      for (int i = 0; i < 9; ++i) {
+        rbar_in += n[i * N + (size_t)y * nx];
+        rbar_out += n[i * N + (size_t)y * nx + nx - 1];
+      }
+    rbar_in /= ny;
+    rbar_out /= ny;
+  }
 
   /* Moments and the provisional velocity u~ = j / sum_i n_i of every node,
    * with j = m + f/2 (Eq. (rhoj), reading R2). */
@@ -341,6 +368,15 @@ int orc_step(const orc_params *p, int nx, int ny, const double *n, const double 
       for (int i = 0; i < 9; ++i) {
         double post = nn[i] - (nn[i] - neq[i]) / p->tau_eff + F[i];
         int xd = (x + CX[i] + nx) % nx, yd = y + CY[i];
+        if (p->dp != 0 && yd >= 0 && yd < ny && (x + CX[i] < 0 || x + CX[i] >= nx)) {
+          /* a link across the periodic boundary: equilibrium at the target
+           * end's density, the source's non-equilibrium part (R10) */
+          double target = (x == nx - 1) ? 1.0 + 1.5 * p->dp - rbar_out : 1.0 - 1.5 * p->dp - rbar_in;
+          double ea[9], eb[9];
+          orc_equilibrium(s + target, mx / (s + target), my / (s + target), ea);
+          orc_equilibrium(s, mx / s, my / s, eb);
+          post += ea[i] - eb[i];
+        }
         if (yd >= 0 && yd < ny)
           n_out[i * N + (size_t)yd * nx + xd] = post;
         else if (yd >= ny)

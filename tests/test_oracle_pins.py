@@ -451,3 +451,53 @@ def test_couette_nlm_steady(orc):
     tauM = 1.0 / (1.0 / tau + gdot / gc)
     assert np.abs(pr["sxy"] - G * gdot * tauM).max() / (G * gdot * tauM) < 1e-9
     assert np.abs(pr["sxx"] - pr["syy"] - 2 * G * gdot ** 2 * tauM ** 2).max() / (2 * G * gdot ** 2 * tauM ** 2) < 1e-9
+
+
+# ---- pressure drive by generalised periodic boundaries (reading R10)
+
+@pytest.mark.parametrize("G", [0.0, 1e-4])
+def test_pressure_drive_equals_body_force(orc, G):
+    """Sec. II.B: the pressure-driven channel (stress-only forcing) and the
+    body-force channel with g = G_p reach the same steady flow up to the
+    compressibility of the LB fluid (the relative density drop along the
+    channel, 3 G_p (nx + 1)); the flux is the same in every column, and the
+    density falls linearly along x with slope G_p / cs2 about the mean rho0
+    (to second order in the density drop)."""
+    nx, ny, grad, tau = 32, 16, 3e-7, 0.8
+    o = orc.Channel(nx, ny, 0.0, tau_lb=tau, G=G, tau0=1e3, gamma_c=0.1, nn_pressure=False,
+                    pressure_gradient=grad)
+    o.run(30000)
+    b = orc.Channel(1, ny, grad, tau_lb=tau, G=G, tau0=1e3, gamma_c=0.1, nn_pressure=False)
+    b.run(30000)
+    f = o.fields()
+    ub = b.profiles()["ux"]
+    drop = 3 * grad * (nx + 1)
+    assert np.abs(f["ux"] - ub[:, None]).max() / ub.max() < drop
+    flux = f["mx"].sum(axis=0)
+    assert (flux.max() - flux.min()) / flux.mean() < 1e-8
+    rho = f["s"].mean(axis=0)
+    slope = np.polyfit(np.arange(nx), rho, 1)[0]
+    assert slope == pytest.approx(-grad / CS2, rel=1e-6)
+    assert rho.mean() == pytest.approx(1.0, abs=drop ** 2)  # second order in the density drop
+
+
+def test_pressure_cuts(orc):
+    """Sec. IV.A, Fig. channelsigma (lower panel): with the pressure drive
+    the overall pressure changes along the channel, and on every cut at
+    constant x the normal-stress difference raises the pressure in the plug:
+    cs2 rho + N1/2 is uniform across y (up to the lattice error), while
+    cs2 rho varies by about N1/2. (The forcing carries the traceless stress,
+    whose yy component is -N1/2 in channel flow.)"""
+    nx, ny, grad = 16, 32, 2e-6
+    o = orc.Channel(nx, ny, 0.0, tau_lb=1.0, G=1e-4, tau0=2e3, gamma_c=0.1, nn_pressure=False,
+                    pressure_gradient=grad)
+    o.run(30000)
+    f = o.fields()
+    p = CS2 * f["s"]
+    n1 = f["sxx"] - f["syy"]
+    for x in (0, nx // 2, nx - 1):
+        tot = p[:, x] + n1[:, x] / 2
+        spread = n1[:, x].max() - n1[:, x].min()
+        assert p[:, x].max() - p[:, x].min() > 0.3 * spread / 2
+        assert tot.max() - tot.min() < 0.1 * spread / 2
+    assert p[:, 0].mean() - p[:, -1].mean() == pytest.approx(grad * (nx - 1), rel=1e-3)
