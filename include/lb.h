@@ -76,6 +76,16 @@ typedef enum {
  *              on the half link and reflects with the wall-momentum term
  *              -2 a_i (c_i . u_w) / c_s^2 (wall density rho0 = 1); |u_w| < 0.3
  *              (low Mach number). 0 gives two fixed walls.
+ *   pressure_gradient  pressure drop per unit length G_p along +x (the
+ *              problem statement's Delta p / L, equivalent to force = G_p)
+ *              imposed by generalised periodic boundaries (Sec. II.B): the
+ *              populations crossing the period take the equilibrium at the
+ *              far end's pressure, p+- = c_s^2 +- (nx + 1) G_p / 2 on the
+ *              virtual nodes beside the inlet (x = 0) and outlet
+ *              (x = nx - 1) columns, plus the source's non-equilibrium part;
+ *              acts for t < t_startup. Needs force = 0, wall_velocity = 0,
+ *              nx >= 2 and the options' nn_pressure = 0 (the forcing keeps
+ *              its first line only). 0: plain periodic x.
  */
 typedef struct {
   int32_t nx;
@@ -89,6 +99,7 @@ typedef struct {
   double visc_split;
   int64_t t_startup;
   double wall_velocity;
+  double pressure_gradient;
 } lb_channel;
 
 /*

@@ -68,6 +68,8 @@
  *      rho_bar_out the mean density of the outlet column; the reverse
  *      direction likewise with p- and the inlet column. With this drive the
  *      forcing keeps its first line only (no body force, no delta rho).
+ *      The drop acts for t < t_startup; afterwards the same boundaries hold
+ *      both ends at rho0 (cessation).
  *
  * Lattice units: dx = dt = 1, rho0 = 1, c_s^2 = 1/3, d = 2.
  * Storage: populations n[i][y][x] (nine planes, x fastest), the previous
@@ -371,7 +373,8 @@ int orc_step(const orc_params *p, int nx, int ny, const double *n, const double 
         if (p->dp != 0 && yd >= 0 && yd < ny && (x + CX[i] < 0 || x + CX[i] >= nx)) {
           /* a link across the periodic boundary: equilibrium at the target
            * end's density, the source's non-equilibrium part (R10) */
-          double target = (x == nx - 1) ? 1.0 + 1.5 * p->dp - rbar_out : 1.0 - 1.5 * p->dp - rbar_in;
+          double dpn = (t < p->t_startup) ? p->dp : 0.0;  /* on for t < t_startup */
+          double target = (x == nx - 1) ? 1.0 + 1.5 * dpn - rbar_out : 1.0 - 1.5 * dpn - rbar_in;
           double ea[9], eb[9];
           orc_equilibrium(s + target, mx / (s + target), my / (s + target), ea);
           orc_equilibrium(s, mx / s, my / s, eb);

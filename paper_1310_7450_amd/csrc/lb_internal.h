@@ -42,6 +42,8 @@ struct ChanDev {
   double inv_gc;        // 1/gamma_c
   double lgt;           // lambda G_inf tau
   double uw;            // top wall x velocity while t < t_startup
+  double pd;            // pressure drive: p+ - p- = (nx + 1) G_p while t < t_startup
+  int gpbc;             // generalised periodic boundaries in x
 };
 
 // Work unit of one wavefront: rows [y0, y1) of channel ch, starting at
@@ -109,5 +111,6 @@ hipError_t launch_reduce(const ChanDev *ch, int n_ch, const double *part, double
                          double *prev_ux, double *scal, int update_residual, int steps_since,
                          hipStream_t s);
 hipError_t launch_advance(ChanDev *ch, int n_ch, int steps, hipStream_t s);
+hipError_t launch_gpbc(int fp32, void *B, const ChanDev *ch, int n_ch, int k, hipStream_t s);
 
 }  // namespace lbnlm

@@ -1054,6 +1054,76 @@ __global__ void __launch_bounds__(256) reduce_kernel(const ChanDev *ch, const do
   }
 }
 
+// Generalised periodic boundaries (Sec. II.B), applied to the state a step
+// has just written: a population that the next pull carries across the
+// period (+x out of the outlet column x = nx-1 into the inlet, -x out of the
+// inlet column into the outlet) becomes the equilibrium at the far end's
+// density plus its own non-equilibrium part. With the moments (rho, j) of its
+// source node, a density shift d = p+-/cs2 - mean column density adds
+// a_i [d + (4.5 (c.j)^2 - 1.5 j^2) (1/(rho + d) - 1/rho)]. Diagonal links
+// that meet a wall are reflected, not carried, and stay. One workgroup per
+// channel; the column means are taken before anything is changed.
+template <typename T, bool SHIFT>
+__global__ void __launch_bounds__(256) gpbc_kernel(T *B, const ChanDev *ch, int k) {
+  const ChanDev c = ch[blockIdx.x];
+  if (!c.gpbc || !c.active) return;
+  const long long t = c.t + k;
+  const double dp = (t < c.t_startup) ? c.pd : 0.0;
+  const int nx = c.nx, ny = c.ny;
+  auto node = [&](int x, int y) -> long long { return c.off + (long long)y * nx + x; };
+  auto load9 = [&](long long n, double f[9], double &rho, double &jx, double &jy) {
+    double s = 0;
+    jx = jy = 0;
+    for (int i = 0; i < 9; ++i) {
+      f[i] = (double)B[slot(i, n)];
+      s += f[i];
+    }
+    jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    rho = SHIFT ? 1.0 + s : s;
+  };
+  __shared__ double red[2][256];
+  double si = 0, so = 0;
+  for (int y = threadIdx.x; y < ny; y += blockDim.x) {
+    double f[9], r, jx, jy;
+    load9(node(0, y), f, r, jx, jy);
+    si += r;
+    load9(node(nx - 1, y), f, r, jx, jy);
+    so += r;
+  }
+  red[0][threadIdx.x] = si;
+  red[1][threadIdx.x] = so;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + st];
+      red[1][threadIdx.x] += red[1][threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  const double d_in = 1.0 + 1.5 * dp - red[1][0] / ny;   // links entering the inlet
+  const double d_out = 1.0 - 1.5 * dp - red[0][0] / ny;  // links entering the outlet
+  auto fix = [&](long long n, double d, int i0, int i1, int i2, int y) {
+    double f[9], r, jx, jy;
+    load9(n, f, r, jx, jy);
+    const double j2 = jx * jx + jy * jy, w = 1.0 / (r + d) - 1.0 / r;
+    const int ids[3] = {i0, i1, i2};
+    for (int q = 0; q < 3; ++q) {
+      const int i = ids[q];
+      const int cy = (i == 5 || i == 6) ? 1 : ((i == 7 || i == 8) ? -1 : 0);
+      if (y + cy < 0 || y + cy >= ny) continue;  // met a wall: reflected
+      const double cx = (i == 1 || i == 5 || i == 8) ? 1.0 : -1.0;
+      const double cj = cx * jx + cy * jy;
+      const double a = (i < 5) ? 1.0 / 9.0 : 1.0 / 36.0;
+      B[slot(i, n)] = (T)(f[i] + a * (d + (4.5 * cj * cj - 1.5 * j2) * w));
+    }
+  };
+  for (int y = threadIdx.x; y < ny; y += blockDim.x) {
+    fix(node(nx - 1, y), d_in, 1, 5, 8, y);
+    fix(node(0, y), d_out, 3, 6, 7, y);
+  }
+}
+
 __global__ void advance_kernel(ChanDev *ch, int n_ch, int steps) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_ch && ch[i].active) ch[i].t += steps;
@@ -1126,6 +1196,16 @@ hipError_t launch_reduce(const ChanDev *ch, int n_ch, const double *part, double
   if (n_ch == 0) return hipSuccess;
   hipLaunchKernelGGL(reduce_kernel, dim3(n_ch), dim3(256), 0, s, ch, part, prof, prev_ux, scal,
                      update_residual, steps_since);
+  return hipGetLastError();
+}
+
+hipError_t launch_gpbc(int fp32, void *B, const ChanDev *ch, int n_ch, int k, hipStream_t s) {
+  if (n_ch == 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL((gpbc_kernel<float, true>), dim3(n_ch), dim3(256), 0, s, static_cast<float *>(B), ch, k);
+  else
+    hipLaunchKernelGGL((gpbc_kernel<double, false>), dim3(n_ch), dim3(256), 0, s, static_cast<double *>(B), ch,
+                       k);
   return hipGetLastError();
 }
 

@@ -71,6 +71,9 @@ std::string validate(const lb_channel *c, int n, const lb_options *o) {
     if (!(q.visc_split >= 0 && q.visc_split <= 1)) return bad("visc_split must be in [0,1]");
     if (q.visc_split > 0 && std::isinf(q.tau0)) return bad("visc_split > 0 needs a finite tau0");
     if (!(std::fabs(q.wall_velocity) < 0.3)) return bad("wall_velocity must be finite with |u_w| < 0.3");
+    if (!std::isfinite(q.pressure_gradient)) return bad("pressure_gradient must be finite");
+    if (q.pressure_gradient != 0 && (q.force != 0 || q.wall_velocity != 0 || q.nx < 2 || o->nn_pressure))
+      return bad("pressure_gradient needs force = 0, wall_velocity = 0, nx >= 2 and nn_pressure = 0");
   }
   return "";
 }
@@ -96,6 +99,8 @@ void resolve(const lb_channel &q, ChanDev &d) {
   d.inv_gc = 1.0 / q.gamma_c;
   d.lgt = lgt;
   d.uw = q.wall_velocity;
+  d.gpbc = q.pressure_gradient != 0;
+  d.pd = (q.nx + 1) * q.pressure_gradient;
 }
 
 // Term the pull adds to population i of a top-row node at step t: the link
@@ -203,6 +208,7 @@ struct lb_handle {
   std::vector<long long> t;  // host mirror of every channel's step
   std::vector<int> active;
   int n_checks = 0;
+  bool any_gpbc = false;     // some channel has the pressure drive
   std::string err;
 };
 
@@ -295,6 +301,10 @@ lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s) {
     a.down = (src == 1);
     HIPCHECK(h, launch_sweep(h->opt.precision == LB_FP32_SHIFTED, c, false, a, s));
   }
+  // generalised periodic boundaries: the inlet/outlet column pass on the
+  // state just written
+  if (h->any_gpbc)
+    HIPCHECK(h, launch_gpbc(h->opt.precision == LB_FP32_SHIFTED, h->buf[src ^ 1], h->dch, h->n_ch, k, s));
   return LB_OK;
 }
 
@@ -439,6 +449,7 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
   }
   h->opt = *o;
   h->n_ch = n;
+  for (int i = 0; i < n; ++i) h->any_gpbc = h->any_gpbc || h->L.ch[i].gpbc;
   h->K = o->obs_every > 0 ? o->obs_every : kDefaultK;
   h->in.assign(c, c + n);
   h->ws = static_cast<char *>(ws);

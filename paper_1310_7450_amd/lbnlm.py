@@ -34,7 +34,8 @@ ABI_FUNCTIONS = ["lb_workspace_bytes", "lb_create", "lb_destroy", "lb_step", "lb
 class LbChannel(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("force", C.c_double), ("tau_lb", C.c_double),
                 ("G", C.c_double), ("tau0", C.c_double), ("gamma_c", C.c_double), ("eps", C.c_double),
-                ("visc_split", C.c_double), ("t_startup", C.c_int64), ("wall_velocity", C.c_double)]
+                ("visc_split", C.c_double), ("t_startup", C.c_int64), ("wall_velocity", C.c_double),
+                ("pressure_gradient", C.c_double)]
 
 
 class LbOptions(C.Structure):
@@ -93,11 +94,12 @@ class ChannelSpec:
     visc_split: float = 0.0
     t_startup: int = 2 ** 62
     wall_velocity: float = 0.0
+    pressure_gradient: float = 0.0
 
     def to_c(self):
         return LbChannel(int(self.nx), int(self.ny), float(self.force), float(self.tau_lb), float(self.G),
                          float(self.tau0), float(self.gamma_c), float(self.eps), float(self.visc_split),
-                         int(self.t_startup), float(self.wall_velocity))
+                         int(self.t_startup), float(self.wall_velocity), float(self.pressure_gradient))
 
 
 def _dp(a):

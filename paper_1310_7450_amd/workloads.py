@@ -148,3 +148,26 @@ def couette_64(nx=8, ny=64, theta=100.0, tau_lb=0.6, G=1e-3, gamma_c=0.1, wall_u
                        wall_velocity=u0)
     return {"name": f"couette_{nx}x{ny}" + ("_newtonian" if newtonian else ""), "channels": [spec],
             "startup": startup, "cessation": 10000, "nn_pressure": False, "theta": theta}
+
+
+def pressure_channel(nx=64, ny=32, pressure_gradient=2e-6, tau_lb=1.0, G=1e-4, tau0=2e3, gamma_c=0.1,
+                     startup=2 ** 62):
+    """A channel driven by a pressure drop instead of a body force: the
+    generalised periodic boundaries impose G_p = ``pressure_gradient``
+    (equivalent to force = G_p), the forcing keeps its stress line only
+    (``nn_pressure = 0`` on the handle). G tau = 0.2 keeps the explicit
+    stress well conditioned. Start from ``linear_density_state``."""
+    spec = ChannelSpec(nx=nx, ny=ny, force=0.0, tau_lb=tau_lb, G=G, tau0=tau0, gamma_c=gamma_c, eps=0.0,
+                       visc_split=0.0, t_startup=startup, pressure_gradient=pressure_gradient)
+    return {"name": f"pressure_channel_{nx}x{ny}", "channels": [spec], "nn_pressure": False}
+
+
+def linear_density_state(spec):
+    """Rest populations with the density falling linearly along x at the
+    slope of the imposed pressure gradient, rho(x) = 1 + 3 G_p ((nx-1)/2 - x)
+    (the switch-on pre-initialisation of Sec. II.B, which avoids the
+    pressure wave of a sudden jump), and P = 0; layout of lb_get_state."""
+    x = np.arange(spec.nx)
+    rho = 1.0 + 3.0 * spec.pressure_gradient * ((spec.nx - 1) / 2.0 - x)
+    pops = REST_WEIGHTS[:, None, None] * np.broadcast_to(rho[None, None, :], (9, spec.ny, spec.nx))
+    return np.ascontiguousarray(pops), np.zeros((spec.ny, spec.nx))
