@@ -44,8 +44,13 @@ typedef enum {
 
 typedef enum {
   LB_FP64 = 0,          /* populations stored and updated in FP64             */
-  LB_FP32_SHIFTED = 1   /* populations stored in FP32 as n_i - a_i (a_i the   */
-                        /* rest weights); moments and updates in FP32         */
+  LB_FP32_SHIFTED = 1   /* populations stored in FP32 as n_i - a_i - E_i(U_y):*/
+                        /* a_i the rest weights, E_i(u) = a_i (3 c_ix u +      */
+                        /* (9/2 c_ix^2 - 3/2) u^2) the velocity part of the    */
+                        /* equilibrium at density 1 and U_y a per-row          */
+                        /* reference velocity, moved to the row's mean u_x at */
+                        /* every block boundary (see lb_step) and at          */
+                        /* lb_set_state; moments and updates in FP32          */
 } lb_precision;
 
 /*
@@ -108,8 +113,9 @@ typedef struct {
  *   nn_pressure  1: full forcing of Eq. (bodyforce) including the
  *                flow-induced density terms of Eq. (rhoplus); 0: those terms
  *                are dropped (dt d(delta rho)/dt = 0);
- *   obs_every    K, steps between convergence checks and the length of one
- *                captured graph; even, >= 2 (default 1000 when 0);
+ *   obs_every    K, the length of one block of steps (one captured graph);
+ *                the convergence check and the FP32 reference move run at
+ *                the block boundaries; even, >= 2 (default 1000 when 0);
  *   strip_rows   rows per wavefront strip of the sweep (0: tuned default);
  *   steady_tol   if > 0, lb_step checks every K steps the residual
  *                R = max_y |ubar(t) - ubar(t-K)| / (K max_y |ubar(t)|) of the
@@ -170,7 +176,10 @@ lb_status lb_destroy(lb_handle *h);
 /* Advances every active channel by up to n_steps steps, asynchronously on the
  * handle's stream, except that with steady_tol > 0 it synchronises every K
  * steps to read the residuals; returns when all channels are frozen or
- * n_steps are done. LB_EUNSTABLE if a check saw NaN/Inf. */
+ * n_steps are done. LB_EUNSTABLE if a check saw NaN/Inf. Block boundaries
+ * fall every K steps of a clock the handle keeps over all lb_step calls, so
+ * that splitting n steps over several calls gives the same state, bit for
+ * bit, as one call. */
 lb_status lb_step(lb_handle *h, int64_t n_steps);
 
 /* Reads one observable of channel ch at its current step into host_out

@@ -65,6 +65,7 @@ struct SweepArgs {
   int nnp;              // keep the flow-induced density terms
   int nt;               // store the new state with nontemporal hints
   int down;             // march the strips downwards (vector sweep)
+  const float *uref;    // FP32: reference velocity of every row (all channels)
 };
 // A state buffer larger than this is written with nontemporal stores: it
 // cannot stay in the 256 MB last-level cache (MALL) until the next step reads
@@ -108,9 +109,11 @@ inline int strip_cols(int cls, int esize) { return cls == kVecClass ? 64 * vec_n
 // Host launchers (defined in lb_kernels.hip).
 hipError_t launch_sweep(int fp32, int cls, bool observe, const SweepArgs &a, hipStream_t s);
 hipError_t launch_reduce(const ChanDev *ch, int n_ch, const double *part, double *prof,
-                         double *prev_ux, double *scal, int update_residual, int steps_since,
-                         hipStream_t s);
+                         double *prev_ux, double *scal, const float *uref, int update_residual,
+                         int steps_since, hipStream_t s);
 hipError_t launch_advance(ChanDev *ch, int n_ch, int steps, hipStream_t s);
-hipError_t launch_gpbc(int fp32, void *B, const ChanDev *ch, int n_ch, int k, hipStream_t s);
+hipError_t launch_gpbc(int fp32, void *B, const ChanDev *ch, int n_ch, int k, const float *uref, hipStream_t s);
+hipError_t launch_rereference(float *A, const ChanDev *ch, int n_ch, int total_rows, const double *prof,
+                              float *uref, hipStream_t s);
 
 }  // namespace lbnlm

@@ -142,10 +142,45 @@ __device__ __forceinline__ U2<T> shfl2(U2<T> v, int src) {
 
 // Provisional velocity u~ = (m + f/2) / sum_i n_i (reading R2 of the design
 // notes: the stencil uses the velocity before the flow-induced density).
+// With SHIFT the populations are stored relative to the equilibrium at the
+// row's reference velocity (ur, 0), mx is the momentum beyond ur and the x
+// component returned is u~_x - ur, kept small so that FP32 resolves it.
+// No fused multiply-adds here or in the two helpers below: the nodes of a row
+// and the halo columns beside a strip take these terms through differently
+// shared code and must still round them identically (an x-uniform state
+// stays exactly x-uniform).
 template <typename T, bool SHIFT>
-__device__ __forceinline__ U2<T> u_tilde(T sd, T mx, T my, T fx) {
+__device__ __forceinline__ U2<T> u_tilde(T sd, T mx, T my, T fx, T ur) {
+#pragma clang fp contract(off)
   const T inv = recip<T>(SHIFT ? T(1) + sd : sd);
+  if constexpr (SHIFT) return U2<T>{(mx + T(0.5) * fx - ur * sd) * inv, my * inv};
   return U2<T>{(mx + T(0.5) * fx) * inv, my * inv};
+}
+
+// FP32 storage: a population emitted by a node of row y is stored as
+// n_i - a_i - E_i(ur_y), E_i(u) = a_i (3 c_ix u + (4.5 c_ix^2 - 1.5) u^2) the
+// equilibrium excess at density 1 and velocity (u, 0). A value pulled from
+// row y' != y therefore changes by E_i(ur_y') - E_i(ur_y); one reflected at a
+// wall comes from the same node's opposite population and changes by
+// E_opp(ur_y) - E_i(ur_y) = -6 a_i c_ix ur_y. Both are formed from
+// differences, so the small stored values stay exact to FP32 rounding.
+template <typename T>
+__device__ __forceinline__ T ref_shift(T a, T cx, T us, T ud) {
+#pragma clang fp contract(off)
+  return a * (us - ud) * (T(3) * cx + (T(4.5) * cx * cx - T(1.5)) * (us + ud));
+}
+template <typename T>
+__device__ __forceinline__ void to_row_reference(T f[9], T urd, T urc, T uru, bool bot, bool top) {
+#pragma clang fp contract(off)
+  constexpr T w1 = T(1.0 / 9.0), w5 = T(1.0 / 36.0);
+  // from below (c_y = +1): 2 (c_x 0), 5 (+1), 6 (-1)
+  f[2] += bot ? T(0) : ref_shift(w1, T(0), urd, urc);
+  f[5] += bot ? -urc * T(1.0 / 6.0) : ref_shift(w5, T(1), urd, urc);
+  f[6] += bot ? urc * T(1.0 / 6.0) : ref_shift(w5, T(-1), urd, urc);
+  // from above (c_y = -1): 4 (0), 7 (-1), 8 (+1)
+  f[4] += top ? T(0) : ref_shift(w1, T(0), uru, urc);
+  f[7] += top ? urc * T(1.0 / 6.0) : ref_shift(w5, T(-1), uru, urc);
+  f[8] += top ? -urc * T(1.0 / 6.0) : ref_shift(w5, T(1), uru, urc);
 }
 
 // Wave-wide sum over a lane group of width GW (power of two).
@@ -172,13 +207,17 @@ struct Coef {
 // the density and velocity of Eq. (rhoj), and either the post-collision
 // populations (equilibrium, forcing of Eq. (bodyforce), BGK) or the
 // observables of the node.
+// With SHIFT, f are stored relative to the row's reference (ur, 0), mx is
+// the momentum beyond ur, the velocities lf, rt, dn, up carry u~_x minus
+// their own row's reference, and kref = (ur_above - ur_below)/2 restores the
+// reference's share of d_y u_x; the outputs are stored relative to ur.
 template <typename T, bool SHIFT, bool OBS>
 __device__ __forceinline__ void node_update(const T f[9], T sd, T mx, T my, T Pc, T fx, U2<T> lf,
-                                            U2<T> rt, U2<T> dn, U2<T> up, const Coef<T> &q,
+                                            U2<T> rt, U2<T> dn, U2<T> up, T ur, T kref, const Coef<T> &q,
                                             int nnp, T out[9], T &trT_out, double obs[OF_COUNT]) {
   // velocity gradient kappa_ab = d_b u_a
   const T kxx = T(0.5) * (rt.x - lf.x);
-  const T kxy = T(0.5) * (up.x - dn.x);
+  const T kxy = T(0.5) * (up.x - dn.x) + kref;
   const T kyx = T(0.5) * (rt.y - lf.y);
   const T kyy = T(0.5) * (up.y - dn.y);
 
@@ -221,11 +260,15 @@ __device__ __forceinline__ void node_update(const T f[9], T sd, T mx, T my, T Pc
   const T rho_dev = sdev + T(0.5) * rr;
   const T rho_e = SHIFT ? T(1) + rho_dev : sd + T(0.5) * rr;
   const T irho = recip<T>(rho_e);
-  const T ux = jx * irho, uy = jy * irho;
+  // SHIFT: jx is j_x - ur, so u_x - ur = (jx - ur rho_dev) / rho_e
+  const T dux = (SHIFT ? jx - ur * rho_dev : jx) * irho;
+  const T ux = SHIFT ? ur + dux : dux, uy = jy * irho;
   trT_out = trT;
 
   if constexpr (OBS) {
-    obs[OF_UX] = (double)ux;
+    // SHIFT: u_x - ur and j_x - ur; the reduction adds ur once per row, so
+    // that row sums of equal values stay exact in any summation order
+    obs[OF_UX] = SHIFT ? (double)dux : (double)ux;
     obs[OF_UY] = (double)uy;
     obs[OF_SXX] = (double)sxx;
     obs[OF_SXY] = (double)sxy;
@@ -244,41 +287,56 @@ __device__ __forceinline__ void node_update(const T f[9], T sd, T mx, T my, T Pc
     const T usq = ux * ux + uy * uy;
     const T uf = ux * fx;
     const T K0 = q.kf * (rr + T(1.5) * rr * usq - T(3) * uf);
-    const T eq0 = SHIFT ? (rho_dev - T(1.5) * rho_e * usq) : rho_e * (T(1) - T(1.5) * usq);
     const T om1 = T(1) - q.om;
-    const T C0 = q.om * eq0 + K0;                      // constant part
-    const T Acu2 = T(4.5) * (q.om * rho_e - q.kf * rr); // coefficient of (c.u)^2
-    const T Bcu = T(3) * q.om * rho_e;                 // coefficient of (c.u), odd
-    const T Ccf = T(3) * q.kf * fx;                    // 3 kf (c.f) for c_x = 1, odd
-    const T Dcf = T(9) * q.kf * fx;                    // 9 kf (c.u)(c.f) for c_x = 1, even
+    // Equilibrium excess n^eq_i - a_i (- E_i(ur) with SHIFT). SHIFT expands it
+    // around the reference so that only small differences are rounded:
+    // a_i [rho_dev (1 + 3 cu + 4.5 cu^2 - 1.5 u^2) + 3 c.du + 4.5 (c.du)(c.(u+ur))
+    //      - 1.5 du.(u + ur)], du = u - (ur, 0); with ur = 0 it is the plain
+    // shifted form.
+    T C0, Acu2, Bcu;
+    if constexpr (SHIFT) {
+      const T mix = dux * (ux + ur) + uy * uy;  // du.(u + ur)
+      C0 = q.om * (rho_dev * (T(1) - T(1.5) * usq) - T(1.5) * mix) + K0;
+      Acu2 = T(4.5) * (q.om * rho_dev - q.kf * rr);
+      Bcu = T(3) * q.om * rho_dev;
+    } else {
+      C0 = q.om * rho_e * (T(1) - T(1.5) * usq) + K0;  // constant part
+      Acu2 = T(4.5) * (q.om * rho_e - q.kf * rr);      // coefficient of (c.u)^2
+      Bcu = T(3) * q.om * rho_e;                       // coefficient of (c.u), odd
+    }
+    const T E4 = SHIFT ? T(4.5) * q.om : T(0);  // (c.du)(c.(u+ur)), even
+    const T B3 = SHIFT ? T(3) * q.om : T(0);    // c.du, odd
+    const T Ccf = T(3) * q.kf * fx;             // 3 kf (c.f) for c_x = 1, odd
+    const T Dcf = T(9) * q.kf * fx;             // 9 kf (c.u)(c.f) for c_x = 1, even
     const T spS = q.sp * Sxx, spT = T(2) * q.sp * Txy;
+    const T usx = ux + ur;                      // (u + ur)_x (ur = 0 without SHIFT)
     constexpr T w0 = weight<T>(0), w1 = weight<T>(1), w5 = weight<T>(5);
     out[0] = om1 * f[0] + w0 * C0;
     {  // (1,0) and (-1,0): c.u = ux, c.f = fx, stress term Sxx
-      const T cu = ux;
-      const T ev = w1 * (C0 + Acu2 * cu * cu + spS + Dcf * cu);
-      const T od = w1 * (Bcu * cu + Ccf);
+      const T cu = ux, cdu = dux, cs = usx;
+      const T ev = w1 * (C0 + Acu2 * cu * cu + E4 * cdu * cs + spS + Dcf * cu);
+      const T od = w1 * (Bcu * cu + B3 * cdu + Ccf);
       out[1] = om1 * f[1] + ev + od;
       out[3] = om1 * f[3] + ev - od;
     }
     {  // (0,1) and (0,-1): c.u = uy, c.f = 0, stress term -Sxx
       const T cu = uy;
-      const T ev = w1 * (C0 + Acu2 * cu * cu - spS);
-      const T od = w1 * (Bcu * cu);
+      const T ev = w1 * (C0 + Acu2 * cu * cu + E4 * cu * cu - spS);
+      const T od = w1 * (Bcu * cu + B3 * cu);
       out[2] = om1 * f[2] + ev + od;
       out[4] = om1 * f[4] + ev - od;
     }
     {  // (1,1) and (-1,-1): c.u = ux + uy, c.f = fx, stress term 2 Sxy
-      const T cu = ux + uy;
-      const T ev = w5 * (C0 + Acu2 * cu * cu + spT + Dcf * cu);
-      const T od = w5 * (Bcu * cu + Ccf);
+      const T cu = ux + uy, cdu = dux + uy, cs = usx + uy;
+      const T ev = w5 * (C0 + Acu2 * cu * cu + E4 * cdu * cs + spT + Dcf * cu);
+      const T od = w5 * (Bcu * cu + B3 * cdu + Ccf);
       out[5] = om1 * f[5] + ev + od;
       out[7] = om1 * f[7] + ev - od;
     }
     {  // (-1,1) and (1,-1): c.u = uy - ux, c.f = -fx, stress term -2 Sxy
-      const T cu = uy - ux;
-      const T ev = w5 * (C0 + Acu2 * cu * cu - spT - Dcf * cu);
-      const T od = w5 * (Bcu * cu - Ccf);
+      const T cu = uy - ux, cdu = uy - dux, cs = uy - usx;
+      const T ev = w5 * (C0 + Acu2 * cu * cu + E4 * cdu * cs - spT - Dcf * cu);
+      const T od = w5 * (Bcu * cu + B3 * cdu - Ccf);
       out[6] = om1 * f[6] + ev + od;
       out[8] = om1 * f[8] + ev - od;
     }
@@ -287,6 +345,9 @@ __device__ __forceinline__ void node_update(const T f[9], T sd, T mx, T my, T Pc
 
 // Momentum handed to the walls in the previous step: the reflected
 // populations sit in the wall rows with the opposite velocity.
+// With the FP32 reference ur the pulled values are n_i - a_i - E_i(ur), and
+// n6 - n5 = f6 - f5 - ur/6, n7 - n8 = f7 - f8 - ur/6; the -ur/3 of each wall
+// node is added per row in the reduction.
 template <typename T>
 __device__ __forceinline__ double wall_drag(const T f[9], int y, int ny, T uw6) {
   double d = 0.0;
@@ -349,41 +410,51 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
   const long long base = c.off;
 
   auto clampy = [&](int y) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
-  auto pull_row = [&](int y, T f[9], T &Pv) {
+  // FP32 reference velocity of row y (0 in FP64)
+  auto ref = [&](int y) -> T {
+    if constexpr (SHIFT) return a.uref[c.row_off + clampy(y)];
+    return T(0);
+  };
+  // pulled populations of row y relative to that row's reference ur
+  auto pull_row = [&](int y, T f[9], T &Pv, T &ur) {
     const int yc = clampy(y);
     const long long row = base + (long long)yc * nx;
     pull<T>(A, row, nx, ny, x, yc, uw6, f);
     Pv = A[slot(9, row + x)];
+    ur = ref(yc);
+    if constexpr (SHIFT) to_row_reference(f, ref(yc - 1), ur, ref(yc + 1), yc == 0, yc == ny - 1);
   };
   auto halo_u = [&](int y) -> U2<T> {
     const int yc = clampy(y);
     T f[9], sd, mx, my;
     pull<T>(A, base + (long long)yc * nx, nx, ny, hx, yc, uw6, f);
+    const T ur = ref(yc);
+    if constexpr (SHIFT) to_row_reference(f, ref(yc - 1), ur, ref(yc + 1), yc == 0, yc == ny - 1);
     moments<T>(f, sd, mx, my);
-    return u_tilde<T, SHIFT>(sd, mx, my, fx);
+    return u_tilde<T, SHIFT>(sd, mx, my, fx, ur);
   };
 
-  T fc[9], fn[9], Pc, Pn;
+  T fc[9], fn[9], Pc, Pn, urc, urn;
   U2<T> uPrev, uCur, uNext, uhCur = {T(0), T(0)}, uhNext = {T(0), T(0)};
   {
-    T ftmp[9], Ptmp, sd, mx, my;
-    pull_row(st.y0 - TYW + ly, ftmp, Ptmp);
+    T ftmp[9], Ptmp, sd, mx, my, urp;
+    pull_row(st.y0 - TYW + ly, ftmp, Ptmp, urp);
     moments<T>(ftmp, sd, mx, my);
-    uPrev = u_tilde<T, SHIFT>(sd, mx, my, fx);
+    uPrev = u_tilde<T, SHIFT>(sd, mx, my, fx, urp);
   }
   T sdc, mxc, myc;
-  pull_row(st.y0 + ly, fc, Pc);
+  pull_row(st.y0 + ly, fc, Pc, urc);
   moments<T>(fc, sdc, mxc, myc);
-  uCur = u_tilde<T, SHIFT>(sdc, mxc, myc, fx);
+  uCur = u_tilde<T, SHIFT>(sdc, mxc, myc, fx, urc);
   if (WIDE) uhCur = halo_u(st.y0);
 
 #pragma unroll 1
   for (int yb = st.y0; yb < st.y1; yb += TYW) {
     T sdn, mxn, myn;
-    pull_row(yb + TYW + ly, fn, Pn);
+    pull_row(yb + TYW + ly, fn, Pn, urn);
     if (WIDE) uhNext = halo_u(yb + TYW);
     moments<T>(fn, sdn, mxn, myn);
-    uNext = u_tilde<T, SHIFT>(sdn, mxn, myn, fx);
+    uNext = u_tilde<T, SHIFT>(sdn, mxn, myn, fx, urn);
     const int y = yb + ly;
 
     U2<T> dn, up;
@@ -405,16 +476,24 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
       if (lane == 0) lf = hl;
       if (lane == 63) rt = hr;
     }
-    // no-slip ghosts behind the half-way walls
+    // no-slip ghosts behind the half-way walls, u~(-1) = -u~(0) and
+    // u~(ny) = 2 u_w - u~(ny-1); with SHIFT the ghost rows take the mirrored
+    // references -ur and 2 u_w - ur, so their deltas are just mirrored
     if (y == 0) dn = U2<T>{-uCur.x, -uCur.y};
-    if (y == ny - 1) up = U2<T>{T(2) * uwg - uCur.x, -uCur.y};
+    if (y == ny - 1) up = U2<T>{(SHIFT ? T(0) : T(2) * uwg) - uCur.x, -uCur.y};
+    T kref = T(0);
+    if constexpr (SHIFT) {
+      const T urd = (y == 0) ? -urc : ref(y - 1);
+      const T uru = (y >= ny - 1) ? T(2) * uwg - urc : ref(y + 1);
+      kref = T(0.5) * (uru - urd);
+    }
 
     // Every lane computes; only valid lanes store. Lanes past the strip or
     // outside the channel read clamped rows and their results are dropped.
     const bool ok = (y < st.y1) && colok;
     T out[9], trT;
     double obs[OF_COUNT];
-    node_update<T, SHIFT, OBS>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, q, a.nnp, out, trT, obs);
+    node_update<T, SHIFT, OBS>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, urc, kref, q, a.nnp, out, trT, obs);
     if constexpr (OBS) {
       obs[OF_DRAG] = wall_drag<T>(fc, y, ny, uw6);
       constexpr int GW = WIDE ? 64 : TXW;
@@ -439,6 +518,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
     uPrev = uCur;
     uCur = uNext;
     uhCur = uhNext;
+    urc = urn;
 #pragma unroll
     for (int i = 0; i < 9; ++i) fc[i] = fn[i];
     Pc = Pn;
@@ -487,6 +567,11 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
   const cptr Ac = (cptr)(A);
   auto ld = [&](long long tl, int col, int p) -> T { return Ac[(tl * kPlanes + p) * F + col]; };
   auto run = [&](long long tl, int p) -> T { return A[(tl * kPlanes + p) * F + lane]; };
+  // FP32 reference velocity of row y (0 in FP64), rows clamped to the channel
+  auto ref = [&](int y) -> T {
+    if constexpr (SHIFT) return a.uref[c.row_off + (y < 0 ? 0 : (y >= ny ? ny - 1 : y))];
+    return T(0);
+  };
 
   // Pull of row y (0 <= y < ny) for every lane from aligned runs of the
   // strip's own tiles; the x-shifted directions are lane shifts whose edge
@@ -516,6 +601,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
       f[7] = shift_down(ld(tu + dr, 0, 7), run(tu, 7));
       f[8] = shift_up(ld(tu + dl, 63, 8), run(tu, 8));
     }
+    if constexpr (SHIFT) to_row_reference(f, ref(y - 1), ref(y), ref(y + 1), bot, top);
   };
   // u~ of the column left of the strip (column 63 of the left tile) and of
   // the column right of it (column 0 of the right tile), from wave-uniform
@@ -562,11 +648,16 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
       b[7] = ld(tu + dr, 1, 7);
       b[8] = ld(tu, 63, 8);
     }
+    const T urc = ref(y);
+    if constexpr (SHIFT) {
+      to_row_reference(a, ref(y - 1), urc, ref(y + 1), bot, top);
+      to_row_reference(b, ref(y - 1), urc, ref(y + 1), bot, top);
+    }
     T sd, mx, my;
     moments<T>(a, sd, mx, my);
-    uL = u_tilde<T, SHIFT>(sd, mx, my, fx);
+    uL = u_tilde<T, SHIFT>(sd, mx, my, fx, urc);
     moments<T>(b, sd, mx, my);
-    uR = u_tilde<T, SHIFT>(sd, mx, my, fx);
+    uR = u_tilde<T, SHIFT>(sd, mx, my, fx, urc);
   };
   auto clampy = [&](int y) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
 
@@ -576,12 +667,12 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
     T ftmp[9], Ptmp, sd, mx, my;
     pull_row(clampy(st.y0 - 1), ftmp, Ptmp);
     moments<T>(ftmp, sd, mx, my);
-    uPrev = u_tilde<T, SHIFT>(sd, mx, my, fx);
+    uPrev = u_tilde<T, SHIFT>(sd, mx, my, fx, ref(st.y0 - 1));
   }
   T sdc, mxc, myc;
   pull_row(st.y0, fc, Pc);
   moments<T>(fc, sdc, mxc, myc);
-  uCur = u_tilde<T, SHIFT>(sdc, mxc, myc, fx);
+  uCur = u_tilde<T, SHIFT>(sdc, mxc, myc, fx, ref(st.y0));
   halo_u(st.y0, uLc, uRc);
 
 #pragma unroll 1
@@ -591,18 +682,26 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
     pull_row(yn, fn, Pn);
     halo_u(yn, uLn, uRn);
     moments<T>(fn, sdn, mxn, myn);
-    uNext = u_tilde<T, SHIFT>(sdn, mxn, myn, fx);
+    uNext = u_tilde<T, SHIFT>(sdn, mxn, myn, fx, ref(yn));
 
     U2<T> dn = uPrev, up = uNext;
     const U2<T> lf{shift_up(uLc.x, uCur.x), shift_up(uLc.y, uCur.y)};
     const U2<T> rt{shift_down(uRc.x, uCur.x), shift_down(uRc.y, uCur.y)};
-    // no-slip ghosts behind the half-way walls
+    // no-slip ghosts behind the half-way walls; with SHIFT the ghost rows take
+    // the mirrored references -ur and 2 u_w - ur (see sweep_kernel)
+    const T urc = ref(y);
     if (y == 0) dn = U2<T>{-uCur.x, -uCur.y};
-    if (y == ny - 1) up = U2<T>{T(2) * uwg - uCur.x, -uCur.y};
+    if (y == ny - 1) up = U2<T>{(SHIFT ? T(0) : T(2) * uwg) - uCur.x, -uCur.y};
+    T kref = T(0);
+    if constexpr (SHIFT) {
+      const T urd = (y == 0) ? -urc : ref(y - 1);
+      const T uru = (y == ny - 1) ? T(2) * uwg - urc : ref(y + 1);
+      kref = T(0.5) * (uru - urd);
+    }
 
     T out[9], trT;
     double obs[OF_COUNT];
-    node_update<T, SHIFT, OBS>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, q, a.nnp, out, trT, obs);
+    node_update<T, SHIFT, OBS>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, urc, kref, q, a.nnp, out, trT, obs);
     if constexpr (OBS) {
       obs[OF_DRAG] = wall_drag<T>(fc, y, ny, uw6);
 #pragma unroll
@@ -729,8 +828,11 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
   // Side values of a row, by lane i < 24 (kSide* below): lanes 0..5 hold the
   // edge populations of the shifted pulls, lanes 6..14 the pulled
   // populations of the column left of the strip, lanes 15..23 those of the
-  // column right of it; wall rows take the bounce-back sources. Other lanes
-  // read node (x0, y). Each lane decodes its entry into an element offset
+  // column right of it; wall rows take the bounce-back sources. With FP32
+  // storage lanes 24..26 hold the reference velocities of rows y-1, y, y+1
+  // (clamped to the channel), so that they arrive with the row's loads and
+  // not through a dependent load in the row step. Other lanes read node
+  // (x0, y). Each lane decodes its entry into an element offset
   // relative to row 0: once per strip for interior rows, again on the wall
   // rows (bottom, top, or both when ny = 1).
   auto side_off = [&](int code) __attribute__((always_inline)) -> long long {
@@ -772,12 +874,18 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
     long long o = o_in;
     if (bot || top)  // wall rows only
       o = side_off(bot * top * c_both + bot * (1 - top) * c_bot + (1 - bot) * c_top);
-    R.side = A[o + (long long)y * row_stride];
+    const T *ps = A + o + (long long)y * row_stride;
+    if constexpr (SHIFT) {
+      const int yr = y + lane - 25;
+      const T *pu = a.uref + c.row_off + (yr < 0 ? 0 : (yr >= ny ? ny - 1 : yr));
+      ps = (lane >= 24 && lane <= 26) ? pu : ps;
+    }
+    R.side = *ps;
   };
   // Pulled populations, P, moments and u~ of the NPL columns of row y, and u~
   // of the two columns beside the strip.
   auto assemble = [&](int y, const Raw &R, T f[9][NPL], T P[NPL], T sd[NPL], T mx[NPL], T my[NPL],
-                      U2<T> u[NPL], U2<T> &uL, U2<T> &uR) __attribute__((always_inline)) {
+                      U2<T> u[NPL], U2<T> &uL, U2<T> &uR, T ur3[3]) __attribute__((always_inline)) {
     const bool bot = (y == 0), top = (y == ny - 1);
     auto from_left = [&](const V &r, T edge, T out[NPL]) __attribute__((always_inline)) {
       out[0] = shift_up(edge, r[NPL - 1]);
@@ -818,13 +926,25 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
       from_right(R.r[7], lane_value(R.side, 4), f[7]);
       from_left(R.r[8], lane_value(R.side, 5), f[8]);
     }
+    // FP32: every pulled value relative to this row's reference
+    const T urd = SHIFT ? lane_value(R.side, 24) : T(0);
+    const T urc = SHIFT ? lane_value(R.side, 25) : T(0);
+    const T uru = SHIFT ? lane_value(R.side, 26) : T(0);
+    ur3[0] = urd;
+    ur3[1] = urc;
+    ur3[2] = uru;
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       T g[9];
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[i] = f[i][k];
+      if constexpr (SHIFT) {
+        to_row_reference(g, urd, urc, uru, bot, top);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i][k] = g[i];
+      }
       moments<T>(g, sd[k], mx[k], my[k]);
-      u[k] = u_tilde<T, SHIFT>(sd[k], mx[k], my[k], fx);
+      u[k] = u_tilde<T, SHIFT>(sd[k], mx[k], my[k], fx, urc);
     }
     // side lanes 6..14 / 15..23 hold populations 0,1,3,2,5,6,4,7,8
     T l[9], r[9];
@@ -851,11 +971,15 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
     l[8] += wc;
     r[7] -= wc;
     r[8] += wc;
+    if constexpr (SHIFT) {
+      to_row_reference(l, urd, urc, uru, bot, top);
+      to_row_reference(r, urd, urc, uru, bot, top);
+    }
     T s0, m0, n0;
     moments<T>(l, s0, m0, n0);
-    uL = u_tilde<T, SHIFT>(s0, m0, n0, fx);
+    uL = u_tilde<T, SHIFT>(s0, m0, n0, fx, urc);
     moments<T>(r, s0, m0, n0);
-    uR = u_tilde<T, SHIFT>(s0, m0, n0, fx);
+    uR = u_tilde<T, SHIFT>(s0, m0, n0, fx, urc);
   };
   auto clampy = [&](int y) __attribute__((always_inline)) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
 
@@ -866,6 +990,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
   const int nrows = st.y1 - st.y0;
   T fc[9][NPL], Pc[NPL], sdc[NPL], mxc[NPL], myc[NPL];
   U2<T> uPrev[NPL], uCur[NPL], uLc, uRc;
+  T urC[3];  // reference velocities of rows y-1, y, y+1 for the current row
   // ring of raw rows: the row i steps ahead of the first lives in slot i mod D
   constexpr int D = LB_VEC_DEPTH;
   Raw S[D];
@@ -878,25 +1003,33 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
     load_raw(yfirst, Rf);
 #pragma unroll
     for (int k = 1; k < D; ++k) load_raw(clampy(yfirst + dir * k), S[k]);
-    T ftmp[9][NPL], Ptmp[NPL], s0[NPL], m0[NPL], n0[NPL];
+    T ftmp[9][NPL], Ptmp[NPL], s0[NPL], m0[NPL], n0[NPL], ur_unused[3];
     U2<T> hl, hr;
-    assemble(yp, Rp, ftmp, Ptmp, s0, m0, n0, uPrev, hl, hr);
-    assemble(yfirst, Rf, fc, Pc, sdc, mxc, myc, uCur, uLc, uRc);
+    assemble(yp, Rp, ftmp, Ptmp, s0, m0, n0, uPrev, hl, hr, ur_unused);
+    assemble(yfirst, Rf, fc, Pc, sdc, mxc, myc, uCur, uLc, uRc, urC);
   }
 
   // Row y: start the loads of the row D ahead, assemble the next row (loaded
   // D - 1 rows earlier), update and store row y.
   auto row_step = [&](int y, Raw &Rload, const Raw &Rasm) __attribute__((always_inline)) {
     load_raw(clampy(y + dir * D), Rload);  // unconditional: a branch here costs more than the loads
-    T fn[9][NPL], Pn[NPL], sdn[NPL], mxn[NPL], myn[NPL];
+    T fn[9][NPL], Pn[NPL], sdn[NPL], mxn[NPL], myn[NPL], urN[3];
     U2<T> uNext[NPL], uLn, uRn;
-    assemble(clampy(y + dir), Rasm, fn, Pn, sdn, mxn, myn, uNext, uLn, uRn);
+    assemble(clampy(y + dir), Rasm, fn, Pn, sdn, mxn, myn, uNext, uLn, uRn, urN);
 
     T out[9][NPL], trT[NPL];
     double obs[OF_COUNT];
     if constexpr (OBS) {
 #pragma unroll
       for (int f = 0; f < OF_COUNT; ++f) obs[f] = 0.0;
+    }
+    // the row's reference and its share of d_y u_x (ghost rows mirrored)
+    const T urc = urC[1];
+    T kref = T(0);
+    if constexpr (SHIFT) {
+      const T urd = (y == 0) ? -urc : urC[0];
+      const T uru = (y == ny - 1) ? T(2) * uwg - urc : urC[2];
+      kref = T(0.5) * (uru - urd);
     }
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
@@ -914,12 +1047,13 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
       U2<T> dn = DOWN ? uNext[k] : uPrev[k], up = DOWN ? uPrev[k] : uNext[k];
       // no-slip ghosts behind the half-way walls
       if (y == 0) dn = U2<T>{-uCur[k].x, -uCur[k].y};
-      if (y == ny - 1) up = U2<T>{T(2) * uwg - uCur[k].x, -uCur[k].y};
+      if (y == ny - 1) up = U2<T>{(SHIFT ? T(0) : T(2) * uwg) - uCur[k].x, -uCur[k].y};
       T g[9], o[9], tr;
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[i] = fc[i][k];
       double ob[OF_COUNT];
-      node_update<T, SHIFT, OBS>(g, sdc[k], mxc[k], myc[k], Pc[k], fx, lf, rt, dn, up, q, a.nnp, o, tr, ob);
+      node_update<T, SHIFT, OBS>(g, sdc[k], mxc[k], myc[k], Pc[k], fx, lf, rt, dn, up, urc, kref, q, a.nnp, o, tr,
+                                 ob);
       if constexpr (OBS) {
         ob[OF_DRAG] = wall_drag<T>(g, y, ny, uw6);
 #pragma unroll
@@ -959,6 +1093,9 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
 
     uLc = uLn;
     uRc = uRn;
+    urC[0] = urN[0];
+    urC[1] = urN[1];
+    urC[2] = urN[2];
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       uPrev[k] = uCur[k];
@@ -983,7 +1120,8 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
 
 __global__ void __launch_bounds__(256) reduce_kernel(const ChanDev *ch, const double *part,
                                                      double *prof, double *prev_ux, double *scal,
-                                                     int update_residual, int steps_since) {
+                                                     const float *uref, int update_residual,
+                                                     int steps_since) {
   const ChanDev c = ch[blockIdx.x];
   __shared__ double red[7][256];
   double mass = 0, momx = 0, flux = 0, drag = 0, umax = 0, dmax = 0, bad = 0;
@@ -996,6 +1134,13 @@ __global__ void __launch_bounds__(256) reduce_kernel(const ChanDev *ch, const do
 #pragma unroll
       for (int f = 0; f < OF_COUNT; ++f) rs[f] += src[f];
     }
+    // FP32 storage: the row's reference velocity, left out of the node
+    // values of u_x, j_x and the wall momentum (0 for FP64)
+    const double ur = (double)uref[c.row_off + y];
+    rs[OF_UX] += c.nx * ur;
+    rs[OF_MOMX] += c.nx * ur;
+    if (y == 0) rs[OF_DRAG] -= c.nx * ur / 3.0;
+    if (y == c.ny - 1) rs[OF_DRAG] -= c.nx * ur / 3.0;
     double *dst = prof + ((long long)c.row_off + y) * OF_COUNT;
 #pragma unroll
     for (int f = 0; f < OF_COUNT; ++f) {
@@ -1064,14 +1209,16 @@ __global__ void __launch_bounds__(256) reduce_kernel(const ChanDev *ch, const do
 // that meet a wall are reflected, not carried, and stay. One workgroup per
 // channel; the column means are taken before anything is changed.
 template <typename T, bool SHIFT>
-__global__ void __launch_bounds__(256) gpbc_kernel(T *B, const ChanDev *ch, int k) {
+__global__ void __launch_bounds__(256) gpbc_kernel(T *B, const ChanDev *ch, int k, const float *uref) {
   const ChanDev c = ch[blockIdx.x];
   if (!c.gpbc || !c.active) return;
   const long long t = c.t + k;
   const double dp = (t < c.t_startup) ? c.pd : 0.0;
   const int nx = c.nx, ny = c.ny;
   auto node = [&](int x, int y) -> long long { return c.off + (long long)y * nx + x; };
-  auto load9 = [&](long long n, double f[9], double &rho, double &jx, double &jy) {
+  // density and momentum of a node (FP32: stored relative to the equilibrium
+  // at density 1 and the row's reference velocity, which carries momentum ur)
+  auto load9 = [&](long long n, int y, double f[9], double &rho, double &jx, double &jy) {
     double s = 0;
     jx = jy = 0;
     for (int i = 0; i < 9; ++i) {
@@ -1080,15 +1227,16 @@ __global__ void __launch_bounds__(256) gpbc_kernel(T *B, const ChanDev *ch, int 
     }
     jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    if (SHIFT) jx += (double)uref[c.row_off + y];
     rho = SHIFT ? 1.0 + s : s;
   };
   __shared__ double red[2][256];
   double si = 0, so = 0;
   for (int y = threadIdx.x; y < ny; y += blockDim.x) {
     double f[9], r, jx, jy;
-    load9(node(0, y), f, r, jx, jy);
+    load9(node(0, y), y, f, r, jx, jy);
     si += r;
-    load9(node(nx - 1, y), f, r, jx, jy);
+    load9(node(nx - 1, y), y, f, r, jx, jy);
     so += r;
   }
   red[0][threadIdx.x] = si;
@@ -1105,7 +1253,7 @@ __global__ void __launch_bounds__(256) gpbc_kernel(T *B, const ChanDev *ch, int 
   const double d_out = 1.0 - 1.5 * dp - red[0][0] / ny;  // links entering the outlet
   auto fix = [&](long long n, double d, int i0, int i1, int i2, int y) {
     double f[9], r, jx, jy;
-    load9(n, f, r, jx, jy);
+    load9(n, y, f, r, jx, jy);
     const double j2 = jx * jx + jy * jy, w = 1.0 / (r + d) - 1.0 / r;
     const int ids[3] = {i0, i1, i2};
     for (int q = 0; q < 3; ++q) {
@@ -1122,6 +1270,42 @@ __global__ void __launch_bounds__(256) gpbc_kernel(T *B, const ChanDev *ch, int 
     fix(node(nx - 1, y), d_in, 1, 5, 8, y);
     fix(node(0, y), d_out, 3, 6, 7, y);
   }
+}
+
+// FP32 storage: moves the reference velocity of every row of the active
+// channels to the row's current x-averaged u_x (prof, from the last
+// observation) and restates the stored populations of the row: a value
+// stored relative to E_i(uo) becomes one relative to E_i(un) by adding
+// E_i(uo) - E_i(un), formed as a difference. One workgroup per row.
+__global__ void __launch_bounds__(256) rereference_kernel(float *A, const ChanDev *ch, int n_ch,
+                                                          const double *prof, float *uref) {
+  const int r = blockIdx.x;  // row over all channels
+  int lo = 0, hi = n_ch - 1;
+  while (lo < hi) {  // the channel holding row r: last one with row_off <= r
+    const int mid = (lo + hi + 1) / 2;
+    if (ch[mid].row_off <= r) lo = mid;
+    else hi = mid - 1;
+  }
+  const ChanDev c = ch[lo];
+  if (!c.active) return;
+  const float uo = uref[r];
+  const double unx = prof[(long long)r * OF_COUNT + OF_UX];
+  if (!(unx == unx) || fabs(unx) > 1.0) return;  // not finite or not a velocity: keep the old one
+  const float un = (float)unx;
+  float d[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const float cx = (i == 1 || i == 5 || i == 8) ? 1.f : ((i == 3 || i == 6 || i == 7) ? -1.f : 0.f);
+    d[i] = ref_shift(weight<float>(i), cx, uo, un);
+  }
+  const int y = r - c.row_off;
+  for (int x = threadIdx.x; x < c.nx; x += blockDim.x) {
+    const long long n = c.off + (long long)y * c.nx + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) A[slot(i, n)] += d[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) uref[r] = un;
 }
 
 __global__ void advance_kernel(ChanDev *ch, int n_ch, int steps) {
@@ -1191,21 +1375,29 @@ hipError_t launch_sweep(int fp32, int cls, bool observe, const SweepArgs &a, hip
 }
 
 hipError_t launch_reduce(const ChanDev *ch, int n_ch, const double *part, double *prof,
-                         double *prev_ux, double *scal, int update_residual, int steps_since,
-                         hipStream_t s) {
+                         double *prev_ux, double *scal, const float *uref, int update_residual,
+                         int steps_since, hipStream_t s) {
   if (n_ch == 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_kernel, dim3(n_ch), dim3(256), 0, s, ch, part, prof, prev_ux, scal,
+  hipLaunchKernelGGL(reduce_kernel, dim3(n_ch), dim3(256), 0, s, ch, part, prof, prev_ux, scal, uref,
                      update_residual, steps_since);
   return hipGetLastError();
 }
 
-hipError_t launch_gpbc(int fp32, void *B, const ChanDev *ch, int n_ch, int k, hipStream_t s) {
+hipError_t launch_gpbc(int fp32, void *B, const ChanDev *ch, int n_ch, int k, const float *uref, hipStream_t s) {
   if (n_ch == 0) return hipSuccess;
   if (fp32)
-    hipLaunchKernelGGL((gpbc_kernel<float, true>), dim3(n_ch), dim3(256), 0, s, static_cast<float *>(B), ch, k);
+    hipLaunchKernelGGL((gpbc_kernel<float, true>), dim3(n_ch), dim3(256), 0, s, static_cast<float *>(B), ch, k,
+                       uref);
   else
     hipLaunchKernelGGL((gpbc_kernel<double, false>), dim3(n_ch), dim3(256), 0, s, static_cast<double *>(B), ch,
-                       k);
+                       k, uref);
+  return hipGetLastError();
+}
+
+hipError_t launch_rereference(float *A, const ChanDev *ch, int n_ch, int total_rows, const double *prof,
+                              float *uref, hipStream_t s) {
+  if (n_ch == 0 || total_rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(rereference_kernel, dim3(total_rows), dim3(256), 0, s, A, ch, n_ch, prof, uref);
   return hipGetLastError();
 }
 

@@ -40,7 +40,7 @@ struct Layout {
   int total_part = 0;
   int max_strips = 0;
   size_t off_state[2] = {0, 0}, off_ch = 0, off_strips = 0, off_astrips = 0, off_rstrips = 0, off_part = 0,
-         off_prof = 0, off_prev = 0, off_scal = 0, bytes = 0;
+         off_prof = 0, off_prev = 0, off_scal = 0, off_uref = 0, bytes = 0;
   std::vector<ChanDev> ch;
 };
 
@@ -177,6 +177,7 @@ Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
   L.off_prof = take(sizeof(double) * OF_COUNT * rows);
   L.off_prev = take(sizeof(double) * rows);
   L.off_scal = take(sizeof(double) * CS_COUNT * n);
+  L.off_uref = take(sizeof(float) * rows);
   L.bytes = at;
   return L;
 }
@@ -196,6 +197,7 @@ struct lb_handle {
   Strip *dact = nullptr;     // active channels, for stepping
   Strip *dact_rev = nullptr; // the same, each class group in reverse order
   double *dpart = nullptr, *dprof = nullptr, *dprev = nullptr, *dscal = nullptr;
+  float *duref = nullptr;    // FP32: reference velocity of every row
   // strips grouped by width class: [begin, begin + count) in the arrays
   int all_begin[kClasses] = {0}, all_count[kClasses] = {0};
   int act_begin[kClasses] = {0}, act_count[kClasses] = {0};
@@ -208,6 +210,7 @@ struct lb_handle {
   std::vector<long long> t;  // host mirror of every channel's step
   std::vector<int> active;
   int n_checks = 0;
+  int since_block = 0;       // steps since the last block boundary (handle clock)
   bool any_gpbc = false;     // some channel has the pressure drive
   std::string err;
 };
@@ -285,6 +288,7 @@ SweepArgs sweep_args(lb_handle *h, const Strip *strips, int begin, int count, in
   a.k = k;
   a.nnp = h->opt.nn_pressure;
   a.nt = (long long)kPlanes * h->L.plane * h->L.esize > kNontemporalBytes;
+  a.uref = h->duref;
   return a;
 }
 
@@ -304,7 +308,8 @@ lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s) {
   // generalised periodic boundaries: the inlet/outlet column pass on the
   // state just written
   if (h->any_gpbc)
-    HIPCHECK(h, launch_gpbc(h->opt.precision == LB_FP32_SHIFTED, h->buf[src ^ 1], h->dch, h->n_ch, k, s));
+    HIPCHECK(h, launch_gpbc(h->opt.precision == LB_FP32_SHIFTED, h->buf[src ^ 1], h->dch, h->n_ch, k, h->duref,
+                            s));
   return LB_OK;
 }
 
@@ -314,7 +319,7 @@ lb_status enqueue_observe(lb_handle *h, int update_residual, int steps_since) {
     SweepArgs a = sweep_args(h, h->dall, h->all_begin[c], h->all_count[c], h->cur, 0);
     HIPCHECK(h, launch_sweep(h->opt.precision == LB_FP32_SHIFTED, c, true, a, h->stream));
   }
-  HIPCHECK(h, launch_reduce(h->dch, h->n_ch, h->dpart, h->dprof, h->dprev, h->dscal,
+  HIPCHECK(h, launch_reduce(h->dch, h->n_ch, h->dpart, h->dprof, h->dprev, h->dscal, h->duref,
                             update_residual, steps_since, h->stream));
   return LB_OK;
 }
@@ -407,6 +412,27 @@ lb_status check_steady(lb_handle *h) {
   return LB_OK;
 }
 
+// FP32 storage: moves every active row's reference velocity to its current
+// mean u_x. Needs the observation of the current state in dprof (taken here
+// unless the convergence check just took it).
+lb_status rereference(lb_handle *h, bool observed) {
+  if (h->opt.precision != LB_FP32_SHIFTED) return LB_OK;
+  if (!observed) {
+    lb_status st = enqueue_observe(h, 0, 0);
+    if (st != LB_OK) return st;
+  }
+  HIPCHECK(h, launch_rereference(static_cast<float *>(h->buf[h->cur]), h->dch, h->n_ch, h->L.total_rows, h->dprof,
+                                 h->duref, h->stream));
+  return LB_OK;
+}
+
+// E_i(u) of the FP32 storage: the velocity part of the equilibrium at
+// density 1, a_i (3 c_ix u + (9/2 c_ix^2 - 3/2) u^2).
+double href_eq(int i, double u) {
+  const double cx = HCX[i];
+  return hweight(i) * (3.0 * cx * u + (4.5 * cx * cx - 1.5) * u * u);
+}
+
 lb_status fill_rest(lb_handle *h, int which);
 
 }  // namespace
@@ -463,6 +489,7 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
   h->dprof = reinterpret_cast<double *>(h->ws + h->L.off_prof);
   h->dprev = reinterpret_cast<double *>(h->ws + h->L.off_prev);
   h->dscal = reinterpret_cast<double *>(h->ws + h->L.off_scal);
+  h->duref = reinterpret_cast<float *>(h->ws + h->L.off_uref);
   h->t.assign(n, 0);
   h->active.assign(n, 1);
   auto bail = [&](lb_status s) {
@@ -484,6 +511,10 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
   std::vector<double> nanrows(std::max(1, h->L.total_rows), std::numeric_limits<double>::quiet_NaN());
   if (hipMemcpyAsync(h->dprev, nanrows.data(), sizeof(double) * h->L.total_rows, hipMemcpyHostToDevice,
                      h->stream) != hipSuccess)
+    return bail(LB_EHIP);
+  std::vector<float> zrows(std::max(1, h->L.total_rows), 0.0f);
+  if (hipMemcpyAsync(h->duref, zrows.data(), sizeof(float) * h->L.total_rows, hipMemcpyHostToDevice, h->stream) !=
+      hipSuccess)
     return bail(LB_EHIP);
   if (upload_strips(h, true) != LB_OK || upload_strips(h, false) != LB_OK) return bail(LB_EHIP);
   if (fill_rest(h, 0) != LB_OK || fill_rest(h, 1) != LB_OK) return bail(LB_EHIP);
@@ -507,35 +538,48 @@ lb_status lb_step(lb_handle *h, int64_t n) {
   if (n < 0) return fail(h, LB_EINVAL, "negative step count");
   h->obs_valid = false;
   int64_t left = n;
+  // Every K steps of the handle's clock end a block: the convergence check
+  // (if enabled) and, for FP32 storage, the move of the row reference
+  // velocities. Whole blocks run as one graph; steps that start or end off
+  // a block boundary are enqueued one by one. The boundaries do not depend
+  // on how the steps are split over calls, so neither does the result.
   while (left > 0) {
     bool any = false;
     for (int a : h->active) any |= (a != 0);
     if (!any) break;
-    if (left >= h->K) {
+    int m;
+    if (h->since_block == 0 && left >= h->K) {
       if (!h->graph[h->cur]) {
         lb_status st = capture(h, h->cur);
         if (st != LB_OK) return st;
       }
       HIPCHECK(h, hipGraphLaunch(h->graph[h->cur], h->stream));
-      for (int i = 0; i < h->n_ch; ++i)
-        if (h->active[i]) h->t[i] += h->K;
-      left -= h->K;
-      h->obs_valid = false;
-      if (h->opt.steady_tol > 0) {
-        lb_status st = check_steady(h);
-        if (st != LB_OK) return st;
-      }
+      m = h->K;
     } else {
-      const int m = (int)left;
+      m = (int)std::min<int64_t>(left, h->K - h->since_block);
       for (int k = 0; k < m; ++k) {
         lb_status st = enqueue_step(h, h->cur ^ (k & 1), k, h->stream);
         if (st != LB_OK) return st;
       }
       HIPCHECK(h, launch_advance(h->dch, h->n_ch, m, h->stream));
-      for (int i = 0; i < h->n_ch; ++i)
-        if (h->active[i]) h->t[i] += m;
       h->cur ^= (m & 1);
-      left = 0;
+    }
+    for (int i = 0; i < h->n_ch; ++i)
+      if (h->active[i]) h->t[i] += m;
+    left -= m;
+    h->since_block += m;
+    h->obs_valid = false;
+    if (h->since_block == h->K) {
+      h->since_block = 0;
+      bool observed = false;
+      if (h->opt.steady_tol > 0) {
+        lb_status st = check_steady(h);
+        if (st != LB_OK) return st;
+        observed = true;
+      }
+      lb_status st = rereference(h, observed);
+      if (st != LB_OK) return st;
+      h->obs_valid = false;
     }
   }
   h->obs_valid = false;
@@ -612,12 +656,17 @@ lb_status lb_get_state(lb_handle *h, int32_t ch, double *pops, double *P) {
   const char *src = static_cast<const char *>(h->buf[h->cur]);
   HIPCHECK(h, hipMemcpyAsync(raw.data(), src + (size_t)slot(0, d.off) * es, raw.size(),
                              hipMemcpyDeviceToHost, h->stream));
+  std::vector<float> ur(d.ny, 0.0f);
+  if (es == 4)
+    HIPCHECK(h, hipMemcpyAsync(ur.data(), h->duref + d.row_off, sizeof(float) * d.ny, hipMemcpyDeviceToHost,
+                               h->stream));
   HIPCHECK(h, hipStreamSynchronize(h->stream));
+  // FP32 slots hold n - a_i - E_i(u_ref) of the row the slot belongs to
   auto at = [&](int p, size_t id) -> double {
     const size_t k = (size_t)slot(p, (long long)id);
     if (es == 8) return reinterpret_cast<const double *>(raw.data())[k];
     const double v = reinterpret_cast<const float *>(raw.data())[k];
-    return p < 9 ? v + hweight(p) : v;
+    return p < 9 ? v + hweight(p) + href_eq(p, ur[id / d.nx]) : v;
   };
   // the pull: stored slot (plane i, source node) -> n_i at the destination
   for (int y = 0; y < d.ny; ++y)
@@ -654,12 +703,31 @@ lb_status lb_set_state(lb_handle *h, int32_t ch, const double *pops, const doubl
   HIPCHECK(h, hipMemcpyAsync(raw.data(), dst + (size_t)slot(0, d.off) * es, raw.size(),
                              hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(h, hipStreamSynchronize(h->stream));
+  // FP32: every row's reference velocity becomes the row mean of u_x of the
+  // new state (0 where that is not a finite velocity)
+  std::vector<float> ur(d.ny, 0.0f);
+  if (es == 4)
+    for (int y = 0; y < d.ny; ++y) {
+      double su = 0;
+      for (int x = 0; x < d.nx; ++x) {
+        const size_t id = (size_t)y * d.nx + x;
+        double rho = 0, jx = 0;
+        for (int i = 0; i < 9; ++i) {
+          const double v = pops[(size_t)i * N + id];
+          rho += v;
+          jx += HCX[i] * v;
+        }
+        su += jx / rho;
+      }
+      const double u = su / d.nx;
+      ur[y] = (std::isfinite(u) && std::fabs(u) <= 1.0) ? (float)u : 0.0f;
+    }
   auto put = [&](int p, size_t id, double v) {
     const size_t k = (size_t)slot(p, (long long)id);
     if (es == 8)
       reinterpret_cast<double *>(raw.data())[k] = v;
     else
-      reinterpret_cast<float *>(raw.data())[k] = (float)(p < 9 ? v - hweight(p) : v);
+      reinterpret_cast<float *>(raw.data())[k] = (float)(p < 9 ? v - hweight(p) - href_eq(p, ur[id / d.nx]) : v);
   };
   // inverse of the pull: every stored slot feeds exactly one (node, i)
   for (int y = 0; y < d.ny; ++y)
@@ -680,6 +748,9 @@ lb_status lb_set_state(lb_handle *h, int32_t ch, const double *pops, const doubl
     }
   HIPCHECK(h, hipMemcpyAsync(dst + (size_t)slot(0, d.off) * es, raw.data(), raw.size(),
                              hipMemcpyHostToDevice, h->stream));
+  if (es == 4)
+    HIPCHECK(h, hipMemcpyAsync(h->duref + d.row_off, ur.data(), sizeof(float) * d.ny, hipMemcpyHostToDevice,
+                               h->stream));
   // step counter and residual history of this channel
   std::vector<ChanDev> cur(h->n_ch);
   HIPCHECK(h, hipMemcpyAsync(cur.data(), h->dch, sizeof(ChanDev) * h->n_ch, hipMemcpyDeviceToHost, h->stream));

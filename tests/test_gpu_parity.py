@@ -195,12 +195,14 @@ def test_bitwise_repeat_and_step_splitting():
         assert np.array_equal(pops, states[0][0]) and np.array_equal(P, states[0][1])
 
 
-@pytest.mark.parametrize("nx", [300, 512])
-def test_x_uniform_stays_bitwise_uniform(nx):
+@pytest.mark.parametrize("precision,nx", [("fp64", 300), ("fp64", 512), ("fp32", 300), ("fp32", 512), ("fp32", 1024)])
+def test_x_uniform_stays_bitwise_uniform(precision, nx):
     """A wide x-periodic channel started from rest stays exactly x-uniform:
-    every halo lane, edge column and wrapped column computes the same values."""
+    every halo lane, edge column and wrapped column computes the same values
+    (FP32: also across the moves of the row reference velocities every 100
+    steps)."""
     spec = ChannelSpec(nx, 40, 1e-6, 1.0, 1e-4, 1e3, 0.1)
-    with solver([spec], precision="fp64", obs_every=100) as s:
+    with solver([spec], precision=precision, obs_every=100) as s:
         s.step(777)
         pops, P = s.get_state(0)
         assert np.array_equal(pops, np.broadcast_to(pops[:, :, :1], pops.shape))
