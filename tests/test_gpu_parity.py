@@ -310,6 +310,38 @@ def test_poiseuille_gtau1_short_exact_long_statistical(orc):
         assert abs(s.observe(0, "mass") - 512) < 1e-9
 
 
+def test_batched_sweep_fp32_reaches_fp64_steady_state(orc):
+    """All 256 channels of the batched sweep (nx = 8, ny 32..509, the drawn
+    eps, G tau and g) run to residual < 1e-9 in FP32 and in FP64. Every
+    channel converges in both. The FP32 steady profiles equal the FP64 ones
+    within 5e-5 of max |u_x|: a frozen profile still moves at < 1e-9 max|u|
+    per step, and the slowest channel relaxes over ~4e4 steps (H^2 / (pi^2 nu),
+    H = 255, nu = 1/6). FP32 resolves the slow last stretch of convergence.
+    The FP64 profiles are within 2e-3 of the analytic steady profile of
+    Sec. III.B: the lattice discretisation error, largest in the narrowest
+    channels."""
+    from oracle import analytic
+    wl = workloads.batched_sweep()
+    chans = wl["channels"]
+    prof = {}
+    for prec in ("fp32", "fp64"):
+        with solver(chans, precision=prec, obs_every=1000, steady_tol=1e-9, strip_rows=16) as s:
+            s.step(3_000_000)
+            assert all(s.observe(i, "active") == 0 for i in range(len(chans))), prec
+            prof[prec] = [s.observe(i, "ux") for i in range(len(chans))]
+    d32 = []
+    e64 = []
+    for i, c in enumerate(chans):
+        p = orc.resolve(c.tau_lb, c.G, c.tau0, c.gamma_c, c.eps)
+        ua = analytic.steady_profile(c.ny, c.force, (c.tau_lb - 0.5) / 3, p.G, p.tau, c.gamma_c)
+        u64 = prof["fp64"][i]
+        d32.append(np.abs(prof["fp32"][i] - u64).max() / np.abs(u64).max())
+        e64.append(np.abs(u64 - ua).max() / np.abs(ua).max())
+    d32, e64 = np.array(d32), np.array(e64)
+    assert d32.max() < 5e-5 and np.median(d32) < 1e-6, (d32.max(), np.median(d32))
+    assert e64.max() < 2e-3 and np.median(e64) < 2e-4, (e64.max(), np.median(e64))
+
+
 def test_batched_sweep_subset_to_steady(orc):
     """The first 24 channels of the batched sweep (nx = 8, ragged widths and
     parameters) in one FP32 handle, each frozen at residual < 1e-9: all
