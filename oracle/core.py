@@ -4,7 +4,9 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The oracle state is the post-streaming population n_i(r, t) of the paper's
 Eq. (lbupdate), stored as ``n[9, ny, nx]``, plus the previous stress trace
-``P[ny, nx]`` that Eq. (rhoplus) differences against.
+``P[ny, nx]`` that Eq. (rhoplus) differences against, and, with the
+time-integrated (viscoelastic) model, the stress of the previous step
+``S[3, ny, nx]`` (xx, xy, yy).
 """
 import ctypes as C
 
@@ -26,7 +28,7 @@ class OrcParams(C.Structure):
     _fields_ = [("g", C.c_double), ("tau_eff", C.c_double), ("G", C.c_double),
                 ("tau", C.c_double), ("gamma_c", C.c_double), ("lam", C.c_double),
                 ("t_startup", C.c_longlong), ("nn_pressure", C.c_int), ("uw", C.c_double),
-                ("dp", C.c_double)]
+                ("dp", C.c_double), ("ve", C.c_int)]
 
 
 def lib():
@@ -36,7 +38,7 @@ def lib():
         L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         L.orc_resolve.argtypes = [C.c_double] * 6 + [C.c_double, C.c_longlong, C.c_int, C.c_double,
-                                                     C.c_double, C.POINTER(OrcParams)]
+                                                     C.c_double, C.c_int, C.POINTER(OrcParams)]
         L.orc_resolve.restype = C.c_int
         L.orc_equilibrium.argtypes = [C.c_double] * 3 + [dp]
         L.orc_forcing.argtypes = [C.c_double, dp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, dp]
@@ -44,11 +46,13 @@ def lib():
         L.orc_stress_series.restype = C.c_int
         L.orc_tau_M.argtypes = [dp, C.c_double, C.c_double]
         L.orc_tau_M.restype = C.c_double
-        L.orc_step.argtypes = [C.POINTER(OrcParams), C.c_int, C.c_int, dp, dp, C.c_longlong, dp, dp, dp]
+        L.orc_stress_ve_step.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp, dp]
+        L.orc_step.argtypes = [C.POINTER(OrcParams), C.c_int, C.c_int, dp, dp, dp, C.c_longlong, dp, dp, dp,
+                               dp]
         L.orc_step.restype = C.c_int
-        L.orc_run.argtypes = [C.POINTER(OrcParams), C.c_int, C.c_int, dp, dp, C.c_longlong, C.c_longlong]
+        L.orc_run.argtypes = [C.POINTER(OrcParams), C.c_int, C.c_int, dp, dp, dp, C.c_longlong, C.c_longlong]
         L.orc_run.restype = C.c_longlong
-        L.orc_init_rest.argtypes = [C.c_int, C.c_int, dp, dp]
+        L.orc_init_rest.argtypes = [C.c_int, C.c_int, dp, dp, dp]
         L.orc_wall_drag.argtypes = [C.c_int, C.c_int, dp, C.c_double]
         L.orc_wall_drag.restype = C.c_double
         L.orc_num_fields.restype = C.c_int
@@ -93,17 +97,27 @@ def stress_series(kappa, G, tauM):
     return out, nt
 
 
+def stress_ve_step(kappa, G, tau, gamma_c, sigma_prev):
+    """One step of the time-integrated stress (xx, xy, yy) from sigma_prev
+    under the velocity gradient kappa[a][b] = d_b u_a."""
+    k = np.ascontiguousarray(kappa, dtype=np.float64).reshape(2, 2)
+    sp = np.ascontiguousarray(sigma_prev, dtype=np.float64)
+    out = np.zeros(3)
+    lib().orc_stress_ve_step(_p(k), G, tau, gamma_c, _p(sp), _p(out))
+    return out
+
+
 def tau_M(kappa, tau, gamma_c):
     k = np.ascontiguousarray(kappa, dtype=np.float64).reshape(2, 2)
     return lib().orc_tau_M(_p(k), tau, gamma_c)
 
 
 def resolve(tau_lb, G, tau0, gamma_c, eps=0.0, visc_split=0.0, force=0.0,
-            t_startup=2 ** 62, nn_pressure=True, wall_velocity=0.0, pressure_drop=0.0):
+            t_startup=2 ** 62, nn_pressure=True, wall_velocity=0.0, pressure_drop=0.0, viscoelastic=False):
     p = OrcParams()
     rc = lib().orc_resolve(tau_lb, G, tau0, gamma_c, eps, visc_split, force,
                            int(t_startup), int(bool(nn_pressure)), float(wall_velocity),
-                           float(pressure_drop), C.byref(p))
+                           float(pressure_drop), int(bool(viscoelastic)), C.byref(p))
     if rc != 0:
         raise ValueError("invalid channel parameters")
     return p
@@ -114,28 +128,34 @@ class Channel:
 
     def __init__(self, nx, ny, force, tau_lb=1.0, G=1e-4, tau0=1e4, gamma_c=0.1,
                  eps=0.0, visc_split=0.0, t_startup=2 ** 62, nn_pressure=True, wall_velocity=0.0,
-                 pressure_gradient=0.0):
+                 pressure_gradient=0.0, viscoelastic=False):
         """wall_velocity: x velocity of the top wall while t < t_startup
         (planar Couette flow); 0 gives the channel with two fixed walls.
         pressure_gradient: pressure drop per unit length G_p imposed by
         generalised periodic boundaries (R10: p+ - p- = (nx + 1) G_p between
-        the virtual nodes; needs force 0 and nn_pressure False)."""
+        the virtual nodes; needs force 0 and nn_pressure False).
+        viscoelastic: the time-integrated nonlinear Maxwell stress (R11),
+        carried in ``S`` from step to step, in place of the instantaneous one."""
         self.nx, self.ny = int(nx), int(ny)
         self.params = resolve(tau_lb, G, tau0, gamma_c, eps, visc_split, force,
-                              t_startup, nn_pressure, wall_velocity, (self.nx + 1) * pressure_gradient)
+                              t_startup, nn_pressure, wall_velocity, (self.nx + 1) * pressure_gradient,
+                              viscoelastic)
         self.n = np.empty((9, self.ny, self.nx))
         self.P = np.empty((self.ny, self.nx))
-        lib().orc_init_rest(self.nx, self.ny, _p(self.n), _p(self.P))
+        self.S = np.zeros((3, self.ny, self.nx))
+        lib().orc_init_rest(self.nx, self.ny, _p(self.n), _p(self.P), _p(self.S))
         self.t = 0
 
-    def set_state(self, n, P, t=None):
+    def set_state(self, n, P, t=None, S=None):
         self.n[...] = n
         self.P[...] = P
+        if S is not None:
+            self.S[...] = S
         if t is not None:
             self.t = int(t)
 
     def run(self, steps):
-        bad = lib().orc_run(C.byref(self.params), self.nx, self.ny, _p(self.n), _p(self.P),
+        bad = lib().orc_run(C.byref(self.params), self.nx, self.ny, _p(self.n), _p(self.P), _p(self.S),
                             self.t, int(steps))
         if bad != 0:
             raise RuntimeError(f"oracle: stress series failed at {bad} node-steps")
@@ -144,8 +164,8 @@ class Channel:
     def fields(self):
         """Per-node observables of the current step, dict name -> [ny, nx]."""
         f = np.empty((len(FIELDS), self.ny, self.nx))
-        bad = lib().orc_step(C.byref(self.params), self.nx, self.ny, _p(self.n), _p(self.P),
-                             self.t, None, None, _p(f))
+        bad = lib().orc_step(C.byref(self.params), self.nx, self.ny, _p(self.n), _p(self.P), _p(self.S),
+                             self.t, None, None, None, _p(f))
         if bad != 0:
             raise RuntimeError("oracle: stress series failed")
         return {name: f[q] for q, name in enumerate(FIELDS)}

@@ -70,6 +70,21 @@
  *      forcing keeps its first line only (no body force, no delta rho).
  *      The drop acts for t < t_startup; afterwards the same boundaries hold
  *      both ends at rho0 (cessation).
+ *   R11 the time-integrated (viscoelastic) nonlinear Maxwell model: the
+ *      differential form of Eq. (gkder) with d_t G = -G / tau_M(t), tau_M from
+ *      Eq. (nlmaxwell) at the current kappa (the time-dependent generalisation
+ *      Sec. III.A mentions and leaves aside):
+ *        d sigma/dt - kappa sigma - sigma kappa^T = G D - sigma / tau_M.
+ *      One step (dt = 1) takes the upper-convected terms and the source
+ *      explicitly and the relaxation implicitly,
+ *        sigma(t) = [sigma(t-1) + kappa sigma(t-1) + sigma(t-1) kappa^T + G D]
+ *                   / (1 + 1/tau_M),
+ *      with kappa, D and tau_M of step t. Its fixed point satisfies
+ *      sigma = tau_M (kappa sigma + sigma kappa^T + G D), the relation whose
+ *      solution is the series of Eq. (sigtsum), so the steady states of both
+ *      models coincide. The stress of step t then enters the forcing as in
+ *      the instantaneous model. The state carries sigma(t-1) (three more
+ *      fields per node, zero at rest).
  *
  * Lattice units: dx = dt = 1, rho0 = 1, c_s^2 = 1/3, d = 2.
  * Storage: populations n[i][y][x] (nine planes, x fastest), the previous
@@ -108,12 +123,13 @@ typedef struct {
   int nn_pressure;  /* 1: keep the delta-rho terms of the forcing            */
   double uw;        /* x velocity of the top wall while t < t_startup (R9)   */
   double dp;        /* pressure drop p+ - p- across the period (R10), 0: off */
+  int ve;           /* 1: time-integrated stress (R11); 0: instantaneous     */
 } orc_params;
 
 /* Parameter resolution (readings R7, R8). Returns 0, or -1 for invalid input. */
 int orc_resolve(double tau_lb, double G, double tau0, double gamma_c, double eps,
                 double lam, double g, long long t_startup, int nn_pressure, double uw,
-                double dp, orc_params *out) {
+                double dp, int ve, orc_params *out) {
   if (!(tau_lb > 0.5) || !(G >= 0) || !(tau0 > 0) || !(gamma_c > 0) ||
       !(lam >= 0 && lam <= 1) || !isfinite(g) || !isfinite(eps) || !isfinite(uw) || !isfinite(dp))
     return -1;
@@ -133,6 +149,7 @@ int orc_resolve(double tau_lb, double G, double tau0, double gamma_c, double eps
   out->nn_pressure = nn_pressure;
   out->uw = uw;
   out->dp = dp;
+  out->ve = ve ? 1 : 0;
   return 0;
 }
 
@@ -224,6 +241,33 @@ double orc_tau_M(const double k[2][2], double tau, double gamma_c) {
   return 1.0 / rate;
 }
 
+/* One step of the time-integrated stress (reading R11): sigma_prev (xx, xy,
+ * yy) at step t-1, velocity gradient k[a][b] = d_b u_a of step t, modulus G,
+ * relaxation rate 1/tau_M = 1/tau + sqrt(II_D)/gamma_c (Eq. (nlmaxwell)).
+ * Writes sigma of step t to sig. */
+void orc_stress_ve_step(const double k[2][2], double G, double tau, double gamma_c,
+                        const double sigma_prev[3], double sig[3]) {
+  double s[2][2] = {{sigma_prev[0], sigma_prev[1]}, {sigma_prev[1], sigma_prev[2]}};
+  double D[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) D[a][b] = k[a][b] + k[b][a];
+  double trD2 = 0.0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) trD2 += D[a][b] * D[b][a];
+  double rate = 1.0 / tau + sqrt(0.5 * trD2) / gamma_c;  /* 1 / tau_M */
+  double out[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      /* (kappa sigma + sigma kappa^T)_ab = sum_c k_ac s_cb + s_ac k_bc */
+      double conv = 0.0;
+      for (int c = 0; c < 2; ++c) conv += k[a][c] * s[c][b] + s[a][c] * k[b][c];
+      out[a][b] = (s[a][b] + conv + G * D[a][b]) / (1.0 + rate);
+    }
+  sig[0] = out[0][0];
+  sig[1] = out[0][1];
+  sig[2] = out[1][1];
+}
+
 /* Per-node observables written by orc_step / orc_observe, field-major
  * [field][y][x]. */
 enum {
@@ -251,13 +295,16 @@ void orc_set_num_threads(int n) {
 }
 
 /* One time step t -> t+1 of one channel. n: 9 planes of nx*ny post-streaming
- * populations at time t; P: stress trace of step t-1. Writes the state at
- * t+1 to n_out, P_out (which must not alias n, P). If fields != NULL the
- * per-node observables of step t are stored there. If n_out == NULL nothing is
- * advanced (observation only). Returns the number of nodes at which the
- * stress series did not converge (0 on success). */
+ * populations at time t; P: stress trace of step t-1; S: with the
+ * time-integrated model (R11), the stress (xx, xy, yy planes) of step t-1,
+ * else unused (may be NULL). Writes the state at t+1 to n_out, P_out, S_out
+ * (which must not alias n, P, S). If fields != NULL the per-node observables
+ * of step t are stored there. If n_out == NULL nothing is advanced
+ * (observation only). Returns the number of nodes at which the stress series
+ * did not converge (0 on success). */
 int orc_step(const orc_params *p, int nx, int ny, const double *n, const double *P,
-             long long t, double *n_out, double *P_out, double *fields) {
+             const double *S, long long t, double *n_out, double *P_out, double *S_out,
+             double *fields) {
   const size_t N = (size_t)nx * ny;
   double fx = (t < p->t_startup) ? p->g : 0.0, fy = 0.0;
   double uw = (t < p->t_startup) ? p->uw : 0.0;  /* top wall velocity at step t */
@@ -323,13 +370,18 @@ int orc_step(const orc_params *p, int nx, int ny, const double *n, const double 
       k[1][0] = 0.5 * (uyp - uym);  /* d_x u_y */
       k[1][1] = 0.5 * (uyu - uyd);  /* d_y u_y */
 
-      /* inlM stress: Maxwell time of Eq. (nlmaxwell), then Eq. (sigtsum). */
+      /* inlM stress: Maxwell time of Eq. (nlmaxwell), then Eq. (sigtsum);
+       * time-integrated model: one step of reading R11 from the stress of
+       * the previous step. */
       double sig[3] = {0, 0, 0};
       double tauM = orc_tau_M(k, p->tau, p->gamma_c);
-      if (p->G > 0 && isfinite(tauM)) {
+      if (p->ve) {
+        const double sp[3] = {S[id], S[N + id], S[2 * N + id]};
+        orc_stress_ve_step(k, p->G, p->tau, p->gamma_c, sp, sig);
+      } else if (p->G > 0 && isfinite(tauM)) {
         if (orc_stress_series(k, p->G, tauM, sig) < 0) bad++;
       }
-      /* tau_M infinite means tau = inf and D = 0: the series is zero. */
+      /* inlM: tau_M infinite means tau = inf and D = 0, the series is zero. */
 
       /* Non-Newtonian stress carried by the forcing (viscosity split). */
       double D[2][2] = {{2 * k[0][0], k[0][1] + k[1][0]}, {k[0][1] + k[1][0], 2 * k[1][1]}};
@@ -388,35 +440,46 @@ int orc_step(const orc_params *p, int nx, int ny, const double *n, const double 
           n_out[opposite(i) * N + id] = post;
       }
       P_out[id] = trT;
+      if (p->ve) {
+        S_out[id] = sig[0];
+        S_out[N + id] = sig[1];
+        S_out[2 * N + id] = sig[2];
+      }
     }
   free(utx);
   free(uty);
   return bad;
 }
 
-/* Rest state: n_i = a_i, P = 0. */
-void orc_init_rest(int nx, int ny, double *n, double *P) {
+/* Rest state: n_i = a_i, P = 0, and (if S != NULL) zero stress. */
+void orc_init_rest(int nx, int ny, double *n, double *P, double *S) {
   const size_t N = (size_t)nx * ny;
   for (int i = 0; i < 9; ++i)
     for (size_t id = 0; id < N; ++id) n[i * N + id] = W[i];
   for (size_t id = 0; id < N; ++id) P[id] = 0.0;
+  if (S)
+    for (size_t id = 0; id < 3 * N; ++id) S[id] = 0.0;
 }
 
-/* Advances (n, P) in place from step t0 by nsteps. Returns the total count of
- * non-converged stress evaluations, or -1 on allocation failure. */
-long long orc_run(const orc_params *p, int nx, int ny, double *n, double *P,
+/* Advances (n, P, and S with the time-integrated model) in place from step t0
+ * by nsteps. Returns the total count of non-converged stress evaluations, or
+ * -1 on allocation failure. */
+long long orc_run(const orc_params *p, int nx, int ny, double *n, double *P, double *S,
                   long long t0, long long nsteps) {
   const size_t N = (size_t)nx * ny;
   double *n2 = malloc(9 * N * sizeof(double)), *P2 = malloc(N * sizeof(double));
-  if (!n2 || !P2) { free(n2); free(P2); return -1; }
+  double *S2 = p->ve ? malloc(3 * N * sizeof(double)) : NULL;
+  if (!n2 || !P2 || (p->ve && !S2)) { free(n2); free(P2); free(S2); return -1; }
   long long bad = 0;
   for (long long s = 0; s < nsteps; ++s) {
-    bad += orc_step(p, nx, ny, n, P, t0 + s, n2, P2, NULL);
+    bad += orc_step(p, nx, ny, n, P, S, t0 + s, n2, P2, S2, NULL);
     memcpy(n, n2, 9 * N * sizeof(double));
     memcpy(P, P2, N * sizeof(double));
+    if (p->ve) memcpy(S, S2, 3 * N * sizeof(double));
   }
   free(n2);
   free(P2);
+  free(S2);
   return bad;
 }
 
