@@ -120,7 +120,19 @@ typedef struct {
  *   steady_tol   if > 0, lb_step checks every K steps the residual
  *                R = max_y |ubar(t) - ubar(t-K)| / (K max_y |ubar(t)|) of the
  *                x-averaged velocity ubar and freezes each channel once
- *                R < steady_tol; 0 disables the checks.
+ *                R < steady_tol; 0 disables the checks;
+ *   viscoelastic 0: the instantaneous model of Sec. III.A (the stress is the
+ *                steady sum of Eq. (sigtsum) at the current velocity
+ *                gradient); 1: the time-integrated nonlinear Maxwell model,
+ *                Eq. (gkder) with d_t G = -G / tau_M(t) and tau_M of
+ *                Eq. (nlmaxwell), stepped as
+ *                sigma(t) = [sigma(t-1) + kappa sigma(t-1) + sigma(t-1) kappa^T
+ *                            + G_inf D] / (1 + 1/tau_M)
+ *                (upper-convected terms explicit, relaxation implicit; the
+ *                fixed point is the instantaneous model's stress). The stress
+ *                is then part of the state (three more fields per node, in
+ *                the precision of the populations, zero at rest; see
+ *                lb_get_stress), and the workspace grows accordingly.
  */
 typedef struct {
   int32_t precision;
@@ -128,6 +140,7 @@ typedef struct {
   int32_t obs_every;
   int32_t strip_rows;
   double steady_tol;
+  int32_t viscoelastic;
 } lb_options;
 
 /* Observables for lb_observe. Profiles return ny doubles (x-averages per row,
@@ -135,7 +148,9 @@ typedef struct {
 enum {
   LB_OBS_UX = 0,        /* u_x = j_x / rho_e                                 */
   LB_OBS_UY = 1,
-  LB_OBS_SXX = 2,       /* Maxwell stress sigma (Eq. (sigtsum))             */
+  LB_OBS_SXX = 2,       /* Maxwell stress sigma (Eq. (sigtsum); with the    */
+                        /* viscoelastic option the sigma(t) the next step   */
+                        /* computes from the stored sigma(t-1))             */
   LB_OBS_SXY = 3,
   LB_OBS_SYY = 4,
   LB_OBS_N1 = 5,        /* sigma_xx - sigma_yy                              */
@@ -195,6 +210,14 @@ lb_status lb_get_state(lb_handle *h, int32_t ch, double *pops, double *P);
 /* Overwrites the state of channel ch (same layout as lb_get_state) and sets
  * its step counter to t. Synchronises the stream. */
 lb_status lb_set_state(lb_handle *h, int32_t ch, const double *pops, const double *P, int64_t t);
+
+/* Time-integrated stress of channel ch (viscoelastic option only): the
+ * stress sigma(t-1) the next step starts from, as sigma[3][ny][nx] (planes
+ * xx, xy, yy), in FP64. lb_set_state and lb_set_profile leave it unchanged.
+ * LB_EINVAL if the handle runs the instantaneous model. Synchronise the
+ * stream. */
+lb_status lb_get_stress(lb_handle *h, int32_t ch, double *sigma);
+lb_status lb_set_stress(lb_handle *h, int32_t ch, const double *sigma);
 
 /* Point sets of lb_set_profile. */
 enum {

@@ -13,6 +13,12 @@ constexpr int kTile = 64;
 __host__ __device__ inline long long slot(int p, long long n) {
   return ((n >> 6) * kPlanes + p) * kTile + (n & (kTile - 1));
 }
+// Time-integrated stress (viscoelastic model): sigma_xx, sigma_xy, sigma_yy
+// of the previous step, in buffers of their own tiled like the state.
+constexpr int kStressPlanes = 3;
+__host__ __device__ inline long long sslot(int p, long long n) {
+  return ((n >> 6) * kStressPlanes + p) * kTile + (n & (kTile - 1));
+}
 // Per-row observation fields accumulated in FP64 (x sums per row).
 enum ObsField {
   OF_UX = 0, OF_UY, OF_SXX, OF_SXY, OF_SYY, OF_RHOE_DEV, OF_MASS_DEV, OF_MOMX,
@@ -66,6 +72,9 @@ struct SweepArgs {
   int nt;               // store the new state with nontemporal hints
   int down;             // march the strips downwards (vector sweep)
   const float *uref;    // FP32: reference velocity of every row (all channels)
+  const void *SA;       // viscoelastic model: stress read (3 planes)
+  void *SB;             // viscoelastic model: stress written (3 planes)
+  int ve;               // time-integrated stress in place of the instantaneous one
 };
 // A state buffer larger than this is written with nontemporal stores: it
 // cannot stay in the 256 MB last-level cache (MALL) until the next step reads

@@ -211,10 +211,13 @@ struct Coef {
 // the momentum beyond ur, the velocities lf, rt, dn, up carry u~_x minus
 // their own row's reference, and kref = (ur_above - ur_below)/2 restores the
 // reference's share of d_y u_x; the outputs are stored relative to ur.
-template <typename T, bool SHIFT, bool OBS>
+// With VE the stress is the time-integrated one: sp holds (xx, xy, yy) of the
+// previous step and sn receives those of this step.
+template <typename T, bool SHIFT, bool OBS, bool VE>
 __device__ __forceinline__ void node_update(const T f[9], T sd, T mx, T my, T Pc, T fx, U2<T> lf,
                                             U2<T> rt, U2<T> dn, U2<T> up, T ur, T kref, const Coef<T> &q,
-                                            int nnp, T out[9], T &trT_out, double obs[OF_COUNT]) {
+                                            int nnp, const T sp[3], T sn[3], T out[9], T &trT_out,
+                                            double obs[OF_COUNT]) {
   // velocity gradient kappa_ab = d_b u_a
   const T kxx = T(0.5) * (rt.x - lf.x);
   const T kxy = T(0.5) * (up.x - dn.x) + kref;
@@ -227,7 +230,25 @@ __device__ __forceinline__ void node_update(const T f[9], T sd, T mx, T my, T Pc
   // form (Cramer) for (sigma_xx, sigma_xy, sigma_yy).
   const T Dxx = T(2) * kxx, Dxy = kxy + kyx, Dyy = T(2) * kyy;
   T sxx = T(0), sxy = T(0), syy = T(0);
-  if (q.stress_on) {
+  if constexpr (VE) {
+    // Time-integrated stress, Eq. (gkder) with d_t G = -G / tau_M(t): one
+    // step with the upper-convected terms and the source explicit and the
+    // relaxation implicit, sigma' = [sigma + kappa sigma + sigma kappa^T +
+    // G D] / (1 + 1/tau_M), written as sigma plus its increment so that FP32
+    // rounds only the increment.
+    const T II = T(0.5) * (Dxx * Dxx + T(2) * Dxy * Dxy + Dyy * Dyy);
+    const T rate = q.inv_tau + sqrt(II) * q.inv_gc;  // 1 / tau_M
+    const T d = recip<T>(T(1) + rate);
+    const T cxx = T(2) * (kxx * sp[0] + kxy * sp[1]);
+    const T cxy = kxx * sp[1] + kxy * sp[2] + kyx * sp[0] + kyy * sp[1];
+    const T cyy = T(2) * (kyx * sp[1] + kyy * sp[2]);
+    sxx = sp[0] + (cxx + q.G * Dxx - rate * sp[0]) * d;
+    sxy = sp[1] + (cxy + q.G * Dxy - rate * sp[1]) * d;
+    syy = sp[2] + (cyy + q.G * Dyy - rate * sp[2]) * d;
+    sn[0] = sxx;
+    sn[1] = sxy;
+    sn[2] = syy;
+  } else if (q.stress_on) {
     const T II = T(0.5) * (Dxx * Dxx + T(2) * Dxy * Dxy + Dyy * Dyy);
     const T rate = q.inv_tau + sqrt(II) * q.inv_gc;
     if (rate > T(0)) {
@@ -367,7 +388,7 @@ __device__ __forceinline__ int strip_index(const SweepArgs &a) {
   return L * LB_WG_WAVES + wave;
 }
 
-template <typename T, bool SHIFT, int TXW, bool WIDE, bool OBS>
+template <typename T, bool SHIFT, int TXW, bool WIDE, bool OBS, bool VE>
 __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
   constexpr int TYW = 64 / TXW;
   const int lane = threadIdx.x & 63;
@@ -433,8 +454,20 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
     moments<T>(f, sd, mx, my);
     return u_tilde<T, SHIFT>(sd, mx, my, fx, ur);
   };
+  // viscoelastic model: the stress of the previous step at (x, y)
+  const T *__restrict__ SA = static_cast<const T *>(a.SA);
+  T *__restrict__ SB = static_cast<T *>(a.SB);
+  auto load_sigma = [&](int y, T sg[3]) {
+    if constexpr (VE) {
+      const long long o = base + (long long)clampy(y) * nx + x;
+#pragma unroll
+      for (int p = 0; p < 3; ++p) sg[p] = SA[sslot(p, o)];
+    } else {
+      sg[0] = sg[1] = sg[2] = T(0);
+    }
+  };
 
-  T fc[9], fn[9], Pc, Pn, urc, urn;
+  T fc[9], fn[9], Pc, Pn, urc, urn, sgc[3], sgn[3];
   U2<T> uPrev, uCur, uNext, uhCur = {T(0), T(0)}, uhNext = {T(0), T(0)};
   {
     T ftmp[9], Ptmp, sd, mx, my, urp;
@@ -444,6 +477,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
   }
   T sdc, mxc, myc;
   pull_row(st.y0 + ly, fc, Pc, urc);
+  load_sigma(st.y0 + ly, sgc);
   moments<T>(fc, sdc, mxc, myc);
   uCur = u_tilde<T, SHIFT>(sdc, mxc, myc, fx, urc);
   if (WIDE) uhCur = halo_u(st.y0);
@@ -452,6 +486,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
   for (int yb = st.y0; yb < st.y1; yb += TYW) {
     T sdn, mxn, myn;
     pull_row(yb + TYW + ly, fn, Pn, urn);
+    load_sigma(yb + TYW + ly, sgn);
     if (WIDE) uhNext = halo_u(yb + TYW);
     moments<T>(fn, sdn, mxn, myn);
     uNext = u_tilde<T, SHIFT>(sdn, mxn, myn, fx, urn);
@@ -491,9 +526,10 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
     // Every lane computes; only valid lanes store. Lanes past the strip or
     // outside the channel read clamped rows and their results are dropped.
     const bool ok = (y < st.y1) && colok;
-    T out[9], trT;
+    T out[9], trT, sg[3];
     double obs[OF_COUNT];
-    node_update<T, SHIFT, OBS>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, urc, kref, q, a.nnp, out, trT, obs);
+    node_update<T, SHIFT, OBS, VE>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, urc, kref, q, a.nnp, sgc, sg, out,
+                                   trT, obs);
     if constexpr (OBS) {
       obs[OF_DRAG] = wall_drag<T>(fc, y, ny, uw6);
       constexpr int GW = WIDE ? 64 : TXW;
@@ -512,6 +548,10 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) B[slot(i, o)] = out[i];
         B[slot(9, o)] = trT;
+        if constexpr (VE) {
+#pragma unroll
+          for (int p = 0; p < 3; ++p) SB[sslot(p, o)] = sg[p];
+        }
       }
     }
 
@@ -519,6 +559,8 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
     uCur = uNext;
     uhCur = uhNext;
     urc = urn;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) sgc[p] = sgn[p];
 #pragma unroll
     for (int i = 0; i < 9; ++i) fc[i] = fn[i];
     Pc = Pn;
@@ -531,7 +573,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
 // Aligned 64-column strips of a channel whose width is a multiple of 64
 // (and at least 128). Row y of the strip is tile (off + y nx + x0)/64; lane
 // l owns column x0 + l.
-template <typename T, bool SHIFT, bool OBS>
+template <typename T, bool SHIFT, bool OBS, bool VE>
 __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArgs a) {
   const int lane = threadIdx.x & 63;
   const int sidx = strip_index(a);
@@ -660,8 +702,20 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
     uR = u_tilde<T, SHIFT>(sd, mx, my, fx, urc);
   };
   auto clampy = [&](int y) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
+  // viscoelastic model: the stress of the previous step, one tile row of the
+  // stress buffers (three fields per 64-node tile) per row
+  const T *__restrict__ SA = static_cast<const T *>(a.SA);
+  T *__restrict__ SB = static_cast<T *>(a.SB);
+  auto load_sigma = [&](int y, T sg[3]) {
+    if constexpr (VE) {
+#pragma unroll
+      for (int p = 0; p < 3; ++p) sg[p] = SA[(tile(y) * kStressPlanes + p) * F + lane];
+    } else {
+      sg[0] = sg[1] = sg[2] = T(0);
+    }
+  };
 
-  T fc[9], fn[9], Pc, Pn;
+  T fc[9], fn[9], Pc, Pn, sgc[3], sgn[3];
   U2<T> uPrev, uCur, uNext, uLc, uRc, uLn, uRn;
   {
     T ftmp[9], Ptmp, sd, mx, my;
@@ -671,6 +725,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
   }
   T sdc, mxc, myc;
   pull_row(st.y0, fc, Pc);
+  load_sigma(st.y0, sgc);
   moments<T>(fc, sdc, mxc, myc);
   uCur = u_tilde<T, SHIFT>(sdc, mxc, myc, fx, ref(st.y0));
   halo_u(st.y0, uLc, uRc);
@@ -680,6 +735,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
     const int yn = clampy(y + 1);
     T sdn, mxn, myn;
     pull_row(yn, fn, Pn);
+    load_sigma(yn, sgn);
     halo_u(yn, uLn, uRn);
     moments<T>(fn, sdn, mxn, myn);
     uNext = u_tilde<T, SHIFT>(sdn, mxn, myn, fx, ref(yn));
@@ -699,9 +755,10 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
       kref = T(0.5) * (uru - urd);
     }
 
-    T out[9], trT;
+    T out[9], trT, sg[3];
     double obs[OF_COUNT];
-    node_update<T, SHIFT, OBS>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, urc, kref, q, a.nnp, out, trT, obs);
+    node_update<T, SHIFT, OBS, VE>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, urc, kref, q, a.nnp, sgc, sg, out,
+                                   trT, obs);
     if constexpr (OBS) {
       obs[OF_DRAG] = wall_drag<T>(fc, y, ny, uw6);
 #pragma unroll
@@ -717,12 +774,19 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
 #pragma unroll
       for (int i = 0; i < 9; ++i) w[i * F + lane] = out[i];
       w[9 * F + lane] = trT;
+      if constexpr (VE) {
+        T *ws = SB + tile(y) * (kStressPlanes * F);
+#pragma unroll
+        for (int p = 0; p < 3; ++p) ws[p * F + lane] = sg[p];
+      }
     }
 
     uPrev = uCur;
     uCur = uNext;
     uLc = uLn;
     uRc = uRn;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) sgc[p] = sgn[p];
 #pragma unroll
     for (int i = 0; i < 9; ++i) fc[i] = fn[i];
     Pc = Pn;
@@ -789,7 +853,7 @@ constexpr int kSideTop[25] = {
 // the nine pulled populations of each neighbour column, for its u~) come in
 // one lane-indexed vector load, lane i holding value i, so that they complete
 // in order with the row's other loads; they are read out with readlane.
-template <typename T, bool SHIFT, bool OBS, int NPL, bool NT, bool DOWN>
+template <typename T, bool SHIFT, bool OBS, int NPL, bool NT, bool DOWN, bool VE>
 __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a) {
   typedef typename Vec<T, NPL>::type V;
   constexpr int LPT = 64 / NPL;  // lanes per tile
@@ -854,7 +918,12 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
   // Raw loads of row y: the ten runs (fields 0, 1, 3, 9 of row y; 2, 5, 6 of
   // row y-1 or, at the bottom wall, 4, 7, 8 of row y; 4, 7, 8 of row y+1 or,
   // at the top wall, 2, 5, 6 of row y) and the side values.
+  // viscoelastic model: the stress of the previous step comes with each
+  // row's loads (three fields of this lane's NPL columns)
+  const T *__restrict__ SA = static_cast<const T *>(a.SA);
+  T *__restrict__ SB = static_cast<T *>(a.SB);
   struct Raw {
+    V sg[VE ? 3 : 1];
     V r[10];
     T side;
   };
@@ -881,6 +950,11 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
       ps = (lane >= 24 && lane <= 26) ? pu : ps;
     }
     R.side = *ps;
+    if constexpr (VE) {
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+        R.sg[p] = *reinterpret_cast<const V *>(SA + (tile(y, xt + lt) * kStressPlanes + p) * F + lo);
+    }
   };
   // Pulled populations, P, moments and u~ of the NPL columns of row y, and u~
   // of the two columns beside the strip.
@@ -991,6 +1065,13 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
   T fc[9][NPL], Pc[NPL], sdc[NPL], mxc[NPL], myc[NPL];
   U2<T> uPrev[NPL], uCur[NPL], uLc, uRc;
   T urC[3];  // reference velocities of rows y-1, y, y+1 for the current row
+  T sgc[3][NPL];  // viscoelastic model: stress of the previous step, current row
+  auto take_sigma = [&](const Raw &R, T sg[3][NPL]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) sg[p][k] = VE ? R.sg[VE ? p : 0][k] : T(0);
+  };
   // ring of raw rows: the row i steps ahead of the first lives in slot i mod D
   constexpr int D = LB_VEC_DEPTH;
   Raw S[D];
@@ -1007,6 +1088,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
     U2<T> hl, hr;
     assemble(yp, Rp, ftmp, Ptmp, s0, m0, n0, uPrev, hl, hr, ur_unused);
     assemble(yfirst, Rf, fc, Pc, sdc, mxc, myc, uCur, uLc, uRc, urC);
+    take_sigma(Rf, sgc);
   }
 
   // Row y: start the loads of the row D ahead, assemble the next row (loaded
@@ -1016,6 +1098,8 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
     T fn[9][NPL], Pn[NPL], sdn[NPL], mxn[NPL], myn[NPL], urN[3];
     U2<T> uNext[NPL], uLn, uRn;
     assemble(clampy(y + dir), Rasm, fn, Pn, sdn, mxn, myn, uNext, uLn, uRn, urN);
+    T sgn[3][NPL], sgo[3][NPL];
+    take_sigma(Rasm, sgn);
 
     T out[9][NPL], trT[NPL];
     double obs[OF_COUNT];
@@ -1052,8 +1136,14 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[i] = fc[i][k];
       double ob[OF_COUNT];
-      node_update<T, SHIFT, OBS>(g, sdc[k], mxc[k], myc[k], Pc[k], fx, lf, rt, dn, up, urc, kref, q, a.nnp, o, tr,
-                                 ob);
+      const T sp[3] = {sgc[0][k], sgc[1][k], sgc[2][k]};
+      T sn[3];
+      node_update<T, SHIFT, OBS, VE>(g, sdc[k], mxc[k], myc[k], Pc[k], fx, lf, rt, dn, up, urc, kref, q, a.nnp, sp,
+                                     sn, o, tr, ob);
+      if constexpr (VE) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) sgo[p][k] = sn[p];
+      }
       if constexpr (OBS) {
         ob[OF_DRAG] = wall_drag<T>(g, y, ny, uw6);
 #pragma unroll
@@ -1089,6 +1179,17 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
 #pragma unroll
         for (int i = 0; i < kPlanes; ++i) *reinterpret_cast<V *>(w + i * F) = v[i];
       }
+      if constexpr (VE) {
+        T *ws = SB + tile(y, xt + lt) * (kStressPlanes * F) + lo;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          V vs;
+#pragma unroll
+          for (int k = 0; k < NPL; ++k) vs[k] = sgo[p][k];
+          if constexpr (NT) __builtin_nontemporal_store(vs, reinterpret_cast<V *>(ws + p * F));
+          else *reinterpret_cast<V *>(ws + p * F) = vs;
+        }
+      }
     }
 
     uLc = uLn;
@@ -1096,6 +1197,10 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
     urC[0] = urN[0];
     urC[1] = urN[1];
     urC[2] = urN[2];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) sgc[p][k] = sgn[p][k];
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       uPrev[k] = uCur[k];
@@ -1313,58 +1418,67 @@ __global__ void advance_kernel(ChanDev *ch, int n_ch, int steps) {
   if (i < n_ch && ch[i].active) ch[i].t += steps;
 }
 
-template <typename T, bool SHIFT, int TXW, bool WIDE>
+template <typename T, bool SHIFT, int TXW, bool WIDE, bool VE>
 hipError_t launch_cls(bool observe, const SweepArgs &a, hipStream_t s) {
   if (a.n_strips == 0) return hipSuccess;
   dim3 grid(a.n_wg), block(64 * LB_WG_WAVES);
   if (observe)
-    hipLaunchKernelGGL((sweep_kernel<T, SHIFT, TXW, WIDE, true>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((sweep_kernel<T, SHIFT, TXW, WIDE, true, VE>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((sweep_kernel<T, SHIFT, TXW, WIDE, false>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((sweep_kernel<T, SHIFT, TXW, WIDE, false, VE>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
-template <typename T, bool SHIFT>
+template <typename T, bool SHIFT, bool VE>
 hipError_t launch_wide64(bool observe, const SweepArgs &a, hipStream_t s) {
   if (a.n_strips == 0) return hipSuccess;
   dim3 grid(a.n_wg), block(64 * LB_WG_WAVES);
   if (observe)
-    hipLaunchKernelGGL((sweep_wide64_kernel<T, SHIFT, true>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((sweep_wide64_kernel<T, SHIFT, true, VE>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((sweep_wide64_kernel<T, SHIFT, false>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((sweep_wide64_kernel<T, SHIFT, false, VE>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
-template <typename T, bool SHIFT>
+template <typename T, bool SHIFT, bool VE>
 hipError_t launch_vec(bool observe, const SweepArgs &a, hipStream_t s) {
   if (a.n_strips == 0) return hipSuccess;
   constexpr int NPL = sizeof(T) == 4 ? LB_VEC_NPL32 : LB_VEC_NPL64;
   dim3 grid(a.n_wg), block(64 * LB_WG_WAVES);
   if (observe)
-    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, true, NPL, false, false>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, true, NPL, false, false, VE>), grid, block, 0, s, a);
   else if (a.nt)
-    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, true, false>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, true, false, VE>), grid, block, 0, s, a);
   else if (a.down)
-    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, false, true>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, false, true, VE>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, false, false>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, false, false, VE>), grid, block, 0, s, a);
   return hipGetLastError();
+}
+
+template <typename T, bool SHIFT, bool VE>
+hipError_t launch_model(int cls, bool observe, const SweepArgs &a, hipStream_t s) {
+  switch (cls) {
+    case 0: return launch_cls<T, SHIFT, 1, false, VE>(observe, a, s);
+    case 1: return launch_cls<T, SHIFT, 2, false, VE>(observe, a, s);
+    case 2: return launch_cls<T, SHIFT, 4, false, VE>(observe, a, s);
+    case 3: return launch_cls<T, SHIFT, 8, false, VE>(observe, a, s);
+    case 4: return launch_cls<T, SHIFT, 16, false, VE>(observe, a, s);
+    case 5: return launch_cls<T, SHIFT, 32, false, VE>(observe, a, s);
+    case 6: return launch_cls<T, SHIFT, 64, false, VE>(observe, a, s);
+    case kWide64Class: return launch_wide64<T, SHIFT, VE>(observe, a, s);
+    case kVecClass: return launch_vec<T, SHIFT, VE>(observe, a, s);
+    default: return launch_cls<T, SHIFT, 64, true, VE>(observe, a, s);
+  }
 }
 
 template <typename T, bool SHIFT>
 hipError_t launch_prec(int cls, bool observe, const SweepArgs &a, hipStream_t s) {
-  switch (cls) {
-    case 0: return launch_cls<T, SHIFT, 1, false>(observe, a, s);
-    case 1: return launch_cls<T, SHIFT, 2, false>(observe, a, s);
-    case 2: return launch_cls<T, SHIFT, 4, false>(observe, a, s);
-    case 3: return launch_cls<T, SHIFT, 8, false>(observe, a, s);
-    case 4: return launch_cls<T, SHIFT, 16, false>(observe, a, s);
-    case 5: return launch_cls<T, SHIFT, 32, false>(observe, a, s);
-    case 6: return launch_cls<T, SHIFT, 64, false>(observe, a, s);
-    case kWide64Class: return launch_wide64<T, SHIFT>(observe, a, s);
-    case kVecClass: return launch_vec<T, SHIFT>(observe, a, s);
-    default: return launch_cls<T, SHIFT, 64, true>(observe, a, s);
+  if (a.ve) {
+    if (!a.SA || !a.SB) return hipErrorInvalidValue;
+    return launch_model<T, SHIFT, true>(cls, observe, a, s);
   }
+  return launch_model<T, SHIFT, false>(cls, observe, a, s);
 }
 
 }  // namespace

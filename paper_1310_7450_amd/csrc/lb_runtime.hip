@@ -41,6 +41,7 @@ struct Layout {
   int max_strips = 0;
   size_t off_state[2] = {0, 0}, off_ch = 0, off_strips = 0, off_astrips = 0, off_rstrips = 0, off_part = 0,
          off_prof = 0, off_prev = 0, off_scal = 0, off_uref = 0, bytes = 0;
+  size_t off_stress[2] = {0, 0};  // viscoelastic model only
   std::vector<ChanDev> ch;
 };
 
@@ -53,6 +54,7 @@ std::string validate(const lb_channel *c, int n, const lb_options *o) {
     return "obs_every must be 0 or an even number >= 2";
   if (o->strip_rows < 0 || o->strip_rows > 4096) return "strip_rows out of range";
   if (!(o->steady_tol >= 0) || !std::isfinite(o->steady_tol)) return "steady_tol must be >= 0";
+  if (o->viscoelastic != 0 && o->viscoelastic != 1) return "viscoelastic must be 0 or 1";
   for (int i = 0; i < n; ++i) {
     const lb_channel &q = c[i];
     char buf[160];
@@ -178,6 +180,11 @@ Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
   L.off_prev = take(sizeof(double) * rows);
   L.off_scal = take(sizeof(double) * CS_COUNT * n);
   L.off_uref = take(sizeof(float) * rows);
+  if (o->viscoelastic) {
+    const size_t stress = (size_t)kStressPlanes * L.plane * L.esize;
+    L.off_stress[0] = take(stress);
+    L.off_stress[1] = take(stress);
+  }
   L.bytes = at;
   return L;
 }
@@ -198,6 +205,7 @@ struct lb_handle {
   Strip *dact_rev = nullptr; // the same, each class group in reverse order
   double *dpart = nullptr, *dprof = nullptr, *dprev = nullptr, *dscal = nullptr;
   float *duref = nullptr;    // FP32: reference velocity of every row
+  void *sbuf[2] = {nullptr, nullptr};  // viscoelastic model: stress buffers (same parity as buf)
   // strips grouped by width class: [begin, begin + count) in the arrays
   int all_begin[kClasses] = {0}, all_count[kClasses] = {0};
   int act_begin[kClasses] = {0}, act_count[kClasses] = {0};
@@ -289,6 +297,9 @@ SweepArgs sweep_args(lb_handle *h, const Strip *strips, int begin, int count, in
   a.nnp = h->opt.nn_pressure;
   a.nt = (long long)kPlanes * h->L.plane * h->L.esize > kNontemporalBytes;
   a.uref = h->duref;
+  a.ve = h->opt.viscoelastic;
+  a.SA = h->sbuf[src];
+  a.SB = h->sbuf[src ^ 1];
   return a;
 }
 
@@ -490,6 +501,10 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
   h->dprev = reinterpret_cast<double *>(h->ws + h->L.off_prev);
   h->dscal = reinterpret_cast<double *>(h->ws + h->L.off_scal);
   h->duref = reinterpret_cast<float *>(h->ws + h->L.off_uref);
+  if (o->viscoelastic) {
+    h->sbuf[0] = h->ws + h->L.off_stress[0];
+    h->sbuf[1] = h->ws + h->L.off_stress[1];
+  }
   h->t.assign(n, 0);
   h->active.assign(n, 1);
   auto bail = [&](lb_status s) {
@@ -518,6 +533,11 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
     return bail(LB_EHIP);
   if (upload_strips(h, true) != LB_OK || upload_strips(h, false) != LB_OK) return bail(LB_EHIP);
   if (fill_rest(h, 0) != LB_OK || fill_rest(h, 1) != LB_OK) return bail(LB_EHIP);
+  // zero stress at rest (outside any graph)
+  for (int b = 0; b < 2; ++b)
+    if (h->sbuf[b] &&
+        hipMemsetAsync(h->sbuf[b], 0, (size_t)kStressPlanes * h->L.plane * h->L.esize, h->stream) != hipSuccess)
+      return bail(LB_EHIP);
   if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(LB_EHIP);
   *out = h;
   return LB_OK;
@@ -762,6 +782,60 @@ lb_status lb_set_state(lb_handle *h, int32_t ch, const double *pops, const doubl
                              hipMemcpyHostToDevice, h->stream));
   HIPCHECK(h, hipStreamSynchronize(h->stream));
   h->t[ch] = t;
+  h->obs_valid = false;
+  return LB_OK;
+}
+
+lb_status lb_get_stress(lb_handle *h, int32_t ch, double *sigma) {
+  if (!h) return LB_EINVAL;
+  if (ch < 0 || ch >= h->n_ch || !sigma) return fail(h, LB_EINVAL, "bad channel or output");
+  if (!h->opt.viscoelastic) return fail(h, LB_EINVAL, "the handle runs the instantaneous model (no stored stress)");
+  const ChanDev &d = h->L.ch[ch];
+  const size_t N = (size_t)d.nx * d.ny;
+  const size_t Npad = align_up(N, kTile);
+  const int es = h->L.esize;
+  // the channel's stress tiles are one contiguous block of the buffer
+  std::vector<char> raw((size_t)kStressPlanes * Npad * es);
+  const char *src = static_cast<const char *>(h->sbuf[h->cur]);
+  HIPCHECK(h, hipMemcpyAsync(raw.data(), src + (size_t)sslot(0, d.off) * es, raw.size(), hipMemcpyDeviceToHost,
+                             h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  for (int p = 0; p < kStressPlanes; ++p)
+    for (size_t id = 0; id < N; ++id) {
+      const size_t k = (size_t)sslot(p, (long long)id);
+      sigma[(size_t)p * N + id] = es == 8 ? reinterpret_cast<const double *>(raw.data())[k]
+                                          : (double)reinterpret_cast<const float *>(raw.data())[k];
+    }
+  return LB_OK;
+}
+
+lb_status lb_set_stress(lb_handle *h, int32_t ch, const double *sigma) {
+  if (!h) return LB_EINVAL;
+  if (ch < 0 || ch >= h->n_ch || !sigma) return fail(h, LB_EINVAL, "bad channel or input");
+  if (!h->opt.viscoelastic) return fail(h, LB_EINVAL, "the handle runs the instantaneous model (no stored stress)");
+  const ChanDev &d = h->L.ch[ch];
+  const size_t N = (size_t)d.nx * d.ny;
+  const size_t Npad = align_up(N, kTile);
+  const int es = h->L.esize;
+  // start from the device copy so the padding slots of the last tile keep
+  // their values
+  std::vector<char> raw((size_t)kStressPlanes * Npad * es);
+  char *dst = static_cast<char *>(h->sbuf[h->cur]);
+  HIPCHECK(h, hipMemcpyAsync(raw.data(), dst + (size_t)sslot(0, d.off) * es, raw.size(), hipMemcpyDeviceToHost,
+                             h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  for (int p = 0; p < kStressPlanes; ++p)
+    for (size_t id = 0; id < N; ++id) {
+      const size_t k = (size_t)sslot(p, (long long)id);
+      const double v = sigma[(size_t)p * N + id];
+      if (es == 8)
+        reinterpret_cast<double *>(raw.data())[k] = v;
+      else
+        reinterpret_cast<float *>(raw.data())[k] = (float)v;
+    }
+  HIPCHECK(h, hipMemcpyAsync(dst + (size_t)sslot(0, d.off) * es, raw.data(), raw.size(), hipMemcpyHostToDevice,
+                             h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
   h->obs_valid = false;
   return LB_OK;
 }

@@ -27,8 +27,8 @@ STATUS = {0: "LB_OK", -1: "LB_EINVAL", -2: "LB_ENOMEM", -3: "LB_EHIP", -4: "LB_E
 
 # Names of every function include/lb.h declares.
 ABI_FUNCTIONS = ["lb_workspace_bytes", "lb_create", "lb_destroy", "lb_step", "lb_observe",
-                 "lb_get_state", "lb_set_state", "lb_set_profile", "lb_last_error",
-                 "lb_status_string"]
+                 "lb_get_state", "lb_set_state", "lb_get_stress", "lb_set_stress", "lb_set_profile",
+                 "lb_last_error", "lb_status_string"]
 
 
 class LbChannel(C.Structure):
@@ -40,7 +40,7 @@ class LbChannel(C.Structure):
 
 class LbOptions(C.Structure):
     _fields_ = [("precision", C.c_int32), ("nn_pressure", C.c_int32), ("obs_every", C.c_int32),
-                ("strip_rows", C.c_int32), ("steady_tol", C.c_double)]
+                ("strip_rows", C.c_int32), ("steady_tol", C.c_double), ("viscoelastic", C.c_int32)]
 
 
 class LbError(RuntimeError):
@@ -68,6 +68,8 @@ def load_library():
     L.lb_observe.argtypes = [vp, C.c_int32, C.c_int32, dp, sz]
     L.lb_get_state.argtypes = [vp, C.c_int32, dp, dp]
     L.lb_set_state.argtypes = [vp, C.c_int32, dp, dp, C.c_int64]
+    L.lb_get_stress.argtypes = [vp, C.c_int32, dp]
+    L.lb_set_stress.argtypes = [vp, C.c_int32, dp]
     L.lb_set_profile.argtypes = [vp, C.c_int32, dp, dp, C.c_int32, C.c_int32]
     L.lb_last_error.argtypes = [vp]
     L.lb_last_error.restype = C.c_char_p
@@ -107,10 +109,11 @@ def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def options(precision=FP64, nn_pressure=True, obs_every=1000, strip_rows=0, steady_tol=0.0):
+def options(precision=FP64, nn_pressure=True, obs_every=1000, strip_rows=0, steady_tol=0.0, viscoelastic=False):
     if isinstance(precision, str):
         precision = {"fp64": FP64, "fp32": FP32_SHIFTED, "fp32_shifted": FP32_SHIFTED}[precision]
-    return LbOptions(int(precision), int(bool(nn_pressure)), int(obs_every), int(strip_rows), float(steady_tol))
+    return LbOptions(int(precision), int(bool(nn_pressure)), int(obs_every), int(strip_rows), float(steady_tol),
+                     int(bool(viscoelastic)))
 
 
 def workspace_bytes(channels: Sequence[ChannelSpec], opts: LbOptions) -> int:
@@ -124,16 +127,18 @@ def workspace_bytes(channels: Sequence[ChannelSpec], opts: LbOptions) -> int:
 
 
 class Solver:
-    """A handle of the C library over ``channels``, on one CUDA/HIP stream."""
+    """A handle of the C library over ``channels``, on one CUDA/HIP stream.
+    ``viscoelastic`` selects the time-integrated nonlinear Maxwell stress
+    (lb_options.viscoelastic) in place of the instantaneous one."""
 
     def __init__(self, channels: Sequence[ChannelSpec], precision="fp64", nn_pressure=True,
-                 obs_every=1000, strip_rows=0, steady_tol=0.0, stream=None, device="cuda"):
+                 obs_every=1000, strip_rows=0, steady_tol=0.0, stream=None, device="cuda", viscoelastic=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("lbnlm needs a GPU; no CPU fallback exists")
         self.L = load_library()
         self.channels = list(channels)
-        self.opts = options(precision, nn_pressure, obs_every, strip_rows, steady_tol)
+        self.opts = options(precision, nn_pressure, obs_every, strip_rows, steady_tol, viscoelastic)
         nbytes = workspace_bytes(self.channels, self.opts)
         self.device = torch.device(device)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -183,6 +188,20 @@ class Solver:
         c = self.channels[ch]
         assert pops.shape == (9, c.ny, c.nx) and P.shape == (c.ny, c.nx)
         self._check(self.L.lb_set_state(self.h, ch, _dp(pops), _dp(P), int(t)))
+
+    def get_stress(self, ch: int):
+        """Stored stress sigma(t-1) of channel ch as [3, ny, nx] (xx, xy, yy);
+        viscoelastic handles only."""
+        c = self.channels[ch]
+        sig = np.zeros((3, c.ny, c.nx))
+        self._check(self.L.lb_get_stress(self.h, ch, _dp(sig)))
+        return sig
+
+    def set_stress(self, ch: int, sigma):
+        sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+        c = self.channels[ch]
+        assert sigma.shape == (3, c.ny, c.nx)
+        self._check(self.L.lb_set_stress(self.h, ch, _dp(sigma)))
 
     def set_profile(self, ch: int, ux, n1, points="rows"):
         """Warm start of channel ch from u_x and N1 at the lattice rows

@@ -71,6 +71,13 @@ def random_state(nx, ny, seed, amplitude=1e-3):
     return np.ascontiguousarray(pops), np.ascontiguousarray(P)
 
 
+def random_stress(nx, ny, seed, amplitude=1e-6):
+    """Seeded random stress fields sigma[3][ny][nx] (xx, xy, yy) in the layout
+    of ``lb_get_stress``, for state tests of the time-integrated model."""
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(amplitude * rng.uniform(-1, 1, size=(3, ny, nx)))
+
+
 # Admission rules of the batched sweep (input recipe; see the design notes):
 # the explicit stress is well conditioned for G_inf tau <= 0.3 at
 # visc_split 0 (a measured stability map of the scheme), and the low-Mach
