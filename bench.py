@@ -5,7 +5,9 @@ channel (every node pulled, stress evaluated, collided and stored). The
 headline value is FP32-shifted MLUPS (million lattice-node updates per
 second) with the state resident in HBM; the FP64 run of the same workload is
 reported beside it, and the FP64 CPU oracle is timed on a bounded sample of
-the same lattice on the host.
+the same lattice on the host. Further legs: the batched channels to steady
+state, the 16 x 8192 x 2048 start-up lattice, the same 4096 x 1024 lattice
+with the time-integrated (viscoelastic) stress, and the learned warm start.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu]
 """
@@ -22,8 +24,10 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS + % HBM roofline (FP32 vs FP64); steps-to-steady, learned vs from-rest"
 HBM_PEAK_GBS = 8000.0
 # Algorithmic HBM bytes per node update: read 9 populations + the previous
-# stress trace, write 9 populations + the new trace.
+# stress trace, write 9 populations + the new trace; the time-integrated
+# (viscoelastic) model also reads and writes the three stress fields.
 BYTES_PER_NODE = {"fp32": 80, "fp64": 160}
+BYTES_PER_NODE_VE = {"fp32": 104, "fp64": 208}
 
 
 def measured_traffic(key):
@@ -44,12 +48,13 @@ def measured_traffic(key):
     return None if k is None else round(k["traffic_bytes"])
 
 
-def time_solver(precision, wl, steps, warmup, strip_rows=0):
+def time_solver(precision, wl, steps, warmup, strip_rows=0, viscoelastic=False):
     import torch
     from paper_1310_7450_amd import Solver
     spec = wl["channels"][0]
     nodes = spec.nx * spec.ny
-    with Solver([spec], precision=precision, obs_every=1000, strip_rows=strip_rows) as s:
+    with Solver([spec], precision=precision, obs_every=1000, strip_rows=strip_rows,
+                viscoelastic=viscoelastic) as s:
         s.step(warmup)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -66,7 +71,7 @@ def time_solver(precision, wl, steps, warmup, strip_rows=0):
     sec = ms / 1e3
     per_step = sec / steps
     mlups = nodes * steps / sec / 1e6
-    achieved = BYTES_PER_NODE[precision] * nodes / per_step / 1e9
+    achieved = (BYTES_PER_NODE_VE if viscoelastic else BYTES_PER_NODE)[precision] * nodes / per_step / 1e9
     return {"mlups": mlups, "ms_total": ms, "ms_per_step": ms / steps, "wall_s": wall,
             "achieved_GBs": achieved, "frac": achieved / HBM_PEAK_GBS, "umid": umid,
             "mass_rel_drift": (mass - nodes) / nodes}
@@ -133,6 +138,23 @@ def run_transient_scale(steps=200, warmup=50):
             "unit": "MLUPS", "ms_per_step": round(sec * 1e3 / steps, 4),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("transient_fp32")}}
+
+
+def run_viscoelastic(steps=2000, warmup=1000):
+    """The same 4096 x 1024 workload with the time-integrated nonlinear
+    Maxwell stress (three more fields per node read and written), FP32 and
+    FP64."""
+    from paper_1310_7450_amd import workloads
+    wl = workloads.large_channel()
+    out = {"workload": wl["name"] + "_viscoelastic", "steps": steps}
+    for prec in ("fp32", "fp64"):
+        r = time_solver(prec, wl, steps, warmup, viscoelastic=True)
+        out[prec] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
+                     "bytes_per_node": BYTES_PER_NODE_VE[prec],
+                     "roofline": {"bound": "hbm", "achieved": round(r["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
+                                  "unit": "GB/s", "frac": round(r["frac"], 4),
+                                  "traffic": measured_traffic("ve_" + prec)}}
+    return out
 
 
 def run_warm_start(verbose=True):
@@ -219,6 +241,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-channel sweep")
     ap.add_argument("--no-transient", action="store_true", help="skip the 16 x 8192 x 2048 throughput leg")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start experiment")
+    ap.add_argument("--no-viscoelastic", action="store_true", help="skip the time-integrated stress leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB, 5 times (counter calibration)")
     args = ap.parse_args()
@@ -266,6 +289,12 @@ def main():
         transient = run_transient_scale()
         print(f"bench: transient_scale {transient['value']:.0f} MLUPS "
               f"({100 * transient['roofline']['frac']:.1f}% of HBM peak)", file=sys.stderr, flush=True)
+    ve = None
+    if not args.no_viscoelastic:
+        ve = run_viscoelastic()
+        print(f"bench: viscoelastic fp32 {ve['fp32']['value']:.0f} MLUPS "
+              f"({100 * ve['fp32']['roofline']['frac']:.1f}%), fp64 {ve['fp64']['value']:.0f} MLUPS "
+              f"({100 * ve['fp64']['roofline']['frac']:.1f}%)", file=sys.stderr, flush=True)
     warm = None
     if not args.no_warm:
         warm = run_warm_start()
@@ -302,6 +331,7 @@ def main():
                          "unit": "GB/s", "frac": round(r64["frac"], 4), "traffic": measured_traffic("fp64")}},
         "batched": batched,
         "transient_scale": transient,
+        "viscoelastic": ve,
         "warm_start": warm,
         "cpu_baseline": cpu,
     }

@@ -140,7 +140,7 @@ def train(X, Y, steps=4000, batch=256, lr=1e-3, seed=0, verbose=True):
         net.adam_step(lr=lr * 0.5 * (1 + math.cos(math.pi * it / steps)) + 1e-5)
         if want:
             hist.append((it, loss))
-            if verbose:
+            if verbose and (it % 5000 == 0 or it == steps - 1):
                 print(f"warmstart: train step {it} loss {loss:.4e}", file=sys.stderr, flush=True)
     return net, norm, hist
 
@@ -160,8 +160,8 @@ def predict(net, norm, specs):
     return res
 
 
-def experiment(train_seeds=range(100, 116), test_seed=200, n_per_seed=256, train_steps=4000, agree_tol=5e-3,
-               n_test=None, verbose=True, details=False):
+def experiment(train_seeds=range(100, 116), test_seed=200, n_per_seed=256, train_steps=20000, train_lr=2e-3,
+               train_batch=512, agree_tol=5e-3, n_test=None, verbose=True, details=False):
     """Trains on steady states of ``train_seeds`` and warm-starts the held-out
     ``test_seed`` batch (its first ``n_test`` channels, default all); returns
     a report of steps to steady, warm vs rest, and with ``details`` also the
@@ -169,7 +169,7 @@ def experiment(train_seeds=range(100, 116), test_seed=200, n_per_seed=256, train
     t0 = time.perf_counter()
     specs, X, Y = generate(list(train_seeds), n_per_seed, verbose)
     t_gen = time.perf_counter() - t0
-    net, norm, hist = train(X, Y, steps=train_steps, verbose=verbose)
+    net, norm, hist = train(X, Y, steps=train_steps, batch=train_batch, lr=train_lr, verbose=verbose)
     t_train = time.perf_counter() - t0 - t_gen
     test = workloads.batched_sweep(seed=test_seed, n_channels=n_per_seed)["channels"]
     if n_test is not None:
