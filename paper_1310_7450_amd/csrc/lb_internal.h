@@ -53,9 +53,10 @@ struct ChanDev {
 };
 
 // Work unit of one wavefront: rows [y0, y1) of channel ch, starting at
-// column x0 (wide mode: first interior column; narrow mode: 0).
+// column x0 (wide mode: first interior column; narrow mode: 0). flip: the
+// vector sweep marches this strip against the step's direction (odd bands).
 struct Strip {
-  int ch, x0, y0, y1;
+  int ch, x0, y0, y1, flip;
 };
 
 struct SweepArgs {

@@ -853,7 +853,7 @@ constexpr int kSideTop[25] = {
 // the nine pulled populations of each neighbour column, for its u~) come in
 // one lane-indexed vector load, lane i holding value i, so that they complete
 // in order with the row's other loads; they are read out with readlane.
-template <typename T, bool SHIFT, bool OBS, int NPL, bool NT, bool DOWN, bool VE>
+template <typename T, bool SHIFT, bool OBS, int NPL, bool NT, bool VE>
 __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a) {
   typedef typename Vec<T, NPL>::type V;
   constexpr int LPT = 64 / NPL;  // lanes per tile
@@ -1057,10 +1057,12 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
   };
   auto clampy = [&](int y) __attribute__((always_inline)) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
 
-  // The march runs upwards from y0, or with DOWN downwards from y1 - 1; "prev"
-  // and "next" are the rows behind and ahead of the current one.
-  constexpr int dir = DOWN ? -1 : 1;
-  const int yfirst = DOWN ? st.y1 - 1 : st.y0;
+  // The march runs upwards from y0, or downwards from y1 - 1 (the step's
+  // direction, reversed on flipped strips); "prev" and "next" are the rows
+  // behind and ahead of the current one.
+  const bool down = (a.down != 0) != (st.flip != 0);
+  const int dir = down ? -1 : 1;
+  const int yfirst = down ? st.y1 - 1 : st.y0;
   const int nrows = st.y1 - st.y0;
   T fc[9][NPL], Pc[NPL], sdc[NPL], mxc[NPL], myc[NPL];
   U2<T> uPrev[NPL], uCur[NPL], uLc, uRc;
@@ -1128,7 +1130,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
       } else {
         rt = uCur[k + 1];
       }
-      U2<T> dn = DOWN ? uNext[k] : uPrev[k], up = DOWN ? uPrev[k] : uNext[k];
+      U2<T> dn = down ? uNext[k] : uPrev[k], up = down ? uPrev[k] : uNext[k];
       // no-slip ghosts behind the half-way walls
       if (y == 0) dn = U2<T>{-uCur[k].x, -uCur[k].y};
       if (y == ny - 1) up = U2<T>{(SHIFT ? T(0) : T(2) * uwg) - uCur[k].x, -uCur[k].y};
@@ -1446,13 +1448,11 @@ hipError_t launch_vec(bool observe, const SweepArgs &a, hipStream_t s) {
   constexpr int NPL = sizeof(T) == 4 ? LB_VEC_NPL32 : LB_VEC_NPL64;
   dim3 grid(a.n_wg), block(64 * LB_WG_WAVES);
   if (observe)
-    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, true, NPL, false, false, VE>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, true, NPL, false, VE>), grid, block, 0, s, a);
   else if (a.nt)
-    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, true, false, VE>), grid, block, 0, s, a);
-  else if (a.down)
-    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, false, true, VE>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, true, VE>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, false, false, VE>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, false, VE>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 

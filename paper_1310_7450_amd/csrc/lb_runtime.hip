@@ -128,13 +128,29 @@ int strip_rows_for(int cls, int nx, int ny, int requested) {
 // Strips of one channel in row-band order: the strips of one band of rows
 // are consecutive (x neighbours, which share cache lines at their edges,
 // land on the same XCD), and bands follow each other upwards.
-void add_strips(int ci, const ChanDev &d, int esize, int srows, std::vector<Strip> &out) {
+// With stack set, vector-sweep strips come in stacks of kWaves bands at one
+// x, so that one workgroup (one CU) holds vertically adjacent strips, and odd
+// bands march against the step's direction: two neighbouring strips then
+// reach the rows they share (each one's halo and prefetch overrun) at the
+// same time, and the second read hits in cache. That pays while a state
+// buffer fits the last-level cache (measured: +1.4 points of HBM peak on
+// 4096 x 1024 FP32); on larger states the row-band order of x neighbours is
+// faster (-1.3 points with stacks on 16 x 8192 x 2048).
+void add_strips(int ci, const ChanDev &d, int esize, int srows, bool stack, std::vector<Strip> &out) {
   const int cls = width_class(d.nx, esize);
   const int w = strip_cols(cls, esize);
   const int nxs = is_strip_class(cls) ? (d.nx + w - 1) / w : 1;
-  for (int y0 = 0; y0 < d.ny; y0 += srows)
+  const int nb = (d.ny + srows - 1) / srows;
+  if (cls == kVecClass && stack) {
+    for (int b0 = 0; b0 < nb; b0 += kWaves)
+      for (int xs = 0; xs < nxs; ++xs)
+        for (int b = b0; b < std::min(b0 + kWaves, nb); ++b)
+          out.push_back(Strip{ci, xs * w, b * srows, std::min((b + 1) * srows, d.ny), b & 1});
+    return;
+  }
+  for (int b = 0; b < nb; ++b)
     for (int xs = 0; xs < nxs; ++xs)
-      out.push_back(Strip{ci, xs * w, y0, std::min(y0 + srows, d.ny)});
+      out.push_back(Strip{ci, xs * w, b * srows, std::min((b + 1) * srows, d.ny), 0});
 }
 
 Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
@@ -253,11 +269,14 @@ void group_strips(const std::vector<Strip> &s, const std::vector<ChanDev> &ch, i
 
 lb_status upload_strips(lb_handle *h, bool all) {
   std::vector<Strip> raw, grouped;
+  // stacks while a state buffer fits the last-level cache (the stores are
+  // then cached, see sweep_args)
+  const bool stack = (long long)kPlanes * h->L.plane * h->L.esize <= kNontemporalBytes;
   for (int i = 0; i < h->n_ch; ++i) {
     if (!all && !h->active[i]) continue;
     const ChanDev &d = h->L.ch[i];
     add_strips(i, d, h->L.esize, strip_rows_for(width_class(d.nx, h->L.esize), d.nx, d.ny, h->opt.strip_rows),
-               raw);
+               stack, raw);
   }
   if (all) {
     group_strips(raw, h->L.ch, h->L.esize, grouped, h->all_begin, h->all_count);
