@@ -1063,6 +1063,12 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
   const bool down = (a.down != 0) != (st.flip != 0);
   const int dir = down ? -1 : 1;
   const int yfirst = down ? st.y1 - 1 : st.y0;
+  // Rows the ring loads: the strip and its two halo rows. Its last loads run
+  // past the far halo row and are never assembled; they re-read that halo
+  // row (fetched a row or two earlier, so from cache) instead of new rows.
+  auto ring_row = [&](int y) __attribute__((always_inline)) {
+    return clampy(y < st.y0 - 1 ? st.y0 - 1 : (y > st.y1 ? st.y1 : y));
+  };
   const int nrows = st.y1 - st.y0;
   T fc[9][NPL], Pc[NPL], sdc[NPL], mxc[NPL], myc[NPL];
   U2<T> uPrev[NPL], uCur[NPL], uLc, uRc;
@@ -1085,7 +1091,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
     load_raw(yp, Rp);
     load_raw(yfirst, Rf);
 #pragma unroll
-    for (int k = 1; k < D; ++k) load_raw(clampy(yfirst + dir * k), S[k]);
+    for (int k = 1; k < D; ++k) load_raw(ring_row(yfirst + dir * k), S[k]);
     T ftmp[9][NPL], Ptmp[NPL], s0[NPL], m0[NPL], n0[NPL], ur_unused[3];
     U2<T> hl, hr;
     assemble(yp, Rp, ftmp, Ptmp, s0, m0, n0, uPrev, hl, hr, ur_unused);
@@ -1096,7 +1102,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
   // Row y: start the loads of the row D ahead, assemble the next row (loaded
   // D - 1 rows earlier), update and store row y.
   auto row_step = [&](int y, Raw &Rload, const Raw &Rasm) __attribute__((always_inline)) {
-    load_raw(clampy(y + dir * D), Rload);  // unconditional: a branch here costs more than the loads
+    load_raw(ring_row(y + dir * D), Rload);  // unconditional: a branch here costs more than the loads
     T fn[9][NPL], Pn[NPL], sdn[NPL], mxn[NPL], myn[NPL], urN[3];
     U2<T> uNext[NPL], uLn, uRn;
     assemble(clampy(y + dir), Rasm, fn, Pn, sdn, mxn, myn, uNext, uLn, uRn, urN);
