@@ -28,7 +28,7 @@ class OrcParams(C.Structure):
     _fields_ = [("g", C.c_double), ("tau_eff", C.c_double), ("G", C.c_double),
                 ("tau", C.c_double), ("gamma_c", C.c_double), ("lam", C.c_double),
                 ("t_startup", C.c_longlong), ("nn_pressure", C.c_int), ("uw", C.c_double),
-                ("dp", C.c_double), ("ve", C.c_int)]
+                ("dp", C.c_double), ("ve", C.c_int), ("saf", C.c_int)]
 
 
 def lib():
@@ -38,7 +38,7 @@ def lib():
         L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         L.orc_resolve.argtypes = [C.c_double] * 6 + [C.c_double, C.c_longlong, C.c_int, C.c_double,
-                                                     C.c_double, C.c_int, C.POINTER(OrcParams)]
+                                                     C.c_double, C.c_int, C.c_int, C.POINTER(OrcParams)]
         L.orc_resolve.restype = C.c_int
         L.orc_equilibrium.argtypes = [C.c_double] * 3 + [dp]
         L.orc_forcing.argtypes = [C.c_double, dp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, dp]
@@ -113,11 +113,12 @@ def tau_M(kappa, tau, gamma_c):
 
 
 def resolve(tau_lb, G, tau0, gamma_c, eps=0.0, visc_split=0.0, force=0.0,
-            t_startup=2 ** 62, nn_pressure=True, wall_velocity=0.0, pressure_drop=0.0, viscoelastic=False):
+            t_startup=2 ** 62, nn_pressure=True, wall_velocity=0.0, pressure_drop=0.0, viscoelastic=False,
+            stress_force=False):
     p = OrcParams()
     rc = lib().orc_resolve(tau_lb, G, tau0, gamma_c, eps, visc_split, force,
                            int(t_startup), int(bool(nn_pressure)), float(wall_velocity),
-                           float(pressure_drop), int(bool(viscoelastic)), C.byref(p))
+                           float(pressure_drop), int(bool(viscoelastic)), int(bool(stress_force)), C.byref(p))
     if rc != 0:
         raise ValueError("invalid channel parameters")
     return p
@@ -128,18 +129,20 @@ class Channel:
 
     def __init__(self, nx, ny, force, tau_lb=1.0, G=1e-4, tau0=1e4, gamma_c=0.1,
                  eps=0.0, visc_split=0.0, t_startup=2 ** 62, nn_pressure=True, wall_velocity=0.0,
-                 pressure_gradient=0.0, viscoelastic=False):
+                 pressure_gradient=0.0, viscoelastic=False, stress_force=False):
         """wall_velocity: x velocity of the top wall while t < t_startup
         (planar Couette flow); 0 gives the channel with two fixed walls.
         pressure_gradient: pressure drop per unit length G_p imposed by
         generalised periodic boundaries (R10: p+ - p- = (nx + 1) G_p between
         the virtual nodes; needs force 0 and nn_pressure False).
         viscoelastic: the time-integrated nonlinear Maxwell stress (R11),
-        carried in ``S`` from step to step, in place of the instantaneous one."""
+        carried in ``S`` from step to step, in place of the instantaneous one.
+        stress_force: the non-Newtonian stress enters as the force density
+        div Sigma^nN (R12; needs nn_pressure False)."""
         self.nx, self.ny = int(nx), int(ny)
         self.params = resolve(tau_lb, G, tau0, gamma_c, eps, visc_split, force,
                               t_startup, nn_pressure, wall_velocity, (self.nx + 1) * pressure_gradient,
-                              viscoelastic)
+                              viscoelastic, stress_force)
         self.n = np.empty((9, self.ny, self.nx))
         self.P = np.empty((self.ny, self.nx))
         self.S = np.zeros((3, self.ny, self.nx))

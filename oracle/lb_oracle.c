@@ -85,6 +85,19 @@
  *      models coincide. The stress of step t then enters the forcing as in
  *      the instantaneous model. The state carries sigma(t-1) (three more
  *      fields per node, zero at rest).
+ *   R12 stress as a force (the alternative Sec. II.C names: the divergence of
+ *      the stress taken as an external force density in Eq. (ns)): the
+ *      non-Newtonian stress Sigma^nN = sigma - lambda G tau D of every node
+ *      is formed first (kappa from u~ = (m + rho0 g/2)/s as in R2); the
+ *      forcing then carries the total force f = rho0 g + div Sigma^nN in its
+ *      body-force terms only, with no stress term in its second moment and
+ *      no flow-induced density (the trace acts through the divergence, so
+ *      r = 0). div Sigma^nN is taken by central differences, x periodic, with
+ *      ghost rows extrapolated linearly through the walls,
+ *      Sigma(-1) = 2 Sigma(0) - Sigma(1), Sigma(ny) = 2 Sigma(ny-1) -
+ *      Sigma(ny-2) (one row: zero gradient), so that the summed force is
+ *      the stress at the half-way walls. The equilibrium and forcing use
+ *      u = (m + f/2)/s.
  *
  * Lattice units: dx = dt = 1, rho0 = 1, c_s^2 = 1/3, d = 2.
  * Storage: populations n[i][y][x] (nine planes, x fastest), the previous
@@ -124,17 +137,21 @@ typedef struct {
   double uw;        /* x velocity of the top wall while t < t_startup (R9)   */
   double dp;        /* pressure drop p+ - p- across the period (R10), 0: off */
   int ve;           /* 1: time-integrated stress (R11); 0: instantaneous     */
+  int saf;          /* 1: stress as a force density (R12)                    */
 } orc_params;
 
 /* Parameter resolution (readings R7, R8). Returns 0, or -1 for invalid input. */
 int orc_resolve(double tau_lb, double G, double tau0, double gamma_c, double eps,
                 double lam, double g, long long t_startup, int nn_pressure, double uw,
-                double dp, int ve, orc_params *out) {
+                double dp, int ve, int saf, orc_params *out) {
   if (!(tau_lb > 0.5) || !(G >= 0) || !(tau0 > 0) || !(gamma_c > 0) ||
       !(lam >= 0 && lam <= 1) || !isfinite(g) || !isfinite(eps) || !isfinite(uw) || !isfinite(dp))
     return -1;
   /* the pressure drive keeps the first line of Eq. (bodyforce) only */
   if (dp != 0 && (g != 0 || nn_pressure || uw != 0)) return -1;
+  /* the stress force replaces the second-moment stress term and the
+   * flow-induced density, and is defined for the instantaneous model */
+  if (saf && (nn_pressure || ve)) return -1;
   double eta_s = (tau_lb - 0.5) / 3.0;
   double tau = tau0 * pow(10.0, fmin(eps, 0.0) / 0.05);
   double Ginf = G * (1.0 + sqrt(fmax(eps, 0.0)));
@@ -150,6 +167,7 @@ int orc_resolve(double tau_lb, double G, double tau0, double gamma_c, double eps
   out->uw = uw;
   out->dp = dp;
   out->ve = ve ? 1 : 0;
+  out->saf = saf ? 1 : 0;
   return 0;
 }
 
@@ -294,6 +312,9 @@ void orc_set_num_threads(int n) {
 #endif
 }
 
+int orc_step_saf(const orc_params *p, int nx, int ny, const double *n, const double *P,
+                 long long t, double *n_out, double *P_out, double *fields);
+
 /* One time step t -> t+1 of one channel. n: 9 planes of nx*ny post-streaming
  * populations at time t; P: stress trace of step t-1; S: with the
  * time-integrated model (R11), the stress (xx, xy, yy planes) of step t-1,
@@ -305,6 +326,7 @@ void orc_set_num_threads(int n) {
 int orc_step(const orc_params *p, int nx, int ny, const double *n, const double *P,
              const double *S, long long t, double *n_out, double *P_out, double *S_out,
              double *fields) {
+  if (p->saf) return orc_step_saf(p, nx, ny, n, P, t, n_out, P_out, fields);
   const size_t N = (size_t)nx * ny;
   double fx = (t < p->t_startup) ? p->g : 0.0, fy = 0.0;
   double uw = (t < p->t_startup) ? p->uw : 0.0;  /* top wall velocity at step t */
@@ -446,6 +468,148 @@ int orc_step(const orc_params *p, int nx, int ny, const double *n, const double 
         S_out[2 * N + id] = sig[2];
       }
     }
+  free(utx);
+  free(uty);
+  return bad;
+}
+
+/* Non-Newtonian stress Sigma^nN (xx, xy, yy) of every node at step t, into
+ * T[3][ny][nx] (reading R12, first pass); velocity gradient from
+ * u~ = (m + rho0 g / 2)/s. Returns the count of non-converged series. */
+static int saf_stress(const orc_params *p, int nx, int ny, const double *n, long long t, double *T) {
+  const size_t N = (size_t)nx * ny;
+  double fx = (t < p->t_startup) ? p->g : 0.0;
+  double uw = (t < p->t_startup) ? p->uw : 0.0;
+  double *utx = malloc(N * sizeof(double)), *uty = malloc(N * sizeof(double));
+  int bad = 0;
+#pragma omp parallel for
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      size_t id = (size_t)y * nx + x;
+      double s = 0, mx = 0, my = 0;
+      for (int i = 0; i < 9; ++i) {
+        double v = n[i * N + id];
+        s += v;
+        mx += CX[i] * v;
+        my += CY[i] * v;
+      }
+      utx[id] = (mx + 0.5 * fx) / s;
+      uty[id] = my / s;
+    }
+#pragma omp parallel for reduction(+ : bad)
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      size_t id = (size_t)y * nx + x;
+      int xm = (x - 1 + nx) % nx, xp = (x + 1) % nx;
+      double uxd, uyd, uxu, uyu;
+      if (y > 0) { uxd = utx[id - nx]; uyd = uty[id - nx]; }
+      else       { uxd = -utx[id];     uyd = -uty[id]; }
+      if (y < ny - 1) { uxu = utx[id + nx]; uyu = uty[id + nx]; }
+      else            { uxu = 2.0 * uw - utx[id]; uyu = -uty[id]; }
+      double k[2][2];
+      k[0][0] = 0.5 * (utx[(size_t)y * nx + xp] - utx[(size_t)y * nx + xm]);
+      k[0][1] = 0.5 * (uxu - uxd);
+      k[1][0] = 0.5 * (uty[(size_t)y * nx + xp] - uty[(size_t)y * nx + xm]);
+      k[1][1] = 0.5 * (uyu - uyd);
+      double sig[3] = {0, 0, 0};
+      double tauM = orc_tau_M(k, p->tau, p->gamma_c);
+      if (p->G > 0 && isfinite(tauM))
+        if (orc_stress_series(k, p->G, tauM, sig) < 0) bad++;
+      double lgt = (p->lam > 0) ? p->lam * p->G * p->tau : 0.0;
+      T[id] = sig[0] - lgt * 2 * k[0][0];
+      T[N + id] = sig[1] - lgt * (k[0][1] + k[1][0]);
+      T[2 * N + id] = sig[2] - lgt * 2 * k[1][1];
+    }
+  free(utx);
+  free(uty);
+  return bad;
+}
+
+/* Reading R12: one step t -> t+1 with the stress as a force density. Same
+ * arguments as orc_step (P is carried unchanged: there is no flow-induced
+ * density). The fields of step t are stored if fields != NULL. */
+int orc_step_saf(const orc_params *p, int nx, int ny, const double *n, const double *P,
+                 long long t, double *n_out, double *P_out, double *fields) {
+  const size_t N = (size_t)nx * ny;
+  double g = (t < p->t_startup) ? p->g : 0.0;
+  double uw = (t < p->t_startup) ? p->uw : 0.0;
+  double *T = malloc(3 * N * sizeof(double));
+  int bad = saf_stress(p, nx, ny, n, t, T);
+  /* stress component c at (x, y), with the linearly extrapolated ghost rows */
+#define TS(c, x, y) T[(size_t)(c) * N + (size_t)(y) * nx + (x)]
+  double *utx = malloc(N * sizeof(double)), *uty = malloc(N * sizeof(double));
+#pragma omp parallel for
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      size_t id = (size_t)y * nx + x;
+      double s = 0, mx = 0, my = 0;
+      for (int i = 0; i < 9; ++i) {
+        s += n[i * N + id];
+        mx += CX[i] * n[i * N + id];
+        my += CY[i] * n[i * N + id];
+      }
+      utx[id] = (mx + 0.5 * g) / s;
+      uty[id] = my / s;
+    }
+#pragma omp parallel for
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      size_t id = (size_t)y * nx + x;
+      int xm = (x - 1 + nx) % nx, xp = (x + 1) % nx;
+      double Tdn[3], Tup[3];
+      for (int c = 0; c < 3; ++c) {
+        if (ny == 1) {
+          Tdn[c] = Tup[c] = TS(c, x, y);
+        } else {
+          Tdn[c] = (y > 0) ? TS(c, x, y - 1) : 2 * TS(c, x, 0) - TS(c, x, 1);
+          Tup[c] = (y < ny - 1) ? TS(c, x, y + 1) : 2 * TS(c, x, ny - 1) - TS(c, x, ny - 2);
+        }
+      }
+      /* (div Sigma)_a = d_x Sigma_xa + d_y Sigma_ya */
+      double fsx = 0.5 * (TS(0, xp, y) - TS(0, xm, y)) + 0.5 * (Tup[1] - Tdn[1]);
+      double fsy = 0.5 * (TS(1, xp, y) - TS(1, xm, y)) + 0.5 * (Tup[2] - Tdn[2]);
+      double fx = g + fsx, fy = fsy;
+      double nn[9], s = 0, mx = 0, my = 0;
+      for (int i = 0; i < 9; ++i) {
+        nn[i] = n[i * N + id];
+        s += nn[i];
+        mx += CX[i] * nn[i];
+        my += CY[i] * nn[i];
+      }
+      double ux = (mx + 0.5 * fx) / s, uy = (my + 0.5 * fy) / s;
+      double neq[9], F[9];
+      const double zero[3] = {0, 0, 0};
+      orc_equilibrium(s, ux, uy, neq);
+      orc_forcing(p->tau_eff, zero, 0.0, fx, fy, ux, uy, F);
+      if (fields) {
+        double uxd = (y > 0) ? utx[id - nx] : -utx[id], uxu = (y < ny - 1) ? utx[id + nx] : 2.0 * uw - utx[id];
+        double uyd = (y > 0) ? uty[id - nx] : -uty[id], uyu = (y < ny - 1) ? uty[id + nx] : -uty[id];
+        double k[2][2] = {{0.5 * (utx[(size_t)y * nx + xp] - utx[(size_t)y * nx + xm]), 0.5 * (uxu - uxd)},
+                          {0.5 * (uty[(size_t)y * nx + xp] - uty[(size_t)y * nx + xm]), 0.5 * (uyu - uyd)}};
+        double tauM = orc_tau_M(k, p->tau, p->gamma_c);
+        double lgt = (p->lam > 0) ? p->lam * p->G * p->tau : 0.0;
+        /* sigma recovered from Sigma^nN by adding the split part back */
+        double sxx = TS(0, x, y) + lgt * 2 * k[0][0], sxy = TS(1, x, y) + lgt * (k[0][1] + k[1][0]);
+        double syy = TS(2, x, y) + lgt * 2 * k[1][1];
+        double vals[OF_COUNT] = {utx[id], uty[id], k[0][0], k[0][1], k[1][0], k[1][1], sxx, sxy, syy,
+                                 TS(0, x, y) + TS(2, x, y), 0.0, s, ux, uy, s, mx, my, tauM};
+        for (int q = 0; q < OF_COUNT; ++q) fields[q * N + id] = vals[q];
+      }
+      if (!n_out) continue;
+      for (int i = 0; i < 9; ++i) {
+        double post = nn[i] - (nn[i] - neq[i]) / p->tau_eff + F[i];
+        int xd = (x + CX[i] + nx) % nx, yd = y + CY[i];
+        if (yd >= 0 && yd < ny)
+          n_out[i * N + (size_t)yd * nx + xd] = post;
+        else if (yd >= ny)
+          n_out[opposite(i) * N + id] = post - 2.0 * W[i] * (CX[i] * uw) / CS2;
+        else
+          n_out[opposite(i) * N + id] = post;
+      }
+      P_out[id] = P[id];
+    }
+#undef TS
+  free(T);
   free(utx);
   free(uty);
   return bad;
