@@ -7,7 +7,8 @@ second) with the state resident in HBM; the FP64 run of the same workload is
 reported beside it, and the FP64 CPU oracle is timed on a bounded sample of
 the same lattice on the host. Further legs: the batched channels to steady
 state, the 16 x 8192 x 2048 start-up lattice, the same 4096 x 1024 lattice
-with the time-integrated (viscoelastic) stress, and the learned warm start.
+with the time-integrated (viscoelastic) stress and with the stress as a force
+density, and the learned warm start.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu]
 """
@@ -28,6 +29,11 @@ HBM_PEAK_GBS = 8000.0
 # (viscoelastic) model also reads and writes the three stress fields.
 BYTES_PER_NODE = {"fp32": 80, "fp64": 160}
 BYTES_PER_NODE_VE = {"fp32": 104, "fp64": 208}
+# Stress as a force density (FP64, three passes per step): the u~ pass reads
+# 9 pulled populations and writes u~ (72 + 16 B), the stress pass reads u~ and
+# writes Sigma^nN (16 + 24 B), the collide pass reads 9 populations, P and
+# Sigma^nN and writes 9 populations and P (80 + 24 + 80 B).
+BYTES_PER_NODE_SAF = 312
 
 
 def measured_traffic(key):
@@ -48,13 +54,13 @@ def measured_traffic(key):
     return None if k is None else round(k["traffic_bytes"])
 
 
-def time_solver(precision, wl, steps, warmup, strip_rows=0, viscoelastic=False):
+def time_solver(precision, wl, steps, warmup, strip_rows=0, viscoelastic=False, stress_force=False):
     import torch
     from paper_1310_7450_amd import Solver
     spec = wl["channels"][0]
     nodes = spec.nx * spec.ny
-    with Solver([spec], precision=precision, obs_every=1000, strip_rows=strip_rows,
-                viscoelastic=viscoelastic) as s:
+    with Solver([spec], precision=precision, obs_every=1000, strip_rows=strip_rows, viscoelastic=viscoelastic,
+                stress_force=stress_force, nn_pressure=not stress_force) as s:
         s.step(warmup)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -71,7 +77,8 @@ def time_solver(precision, wl, steps, warmup, strip_rows=0, viscoelastic=False):
     sec = ms / 1e3
     per_step = sec / steps
     mlups = nodes * steps / sec / 1e6
-    achieved = (BYTES_PER_NODE_VE if viscoelastic else BYTES_PER_NODE)[precision] * nodes / per_step / 1e9
+    bpn = BYTES_PER_NODE_SAF if stress_force else (BYTES_PER_NODE_VE if viscoelastic else BYTES_PER_NODE)[precision]
+    achieved = bpn * nodes / per_step / 1e9
     return {"mlups": mlups, "ms_total": ms, "ms_per_step": ms / steps, "wall_s": wall,
             "achieved_GBs": achieved, "frac": achieved / HBM_PEAK_GBS, "umid": umid,
             "mass_rel_drift": (mass - nodes) / nodes}
@@ -155,6 +162,18 @@ def run_viscoelastic(steps=2000, warmup=1000):
                                   "unit": "GB/s", "frac": round(r["frac"], 4),
                                   "traffic": measured_traffic("ve_" + prec)}}
     return out
+
+
+def run_stress_force(steps=1000, warmup=1000):
+    """The same 4096 x 1024 workload with the stress as a force density
+    (FP64, no flow-induced density, three passes per step)."""
+    from paper_1310_7450_amd import workloads
+    wl = workloads.large_channel()
+    r = time_solver("fp64", wl, steps, warmup, stress_force=True)
+    return {"workload": wl["name"] + "_stress_force", "steps": steps, "value": round(r["mlups"], 1),
+            "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5), "bytes_per_node": BYTES_PER_NODE_SAF,
+            "roofline": {"bound": "hbm", "achieved": round(r["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(r["frac"], 4), "traffic": None}}
 
 
 def run_warm_start(verbose=True):
@@ -242,6 +261,7 @@ def main():
     ap.add_argument("--no-transient", action="store_true", help="skip the 16 x 8192 x 2048 throughput leg")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start experiment")
     ap.add_argument("--no-viscoelastic", action="store_true", help="skip the time-integrated stress leg")
+    ap.add_argument("--no-stress-force", action="store_true", help="skip the stress-as-force leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB, 5 times (counter calibration)")
     args = ap.parse_args()
@@ -295,6 +315,11 @@ def main():
         print(f"bench: viscoelastic fp32 {ve['fp32']['value']:.0f} MLUPS "
               f"({100 * ve['fp32']['roofline']['frac']:.1f}%), fp64 {ve['fp64']['value']:.0f} MLUPS "
               f"({100 * ve['fp64']['roofline']['frac']:.1f}%)", file=sys.stderr, flush=True)
+    saf = None
+    if not args.no_stress_force:
+        saf = run_stress_force()
+        print(f"bench: stress force fp64 {saf['value']:.0f} MLUPS ({100 * saf['roofline']['frac']:.1f}% at "
+              f"{BYTES_PER_NODE_SAF} B/node)", file=sys.stderr, flush=True)
     warm = None
     if not args.no_warm:
         warm = run_warm_start()
@@ -332,6 +357,7 @@ def main():
         "batched": batched,
         "transient_scale": transient,
         "viscoelastic": ve,
+        "stress_force": saf,
         "warm_start": warm,
         "cpu_baseline": cpu,
     }

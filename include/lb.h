@@ -132,7 +132,16 @@ typedef struct {
  *                fixed point is the instantaneous model's stress). The stress
  *                is then part of the state (three more fields per node, in
  *                the precision of the populations, zero at rest; see
- *                lb_get_stress), and the workspace grows accordingly.
+ *                lb_get_stress), and the workspace grows accordingly;
+ *   stress_force 0: the non-Newtonian stress enters through the second moment
+ *                of the forcing of Eq. (bodyforce); 1: it enters as the force
+ *                density div Sigma^nN in the body-force terms instead (the
+ *                alternative Sec. II.C names), with Sigma^nN formed at every
+ *                node first, central differences for the divergence and ghost
+ *                rows extrapolated linearly through the walls; there is then
+ *                no flow-induced density. Needs LB_FP64, nn_pressure = 0, the
+ *                instantaneous model and no pressure_gradient. Runs as three
+ *                passes per step (u~, Sigma^nN, collide-and-stream).
  */
 typedef struct {
   int32_t precision;
@@ -141,6 +150,7 @@ typedef struct {
   int32_t strip_rows;
   double steady_tol;
   int32_t viscoelastic;
+  int32_t stress_force;
 } lb_options;
 
 /* Observables for lb_observe. Profiles return ny doubles (x-averages per row,

@@ -151,7 +151,7 @@ int orc_resolve(double tau_lb, double G, double tau0, double gamma_c, double eps
   if (dp != 0 && (g != 0 || nn_pressure || uw != 0)) return -1;
   /* the stress force replaces the second-moment stress term and the
    * flow-induced density, and is defined for the instantaneous model */
-  if (saf && (nn_pressure || ve)) return -1;
+  if (saf && (nn_pressure || ve || dp != 0)) return -1;
   double eta_s = (tau_lb - 0.5) / 3.0;
   double tau = tau0 * pow(10.0, fmin(eps, 0.0) / 0.05);
   double Ginf = G * (1.0 + sqrt(fmax(eps, 0.0)));

@@ -123,6 +123,10 @@ hipError_t launch_reduce(const ChanDev *ch, int n_ch, const double *part, double
                          int steps_since, hipStream_t s);
 hipError_t launch_advance(ChanDev *ch, int n_ch, int steps, hipStream_t s);
 hipError_t launch_gpbc(int fp32, void *B, const ChanDev *ch, int n_ch, int k, const float *uref, hipStream_t s);
+hipError_t launch_saf_step(const double *A, double *B, const ChanDev *ch, int n_ch, long long plane, int k,
+                           double *U, double *Tn, hipStream_t s);
+hipError_t launch_saf_observe(const double *A, const ChanDev *ch, int n_ch, long long plane, int total_rows,
+                              double *U, double *Tn, double *part, hipStream_t s);
 hipError_t launch_rereference(float *A, const ChanDev *ch, int n_ch, int total_rows, const double *prof,
                               float *uref, hipStream_t s);
 

@@ -201,6 +201,35 @@ struct Coef {
         inv_gc(T(c.inv_gc)), lgt(T(c.lgt)), stress_on(c.G > 0.0) {}
 };
 
+// Instantaneous stress (Eqs. (nlmaxwell), (sigtsum)) for the velocity
+// gradient k_ab = d_b u_a: tau_M from the shear rate, then the steady sum
+// through the relation it satisfies by Eq. (smalld),
+// sigma - tau_M (kappa sigma + sigma kappa^T) = G tau_M D, solved in closed
+// form (Cramer) for (sigma_xx, sigma_xy, sigma_yy). Leaves the outputs
+// untouched when the relaxation rate vanishes (tau = inf and D = 0).
+template <typename T>
+__device__ __forceinline__ void inlm_stress(T kxx, T kxy, T kyx, T kyy, const Coef<T> &q, T &sxx, T &sxy,
+                                            T &syy) {
+  const T Dxx = T(2) * kxx, Dxy = kxy + kyx, Dyy = T(2) * kyy;
+  const T II = T(0.5) * (Dxx * Dxx + T(2) * Dxy * Dxy + Dyy * Dyy);
+  const T rate = q.inv_tau + sqrt(II) * q.inv_gc;
+  if (rate > T(0)) {
+    const T tM = recip<T>(rate);
+    const T ka = tM * kxx, kb = tM * kxy, kc = tM * kyx, kd = tM * kyy;
+    const T gt = q.G * tM;
+    const T r1 = gt * Dxx, r2 = gt * Dxy, r3 = gt * Dyy;
+    const T m11 = T(1) - T(2) * ka, m12 = T(-2) * kb, m21 = -kc;
+    const T m22 = T(1) - ka - kd, m23 = -kb, m32 = T(-2) * kc, m33 = T(1) - T(2) * kd;
+    const T c11 = m22 * m33 - m23 * m32;
+    const T det = m11 * c11 - m12 * m21 * m33;
+    const T idet = recip<T>(det);
+    const T e2 = r2 * m33 - m23 * r3;
+    sxx = (r1 * c11 - m12 * e2) * idet;
+    sxy = (m11 * e2 - r1 * m21 * m33) * idet;
+    syy = (m11 * (m22 * r3 - r2 * m32) - m12 * m21 * r3 + r1 * m21 * m32) * idet;
+  }
+}
+
 // Everything that happens at one node once its populations and the stencil
 // velocities are known: kappa (Sec. II.C), the inlM stress (Eqs.
 // (nlmaxwell), (sigtsum)), the flow-induced density change (Eq. (rhoplus)),
@@ -249,23 +278,7 @@ __device__ __forceinline__ void node_update(const T f[9], T sd, T mx, T my, T Pc
     sn[1] = sxy;
     sn[2] = syy;
   } else if (q.stress_on) {
-    const T II = T(0.5) * (Dxx * Dxx + T(2) * Dxy * Dxy + Dyy * Dyy);
-    const T rate = q.inv_tau + sqrt(II) * q.inv_gc;
-    if (rate > T(0)) {
-      const T tM = recip<T>(rate);
-      const T ka = tM * kxx, kb = tM * kxy, kc = tM * kyx, kd = tM * kyy;
-      const T gt = q.G * tM;
-      const T r1 = gt * Dxx, r2 = gt * Dxy, r3 = gt * Dyy;
-      const T m11 = T(1) - T(2) * ka, m12 = T(-2) * kb, m21 = -kc;
-      const T m22 = T(1) - ka - kd, m23 = -kb, m32 = T(-2) * kc, m33 = T(1) - T(2) * kd;
-      const T c11 = m22 * m33 - m23 * m32;
-      const T det = m11 * c11 - m12 * m21 * m33;
-      const T idet = recip<T>(det);
-      const T e2 = r2 * m33 - m23 * r3;
-      sxx = (r1 * c11 - m12 * e2) * idet;
-      sxy = (m11 * e2 - r1 * m21 * m33) * idet;
-      syy = (m11 * (m22 * r3 - r2 * m32) - m12 * m21 * r3 + r1 * m21 * m32) * idet;
-    }
+    inlm_stress<T>(kxx, kxy, kyx, kyy, q, sxx, sxy, syy);
   }
   // non-Newtonian stress carried by the forcing (viscosity split)
   const T Txx = sxx - q.lgt * Dxx, Txy = sxy - q.lgt * Dxy, Tyy = syy - q.lgt * Dyy;
@@ -1421,6 +1434,219 @@ __global__ void __launch_bounds__(256) rereference_kernel(float *A, const ChanDe
   if (threadIdx.x == 0) uref[r] = un;
 }
 
+// ---------------------------------------------------------------------------
+// Stress as a force density (FP64, instantaneous model): the divergence of
+// the non-Newtonian stress enters as an external force in Eq. (ns), the
+// alternative Sec. II.C names. Three passes per step over every node of the
+// active channels, one thread per node: u~, then Sigma^nN from the
+// neighbours' u~, then the collision with the force f = rho0 g + div
+// Sigma^nN (central differences, ghost rows extrapolated linearly through
+// the walls) in the body-force terms of the forcing. Scratch: U (u~_x, u~_y)
+// and T (Sigma^nN xx, xy, yy), plane-major over the nodes of the buffer.
+
+// Channel holding node n (channels are laid out by increasing offset).
+__device__ __forceinline__ int channel_of_node(const ChanDev *ch, int n_ch, long long n) {
+  int lo = 0, hi = n_ch - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (ch[mid].off <= n) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct SafNode {
+  ChanDev c;
+  int x, y;
+  long long t;
+};
+
+// Decodes node n; false for padding nodes and (unless all) frozen channels.
+__device__ __forceinline__ bool saf_node(const ChanDev *ch, int n_ch, long long n, int k, bool all, SafNode &s) {
+  s.c = ch[channel_of_node(ch, n_ch, n)];
+  const long long loc = n - s.c.off;
+  if (loc < 0 || loc >= (long long)s.c.nx * s.c.ny) return false;
+  if (!all && !s.c.active) return false;
+  s.y = (int)(loc / s.c.nx);
+  s.x = (int)(loc - (long long)s.y * s.c.nx);
+  s.t = s.c.t + k;
+  return true;
+}
+
+// x and y neighbours' values of a node field F (plane-major, plane nodes),
+// with the ghost rule of the caller.
+__global__ void __launch_bounds__(256) saf_u_kernel(const double *__restrict__ A, const ChanDev *ch, int n_ch,
+                                                    long long plane, int k, int all, double *__restrict__ U) {
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < plane;
+       n += (long long)gridDim.x * blockDim.x) {
+    SafNode q;
+    if (!saf_node(ch, n_ch, n, k, all, q)) continue;
+    const double g = (q.t < q.c.t_startup) ? q.c.g : 0.0;
+    const double uw6 = (q.t >= 1 && q.t - 1 < q.c.t_startup) ? q.c.uw / 6.0 : 0.0;
+    double f[9], sd, mx, my;
+    pull<double>(A, q.c.off + (long long)q.y * q.c.nx, q.c.nx, q.c.ny, q.x, q.y, uw6, f);
+    moments<double>(f, sd, mx, my);
+    U[n] = (mx + 0.5 * g) / sd;
+    U[plane + n] = my / sd;
+  }
+}
+
+// kappa_ab = d_b u~_a of a node by central differences (x periodic; wall
+// ghosts -u~ below, 2 u_w - u~ above for x, -u~ for y).
+__device__ __forceinline__ void saf_kappa(const double *__restrict__ U, long long plane, const SafNode &q,
+                                          double &kxx, double &kxy, double &kyx, double &kyy) {
+  const ChanDev &c = q.c;
+  const long long row = c.off + (long long)q.y * c.nx;
+  const long long n = row + q.x;
+  const int xm = (q.x == 0) ? c.nx - 1 : q.x - 1, xp = (q.x == c.nx - 1) ? 0 : q.x + 1;
+  const double uwg = (q.t < c.t_startup) ? c.uw : 0.0;
+  const double ux = U[n], uy = U[plane + n];
+  const double uxd = (q.y > 0) ? U[n - c.nx] : -ux, uyd = (q.y > 0) ? U[plane + n - c.nx] : -uy;
+  const double uxu = (q.y < c.ny - 1) ? U[n + c.nx] : 2.0 * uwg - ux;
+  const double uyu = (q.y < c.ny - 1) ? U[plane + n + c.nx] : -uy;
+  kxx = 0.5 * (U[row + xp] - U[row + xm]);
+  kxy = 0.5 * (uxu - uxd);
+  kyx = 0.5 * (U[plane + row + xp] - U[plane + row + xm]);
+  kyy = 0.5 * (uyu - uyd);
+}
+
+__global__ void __launch_bounds__(256) saf_stress_kernel(const ChanDev *ch, int n_ch, long long plane, int k,
+                                                         int all, const double *__restrict__ U,
+                                                         double *__restrict__ Tn) {
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < plane;
+       n += (long long)gridDim.x * blockDim.x) {
+    SafNode q;
+    if (!saf_node(ch, n_ch, n, k, all, q)) continue;
+    double kxx, kxy, kyx, kyy;
+    saf_kappa(U, plane, q, kxx, kxy, kyx, kyy);
+    const Coef<double> cf(q.c);
+    double sxx = 0, sxy = 0, syy = 0;
+    if (cf.stress_on) inlm_stress<double>(kxx, kxy, kyx, kyy, cf, sxx, sxy, syy);
+    Tn[n] = sxx - cf.lgt * 2.0 * kxx;
+    Tn[plane + n] = sxy - cf.lgt * (kxy + kyx);
+    Tn[2 * plane + n] = syy - cf.lgt * 2.0 * kyy;
+  }
+}
+
+// f_Sigma = div Sigma^nN at a node: central differences, x periodic, ghost
+// rows Sigma(-1) = 2 Sigma(0) - Sigma(1), Sigma(ny) = 2 Sigma(ny-1) -
+// Sigma(ny-2) (one row: zero gradient).
+__device__ __forceinline__ void saf_force(const double *__restrict__ Tn, long long plane, const SafNode &q,
+                                          double &fsx, double &fsy) {
+  const ChanDev &c = q.c;
+  const long long row = c.off + (long long)q.y * c.nx;
+  const long long n = row + q.x;
+  const int xm = (q.x == 0) ? c.nx - 1 : q.x - 1, xp = (q.x == c.nx - 1) ? 0 : q.x + 1;
+  double dn[3], up[3];
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const double *P = Tn + p * plane;
+    if (c.ny == 1) {
+      dn[p] = up[p] = P[n];
+    } else {
+      dn[p] = (q.y > 0) ? P[n - c.nx] : 2.0 * P[n] - P[n + c.nx];
+      up[p] = (q.y < c.ny - 1) ? P[n + c.nx] : 2.0 * P[n] - P[n - c.nx];
+    }
+  }
+  fsx = 0.5 * (Tn[row + xp] - Tn[row + xm]) + 0.5 * (up[1] - dn[1]);
+  fsy = 0.5 * (Tn[plane + row + xp] - Tn[plane + row + xm]) + 0.5 * (up[2] - dn[2]);
+}
+
+__global__ void __launch_bounds__(256) saf_collide_kernel(const double *__restrict__ A, double *__restrict__ B,
+                                                          const ChanDev *ch, int n_ch, long long plane, int k,
+                                                          const double *__restrict__ Tn) {
+  constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < plane;
+       n += (long long)gridDim.x * blockDim.x) {
+    SafNode q;
+    if (!saf_node(ch, n_ch, n, k, false, q)) continue;
+    const double g = (q.t < q.c.t_startup) ? q.c.g : 0.0;
+    const double uw6 = (q.t >= 1 && q.t - 1 < q.c.t_startup) ? q.c.uw / 6.0 : 0.0;
+    double f[9], sd, mx, my;
+    pull<double>(A, q.c.off + (long long)q.y * q.c.nx, q.c.nx, q.c.ny, q.x, q.y, uw6, f);
+    moments<double>(f, sd, mx, my);
+    double fsx, fsy;
+    saf_force(Tn, plane, q, fsx, fsy);
+    const double fx = g + fsx, fy = fsy;
+    const double ux = (mx + 0.5 * fx) / sd, uy = (my + 0.5 * fy) / sd;
+    const double usq = ux * ux + uy * uy, uf = ux * fx + uy * fy;
+    const double om = q.c.omega, kf = q.c.kf;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      // BGK toward n^eq(s, u) plus the body-force terms of Eq. (bodyforce)
+      // with the total force (no stress term, r = 0)
+      const double cu = cx[i] * ux + cy[i] * uy, cfo = cx[i] * fx + cy[i] * fy;
+      const double a = weight<double>(i);
+      const double neq = a * sd * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+      const double F = a * kf * (3.0 * cfo + 9.0 * cu * cfo - 3.0 * uf);
+      B[slot(i, n)] = f[i] - om * (f[i] - neq) + F;
+    }
+    B[slot(9, n)] = A[slot(9, n)];  // no flow-induced density: P is carried
+  }
+}
+
+// Observation of the stress-force path: one workgroup per row of every
+// channel; the row sums go to the row's first x-strip partial (the others
+// are zeroed) for reduce_kernel.
+__global__ void __launch_bounds__(256) saf_observe_kernel(const double *__restrict__ A, const ChanDev *ch,
+                                                          int n_ch, long long plane, const double *__restrict__ U,
+                                                          const double *__restrict__ Tn, double *part) {
+  __shared__ double red[OF_COUNT][256];
+  const int r = blockIdx.x;
+  int lo = 0, hi = n_ch - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (ch[mid].row_off <= r) lo = mid;
+    else hi = mid - 1;
+  }
+  const ChanDev c = ch[lo];
+  SafNode q;
+  q.c = c;
+  q.y = r - c.row_off;
+  q.t = c.t;
+  double acc[OF_COUNT];
+#pragma unroll
+  for (int f = 0; f < OF_COUNT; ++f) acc[f] = 0.0;
+  const double g = (q.t < c.t_startup) ? c.g : 0.0;
+  const double uw6 = (q.t >= 1 && q.t - 1 < c.t_startup) ? c.uw / 6.0 : 0.0;
+  const Coef<double> cf(c);
+  for (int x = threadIdx.x; x < c.nx; x += blockDim.x) {
+    q.x = x;
+    const long long n = c.off + (long long)q.y * c.nx + x;
+    double f[9], sd, mx, my;
+    pull<double>(A, c.off + (long long)q.y * c.nx, c.nx, c.ny, x, q.y, uw6, f);
+    moments<double>(f, sd, mx, my);
+    double kxx, kxy, kyx, kyy, fsx, fsy;
+    saf_kappa(U, plane, q, kxx, kxy, kyx, kyy);
+    saf_force(Tn, plane, q, fsx, fsy);
+    double sxx = 0, sxy = 0, syy = 0;
+    if (cf.stress_on) inlm_stress<double>(kxx, kxy, kyx, kyy, cf, sxx, sxy, syy);
+    acc[OF_UX] += (mx + 0.5 * (g + fsx)) / sd;
+    acc[OF_UY] += (my + 0.5 * fsy) / sd;
+    acc[OF_SXX] += sxx;
+    acc[OF_SXY] += sxy;
+    acc[OF_SYY] += syy;
+    acc[OF_RHOE_DEV] += sd - 1.0;
+    acc[OF_MASS_DEV] += sd - 1.0;
+    acc[OF_MOMX] += mx;
+    acc[OF_KXY] += kxy;
+    acc[OF_TRT] += Tn[n] + Tn[2 * plane + n];
+    acc[OF_DRAG] += wall_drag<double>(f, q.y, c.ny, uw6);
+    acc[OF_KXX] += kxx;
+  }
+#pragma unroll
+  for (int f = 0; f < OF_COUNT; ++f) red[f][threadIdx.x] = acc[f];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+      for (int f = 0; f < OF_COUNT; ++f) red[f][threadIdx.x] += red[f][threadIdx.x + st];
+    __syncthreads();
+  }
+  double *dst = part + ((long long)c.poff + (long long)q.y * c.nxs) * OF_COUNT;
+  for (int i = threadIdx.x; i < c.nxs * OF_COUNT; i += blockDim.x) dst[i] = (i < OF_COUNT) ? red[i][0] : 0.0;
+}
+
 __global__ void advance_kernel(ChanDev *ch, int n_ch, int steps) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_ch && ch[i].active) ch[i].t += steps;
@@ -1518,6 +1744,31 @@ hipError_t launch_rereference(float *A, const ChanDev *ch, int n_ch, int total_r
                               float *uref, hipStream_t s) {
   if (n_ch == 0 || total_rows == 0) return hipSuccess;
   hipLaunchKernelGGL(rereference_kernel, dim3(total_rows), dim3(256), 0, s, A, ch, n_ch, prof, uref);
+  return hipGetLastError();
+}
+
+static int saf_blocks(long long plane) {
+  const long long b = (plane + 255) / 256;
+  return (int)(b < 16384 ? b : 16384);
+}
+
+hipError_t launch_saf_step(const double *A, double *B, const ChanDev *ch, int n_ch, long long plane, int k,
+                           double *U, double *Tn, hipStream_t s) {
+  if (n_ch == 0 || plane == 0) return hipSuccess;
+  const int nb = saf_blocks(plane);
+  hipLaunchKernelGGL(saf_u_kernel, dim3(nb), dim3(256), 0, s, A, ch, n_ch, plane, k, 0, U);
+  hipLaunchKernelGGL(saf_stress_kernel, dim3(nb), dim3(256), 0, s, ch, n_ch, plane, k, 0, U, Tn);
+  hipLaunchKernelGGL(saf_collide_kernel, dim3(nb), dim3(256), 0, s, A, B, ch, n_ch, plane, k, Tn);
+  return hipGetLastError();
+}
+
+hipError_t launch_saf_observe(const double *A, const ChanDev *ch, int n_ch, long long plane, int total_rows,
+                              double *U, double *Tn, double *part, hipStream_t s) {
+  if (n_ch == 0 || plane == 0 || total_rows == 0) return hipSuccess;
+  const int nb = saf_blocks(plane);
+  hipLaunchKernelGGL(saf_u_kernel, dim3(nb), dim3(256), 0, s, A, ch, n_ch, plane, 0, 1, U);
+  hipLaunchKernelGGL(saf_stress_kernel, dim3(nb), dim3(256), 0, s, ch, n_ch, plane, 0, 1, U, Tn);
+  hipLaunchKernelGGL(saf_observe_kernel, dim3(total_rows), dim3(256), 0, s, A, ch, n_ch, plane, U, Tn, part);
   return hipGetLastError();
 }
 

@@ -42,6 +42,7 @@ struct Layout {
   size_t off_state[2] = {0, 0}, off_ch = 0, off_strips = 0, off_astrips = 0, off_rstrips = 0, off_part = 0,
          off_prof = 0, off_prev = 0, off_scal = 0, off_uref = 0, bytes = 0;
   size_t off_stress[2] = {0, 0};  // viscoelastic model only
+  size_t off_saf_u = 0, off_saf_t = 0;  // stress-as-force scratch (u~, Sigma^nN)
   std::vector<ChanDev> ch;
 };
 
@@ -55,6 +56,9 @@ std::string validate(const lb_channel *c, int n, const lb_options *o) {
   if (o->strip_rows < 0 || o->strip_rows > 4096) return "strip_rows out of range";
   if (!(o->steady_tol >= 0) || !std::isfinite(o->steady_tol)) return "steady_tol must be >= 0";
   if (o->viscoelastic != 0 && o->viscoelastic != 1) return "viscoelastic must be 0 or 1";
+  if (o->stress_force != 0 && o->stress_force != 1) return "stress_force must be 0 or 1";
+  if (o->stress_force && (o->precision != LB_FP64 || o->nn_pressure || o->viscoelastic))
+    return "stress_force needs FP64, nn_pressure = 0 and the instantaneous model";
   for (int i = 0; i < n; ++i) {
     const lb_channel &q = c[i];
     char buf[160];
@@ -76,6 +80,7 @@ std::string validate(const lb_channel *c, int n, const lb_options *o) {
     if (!std::isfinite(q.pressure_gradient)) return bad("pressure_gradient must be finite");
     if (q.pressure_gradient != 0 && (q.force != 0 || q.wall_velocity != 0 || q.nx < 2 || o->nn_pressure))
       return bad("pressure_gradient needs force = 0, wall_velocity = 0, nx >= 2 and nn_pressure = 0");
+    if (q.pressure_gradient != 0 && o->stress_force) return bad("pressure_gradient is not combined with stress_force");
   }
   return "";
 }
@@ -201,6 +206,10 @@ Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
     L.off_stress[0] = take(stress);
     L.off_stress[1] = take(stress);
   }
+  if (o->stress_force) {
+    L.off_saf_u = take(sizeof(double) * 2 * L.plane);
+    L.off_saf_t = take(sizeof(double) * 3 * L.plane);
+  }
   L.bytes = at;
   return L;
 }
@@ -222,6 +231,7 @@ struct lb_handle {
   double *dpart = nullptr, *dprof = nullptr, *dprev = nullptr, *dscal = nullptr;
   float *duref = nullptr;    // FP32: reference velocity of every row
   void *sbuf[2] = {nullptr, nullptr};  // viscoelastic model: stress buffers (same parity as buf)
+  double *saf_u = nullptr, *saf_t = nullptr;  // stress-as-force scratch
   // strips grouped by width class: [begin, begin + count) in the arrays
   int all_begin[kClasses] = {0}, all_count[kClasses] = {0};
   int act_begin[kClasses] = {0}, act_count[kClasses] = {0};
@@ -324,6 +334,11 @@ SweepArgs sweep_args(lb_handle *h, const Strip *strips, int begin, int count, in
 
 // Enqueues the sweeps of one step (source buffer src, step offset k).
 lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s) {
+  if (h->opt.stress_force) {
+    HIPCHECK(h, launch_saf_step(static_cast<const double *>(h->buf[src]), static_cast<double *>(h->buf[src ^ 1]),
+                                h->dch, h->n_ch, h->L.plane, k, h->saf_u, h->saf_t, s));
+    return LB_OK;
+  }
   for (int c = 0; c < kClasses; ++c) {
     if (!h->act_count[c]) continue;
     // Serpentine order: steps reading buffer 0 take the strips in order and
@@ -344,7 +359,11 @@ lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s) {
 }
 
 lb_status enqueue_observe(lb_handle *h, int update_residual, int steps_since) {
-  for (int c = 0; c < kClasses; ++c) {
+  if (h->opt.stress_force) {
+    HIPCHECK(h, launch_saf_observe(static_cast<const double *>(h->buf[h->cur]), h->dch, h->n_ch, h->L.plane,
+                                   h->L.total_rows, h->saf_u, h->saf_t, h->dpart, h->stream));
+  }
+  for (int c = 0; c < kClasses && !h->opt.stress_force; ++c) {
     if (!h->all_count[c]) continue;
     SweepArgs a = sweep_args(h, h->dall, h->all_begin[c], h->all_count[c], h->cur, 0);
     HIPCHECK(h, launch_sweep(h->opt.precision == LB_FP32_SHIFTED, c, true, a, h->stream));
@@ -523,6 +542,10 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
   if (o->viscoelastic) {
     h->sbuf[0] = h->ws + h->L.off_stress[0];
     h->sbuf[1] = h->ws + h->L.off_stress[1];
+  }
+  if (o->stress_force) {
+    h->saf_u = reinterpret_cast<double *>(h->ws + h->L.off_saf_u);
+    h->saf_t = reinterpret_cast<double *>(h->ws + h->L.off_saf_t);
   }
   h->t.assign(n, 0);
   h->active.assign(n, 1);
