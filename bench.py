@@ -173,7 +173,7 @@ def run_stress_force(steps=1000, warmup=1000):
     return {"workload": wl["name"] + "_stress_force", "steps": steps, "value": round(r["mlups"], 1),
             "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5), "bytes_per_node": BYTES_PER_NODE_SAF,
             "roofline": {"bound": "hbm", "achieved": round(r["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(r["frac"], 4), "traffic": None}}
+                         "unit": "GB/s", "frac": round(r["frac"], 4), "traffic": measured_traffic("saf_fp64")}}
 
 
 def run_warm_start(verbose=True):
