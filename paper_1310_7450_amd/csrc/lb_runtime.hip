@@ -419,6 +419,26 @@ lb_status read_observation(lb_handle *h) {
   return LB_OK;
 }
 
+// Copies channel ch's tiles (and stress tiles) from the current buffer to
+// the other one. A frozen channel is no longer swept, so both buffers must
+// hold its state: later steps of odd length change which buffer is current.
+lb_status mirror_channel(lb_handle *h, int ch) {
+  const ChanDev &d = h->L.ch[ch];
+  const size_t Npad = align_up((size_t)d.nx * d.ny, kTile);
+  const int es = h->L.esize;
+  const size_t off = (size_t)slot(0, d.off) * es, bytes = (size_t)kPlanes * Npad * es;
+  HIPCHECK(h, hipMemcpyAsync(static_cast<char *>(h->buf[h->cur ^ 1]) + off,
+                             static_cast<const char *>(h->buf[h->cur]) + off, bytes, hipMemcpyDeviceToDevice,
+                             h->stream));
+  if (h->sbuf[0]) {
+    const size_t soff = (size_t)sslot(0, d.off) * es, sbytes = (size_t)kStressPlanes * Npad * es;
+    HIPCHECK(h, hipMemcpyAsync(static_cast<char *>(h->sbuf[h->cur ^ 1]) + soff,
+                               static_cast<const char *>(h->sbuf[h->cur]) + soff, sbytes, hipMemcpyDeviceToDevice,
+                               h->stream));
+  }
+  return LB_OK;
+}
+
 // Convergence check after a graph: residuals of all channels, freeze the
 // converged ones and rebuild the active work list.
 lb_status check_steady(lb_handle *h) {
@@ -443,6 +463,8 @@ lb_status check_steady(lb_handle *h) {
       h->active[i] = 0;
       h->L.ch[i].active = 0;
       changed = true;
+      lb_status m = mirror_channel(h, i);
+      if (m != LB_OK) return m;
     }
   }
   if (unstable) return fail(h, LB_EUNSTABLE, "NaN/Inf seen in a channel during a convergence check");
@@ -813,6 +835,11 @@ lb_status lb_set_state(lb_handle *h, int32_t ch, const double *pops, const doubl
   if (es == 4)
     HIPCHECK(h, hipMemcpyAsync(h->duref + d.row_off, ur.data(), sizeof(float) * d.ny, hipMemcpyHostToDevice,
                                h->stream));
+  // both buffers: a frozen channel is read from whichever is current later
+  {
+    lb_status m = mirror_channel(h, ch);
+    if (m != LB_OK) return m;
+  }
   // step counter and residual history of this channel
   std::vector<ChanDev> cur(h->n_ch);
   HIPCHECK(h, hipMemcpyAsync(cur.data(), h->dch, sizeof(ChanDev) * h->n_ch, hipMemcpyDeviceToHost, h->stream));
@@ -877,6 +904,10 @@ lb_status lb_set_stress(lb_handle *h, int32_t ch, const double *sigma) {
     }
   HIPCHECK(h, hipMemcpyAsync(dst + (size_t)sslot(0, d.off) * es, raw.data(), raw.size(), hipMemcpyHostToDevice,
                              h->stream));
+  {
+    lb_status m = mirror_channel(h, ch);
+    if (m != LB_OK) return m;
+  }
   HIPCHECK(h, hipStreamSynchronize(h->stream));
   h->obs_valid = false;
   return LB_OK;

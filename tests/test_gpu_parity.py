@@ -233,6 +233,32 @@ def test_convergence_freezes_channels(orc):
             compare_fields(s, i, o, FP64_TOL, f"frozen ch{i} at {steps[i]}")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_frozen_channel_survives_odd_steps(precision):
+    """A channel frozen by the convergence check keeps its state exactly
+    through later steps of odd length, which change the buffer the handle
+    reads from; so does a state set on it while frozen."""
+    specs = [ChannelSpec(8, 16, 2e-6, 1.0, 1e-4, 1e3, 0.1), ChannelSpec(8, 96, 1e-6, 1.0, 1e-4, 1e3, 0.1)]
+    with solver(specs, precision=precision, obs_every=200, steady_tol=1e-7) as s:
+        while s.observe(0, "active") != 0:
+            s.step(200)
+        assert s.observe(1, "active") == 1
+        t0 = s.observe(0, "step")
+        pops0, P0 = s.get_state(0)
+        u0 = s.observe(0, "ux")
+        for n in (1, 2, 3):
+            s.step(n)
+            pops, P = s.get_state(0)
+            assert np.array_equal(pops, pops0) and np.array_equal(P, P0), n
+            assert np.array_equal(s.observe(0, "ux"), u0) and s.observe(0, "step") == t0
+        pops1 = pops0.copy()
+        pops1[0] += 1e-9
+        s.set_state(0, pops1, P0, int(t0))
+        s.step(1)
+        pops, _ = s.get_state(0)
+        assert np.abs(pops - pops1).max() < (1e-16 if precision == "fp64" else 1e-9)
+
+
 def test_warm_start_profile_state():
     """lb_set_profile writes equilibrium populations at the given u_x with
     rho_e = 1 - (3/2) N1 and P = N1, keeping the rest-state mass."""

@@ -30,10 +30,11 @@ def solver(channels, **kw):
     return Solver(channels, viscoelastic=True, **kw)
 
 
-def oracle_channel(orc, spec):
+def oracle_channel(orc, spec, nn_pressure=True):
     return orc.Channel(spec.nx, spec.ny, spec.force, tau_lb=spec.tau_lb, G=spec.G, tau0=spec.tau0,
                        gamma_c=spec.gamma_c, eps=spec.eps, visc_split=spec.visc_split,
-                       t_startup=spec.t_startup, viscoelastic=True)
+                       t_startup=spec.t_startup, viscoelastic=True, nn_pressure=nn_pressure,
+                       wall_velocity=spec.wall_velocity, pressure_gradient=spec.pressure_gradient)
 
 
 def linf(a, b):
@@ -121,6 +122,36 @@ def test_large_channel_sampled_rows(orc, precision):
         o.run(2000)
         compare_profiles(s, 0, o, FP32_TOL if precision == "fp32" else FP64_TOL, f"large {precision}")
         assert np.abs(s.observe(0, "kxx")).max() == 0.0
+
+
+@pytest.mark.parametrize("drive", ["couette", "pressure"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_other_drives_state_parity(orc, drive, precision):
+    """The time-integrated stress with a moving top wall (planar Couette
+    flow) and with the pressure drive of generalised periodic boundaries:
+    random populations and stress match the oracle after 1, 2 and 57 steps,
+    across the switch-off at t = 40."""
+    nx, ny = (64, 9) if drive == "couette" else (100, 13)
+    kw = dict(wall_velocity=2e-3) if drive == "couette" else dict(force=0.0, pressure_gradient=2e-6)
+    spec = ChannelSpec(nx=nx, ny=ny, force=kw.pop("force", 0.0), tau_lb=0.8, G=2e-4, tau0=500.0, gamma_c=0.1,
+                       eps=0.01, visc_split=0.3, t_startup=40, **kw)
+    nnp = drive == "couette"
+    pops, P = workloads.random_state(nx, ny, seed=nx + ny)
+    sig = workloads.random_stress(nx, ny, seed=nx + ny + 1)
+    o = oracle_channel(orc, spec, nn_pressure=nnp)
+    o.set_state(pops, P, t=0, S=sig)
+    with solver([spec], precision=precision, obs_every=16, strip_rows=4, nn_pressure=nnp) as s:
+        s.set_state(0, pops, P, 0)
+        s.set_stress(0, sig)
+        for n in [1, 2, 57]:
+            s.step(n)
+            o.run(n)
+            g_pops, _ = s.get_state(0)
+            err = np.abs(g_pops - o.n).max() / np.abs(o.n - workloads.REST_WEIGHTS[:, None, None]).max()
+            serr = np.abs(s.get_stress(0) - o.S).max() / np.abs(o.S).max()
+            print(f"{precision} {drive} t={o.t}: state {err:.2e} sigma {serr:.2e}", flush=True)
+            assert err < (5e-11 if precision == "fp64" else 1e-4)
+            assert serr < (1e-11 if precision == "fp64" else 1e-5)
 
 
 def test_stress_calls_need_the_option():
