@@ -71,7 +71,7 @@ struct SweepArgs {
   int k;                // step offset added to every channel's t
   int nnp;              // keep the flow-induced density terms
   int nt;               // store the new state with nontemporal hints
-  int down;             // march the strips downwards (vector sweep)
+  int down;             // the step marches downwards (vector sweep; flipped strips go upwards)
   const float *uref;    // FP32: reference velocity of every row (all channels)
   const void *SA;       // viscoelastic model: stress read (3 planes)
   void *SB;             // viscoelastic model: stress written (3 planes)

@@ -343,9 +343,9 @@ lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s) {
     if (!h->act_count[c]) continue;
     // Serpentine order: steps reading buffer 0 take the strips in order and
     // march them upwards, steps reading buffer 1 take them in reverse and
-    // march downwards, so that every step starts on what the previous step
-    // wrote last, the likeliest to still sit in the last-level cache (MALL)
-    // when the state does not fit it whole.
+    // march downwards (flipped strips of a stack the other way in both), so
+    // that every step starts on what the previous step wrote last, the
+    // likeliest to still sit in the last-level cache (MALL).
     SweepArgs a = sweep_args(h, src == 0 ? h->dact : h->dact_rev, h->act_begin[c], h->act_count[c], src, k);
     a.down = (src == 1);
     HIPCHECK(h, launch_sweep(h->opt.precision == LB_FP32_SHIFTED, c, false, a, s));
