@@ -141,13 +141,7 @@ typedef struct {
  *                rows extrapolated linearly through the walls; there is then
  *                no flow-induced density. Needs LB_FP64, nn_pressure = 0, the
  *                instantaneous model and no pressure_gradient. Runs as three
- *                passes per step (u~, Sigma^nN, collide-and-stream);
- *   sweep_only   0: channels of at most 8192 (FP32) or 4096 (FP64) nodes run
- *                every step of a block of K steps in one launch, one
- *                workgroup each (instantaneous model with walls or a body
- *                force; not with the pressure drive, the viscoelastic option
- *                or stress_force); 1: every channel is stepped by the
- *                per-step sweeps. Results agree to rounding either way.
+ *                passes per step (u~, Sigma^nN, collide-and-stream).
  */
 typedef struct {
   int32_t precision;
@@ -157,7 +151,6 @@ typedef struct {
   double steady_tol;
   int32_t viscoelastic;
   int32_t stress_force;
-  int32_t sweep_only;
 } lb_options;
 
 /* Observables for lb_observe. Profiles return ny doubles (x-averages per row,

@@ -77,23 +77,6 @@ struct SweepArgs {
   void *SB;             // viscoelastic model: stress written (3 planes)
   int ve;               // time-integrated stress in place of the instantaneous one
 };
-// Small channels (nx * ny nodes of u~ fit kBlockLdsBytes of LDS) can run
-// every step of a block in one launch, one workgroup per channel.
-constexpr int kBlockLdsBytes = 64 * 1024;
-struct BlockArgs {
-  const void *A;        // state read at the first step
-  void *B;              // state written at the first step (the two alternate)
-  const ChanDev *ch;
-  const int *list;      // channels to run, one per workgroup
-  int n_list;
-  int k0;               // step offset of the first step
-  int steps;            // steps to run
-  int nnp;              // keep the flow-induced density terms
-  int max_nodes;        // largest nx * ny in the list (LDS size)
-  const float *uref;    // FP32: reference velocity of every row
-};
-inline int block_max_nodes(int esize) { return kBlockLdsBytes / (2 * esize); }
-
 // A state buffer larger than this is written with nontemporal stores: it
 // cannot stay in the 256 MB last-level cache (MALL) until the next step reads
 // it, so caching its lines only evicts the reads in flight.
@@ -140,7 +123,6 @@ hipError_t launch_reduce(const ChanDev *ch, int n_ch, const double *part, double
                          int steps_since, hipStream_t s);
 hipError_t launch_advance(ChanDev *ch, int n_ch, int steps, hipStream_t s);
 hipError_t launch_gpbc(int fp32, void *B, const ChanDev *ch, int n_ch, int k, const float *uref, hipStream_t s);
-hipError_t launch_block(int fp32, const BlockArgs &a, hipStream_t s);
 hipError_t launch_saf_step(const double *A, double *B, const ChanDev *ch, int n_ch, long long plane, int k,
                            double *U, double *Tn, hipStream_t s);
 hipError_t launch_saf_observe(const double *A, const ChanDev *ch, int n_ch, long long plane, int total_rows,

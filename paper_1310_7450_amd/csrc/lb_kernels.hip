@@ -1435,82 +1435,6 @@ __global__ void __launch_bounds__(256) rereference_kernel(float *A, const ChanDe
 }
 
 // ---------------------------------------------------------------------------
-// Small channels, one workgroup each, every step of a block in one launch.
-// A step is two phases over the channel's nodes separated by workgroup
-// barriers: u~ of every node into LDS, then kappa from LDS and the node
-// update (the same device functions as the sweeps), stored to the other
-// buffer. The buffers alternate inside the launch exactly as they would
-// between single-step launches. Channels are independent, so no workgroup
-// ever waits for another.
-template <typename T, bool SHIFT>
-__global__ void __launch_bounds__(256) channel_block_kernel(BlockArgs a) {
-  extern __shared__ unsigned char lds_raw[];
-  U2<T> *U = reinterpret_cast<U2<T> *>(lds_raw);
-  const ChanDev c = a.ch[a.list[blockIdx.x]];
-  const int nx = c.nx, ny = c.ny, N = nx * ny;
-  const Coef<T> q(c);
-  auto clampy = [&](int y) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
-  auto ref = [&](int y) -> T {
-    if constexpr (SHIFT) return a.uref[c.row_off + clampy(y)];
-    return T(0);
-  };
-  // pulled populations of node (x, y), relative to the row's reference
-  auto pull_node = [&](const T *A, int x, int y, T uw6, T f[9]) {
-    pull<T>(A, c.off + (long long)y * nx, nx, ny, x, y, uw6, f);
-    if constexpr (SHIFT) to_row_reference(f, ref(y - 1), ref(y), ref(y + 1), y == 0, y == ny - 1);
-  };
-  for (int k = 0; k < a.steps; ++k) {
-    const T *A = static_cast<const T *>((k & 1) ? a.B : a.A);
-    T *B = static_cast<T *>((k & 1) ? const_cast<void *>(a.A) : a.B);
-    const long long t = c.t + a.k0 + k;
-    const T fx = (t < c.t_startup) ? T(c.g) : T(0);
-    const T uwg = (t < c.t_startup) ? T(c.uw) : T(0);
-    const T uw6 = (t >= 1 && t - 1 < c.t_startup) ? T(c.uw / 6.0) : T(0);
-    for (int id = threadIdx.x; id < N; id += blockDim.x) {
-      const int y = id / nx, x = id - y * nx;
-      T f[9], sd, mx, my;
-      pull_node(A, x, y, uw6, f);
-      moments<T>(f, sd, mx, my);
-      U[id] = u_tilde<T, SHIFT>(sd, mx, my, fx, ref(y));
-    }
-    __syncthreads();
-    for (int id = threadIdx.x; id < N; id += blockDim.x) {
-      const int y = id / nx, x = id - y * nx;
-      const long long node = c.off + id;
-      T f[9], sd, mx, my;
-      pull_node(A, x, y, uw6, f);
-      moments<T>(f, sd, mx, my);
-      const T Pc = A[slot(9, node)];
-      const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
-      const U2<T> uc = U[id];
-      const U2<T> lf = U[id - x + xm], rt = U[id - x + xp];
-      // no-slip ghosts behind the half-way walls (with SHIFT the ghost rows
-      // take the mirrored references, as in the sweeps)
-      const U2<T> dn = (y == 0) ? U2<T>{-uc.x, -uc.y} : U[id - nx];
-      const U2<T> up = (y == ny - 1) ? U2<T>{(SHIFT ? T(0) : T(2) * uwg) - uc.x, -uc.y} : U[id + nx];
-      const T urc = ref(y);
-      T kref = T(0);
-      if constexpr (SHIFT) {
-        const T urd = (y == 0) ? -urc : ref(y - 1);
-        const T uru = (y == ny - 1) ? T(2) * uwg - urc : ref(y + 1);
-        kref = T(0.5) * (uru - urd);
-      }
-      T out[9], trT;
-      const T sp[3] = {T(0), T(0), T(0)};
-      T sn[3];
-      double obs[OF_COUNT];
-      node_update<T, SHIFT, false, false>(f, sd, mx, my, Pc, fx, lf, rt, dn, up, urc, kref, q, a.nnp, sp, sn, out,
-                                          trT, obs);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) B[slot(i, node)] = out[i];
-      B[slot(9, node)] = trT;
-    }
-    // the next step pulls what this one stored, from other threads
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Stress as a force density (FP64, instantaneous model): the divergence of
 // the non-Newtonian stress enters as an external force in Eq. (ns), the
 // alternative Sec. II.C names. Three passes per step over every node of the
@@ -1820,17 +1744,6 @@ hipError_t launch_rereference(float *A, const ChanDev *ch, int n_ch, int total_r
                               float *uref, hipStream_t s) {
   if (n_ch == 0 || total_rows == 0) return hipSuccess;
   hipLaunchKernelGGL(rereference_kernel, dim3(total_rows), dim3(256), 0, s, A, ch, n_ch, prof, uref);
-  return hipGetLastError();
-}
-
-hipError_t launch_block(int fp32, const BlockArgs &a, hipStream_t s) {
-  if (a.n_list == 0 || a.steps == 0) return hipSuccess;
-  const size_t lds = (size_t)a.max_nodes * (fp32 ? sizeof(U2<float>) : sizeof(U2<double>));
-  if (lds > (size_t)kBlockLdsBytes) return hipErrorInvalidValue;
-  if (fp32)
-    hipLaunchKernelGGL((channel_block_kernel<float, true>), dim3(a.n_list), dim3(256), lds, s, a);
-  else
-    hipLaunchKernelGGL((channel_block_kernel<double, false>), dim3(a.n_list), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 

@@ -43,7 +43,6 @@ struct Layout {
          off_prof = 0, off_prev = 0, off_scal = 0, off_uref = 0, bytes = 0;
   size_t off_stress[2] = {0, 0};  // viscoelastic model only
   size_t off_saf_u = 0, off_saf_t = 0;  // stress-as-force scratch (u~, Sigma^nN)
-  size_t off_blocks = 0;                // channels stepped one workgroup each
   std::vector<ChanDev> ch;
 };
 
@@ -58,7 +57,6 @@ std::string validate(const lb_channel *c, int n, const lb_options *o) {
   if (!(o->steady_tol >= 0) || !std::isfinite(o->steady_tol)) return "steady_tol must be >= 0";
   if (o->viscoelastic != 0 && o->viscoelastic != 1) return "viscoelastic must be 0 or 1";
   if (o->stress_force != 0 && o->stress_force != 1) return "stress_force must be 0 or 1";
-  if (o->sweep_only != 0 && o->sweep_only != 1) return "sweep_only must be 0 or 1";
   if (o->stress_force && (o->precision != LB_FP64 || o->nn_pressure || o->viscoelastic))
     return "stress_force needs FP64, nn_pressure = 0 and the instantaneous model";
   for (int i = 0; i < n; ++i) {
@@ -212,7 +210,6 @@ Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
     L.off_saf_u = take(sizeof(double) * 2 * L.plane);
     L.off_saf_t = take(sizeof(double) * 3 * L.plane);
   }
-  L.off_blocks = take(sizeof(int) * n);
   L.bytes = at;
   return L;
 }
@@ -235,11 +232,6 @@ struct lb_handle {
   float *duref = nullptr;    // FP32: reference velocity of every row
   void *sbuf[2] = {nullptr, nullptr};  // viscoelastic model: stress buffers (same parity as buf)
   double *saf_u = nullptr, *saf_t = nullptr;  // stress-as-force scratch
-  // Small channels step one workgroup each, a whole block per launch
-  // (channel_block_kernel); the sweeps then skip them.
-  std::vector<char> small;   // channel runs in block mode
-  int *dblocks = nullptr;    // active small channels
-  int n_blocks = 0, block_nodes = 0;
   // strips grouped by width class: [begin, begin + count) in the arrays
   int all_begin[kClasses] = {0}, all_count[kClasses] = {0};
   int act_begin[kClasses] = {0}, act_count[kClasses] = {0};
@@ -290,25 +282,11 @@ lb_status upload_strips(lb_handle *h, bool all) {
   // stacks while a state buffer fits the last-level cache (the stores are
   // then cached, see sweep_args)
   const bool stack = (long long)kPlanes * h->L.plane * h->L.esize <= kNontemporalBytes;
-  std::vector<int> blocks;
-  int block_nodes = 0;
   for (int i = 0; i < h->n_ch; ++i) {
     if (!all && !h->active[i]) continue;
     const ChanDev &d = h->L.ch[i];
-    if (!all && h->small[i]) {
-      blocks.push_back(i);
-      block_nodes = std::max(block_nodes, d.nx * d.ny);
-      continue;
-    }
     add_strips(i, d, h->L.esize, strip_rows_for(width_class(d.nx, h->L.esize), d.nx, d.ny, h->opt.strip_rows),
                stack, raw);
-  }
-  if (!all) {
-    h->n_blocks = (int)blocks.size();
-    h->block_nodes = block_nodes;
-    if (!blocks.empty())
-      HIPCHECK(h, hipMemcpyAsync(h->dblocks, blocks.data(), blocks.size() * sizeof(int), hipMemcpyHostToDevice,
-                                 h->stream));
   }
   if (all) {
     group_strips(raw, h->L.ch, h->L.esize, grouped, h->all_begin, h->all_count);
@@ -380,25 +358,6 @@ lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s) {
   return LB_OK;
 }
 
-// Enqueues m steps (offsets 0..m-1, first read buffer src) of the channels
-// in block mode: one launch, one workgroup per channel.
-lb_status enqueue_blocks(lb_handle *h, int src, int m, hipStream_t s) {
-  if (h->n_blocks == 0 || m == 0) return LB_OK;
-  BlockArgs b{};
-  b.A = h->buf[src];
-  b.B = h->buf[src ^ 1];
-  b.ch = h->dch;
-  b.list = h->dblocks;
-  b.n_list = h->n_blocks;
-  b.k0 = 0;
-  b.steps = m;
-  b.nnp = h->opt.nn_pressure;
-  b.max_nodes = h->block_nodes;
-  b.uref = h->duref;
-  HIPCHECK(h, launch_block(h->opt.precision == LB_FP32_SHIFTED, b, s));
-  return LB_OK;
-}
-
 lb_status enqueue_observe(lb_handle *h, int update_residual, int steps_since) {
   if (h->opt.stress_force) {
     HIPCHECK(h, launch_saf_observe(static_cast<const double *>(h->buf[h->cur]), h->dch, h->n_ch, h->L.plane,
@@ -428,7 +387,6 @@ lb_status capture(lb_handle *h, int src) {
   hipGraph_t g = nullptr;
   HIPCHECK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed));
   lb_status st = LB_OK;
-  st = enqueue_blocks(h, src, h->K, h->cap);
   for (int k = 0; k < h->K && st == LB_OK; ++k) st = enqueue_step(h, src ^ (k & 1), k, h->cap);
   if (st == LB_OK) {
     hipError_t e = launch_advance(h->dch, h->n_ch, h->K, h->cap);
@@ -613,14 +571,6 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
   }
   h->t.assign(n, 0);
   h->active.assign(n, 1);
-  h->dblocks = reinterpret_cast<int *>(h->ws + h->L.off_blocks);
-  // block mode: small channels of the instantaneous model with walls or a
-  // body force (the pressure drive's column pass and the other stress
-  // paths run with the sweeps)
-  h->small.assign(n, 0);
-  if (!o->sweep_only && !o->viscoelastic && !o->stress_force && !h->any_gpbc)
-    for (int i = 0; i < n; ++i)
-      h->small[i] = (long long)c[i].nx * c[i].ny <= block_max_nodes(h->L.esize);
   auto bail = [&](lb_status s) {
     if (h->cap) (void)hipStreamDestroy(h->cap);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -691,10 +641,6 @@ lb_status lb_step(lb_handle *h, int64_t n) {
       m = h->K;
     } else {
       m = (int)std::min<int64_t>(left, h->K - h->since_block);
-      {
-        lb_status st = enqueue_blocks(h, h->cur, m, h->stream);
-        if (st != LB_OK) return st;
-      }
       for (int k = 0; k < m; ++k) {
         lb_status st = enqueue_step(h, h->cur ^ (k & 1), k, h->stream);
         if (st != LB_OK) return st;

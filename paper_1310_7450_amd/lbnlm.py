@@ -41,7 +41,7 @@ class LbChannel(C.Structure):
 class LbOptions(C.Structure):
     _fields_ = [("precision", C.c_int32), ("nn_pressure", C.c_int32), ("obs_every", C.c_int32),
                 ("strip_rows", C.c_int32), ("steady_tol", C.c_double), ("viscoelastic", C.c_int32),
-                ("stress_force", C.c_int32), ("sweep_only", C.c_int32)]
+                ("stress_force", C.c_int32)]
 
 
 class LbError(RuntimeError):
@@ -111,11 +111,11 @@ def _dp(a):
 
 
 def options(precision=FP64, nn_pressure=True, obs_every=1000, strip_rows=0, steady_tol=0.0, viscoelastic=False,
-            stress_force=False, sweep_only=False):
+            stress_force=False):
     if isinstance(precision, str):
         precision = {"fp64": FP64, "fp32": FP32_SHIFTED, "fp32_shifted": FP32_SHIFTED}[precision]
     return LbOptions(int(precision), int(bool(nn_pressure)), int(obs_every), int(strip_rows), float(steady_tol),
-                     int(bool(viscoelastic)), int(bool(stress_force)), int(bool(sweep_only)))
+                     int(bool(viscoelastic)), int(bool(stress_force)))
 
 
 def workspace_bytes(channels: Sequence[ChannelSpec], opts: LbOptions) -> int:
@@ -133,19 +133,17 @@ class Solver:
     ``viscoelastic`` selects the time-integrated nonlinear Maxwell stress
     (lb_options.viscoelastic) in place of the instantaneous one;
     ``stress_force`` makes the stress enter as the force density div Sigma^nN
-    (lb_options.stress_force; FP64, nn_pressure False); ``sweep_only`` keeps
-    small channels on the per-step sweeps (lb_options.sweep_only)."""
+    (lb_options.stress_force; FP64, nn_pressure False)."""
 
     def __init__(self, channels: Sequence[ChannelSpec], precision="fp64", nn_pressure=True,
                  obs_every=1000, strip_rows=0, steady_tol=0.0, stream=None, device="cuda", viscoelastic=False,
-                 stress_force=False, sweep_only=False):
+                 stress_force=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("lbnlm needs a GPU; no CPU fallback exists")
         self.L = load_library()
         self.channels = list(channels)
-        self.opts = options(precision, nn_pressure, obs_every, strip_rows, steady_tol, viscoelastic, stress_force,
-                            sweep_only)
+        self.opts = options(precision, nn_pressure, obs_every, strip_rows, steady_tol, viscoelastic, stress_force)
         nbytes = workspace_bytes(self.channels, self.opts)
         self.device = torch.device(device)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)

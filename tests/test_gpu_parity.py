@@ -109,23 +109,19 @@ def test_poiseuille_fp32_shifted(orc):
 @pytest.mark.parametrize("nx,ny", [(1, 16), (2, 9), (4, 33), (16, 20), (64, 7), (3, 12), (100, 37), (130, 5), (63, 2),
                                    (8, 1), (128, 9), (192, 5), (256, 3), (128, 1), (384, 2)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("mode", ["blocks", "sweeps"])
-def test_perturbed_state_parity(orc, nx, ny, precision, mode):
+def test_perturbed_state_parity(orc, nx, ny, precision):
     """Seeded random populations (every moment non-zero, x gradients present)
     on narrow, aligned-wide (nx a multiple of 64), ragged-wide and odd
     lattices: one and several steps match the oracle node by node; covers the
     lane-group wrap, the edge columns and halo of wide strips, the periodic
-    wrap across strips, partial last strips, and one/two-row channels. Every
-    lattice here is small enough for block mode (one workgroup per channel,
-    a whole block per launch); "sweeps" steps them with the per-step sweep
-    kernels instead."""
+    wrap across strips, partial last strips, and one/two-row channels."""
     spec = ChannelSpec(nx=nx, ny=ny, force=3e-6, tau_lb=0.8, G=2e-4, tau0=500.0, gamma_c=0.1,
                        eps=0.01, visc_split=0.3, t_startup=40)
     pops, P = workloads.random_state(nx, ny, seed=nx * 1000 + ny)
     o = oracle_channel(orc, spec)
     o.set_state(pops, P, t=0)
     tol = 1e-12 if precision == "fp64" else 2e-6
-    with solver([spec], precision=precision, obs_every=16, strip_rows=4, sweep_only=(mode == "sweeps")) as s:
+    with solver([spec], precision=precision, obs_every=16, strip_rows=4) as s:
         s.set_state(0, pops, P, 0)
         g_pops, g_P = s.get_state(0)
         assert np.abs(g_pops - pops).max() <= (0 if precision == "fp64" else 1e-7)
@@ -159,38 +155,6 @@ def test_batched_channels_match_individual_oracles(orc):
             print(f"channel {i}: state rel err {err:.2e}", flush=True)
             assert err < 1e-9
             compare_fields(s, i, o, FP64_TOL, f"batched ch{i}")
-
-
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_block_mode_equals_sweeps(precision):
-    """Thirty ragged channels (every width class, Couette walls on some) in
-    one handle: 2,500 steps in block mode and with the sweeps give the same
-    states, to rounding (the two run the same device functions in different
-    kernels), and the same step counters; split calls included."""
-    rng = np.random.default_rng(5)
-    specs = []
-    for i in range(30):
-        nx = int(rng.choice([1, 2, 8, 33, 64, 100, 128, 256]))
-        ny = int(rng.integers(1, 40))
-        specs.append(ChannelSpec(nx=nx, ny=ny, force=float(rng.uniform(1e-7, 3e-6)), tau_lb=0.8, G=1e-4,
-                                 tau0=float(rng.uniform(300, 1000)), gamma_c=0.1, eps=0.0, visc_split=0.3,
-                                 t_startup=1200, wall_velocity=float(1e-3 * (i % 3 == 0))))
-    states = {}
-    for mode in ("blocks", "sweeps"):
-        with solver(specs, precision=precision, obs_every=100, sweep_only=(mode == "sweeps")) as s:
-            for i, c in enumerate(specs):
-                pops, P = workloads.random_state(c.nx, c.ny, seed=100 + i)
-                s.set_state(i, pops, P, 0)
-            for n in (1, 999, 1500):
-                s.step(n)
-            states[mode] = [s.get_state(i) for i in range(len(specs))]
-            assert all(s.observe(i, "step") == 2500 for i in range(len(specs)))
-    tol = 1e-12 if precision == "fp64" else 1e-5
-    for i in range(len(specs)):
-        (a, pa), (b, pb) = states["blocks"][i], states["sweeps"][i]
-        dev = np.abs(b - workloads.REST_WEIGHTS[:, None, None]).max()
-        assert np.abs(a - b).max() <= tol * dev, (i, specs[i], np.abs(a - b).max() / dev)
-        assert np.abs(pa - pb).max() <= tol * max(np.abs(pb).max(), 1e-30) * 100
 
 
 def test_observables_match_oracle(orc):
