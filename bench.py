@@ -93,7 +93,7 @@ def run_batched(max_steps=None, verbose=True):
     from paper_1310_7450_amd import Solver, autotune, workloads
     wl = workloads.batched_sweep()
     chans = wl["channels"]
-    sr = autotune.tune_strip_rows(chans, "fp32", steps=200, verbose=verbose)
+    sr = autotune.tune_strip_rows(chans, "fp32", steps=200, verbose=verbose, to_steady=True)
     ms = wl["max_steps"] if max_steps is None else max_steps
     with Solver(chans, precision="fp32", obs_every=wl["obs_every"], steady_tol=wl["steady_tol"],
                 strip_rows=sr) as s:
