@@ -77,7 +77,7 @@ def load_library():
     L.lb_status_string.argtypes = [C.c_int32]
     L.lb_status_string.restype = C.c_char_p
     for name in ["lb_workspace_bytes", "lb_create", "lb_destroy", "lb_step", "lb_observe",
-                 "lb_get_state", "lb_set_state", "lb_set_profile"]:
+                 "lb_get_state", "lb_set_state", "lb_get_stress", "lb_set_stress", "lb_set_profile"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

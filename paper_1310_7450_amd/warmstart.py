@@ -76,11 +76,15 @@ def targets(specs, profiles):
     return Y
 
 
-def solve_to_steady(specs, precision="fp32", max_steps=3_000_000, strip_rows=16, warm=None, tol=1e-9):
+def solve_to_steady(specs, precision="fp32", max_steps=3_000_000, strip_rows=None, warm=None, tol=1e-9):
     """Runs every channel to its steady state (residual < tol) in one handle.
-    ``warm`` optionally gives (u_x, N1) at the Chebyshev points per channel.
-    Returns the row profiles (u_x, sigma_xy, N1), the steps each channel took
-    and the wall time."""
+    ``warm`` optionally gives (u_x, N1) at the Chebyshev points per channel;
+    ``strip_rows`` None takes the autotuner's choice for a run to steady
+    state. Returns the row profiles (u_x, sigma_xy, N1), the steps each
+    channel took and the wall time."""
+    if strip_rows is None:
+        from . import autotune
+        strip_rows = autotune.tune_strip_rows(specs, precision, steps=200, to_steady=True)
     t0 = time.perf_counter()
     with Solver(specs, precision=precision, obs_every=1000, steady_tol=tol, strip_rows=strip_rows) as s:
         if warm is not None:
