@@ -29,11 +29,10 @@ HBM_PEAK_GBS = 8000.0
 # (viscoelastic) model also reads and writes the three stress fields.
 BYTES_PER_NODE = {"fp32": 80, "fp64": 160}
 BYTES_PER_NODE_VE = {"fp32": 104, "fp64": 208}
-# Stress as a force density (FP64, three passes per step): the u~ pass reads
-# 9 pulled populations and writes u~ (72 + 16 B), the stress pass reads u~ and
-# writes Sigma^nN (16 + 24 B), the collide pass reads 9 populations, P and
-# Sigma^nN and writes 9 populations and P (80 + 24 + 80 B).
-BYTES_PER_NODE_SAF = 312
+# Stress as a force density (FP64, one fused kernel per step): u~ and
+# Sigma^nN stay on chip, so a node update reads 9 populations and P and
+# writes them (80 + 80 B), as the FP64 sweep does.
+BYTES_PER_NODE_SAF = 160
 
 
 def measured_traffic(key):
@@ -166,7 +165,7 @@ def run_viscoelastic(steps=2000, warmup=1000):
 
 def run_stress_force(steps=1000, warmup=1000):
     """The same 4096 x 1024 workload with the stress as a force density
-    (FP64, no flow-induced density, three passes per step)."""
+    (FP64, no flow-induced density, one fused kernel per step)."""
     from paper_1310_7450_amd import workloads
     wl = workloads.large_channel()
     r = time_solver("fp64", wl, steps, warmup, stress_force=True)

@@ -140,8 +140,10 @@ typedef struct {
  *                node first, central differences for the divergence and ghost
  *                rows extrapolated linearly through the walls; there is then
  *                no flow-induced density. Needs LB_FP64, nn_pressure = 0, the
- *                instantaneous model and no pressure_gradient. Runs as three
- *                passes per step (u~, Sigma^nN, collide-and-stream).
+ *                instantaneous model, no pressure_gradient and channels of
+ *                at most 429,496,704 nodes. Runs as one fused pass per step
+ *                (u~, Sigma^nN and the collide-and-stream of a tile of nodes
+ *                in one workgroup).
  */
 typedef struct {
   int32_t precision;

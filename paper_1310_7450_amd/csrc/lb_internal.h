@@ -123,8 +123,20 @@ hipError_t launch_reduce(const ChanDev *ch, int n_ch, const double *part, double
                          int steps_since, hipStream_t s);
 hipError_t launch_advance(ChanDev *ch, int n_ch, int steps, hipStream_t s);
 hipError_t launch_gpbc(int fp32, void *B, const ChanDev *ch, int n_ch, int k, const float *uref, hipStream_t s);
-hipError_t launch_saf_step(const double *A, double *B, const ChanDev *ch, int n_ch, long long plane, int k,
-                           double *U, double *Tn, hipStream_t s);
+// Fused stress-force step: tiles of kSafTileX x kSafTileY output nodes
+// (x0, y0, y1 of a Strip), one workgroup each.
+#ifndef LB_SAF_TX
+#define LB_SAF_TX 64
+#endif
+#ifndef LB_SAF_TY
+#define LB_SAF_TY 8
+#endif
+#ifndef LB_SAF_THREADS
+#define LB_SAF_THREADS 512
+#endif
+constexpr int kSafTileX = LB_SAF_TX, kSafTileY = LB_SAF_TY, kSafThreads = LB_SAF_THREADS;
+hipError_t launch_saf_fused(const double *A, double *B, const ChanDev *ch, const Strip *tiles, int n_tiles, int k,
+                            hipStream_t s);
 hipError_t launch_saf_observe(const double *A, const ChanDev *ch, int n_ch, long long plane, int total_rows,
                               double *U, double *Tn, double *part, hipStream_t s);
 hipError_t launch_rereference(float *A, const ChanDev *ch, int n_ch, int total_rows, const double *prof,

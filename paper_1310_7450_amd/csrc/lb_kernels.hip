@@ -391,14 +391,17 @@ __device__ __forceinline__ double wall_drag(const T f[9], int y, int ny, T uw6) 
   return d;
 }
 
-// Workgroup w runs on XCD w % 8; give each XCD a contiguous range of strips
-// so that neighbouring strips share halo rows through that XCD's L2.
+// Workgroup w of n runs on XCD w % 8; the work item it takes, such that
+// each XCD takes a contiguous range of the n items (neighbouring items then
+// share their halo rows through that XCD's L2).
+__device__ __forceinline__ int xcd_item(int w, int n) {
+  const int q = n >> 3, rem = n & 7, j = w & 7;
+  return j * q + (j < rem ? j : rem) + (w >> 3);
+}
+
 __device__ __forceinline__ int strip_index(const SweepArgs &a) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int w = blockIdx.x;
-  const int q = a.n_wg >> 3, rem = a.n_wg & 7, j = w & 7;
-  const int L = j * q + (j < rem ? j : rem) + (w >> 3);
-  return L * LB_WG_WAVES + wave;
+  return xcd_item(blockIdx.x, a.n_wg) * LB_WG_WAVES + wave;
 }
 
 template <typename T, bool SHIFT, int TXW, bool WIDE, bool OBS, bool VE>
@@ -1437,12 +1440,13 @@ __global__ void __launch_bounds__(256) rereference_kernel(float *A, const ChanDe
 // ---------------------------------------------------------------------------
 // Stress as a force density (FP64, instantaneous model): the divergence of
 // the non-Newtonian stress enters as an external force in Eq. (ns), the
-// alternative Sec. II.C names. Three passes per step over every node of the
-// active channels, one thread per node: u~, then Sigma^nN from the
-// neighbours' u~, then the collision with the force f = rho0 g + div
-// Sigma^nN (central differences, ghost rows extrapolated linearly through
-// the walls) in the body-force terms of the forcing. Scratch: U (u~_x, u~_y)
-// and T (Sigma^nN xx, xy, yy), plane-major over the nodes of the buffer.
+// alternative Sec. II.C names. A step forms u~ at every node, Sigma^nN from
+// the neighbours' u~, then collides with the force f = rho0 g + div Sigma^nN
+// (central differences, ghost rows extrapolated linearly through the walls)
+// in the body-force terms of the forcing. The step runs as one fused kernel
+// over tiles (saf_fused_kernel); observation runs the same stages as
+// node-wise passes over every channel, with scratch U (u~_x, u~_y) and T
+// (Sigma^nN xx, xy, yy), plane-major over the nodes of the buffer.
 
 // Channel holding node n (channels are laid out by increasing offset).
 __device__ __forceinline__ int channel_of_node(const ChanDev *ch, int n_ch, long long n) {
@@ -1552,38 +1556,157 @@ __device__ __forceinline__ void saf_force(const double *__restrict__ Tn, long lo
   fsy = 0.5 * (Tn[plane + row + xp] - Tn[plane + row + xm]) + 0.5 * (up[2] - dn[2]);
 }
 
-__global__ void __launch_bounds__(256) saf_collide_kernel(const double *__restrict__ A, double *__restrict__ B,
-                                                          const ChanDev *ch, int n_ch, long long plane, int k,
-                                                          const double *__restrict__ Tn) {
+// One step of the stress-force path fused in one kernel, one workgroup per
+// tile of kSafTX x kSafTY output nodes and one thread per output node. Each
+// XCD takes a contiguous run of the tile list, which the host orders so that
+// a run is a block of neighbouring tiles: adjacent tiles share the halo
+// populations they pull and then find them in that XCD's L2. Each
+// thread pulls its node and keeps the populations; u~ of the tile and of a
+// ring of two nodes around it go to LDS, then Sigma^nN of the tile and a ring
+// of one node, then each thread collides its node with div Sigma^nN from
+// LDS. Columns wrap (x periodic; narrow channels repeat columns); rows
+// outside the channel are the wall ghosts of saf_kappa and saf_force. The
+// arithmetic is that of the three separate passes.
+constexpr int kSafTX = kSafTileX, kSafTY = kSafTileY;
+constexpr int kSafUX = kSafTX + 4, kSafUY = kSafTY + 4;  // u~ region
+constexpr int kSafSX = kSafTX + 2, kSafSY = kSafTY + 2;  // Sigma^nN region
+constexpr int kSafRing = 4 * kSafUX + 4 * kSafTY;       // u~ region minus the tile
+static_assert(kSafTX * kSafTY == kSafThreads, "one output node per thread");
+
+// Slot of population q of node m of a channel relative to the channel's first
+// slot (channels start on a tile boundary, so slot(q, off + m) = kPlanes *
+// off + lslot(q, m)); 32-bit, for channels of fewer than 2^32 / kPlanes
+// nodes.
+__device__ __forceinline__ unsigned lslot(int q, unsigned m) {
+  return ((m >> 6) * kPlanes + q) * kTile + (m & (kTile - 1));
+}
+
+// pull() on a channel's own slots (C = the channel's first slot).
+__device__ __forceinline__ void pull_local(const double *__restrict__ C, int nx, int ny, int x, int y, double uw6,
+                                           double f[9]) {
+  const unsigned row = (unsigned)y * nx;
+  const unsigned xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+  const unsigned dn = row - nx, up = row + nx;
+  const bool bot = (y == 0), top = (y == ny - 1);
+  f[0] = C[lslot(0, row + x)];
+  f[1] = C[lslot(1, row + xm)];
+  f[3] = C[lslot(3, row + xp)];
+  f[2] = C[bot ? lslot(4, row + x) : lslot(2, dn + x)];
+  f[5] = C[bot ? lslot(7, row + x) : lslot(5, dn + xm)];
+  f[6] = C[bot ? lslot(8, row + x) : lslot(6, dn + xp)];
+  f[4] = C[top ? lslot(2, row + x) : lslot(4, up + x)];
+  f[7] = C[top ? lslot(5, row + x) : lslot(7, up + xp)] - (top ? uw6 : 0.0);
+  f[8] = C[top ? lslot(6, row + x) : lslot(8, up + xm)] + (top ? uw6 : 0.0);
+}
+
+__global__ void __launch_bounds__(kSafThreads) saf_fused_kernel(const double *__restrict__ A,
+                                                                double *__restrict__ B, const ChanDev *ch,
+                                                                const Strip *tiles, int k) {
+  __shared__ double su[2][kSafUY][kSafUX];
+  __shared__ double sT[3][kSafSY][kSafSX];
   constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
   constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < plane;
-       n += (long long)gridDim.x * blockDim.x) {
-    SafNode q;
-    if (!saf_node(ch, n_ch, n, k, false, q)) continue;
-    const double g = (q.t < q.c.t_startup) ? q.c.g : 0.0;
-    const double uw6 = (q.t >= 1 && q.t - 1 < q.c.t_startup) ? q.c.uw / 6.0 : 0.0;
-    double f[9], sd, mx, my;
-    pull<double>(A, q.c.off + (long long)q.y * q.c.nx, q.c.nx, q.c.ny, q.x, q.y, uw6, f);
+  const Strip tl = tiles[xcd_item(blockIdx.x, gridDim.x)];
+  const ChanDev c = ch[tl.ch];
+  if (!c.active) return;  // frozen channel (uniform over the workgroup)
+  const int nx = c.nx, ny = c.ny;
+  const long long t = c.t + k;
+  const double g = (t < c.t_startup) ? c.g : 0.0;
+  const double uwg = (t < c.t_startup) ? c.uw : 0.0;
+  const double uw6 = (t >= 1 && t - 1 < c.t_startup) ? c.uw / 6.0 : 0.0;
+  const Coef<double> cf(c);
+  const double *__restrict__ Ac = A + c.off * kPlanes;
+  double *__restrict__ Bc = B + c.off * kPlanes;
+  auto wrapx = [&](int x) {
+    const int r = x % nx;
+    return r < 0 ? r + nx : r;
+  };
+  // this thread's node: populations kept to the collision, u~ to LDS
+  const int jo = threadIdx.x / kSafTX, io = threadIdx.x - jo * kSafTX;
+  const int yo = tl.y0 + jo, xo = tl.x0 + io;
+  double f[9], sd = 1.0, mx = 0.0, my = 0.0;
+  if (yo < ny) {
+    pull_local(Ac, nx, ny, wrapx(xo), yo, uw6, f);
     moments<double>(f, sd, mx, my);
-    double fsx, fsy;
-    saf_force(Tn, plane, q, fsx, fsy);
-    const double fx = g + fsx, fy = fsy;
-    const double ux = (mx + 0.5 * fx) / sd, uy = (my + 0.5 * fy) / sd;
-    const double usq = ux * ux + uy * uy, uf = ux * fx + uy * fy;
-    const double om = q.c.omega, kf = q.c.kf;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      // BGK toward n^eq(s, u) plus the body-force terms of Eq. (bodyforce)
-      // with the total force (no stress term, r = 0)
-      const double cu = cx[i] * ux + cy[i] * uy, cfo = cx[i] * fx + cy[i] * fy;
-      const double a = weight<double>(i);
-      const double neq = a * sd * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
-      const double F = a * kf * (3.0 * cfo + 9.0 * cu * cfo - 3.0 * uf);
-      B[slot(i, n)] = f[i] - om * (f[i] - neq) + F;
-    }
-    B[slot(9, n)] = A[slot(9, n)];  // no flow-induced density: P is carried
+    su[0][jo + 2][io + 2] = (mx + 0.5 * g) / sd;
+    su[1][jo + 2][io + 2] = my / sd;
   }
+  // u~ of the ring of two nodes around the tile: two rows below, two above,
+  // two columns on either side
+  for (int h = threadIdx.x; h < kSafRing; h += kSafThreads) {
+    int j, ii;
+    if (h < 2 * kSafUX) {
+      j = h / kSafUX;
+      ii = h - j * kSafUX;
+    } else if (h < 4 * kSafUX) {
+      const int r = h - 2 * kSafUX;
+      j = kSafTY + 2 + r / kSafUX;
+      ii = r % kSafUX;
+    } else {
+      const int r = h - 4 * kSafUX, side = r & 3;
+      j = 2 + (r >> 2);
+      ii = side < 2 ? side : kSafUX - 4 + side;
+    }
+    const int y = tl.y0 - 2 + j;
+    if (y < 0 || y >= ny) continue;
+    double fh[9], hs, hx, hy;
+    pull_local(Ac, nx, ny, wrapx(tl.x0 - 2 + ii), y, uw6, fh);
+    moments<double>(fh, hs, hx, hy);
+    su[0][j][ii] = (hx + 0.5 * g) / hs;
+    su[1][j][ii] = hy / hs;
+  }
+  __syncthreads();
+  // Sigma^nN of the tile and a ring of one node (kappa with the wall ghosts)
+  for (int i = threadIdx.x; i < kSafSX * kSafSY; i += kSafThreads) {
+    const int j = i / kSafSX, ii = i - j * kSafSX;
+    const int y = tl.y0 - 1 + j;
+    if (y < 0 || y >= ny) continue;
+    const int ju = j + 1, iu = ii + 1;
+    const double ux = su[0][ju][iu], uy = su[1][ju][iu];
+    const double uxd = (y > 0) ? su[0][ju - 1][iu] : -ux, uyd = (y > 0) ? su[1][ju - 1][iu] : -uy;
+    const double uxu = (y < ny - 1) ? su[0][ju + 1][iu] : 2.0 * uwg - ux;
+    const double uyu = (y < ny - 1) ? su[1][ju + 1][iu] : -uy;
+    const double kxx = 0.5 * (su[0][ju][iu + 1] - su[0][ju][iu - 1]);
+    const double kxy = 0.5 * (uxu - uxd);
+    const double kyx = 0.5 * (su[1][ju][iu + 1] - su[1][ju][iu - 1]);
+    const double kyy = 0.5 * (uyu - uyd);
+    double sxx = 0, sxy = 0, syy = 0;
+    if (cf.stress_on) inlm_stress<double>(kxx, kxy, kyx, kyy, cf, sxx, sxy, syy);
+    sT[0][j][ii] = sxx - cf.lgt * 2.0 * kxx;
+    sT[1][j][ii] = sxy - cf.lgt * (kxy + kyx);
+    sT[2][j][ii] = syy - cf.lgt * 2.0 * kyy;
+  }
+  __syncthreads();
+  // collide and stream this thread's node
+  if (yo >= tl.y1 || xo >= nx) return;
+  const int js = jo + 1, is = io + 1;
+  double dn[3], up[3];
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const double Tc = sT[p][js][is];
+    if (ny == 1) {
+      dn[p] = up[p] = Tc;
+    } else {
+      dn[p] = (yo > 0) ? sT[p][js - 1][is] : 2.0 * Tc - sT[p][js + 1][is];
+      up[p] = (yo < ny - 1) ? sT[p][js + 1][is] : 2.0 * Tc - sT[p][js - 1][is];
+    }
+  }
+  const double fsx = 0.5 * (sT[0][js][is + 1] - sT[0][js][is - 1]) + 0.5 * (up[1] - dn[1]);
+  const double fsy = 0.5 * (sT[1][js][is + 1] - sT[1][js][is - 1]) + 0.5 * (up[2] - dn[2]);
+  const unsigned m = (unsigned)yo * nx + xo;
+  const double fx = g + fsx, fy = fsy;
+  const double ux = (mx + 0.5 * fx) / sd, uy = (my + 0.5 * fy) / sd;
+  const double usq = ux * ux + uy * uy, uf = ux * fx + uy * fy;
+  const double om = c.omega, kf = c.kf;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const double cu = cx[q] * ux + cy[q] * uy, cfo = cx[q] * fx + cy[q] * fy;
+    const double a = weight<double>(q);
+    const double neq = a * sd * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+    const double F = a * kf * (3.0 * cfo + 9.0 * cu * cfo - 3.0 * uf);
+    Bc[lslot(q, m)] = f[q] - om * (f[q] - neq) + F;
+  }
+  Bc[lslot(9, m)] = Ac[lslot(9, m)];
 }
 
 // Observation of the stress-force path: one workgroup per row of every
@@ -1752,13 +1875,10 @@ static int saf_blocks(long long plane) {
   return (int)(b < 16384 ? b : 16384);
 }
 
-hipError_t launch_saf_step(const double *A, double *B, const ChanDev *ch, int n_ch, long long plane, int k,
-                           double *U, double *Tn, hipStream_t s) {
-  if (n_ch == 0 || plane == 0) return hipSuccess;
-  const int nb = saf_blocks(plane);
-  hipLaunchKernelGGL(saf_u_kernel, dim3(nb), dim3(256), 0, s, A, ch, n_ch, plane, k, 0, U);
-  hipLaunchKernelGGL(saf_stress_kernel, dim3(nb), dim3(256), 0, s, ch, n_ch, plane, k, 0, U, Tn);
-  hipLaunchKernelGGL(saf_collide_kernel, dim3(nb), dim3(256), 0, s, A, B, ch, n_ch, plane, k, Tn);
+hipError_t launch_saf_fused(const double *A, double *B, const ChanDev *ch, const Strip *tiles, int n_tiles, int k,
+                            hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(saf_fused_kernel, dim3(n_tiles), dim3(kSafThreads), 0, s, A, B, ch, tiles, k);
   return hipGetLastError();
 }
 

@@ -39,10 +39,12 @@ struct Layout {
   int total_rows = 0;
   int total_part = 0;
   int max_strips = 0;
+  int saf_tiles = 0;  // stress-force path: tiles of the fused step
   size_t off_state[2] = {0, 0}, off_ch = 0, off_strips = 0, off_astrips = 0, off_rstrips = 0, off_part = 0,
          off_prof = 0, off_prev = 0, off_scal = 0, off_uref = 0, bytes = 0;
   size_t off_stress[2] = {0, 0};  // viscoelastic model only
   size_t off_saf_u = 0, off_saf_t = 0;  // stress-as-force scratch (u~, Sigma^nN)
+  size_t off_saf_tiles = 0;             // stress-as-force tiles
   std::vector<ChanDev> ch;
 };
 
@@ -81,6 +83,8 @@ std::string validate(const lb_channel *c, int n, const lb_options *o) {
     if (q.pressure_gradient != 0 && (q.force != 0 || q.wall_velocity != 0 || q.nx < 2 || o->nn_pressure))
       return bad("pressure_gradient needs force = 0, wall_velocity = 0, nx >= 2 and nn_pressure = 0");
     if (q.pressure_gradient != 0 && o->stress_force) return bad("pressure_gradient is not combined with stress_force");
+    if (o->stress_force && align_up((size_t)q.nx * q.ny, kTile) * kPlanes > 0xffffffffull)
+      return bad("stress_force needs nx * ny <= 429,496,704 per channel");
   }
   return "";
 }
@@ -209,6 +213,9 @@ Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
   if (o->stress_force) {
     L.off_saf_u = take(sizeof(double) * 2 * L.plane);
     L.off_saf_t = take(sizeof(double) * 3 * L.plane);
+    for (int i = 0; i < n; ++i)
+      L.saf_tiles += ((c[i].nx + kSafTileX - 1) / kSafTileX) * ((c[i].ny + kSafTileY - 1) / kSafTileY);
+    L.off_saf_tiles = take(sizeof(Strip) * L.saf_tiles);
   }
   L.bytes = at;
   return L;
@@ -232,6 +239,7 @@ struct lb_handle {
   float *duref = nullptr;    // FP32: reference velocity of every row
   void *sbuf[2] = {nullptr, nullptr};  // viscoelastic model: stress buffers (same parity as buf)
   double *saf_u = nullptr, *saf_t = nullptr;  // stress-as-force scratch
+  Strip *saf_tiles = nullptr;                 // stress-as-force tiles of every channel
   // strips grouped by width class: [begin, begin + count) in the arrays
   int all_begin[kClasses] = {0}, all_count[kClasses] = {0};
   int act_begin[kClasses] = {0}, act_count[kClasses] = {0};
@@ -335,8 +343,8 @@ SweepArgs sweep_args(lb_handle *h, const Strip *strips, int begin, int count, in
 // Enqueues the sweeps of one step (source buffer src, step offset k).
 lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s) {
   if (h->opt.stress_force) {
-    HIPCHECK(h, launch_saf_step(static_cast<const double *>(h->buf[src]), static_cast<double *>(h->buf[src ^ 1]),
-                                h->dch, h->n_ch, h->L.plane, k, h->saf_u, h->saf_t, s));
+    HIPCHECK(h, launch_saf_fused(static_cast<const double *>(h->buf[src]), static_cast<double *>(h->buf[src ^ 1]),
+                                 h->dch, h->saf_tiles, h->L.saf_tiles, k, s));
     return LB_OK;
   }
   for (int c = 0; c < kClasses; ++c) {
@@ -568,6 +576,7 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
   if (o->stress_force) {
     h->saf_u = reinterpret_cast<double *>(h->ws + h->L.off_saf_u);
     h->saf_t = reinterpret_cast<double *>(h->ws + h->L.off_saf_t);
+    h->saf_tiles = reinterpret_cast<Strip *>(h->ws + h->L.off_saf_tiles);
   }
   h->t.assign(n, 0);
   h->active.assign(n, 1);
@@ -596,6 +605,23 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
       hipSuccess)
     return bail(LB_EHIP);
   if (upload_strips(h, true) != LB_OK || upload_strips(h, false) != LB_OK) return bail(LB_EHIP);
+  std::vector<Strip> tiles;  // kept until the synchronisation below
+  if (o->stress_force) {
+    // The kernel hands each of the 8 XCDs a contiguous run of the list:
+    // the tile columns of a channel are split into 8 groups, each group
+    // listed band by band, so that an XCD's tiles have their horizontal and
+    // vertical neighbours (which share halo populations) on the same L2.
+    for (int i = 0; i < n; ++i) {
+      const int cols = (c[i].nx + kSafTileX - 1) / kSafTileX;
+      for (int g = 0; g < 8; ++g)
+        for (int y0 = 0; y0 < c[i].ny; y0 += kSafTileY)
+          for (int cx = g * cols / 8; cx < (g + 1) * cols / 8; ++cx)
+            tiles.push_back(Strip{i, cx * kSafTileX, y0, std::min(y0 + kSafTileY, c[i].ny), 0});
+    }
+    if (hipMemcpyAsync(h->saf_tiles, tiles.data(), sizeof(Strip) * tiles.size(), hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess)
+      return bail(LB_EHIP);
+  }
   if (fill_rest(h, 0) != LB_OK || fill_rest(h, 1) != LB_OK) return bail(LB_EHIP);
   // zero stress at rest (outside any graph)
   for (int b = 0; b < 2; ++b)

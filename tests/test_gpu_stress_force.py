@@ -2,8 +2,10 @@
 the FP64 oracle's reading R12, through the C ABI.
 
 The divergence of the non-Newtonian stress enters as a force density. The
-GPU runs three passes per step (u~, Sigma^nN, collide-and-stream) in FP64.
-It agrees with the oracle to rounding (well conditioned, G tau <= 0.2).
+GPU runs a step as one fused FP64 kernel over tiles of nodes (u~ and Sigma^nN
+of the tile and its halo in LDS, then collide-and-stream); observation runs
+the same stages as separate node-wise passes. It agrees with the oracle to
+rounding (well conditioned, G tau <= 0.2).
 """
 import dataclasses
 
