@@ -1572,6 +1572,7 @@ constexpr int kSafUX = kSafTX + 4, kSafUY = kSafTY + 4;  // u~ region
 constexpr int kSafSX = kSafTX + 2, kSafSY = kSafTY + 2;  // Sigma^nN region
 constexpr int kSafRing = 4 * kSafUX + 4 * kSafTY;       // u~ region minus the tile
 static_assert(kSafTX * kSafTY == kSafThreads, "one output node per thread");
+static_assert(kSafRing <= kSafThreads, "at most one ring node per thread");
 
 // Slot of population q of node m of a channel relative to the channel's first
 // slot (channels start on a tile boundary, so slot(q, off + m) = kPlanes *
@@ -1617,43 +1618,55 @@ __global__ void __launch_bounds__(kSafThreads) saf_fused_kernel(const double *__
   const Coef<double> cf(c);
   const double *__restrict__ Ac = A + c.off * kPlanes;
   double *__restrict__ Bc = B + c.off * kPlanes;
+  const bool wide = nx >= kSafTX + 4;  // then halo columns wrap at most once
   auto wrapx = [&](int x) {
+    if (wide) return x < 0 ? x + nx : (x >= nx ? x - nx : x);
     const int r = x % nx;
     return r < 0 ? r + nx : r;
   };
-  // this thread's node: populations kept to the collision, u~ to LDS
+  auto clampy = [&](int y) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
+  // This thread's node, whose populations it keeps to the collision, and
+  // (threads below kSafRing) one node of the ring of two around the tile:
+  // two rows below, two above, two columns on either side. Both are pulled
+  // before either is used, so that their loads overlap; rows outside the
+  // channel pull a row inside and store nothing.
   const int jo = threadIdx.x / kSafTX, io = threadIdx.x - jo * kSafTX;
   const int yo = tl.y0 + jo, xo = tl.x0 + io;
-  double f[9], sd = 1.0, mx = 0.0, my = 0.0;
-  if (yo < ny) {
-    pull_local(Ac, nx, ny, wrapx(xo), yo, uw6, f);
-    moments<double>(f, sd, mx, my);
-    su[0][jo + 2][io + 2] = (mx + 0.5 * g) / sd;
-    su[1][jo + 2][io + 2] = my / sd;
+  const int h = threadIdx.x;
+  int hj, hi;
+  if (h < 2 * kSafUX) {
+    hj = h / kSafUX;
+    hi = h - hj * kSafUX;
+  } else if (h < 4 * kSafUX) {
+    const int r = h - 2 * kSafUX;
+    hj = kSafTY + 2 + r / kSafUX;
+    hi = r % kSafUX;
+  } else {
+    const int r = h - 4 * kSafUX, side = r & 3;
+    hj = 2 + (r >> 2);
+    hi = side < 2 ? side : kSafUX - 4 + side;
   }
-  // u~ of the ring of two nodes around the tile: two rows below, two above,
-  // two columns on either side
-  for (int h = threadIdx.x; h < kSafRing; h += kSafThreads) {
-    int j, ii;
-    if (h < 2 * kSafUX) {
-      j = h / kSafUX;
-      ii = h - j * kSafUX;
-    } else if (h < 4 * kSafUX) {
-      const int r = h - 2 * kSafUX;
-      j = kSafTY + 2 + r / kSafUX;
-      ii = r % kSafUX;
-    } else {
-      const int r = h - 4 * kSafUX, side = r & 3;
-      j = 2 + (r >> 2);
-      ii = side < 2 ? side : kSafUX - 4 + side;
-    }
-    const int y = tl.y0 - 2 + j;
-    if (y < 0 || y >= ny) continue;
-    double fh[9], hs, hx, hy;
-    pull_local(Ac, nx, ny, wrapx(tl.x0 - 2 + ii), y, uw6, fh);
-    moments<double>(fh, hs, hx, hy);
-    su[0][j][ii] = (hx + 0.5 * g) / hs;
-    su[1][j][ii] = hy / hs;
+  const int hy = tl.y0 - 2 + hj;
+  const bool ring = h < kSafRing;
+  const unsigned m = (unsigned)clampy(yo) * nx + wrapx(xo);
+  double f[9], fh[9];
+  pull_local(Ac, nx, ny, wrapx(xo), clampy(yo), uw6, f);
+  const double Pc = Ac[lslot(9, m)];
+  if (ring) pull_local(Ac, nx, ny, wrapx(tl.x0 - 2 + hi), clampy(hy), uw6, fh);
+  double sd, mx, my;
+  moments<double>(f, sd, mx, my);
+  const double inv = recip<double>(sd);  // shared with the collision
+  if (yo < ny) {
+    const U2<double> u = u_tilde<double, false>(sd, mx, my, g, 0.0);
+    su[0][jo + 2][io + 2] = u.x;
+    su[1][jo + 2][io + 2] = u.y;
+  }
+  if (ring && hy >= 0 && hy < ny) {
+    double hs, hx, hv;
+    moments<double>(fh, hs, hx, hv);
+    const U2<double> u = u_tilde<double, false>(hs, hx, hv, g, 0.0);
+    su[0][hj][hi] = u.x;
+    su[1][hj][hi] = u.y;
   }
   __syncthreads();
   // Sigma^nN of the tile and a ring of one node (kappa with the wall ghosts)
@@ -1693,9 +1706,8 @@ __global__ void __launch_bounds__(kSafThreads) saf_fused_kernel(const double *__
   }
   const double fsx = 0.5 * (sT[0][js][is + 1] - sT[0][js][is - 1]) + 0.5 * (up[1] - dn[1]);
   const double fsy = 0.5 * (sT[1][js][is + 1] - sT[1][js][is - 1]) + 0.5 * (up[2] - dn[2]);
-  const unsigned m = (unsigned)yo * nx + xo;
   const double fx = g + fsx, fy = fsy;
-  const double ux = (mx + 0.5 * fx) / sd, uy = (my + 0.5 * fy) / sd;
+  const double ux = (mx + 0.5 * fx) * inv, uy = (my + 0.5 * fy) * inv;
   const double usq = ux * ux + uy * uy, uf = ux * fx + uy * fy;
   const double om = c.omega, kf = c.kf;
 #pragma unroll
@@ -1706,7 +1718,7 @@ __global__ void __launch_bounds__(kSafThreads) saf_fused_kernel(const double *__
     const double F = a * kf * (3.0 * cfo + 9.0 * cu * cfo - 3.0 * uf);
     Bc[lslot(q, m)] = f[q] - om * (f[q] - neq) + F;
   }
-  Bc[lslot(9, m)] = Ac[lslot(9, m)];
+  Bc[lslot(9, m)] = Pc;
 }
 
 // Observation of the stress-force path: one workgroup per row of every
