@@ -123,6 +123,19 @@ hipError_t launch_reduce(const ChanDev *ch, int n_ch, const double *part, double
                          int steps_since, hipStream_t s);
 hipError_t launch_advance(ChanDev *ch, int n_ch, int steps, hipStream_t s);
 hipError_t launch_gpbc(int fp32, void *B, const ChanDev *ch, int n_ch, int k, const float *uref, hipStream_t s);
+// FP64 step over tiles of kMainTileX x kMainTileY nodes (x0, y0, y1 of a
+// Strip; SweepArgs.strips holds the tiles, n_strips their number).
+#ifndef LB_MAIN_TX
+#define LB_MAIN_TX 64
+#endif
+#ifndef LB_MAIN_TY
+#define LB_MAIN_TY 8
+#endif
+#ifndef LB_MAIN_THREADS
+#define LB_MAIN_THREADS 512
+#endif
+constexpr int kMainTileX = LB_MAIN_TX, kMainTileY = LB_MAIN_TY, kMainThreads = LB_MAIN_THREADS;
+hipError_t launch_tiles(const SweepArgs &a, hipStream_t s);
 // Fused stress-force step: tiles of kSafTileX x kSafTileY output nodes
 // (x0, y0, y1 of a Strip), one workgroup each.
 #ifndef LB_SAF_TX

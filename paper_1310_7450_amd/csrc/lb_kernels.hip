@@ -119,6 +119,32 @@ __device__ __forceinline__ void pull(const T *__restrict__ A, long long row, int
   f[8] = A[top ? slot(6, row + x) : slot(8, up + xm)] + (top ? uw6 : T(0));
 }
 
+// Slot of population q of node m of a channel relative to the channel's first
+// slot (channels start on a tile boundary, so slot(q, off + m) = kPlanes *
+// off + lslot(q, m)); 32-bit, for channels of fewer than 2^32 / kPlanes
+// nodes.
+__device__ __forceinline__ unsigned lslot(int q, unsigned m) {
+  return ((m >> 6) * kPlanes + q) * kTile + (m & (kTile - 1));
+}
+
+// pull() on a channel's own slots (C = the channel's first slot).
+__device__ __forceinline__ void pull_local(const double *__restrict__ C, int nx, int ny, int x, int y, double uw6,
+                                           double f[9]) {
+  const unsigned row = (unsigned)y * nx;
+  const unsigned xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+  const unsigned dn = row - nx, up = row + nx;
+  const bool bot = (y == 0), top = (y == ny - 1);
+  f[0] = C[lslot(0, row + x)];
+  f[1] = C[lslot(1, row + xm)];
+  f[3] = C[lslot(3, row + xp)];
+  f[2] = C[bot ? lslot(4, row + x) : lslot(2, dn + x)];
+  f[5] = C[bot ? lslot(7, row + x) : lslot(5, dn + xm)];
+  f[6] = C[bot ? lslot(8, row + x) : lslot(6, dn + xp)];
+  f[4] = C[top ? lslot(2, row + x) : lslot(4, up + x)];
+  f[7] = C[top ? lslot(5, row + x) : lslot(7, up + xp)] - (top ? uw6 : 0.0);
+  f[8] = C[top ? lslot(6, row + x) : lslot(8, up + xm)] + (top ? uw6 : 0.0);
+}
+
 // Zeroth and first moments of the stored values: sd = sum_i f_i, m = sum_i
 // c_i f_i. With SHIFT the stored values are n_i - a_i, so sd is the density
 // deviation rho - 1 (kept separate so FP32 does not round it against 1) and
@@ -583,6 +609,115 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
     sdc = sdn;
     mxc = mxn;
     myc = myn;
+  }
+}
+
+// FP64 step of the instantaneous or time-integrated model over tiles of
+// kMainTileX x kMainTileY nodes, one workgroup per tile and one thread per
+// node. Each thread pulls its node and keeps the populations; u~ of the tile
+// and of the ring of one node around it go to LDS, and after one barrier each
+// thread has its four stencil velocities (no-slip ghosts behind the walls, as
+// in the strip sweeps) and runs the node update. Each XCD takes a contiguous
+// run of the tile list, which the host orders as blocks of neighbouring tiles
+// (they share the halo populations they pull through that XCD's L2).
+constexpr int kMainUX = kMainTileX + 2, kMainUY = kMainTileY + 2;
+constexpr int kMainRing = 2 * kMainUX + 2 * kMainTileY;
+static_assert(kMainTileX * kMainTileY == kMainThreads, "one node per thread");
+static_assert(kMainRing <= kMainThreads, "at most one ring node per thread");
+
+template <bool VE, bool NT>
+__global__ void __launch_bounds__(kMainThreads) sweep_tile_kernel(SweepArgs a) {
+  __shared__ double su[2][kMainUY][kMainUX];
+  const Strip tl = a.strips[xcd_item(blockIdx.x, gridDim.x)];
+  const ChanDev c = a.ch[tl.ch];
+  if (!c.active) return;  // frozen channel (uniform over the workgroup)
+  const int nx = c.nx, ny = c.ny;
+  const long long t = c.t + a.k;
+  const double fx = (t < c.t_startup) ? c.g : 0.0;
+  const double uwg = (t < c.t_startup) ? c.uw : 0.0;
+  const double uw6 = (t >= 1 && t - 1 < c.t_startup) ? c.uw / 6.0 : 0.0;
+  const Coef<double> q(c);
+  const double *__restrict__ Ac = static_cast<const double *>(a.A) + c.off * kPlanes;
+  double *__restrict__ Bc = static_cast<double *>(a.B) + c.off * kPlanes;
+  const bool wide = nx >= kMainTileX + 2;  // then halo columns wrap at most once
+  auto wrapx = [&](int x) {
+    if (wide) return x < 0 ? x + nx : (x >= nx ? x - nx : x);
+    const int r = x % nx;
+    return r < 0 ? r + nx : r;
+  };
+  auto clampy = [&](int y) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
+  // this thread's node and (threads below kMainRing) one node of the ring:
+  // the row below, the row above, one column on either side; both pulled
+  // before either is used (rows outside the channel pull a row inside and
+  // store nothing)
+  const int jo = threadIdx.x / kMainTileX, io = threadIdx.x - jo * kMainTileX;
+  const int yo = tl.y0 + jo, xo = tl.x0 + io;
+  const int h = threadIdx.x;
+  int hj, hi;
+  if (h < kMainUX) {
+    hj = 0;
+    hi = h;
+  } else if (h < 2 * kMainUX) {
+    hj = kMainTileY + 1;
+    hi = h - kMainUX;
+  } else {
+    const int r = h - 2 * kMainUX;
+    hj = 1 + (r >> 1);
+    hi = (r & 1) ? kMainUX - 1 : 0;
+  }
+  const int hy = tl.y0 - 1 + hj;
+  const bool ring = h < kMainRing;
+  const unsigned m = (unsigned)clampy(yo) * nx + wrapx(xo);
+  double f[9], fh[9], sgc[3] = {0.0, 0.0, 0.0};
+  pull_local(Ac, nx, ny, wrapx(xo), clampy(yo), uw6, f);
+  const double Pc = Ac[lslot(9, m)];
+  const double *__restrict__ SAc = static_cast<const double *>(a.SA) + c.off * kStressPlanes;
+  if constexpr (VE) {
+#pragma unroll
+    for (int p = 0; p < 3; ++p) sgc[p] = SAc[((m >> 6) * kStressPlanes + p) * kTile + (m & (kTile - 1))];
+  }
+  if (ring) pull_local(Ac, nx, ny, wrapx(tl.x0 - 1 + hi), clampy(hy), uw6, fh);
+  double sd, mx, my;
+  moments<double>(f, sd, mx, my);
+  const U2<double> uc = u_tilde<double, false>(sd, mx, my, fx, 0.0);
+  if (yo < ny) {
+    su[0][jo + 1][io + 1] = uc.x;
+    su[1][jo + 1][io + 1] = uc.y;
+  }
+  if (ring && hy >= 0 && hy < ny) {
+    double hs, hx, hv;
+    moments<double>(fh, hs, hx, hv);
+    const U2<double> u = u_tilde<double, false>(hs, hx, hv, fx, 0.0);
+    su[0][hj][hi] = u.x;
+    su[1][hj][hi] = u.y;
+  }
+  __syncthreads();
+  if (yo >= tl.y1 || xo >= nx) return;
+  const int js = jo + 1, is = io + 1;
+  const U2<double> lf{su[0][js][is - 1], su[1][js][is - 1]};
+  const U2<double> rt{su[0][js][is + 1], su[1][js][is + 1]};
+  U2<double> dn{su[0][js - 1][is], su[1][js - 1][is]};
+  U2<double> up{su[0][js + 1][is], su[1][js + 1][is]};
+  if (yo == 0) dn = U2<double>{-uc.x, -uc.y};
+  if (yo == ny - 1) up = U2<double>{2.0 * uwg - uc.x, -uc.y};
+  double out[9], trT, sg[3], obs[OF_COUNT];
+  node_update<double, false, false, VE>(f, sd, mx, my, Pc, fx, lf, rt, dn, up, 0.0, 0.0, q, a.nnp, sgc, sg, out,
+                                        trT, obs);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    if constexpr (NT) __builtin_nontemporal_store(out[i], &Bc[lslot(i, m)]);
+    else Bc[lslot(i, m)] = out[i];
+  }
+  if constexpr (NT) __builtin_nontemporal_store(trT, &Bc[lslot(9, m)]);
+  else Bc[lslot(9, m)] = trT;
+  if constexpr (VE) {
+    double *__restrict__ SBc = static_cast<double *>(a.SB) + c.off * kStressPlanes;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      double *d = &SBc[((m >> 6) * kStressPlanes + p) * kTile + (m & (kTile - 1))];
+      if constexpr (NT) __builtin_nontemporal_store(sg[p], d);
+      else *d = sg[p];
+    }
   }
 }
 
@@ -1574,32 +1709,6 @@ constexpr int kSafRing = 4 * kSafUX + 4 * kSafTY;       // u~ region minus the t
 static_assert(kSafTX * kSafTY == kSafThreads, "one output node per thread");
 static_assert(kSafRing <= kSafThreads, "at most one ring node per thread");
 
-// Slot of population q of node m of a channel relative to the channel's first
-// slot (channels start on a tile boundary, so slot(q, off + m) = kPlanes *
-// off + lslot(q, m)); 32-bit, for channels of fewer than 2^32 / kPlanes
-// nodes.
-__device__ __forceinline__ unsigned lslot(int q, unsigned m) {
-  return ((m >> 6) * kPlanes + q) * kTile + (m & (kTile - 1));
-}
-
-// pull() on a channel's own slots (C = the channel's first slot).
-__device__ __forceinline__ void pull_local(const double *__restrict__ C, int nx, int ny, int x, int y, double uw6,
-                                           double f[9]) {
-  const unsigned row = (unsigned)y * nx;
-  const unsigned xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
-  const unsigned dn = row - nx, up = row + nx;
-  const bool bot = (y == 0), top = (y == ny - 1);
-  f[0] = C[lslot(0, row + x)];
-  f[1] = C[lslot(1, row + xm)];
-  f[3] = C[lslot(3, row + xp)];
-  f[2] = C[bot ? lslot(4, row + x) : lslot(2, dn + x)];
-  f[5] = C[bot ? lslot(7, row + x) : lslot(5, dn + xm)];
-  f[6] = C[bot ? lslot(8, row + x) : lslot(6, dn + xp)];
-  f[4] = C[top ? lslot(2, row + x) : lslot(4, up + x)];
-  f[7] = C[top ? lslot(5, row + x) : lslot(7, up + xp)] - (top ? uw6 : 0.0);
-  f[8] = C[top ? lslot(6, row + x) : lslot(8, up + xm)] + (top ? uw6 : 0.0);
-}
-
 __global__ void __launch_bounds__(kSafThreads) saf_fused_kernel(const double *__restrict__ A,
                                                                 double *__restrict__ B, const ChanDev *ch,
                                                                 const Strip *tiles, int k) {
@@ -1853,6 +1962,19 @@ hipError_t launch_prec(int cls, bool observe, const SweepArgs &a, hipStream_t s)
 hipError_t launch_sweep(int fp32, int cls, bool observe, const SweepArgs &a, hipStream_t s) {
   return fp32 ? launch_prec<float, true>(cls, observe, a, s)
               : launch_prec<double, false>(cls, observe, a, s);
+}
+
+hipError_t launch_tiles(const SweepArgs &a, hipStream_t s) {
+  if (a.n_strips == 0) return hipSuccess;
+  const dim3 grid(a.n_strips), block(kMainThreads);
+  if (a.ve) {
+    if (a.nt) hipLaunchKernelGGL((sweep_tile_kernel<true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((sweep_tile_kernel<true, false>), grid, block, 0, s, a);
+  } else {
+    if (a.nt) hipLaunchKernelGGL((sweep_tile_kernel<false, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((sweep_tile_kernel<false, false>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const ChanDev *ch, int n_ch, const double *part, double *prof,

@@ -39,12 +39,12 @@ struct Layout {
   int total_rows = 0;
   int total_part = 0;
   int max_strips = 0;
-  int saf_tiles = 0;  // stress-force path: tiles of the fused step
+  int n_tiles = 0;  // tiles of the tiled step (stress force, or FP64 strip-class channels)
   size_t off_state[2] = {0, 0}, off_ch = 0, off_strips = 0, off_astrips = 0, off_rstrips = 0, off_part = 0,
          off_prof = 0, off_prev = 0, off_scal = 0, off_uref = 0, bytes = 0;
   size_t off_stress[2] = {0, 0};  // viscoelastic model only
   size_t off_saf_u = 0, off_saf_t = 0;  // stress-as-force scratch (u~, Sigma^nN)
-  size_t off_saf_tiles = 0;             // stress-as-force tiles
+  size_t off_tiles = 0;                 // tiles of the tiled step
   std::vector<ChanDev> ch;
 };
 
@@ -162,6 +162,35 @@ void add_strips(int ci, const ChanDev &d, int esize, int srows, bool stack, std:
       out.push_back(Strip{ci, xs * w, b * srows, std::min((b + 1) * srows, d.ny), 0});
 }
 
+// The tiled step: the fused stress-force kernel for every channel of a
+// stress-force handle; the FP64 tile sweep for FP64 channels of the strip
+// classes whose slots fit 32-bit offsets (the others keep the strip sweeps).
+#ifndef LB_TILE_SWEEP
+#define LB_TILE_SWEEP 1
+#endif
+struct TileShape {
+  int tx, ty;
+};
+TileShape tile_shape(const lb_options *o) {
+  return o->stress_force ? TileShape{kSafTileX, kSafTileY} : TileShape{kMainTileX, kMainTileY};
+}
+bool tiled(const lb_options *o, const lb_channel &c) {
+  if (o->stress_force) return true;
+  return LB_TILE_SWEEP && o->precision == LB_FP64 && is_strip_class(width_class(c.nx, 8)) &&
+         align_up((size_t)c.nx * c.ny, kTile) * kPlanes <= 0xffffffffull;
+}
+// Tiles of channel i. The kernels hand each of the 8 XCDs a contiguous run
+// of the list: the tile columns of a channel are split into 8 groups, each
+// group listed band by band, so that an XCD's tiles have their horizontal
+// and vertical neighbours (which share halo populations) on the same L2.
+void add_tiles(int i, const lb_channel &c, TileShape ts, std::vector<Strip> &out) {
+  const int cols = (c.nx + ts.tx - 1) / ts.tx;
+  for (int g = 0; g < 8; ++g)
+    for (int y0 = 0; y0 < c.ny; y0 += ts.ty)
+      for (int cx = g * cols / 8; cx < (g + 1) * cols / 8; ++cx)
+        out.push_back(Strip{i, cx * ts.tx, y0, std::min(y0 + ts.ty, c.ny), 0});
+}
+
 Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
   Layout L;
   L.esize = (o->precision == LB_FP32_SHIFTED) ? 4 : 8;
@@ -213,10 +242,11 @@ Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
   if (o->stress_force) {
     L.off_saf_u = take(sizeof(double) * 2 * L.plane);
     L.off_saf_t = take(sizeof(double) * 3 * L.plane);
-    for (int i = 0; i < n; ++i)
-      L.saf_tiles += ((c[i].nx + kSafTileX - 1) / kSafTileX) * ((c[i].ny + kSafTileY - 1) / kSafTileY);
-    L.off_saf_tiles = take(sizeof(Strip) * L.saf_tiles);
   }
+  const TileShape ts = tile_shape(o);
+  for (int i = 0; i < n; ++i)
+    if (tiled(o, c[i])) L.n_tiles += ((c[i].nx + ts.tx - 1) / ts.tx) * ((c[i].ny + ts.ty - 1) / ts.ty);
+  L.off_tiles = take(sizeof(Strip) * L.n_tiles);
   L.bytes = at;
   return L;
 }
@@ -239,7 +269,7 @@ struct lb_handle {
   float *duref = nullptr;    // FP32: reference velocity of every row
   void *sbuf[2] = {nullptr, nullptr};  // viscoelastic model: stress buffers (same parity as buf)
   double *saf_u = nullptr, *saf_t = nullptr;  // stress-as-force scratch
-  Strip *saf_tiles = nullptr;                 // stress-as-force tiles of every channel
+  Strip *tiles = nullptr;                     // tiles of the tiled step (every tiled channel)
   // strips grouped by width class: [begin, begin + count) in the arrays
   int all_begin[kClasses] = {0}, all_count[kClasses] = {0};
   int act_begin[kClasses] = {0}, act_count[kClasses] = {0};
@@ -291,7 +321,7 @@ lb_status upload_strips(lb_handle *h, bool all) {
   // then cached, see sweep_args)
   const bool stack = (long long)kPlanes * h->L.plane * h->L.esize <= kNontemporalBytes;
   for (int i = 0; i < h->n_ch; ++i) {
-    if (!all && !h->active[i]) continue;
+    if (!all && (!h->active[i] || tiled(&h->opt, h->in[i]))) continue;
     const ChanDev &d = h->L.ch[i];
     add_strips(i, d, h->L.esize, strip_rows_for(width_class(d.nx, h->L.esize), d.nx, d.ny, h->opt.strip_rows),
                stack, raw);
@@ -344,9 +374,10 @@ SweepArgs sweep_args(lb_handle *h, const Strip *strips, int begin, int count, in
 lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s) {
   if (h->opt.stress_force) {
     HIPCHECK(h, launch_saf_fused(static_cast<const double *>(h->buf[src]), static_cast<double *>(h->buf[src ^ 1]),
-                                 h->dch, h->saf_tiles, h->L.saf_tiles, k, s));
+                                 h->dch, h->tiles, h->L.n_tiles, k, s));
     return LB_OK;
   }
+  if (h->L.n_tiles) HIPCHECK(h, launch_tiles(sweep_args(h, h->tiles, 0, h->L.n_tiles, src, k), s));
   for (int c = 0; c < kClasses; ++c) {
     if (!h->act_count[c]) continue;
     // Serpentine order: steps reading buffer 0 take the strips in order and
@@ -561,6 +592,7 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
   h->buf[0] = h->ws + h->L.off_state[0];
   h->buf[1] = h->ws + h->L.off_state[1];
   h->dch = reinterpret_cast<ChanDev *>(h->ws + h->L.off_ch);
+  h->tiles = reinterpret_cast<Strip *>(h->ws + h->L.off_tiles);
   h->dall = reinterpret_cast<Strip *>(h->ws + h->L.off_strips);
   h->dact = reinterpret_cast<Strip *>(h->ws + h->L.off_astrips);
   h->dact_rev = reinterpret_cast<Strip *>(h->ws + h->L.off_rstrips);
@@ -576,7 +608,6 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
   if (o->stress_force) {
     h->saf_u = reinterpret_cast<double *>(h->ws + h->L.off_saf_u);
     h->saf_t = reinterpret_cast<double *>(h->ws + h->L.off_saf_t);
-    h->saf_tiles = reinterpret_cast<Strip *>(h->ws + h->L.off_saf_tiles);
   }
   h->t.assign(n, 0);
   h->active.assign(n, 1);
@@ -606,22 +637,11 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
     return bail(LB_EHIP);
   if (upload_strips(h, true) != LB_OK || upload_strips(h, false) != LB_OK) return bail(LB_EHIP);
   std::vector<Strip> tiles;  // kept until the synchronisation below
-  if (o->stress_force) {
-    // The kernel hands each of the 8 XCDs a contiguous run of the list:
-    // the tile columns of a channel are split into 8 groups, each group
-    // listed band by band, so that an XCD's tiles have their horizontal and
-    // vertical neighbours (which share halo populations) on the same L2.
-    for (int i = 0; i < n; ++i) {
-      const int cols = (c[i].nx + kSafTileX - 1) / kSafTileX;
-      for (int g = 0; g < 8; ++g)
-        for (int y0 = 0; y0 < c[i].ny; y0 += kSafTileY)
-          for (int cx = g * cols / 8; cx < (g + 1) * cols / 8; ++cx)
-            tiles.push_back(Strip{i, cx * kSafTileX, y0, std::min(y0 + kSafTileY, c[i].ny), 0});
-    }
-    if (hipMemcpyAsync(h->saf_tiles, tiles.data(), sizeof(Strip) * tiles.size(), hipMemcpyHostToDevice,
-                       h->stream) != hipSuccess)
-      return bail(LB_EHIP);
-  }
+  for (int i = 0; i < n; ++i)
+    if (tiled(o, c[i])) add_tiles(i, c[i], tile_shape(o), tiles);
+  if (!tiles.empty() && hipMemcpyAsync(h->tiles, tiles.data(), sizeof(Strip) * tiles.size(),
+                                       hipMemcpyHostToDevice, h->stream) != hipSuccess)
+    return bail(LB_EHIP);
   if (fill_rest(h, 0) != LB_OK || fill_rest(h, 1) != LB_OK) return bail(LB_EHIP);
   // zero stress at rest (outside any graph)
   for (int b = 0; b < 2; ++b)
