@@ -117,6 +117,9 @@ typedef struct {
  *                the convergence check and the FP32 reference move run at
  *                the block boundaries; even, >= 2 (default 1000 when 0);
  *   strip_rows   rows per wavefront strip of the sweep (0: tuned default);
+ *                FP64 channels whose width is not a power of two up to 64
+ *                (and whose nx * ny is at most 429,496,704) step on tiles of
+ *                64 x 8 nodes instead and do not use it;
  *   steady_tol   if > 0, lb_step checks every K steps the residual
  *                R = max_y |ubar(t) - ubar(t-K)| / (K max_y |ubar(t)|) of the
  *                x-averaged velocity ubar and freezes each channel once
