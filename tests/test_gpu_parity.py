@@ -107,14 +107,18 @@ def test_poiseuille_fp32_shifted(orc):
 
 
 @pytest.mark.parametrize("nx,ny", [(1, 16), (2, 9), (4, 33), (16, 20), (64, 7), (3, 12), (100, 37), (130, 5), (63, 2),
-                                   (8, 1), (128, 9), (192, 5), (256, 3), (128, 1), (384, 2)])
+                                   (8, 1), (128, 9), (192, 5), (256, 3), (128, 1), (384, 2), (65, 6), (66, 3)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_perturbed_state_parity(orc, nx, ny, precision):
     """Seeded random populations (every moment non-zero, x gradients present)
     on narrow, aligned-wide (nx a multiple of 64), ragged-wide and odd
     lattices: one and several steps match the oracle node by node; covers the
     lane-group wrap, the edge columns and halo of wide strips, the periodic
-    wrap across strips, partial last strips, and one/two-row channels."""
+    wrap across strips, partial last strips, and one/two-row channels. In
+    FP64 the widths that are not powers of two run on 64 x 8 tiles: 3, 63
+    and 65 wrap their halo columns by a modulo (65: a second tile of one
+    column), 66 and up by one add or subtract, and 100, 130 end in a
+    partial tile."""
     spec = ChannelSpec(nx=nx, ny=ny, force=3e-6, tau_lb=0.8, G=2e-4, tau0=500.0, gamma_c=0.1,
                        eps=0.01, visc_split=0.3, t_startup=40)
     pops, P = workloads.random_state(nx, ny, seed=nx * 1000 + ny)
@@ -233,12 +237,15 @@ def test_convergence_freezes_channels(orc):
             compare_fields(s, i, o, FP64_TOL, f"frozen ch{i} at {steps[i]}")
 
 
+@pytest.mark.parametrize("nx", [8, 100])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_frozen_channel_survives_odd_steps(precision):
+def test_frozen_channel_survives_odd_steps(precision, nx):
     """A channel frozen by the convergence check keeps its state exactly
     through later steps of odd length, which change the buffer the handle
-    reads from; so does a state set on it while frozen."""
-    specs = [ChannelSpec(8, 16, 2e-6, 1.0, 1e-4, 1e3, 0.1), ChannelSpec(8, 96, 1e-6, 1.0, 1e-4, 1e3, 0.1)]
+    reads from; so does a state set on it while frozen. nx = 8 runs the
+    narrow strip sweep; nx = 100 the tile sweep in FP64 (whose workgroups
+    skip a frozen channel) and the generic strip sweep in FP32."""
+    specs = [ChannelSpec(nx, 16, 2e-6, 1.0, 1e-4, 1e3, 0.1), ChannelSpec(nx, 96, 1e-6, 1.0, 1e-4, 1e3, 0.1)]
     with solver(specs, precision=precision, obs_every=200, steady_tol=1e-7) as s:
         while s.observe(0, "active") != 0:
             s.step(200)

@@ -105,6 +105,28 @@ def test_large_channel_sampled_rows(orc):
         assert linf(s.observe(0, "sxy"), f["sxy"][:, 0]) < FP64_TOL
 
 
+def test_frozen_channel_keeps_its_state():
+    """With steady_tol, the narrow channel freezes first: its state stays
+    exactly the same through later steps of odd length (the fused kernel's
+    workgroups skip it) while the wide one keeps stepping."""
+    specs = [ChannelSpec(nx=8, ny=16, force=2e-6, tau_lb=1.0, G=1e-4, tau0=1e3, gamma_c=0.1),
+             ChannelSpec(nx=100, ny=96, force=1e-6, tau_lb=1.0, G=1e-4, tau0=1e3, gamma_c=0.1)]
+    with solver(specs, obs_every=200, steady_tol=1e-7) as s:
+        while s.observe(0, "active") != 0:
+            s.step(200)
+        assert s.observe(1, "active") == 1
+        t0, t1 = s.observe(0, "step"), s.observe(1, "step")
+        pops0, P0 = s.get_state(0)
+        wide0, _ = s.get_state(1)
+        for n in (1, 2, 3):
+            s.step(n)
+            pops, P = s.get_state(0)
+            assert np.array_equal(pops, pops0) and np.array_equal(P, P0), n
+            assert s.observe(0, "step") == t0
+        assert s.observe(1, "step") == t1 + 6
+        assert not np.array_equal(s.get_state(1)[0], wide0)
+
+
 @pytest.mark.parametrize("kw", [dict(precision="fp32"), dict(nn_pressure=True), dict(viscoelastic=True)])
 def test_rejected_combinations(kw):
     """The stress force needs FP64, no flow-induced density and the
