@@ -149,7 +149,7 @@ hipError_t launch_tiles(const SweepArgs &a, hipStream_t s);
 #endif
 constexpr int kSafTileX = LB_SAF_TX, kSafTileY = LB_SAF_TY, kSafThreads = LB_SAF_THREADS;
 hipError_t launch_saf_fused(const double *A, double *B, const ChanDev *ch, const Strip *tiles, int n_tiles, int k,
-                            hipStream_t s);
+                            int nt, hipStream_t s);
 hipError_t launch_saf_observe(const double *A, const ChanDev *ch, int n_ch, long long plane, int total_rows,
                               double *U, double *Tn, double *part, hipStream_t s);
 hipError_t launch_rereference(float *A, const ChanDev *ch, int n_ch, int total_rows, const double *prof,

@@ -1709,6 +1709,7 @@ constexpr int kSafRing = 4 * kSafUX + 4 * kSafTY;       // u~ region minus the t
 static_assert(kSafTX * kSafTY == kSafThreads, "one output node per thread");
 static_assert(kSafRing <= kSafThreads, "at most one ring node per thread");
 
+template <bool NT>
 __global__ void __launch_bounds__(kSafThreads) saf_fused_kernel(const double *__restrict__ A,
                                                                 double *__restrict__ B, const ChanDev *ch,
                                                                 const Strip *tiles, int k) {
@@ -1825,9 +1826,12 @@ __global__ void __launch_bounds__(kSafThreads) saf_fused_kernel(const double *__
     const double a = weight<double>(q);
     const double neq = a * sd * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
     const double F = a * kf * (3.0 * cfo + 9.0 * cu * cfo - 3.0 * uf);
-    Bc[lslot(q, m)] = f[q] - om * (f[q] - neq) + F;
+    const double v = f[q] - om * (f[q] - neq) + F;
+    if constexpr (NT) __builtin_nontemporal_store(v, &Bc[lslot(q, m)]);
+    else Bc[lslot(q, m)] = v;
   }
-  Bc[lslot(9, m)] = Pc;
+  if constexpr (NT) __builtin_nontemporal_store(Pc, &Bc[lslot(9, m)]);
+  else Bc[lslot(9, m)] = Pc;
 }
 
 // Observation of the stress-force path: one workgroup per row of every
@@ -2010,9 +2014,10 @@ static int saf_blocks(long long plane) {
 }
 
 hipError_t launch_saf_fused(const double *A, double *B, const ChanDev *ch, const Strip *tiles, int n_tiles, int k,
-                            hipStream_t s) {
+                            int nt, hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(saf_fused_kernel, dim3(n_tiles), dim3(kSafThreads), 0, s, A, B, ch, tiles, k);
+  if (nt) hipLaunchKernelGGL(saf_fused_kernel<true>, dim3(n_tiles), dim3(kSafThreads), 0, s, A, B, ch, tiles, k);
+  else hipLaunchKernelGGL(saf_fused_kernel<false>, dim3(n_tiles), dim3(kSafThreads), 0, s, A, B, ch, tiles, k);
   return hipGetLastError();
 }
 

@@ -374,7 +374,8 @@ SweepArgs sweep_args(lb_handle *h, const Strip *strips, int begin, int count, in
 lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s) {
   if (h->opt.stress_force) {
     HIPCHECK(h, launch_saf_fused(static_cast<const double *>(h->buf[src]), static_cast<double *>(h->buf[src ^ 1]),
-                                 h->dch, h->tiles, h->L.n_tiles, k, s));
+                                 h->dch, h->tiles, h->L.n_tiles, k,
+                                 (long long)kPlanes * h->L.plane * h->L.esize > kNontemporalBytes, s));
     return LB_OK;
   }
   if (h->L.n_tiles) HIPCHECK(h, launch_tiles(sweep_args(h, h->tiles, 0, h->L.n_tiles, src, k), s));
