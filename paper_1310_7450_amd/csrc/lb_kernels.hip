@@ -36,9 +36,17 @@ namespace {
 #ifndef LB_WG_WAVES
 #define LB_WG_WAVES 4
 #endif
-// rows of loads in flight per wavefront in the vector sweep
+// Rows of loads in flight per wavefront in the vector sweep. A state that
+// stays in the last-level cache (cached stores) runs best with two: the
+// third row's registers push the FP32 kernel into accumulator registers
+// (76 of them against 11), whose moves cost more than the deeper prefetch
+// gains. A state written with nontemporal stores, streamed from HBM, runs
+// best with three.
 #ifndef LB_VEC_DEPTH
-#define LB_VEC_DEPTH 3
+#define LB_VEC_DEPTH 2
+#endif
+#ifndef LB_VEC_DEPTH_NT
+#define LB_VEC_DEPTH_NT 3
 #endif
 
 template <typename T>
@@ -1232,7 +1240,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
       for (int k = 0; k < NPL; ++k) sg[p][k] = VE ? R.sg[VE ? p : 0][k] : T(0);
   };
   // ring of raw rows: the row i steps ahead of the first lives in slot i mod D
-  constexpr int D = LB_VEC_DEPTH;
+  constexpr int D = NT ? LB_VEC_DEPTH_NT : LB_VEC_DEPTH;
   Raw S[D];
   {
     // every load of the prologue is issued before the first is used, so the
