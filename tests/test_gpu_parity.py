@@ -13,6 +13,8 @@ exceeds about 0.3 at visc_split 0: the 8 x 64, G tau = 1 channel turns a
 500 steps. Long parity runs therefore use G tau <= 0.2; the G tau = 1
 workload is compared exactly over its first steps and statistically after.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -392,3 +394,24 @@ def test_batched_sweep_subset_to_steady(orc):
             o = oracle_channel(orc, dataclasses.replace(chans[i], nx=1))
             o.run(steps[i])
             compare_fields(s, int(i), o, FP32_TOL, f"batched ny={chans[i].ny} steps={steps[i]}")
+
+
+@pytest.mark.parametrize("ny,path", [(104_857, "tiles"), (104_961, "strips")])
+def test_fp64_channel_at_the_tile_offset_limit(orc, ny, path):
+    """FP64 channels of 4096 x 104,857 nodes (429,494,272: the tile sweep,
+    whose in-channel slot offsets then reach 4,294,942,719, just below
+    2^32) and of 4096 x 104,961 (beyond 429,496,704 nodes: the strip sweep,
+    with 64-bit offsets). About 69 GB of state each. From rest, after 6
+    steps the x-averaged u_x and sigma_xy of every row equal the nx = 1
+    oracle, the walls included (the top rows sit at the highest offsets)."""
+    spec = ChannelSpec(nx=4096, ny=ny, force=1e-6, tau_lb=1.0, G=1e-4, tau0=1e3, gamma_c=0.1, eps=0.02)
+    print(f"fp64 4096 x {ny} ({path})", flush=True)
+    with solver([spec], precision="fp64", obs_every=6) as s:
+        s.step(6)
+        o = oracle_channel(orc, dataclasses.replace(spec, nx=1))
+        o.run(6)
+        compare_fields(s, 0, o, 1e-10, f"fp64 4096 x {ny} ({path})")
+        ux = s.observe(0, "ux")
+        # the two wall rows mirror each other up to the rounding of their
+        # different bounce-back terms (3e-12 of max u_x measured)
+        assert np.all(np.isfinite(ux)) and abs(ux[-1] - ux[0]) < 1e-10 * abs(ux).max()
