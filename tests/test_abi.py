@@ -74,6 +74,31 @@ def test_invalid_options_rejected(L, kw):
         lbnlm.workspace_bytes([spec()], o)
 
 
+@pytest.mark.parametrize("kw", [dict(precision="fp32"), dict(nn_pressure=True), dict(viscoelastic=True)])
+def test_stress_force_combinations_rejected(L, kw):
+    """The stress force needs FP64, no flow-induced density and the
+    instantaneous model."""
+    args = dict(precision="fp64", nn_pressure=False, stress_force=True)
+    args.update(kw)
+    with pytest.raises(lbnlm.LbError) as e:
+        lbnlm.workspace_bytes([spec()], lbnlm.options(**args))
+    assert e.value.status == -1
+
+
+def test_stress_force_channel_size_limit(L):
+    """The fused stress-force step addresses a channel's slots with 32-bit
+    offsets: 4096 x 104,857 nodes (429,494,272) is accepted, 4096 x 104,961
+    (beyond 429,496,704) is rejected; the same sizes without the stress
+    force are accepted (FP64 channels beyond the limit step on strips)."""
+    o = lbnlm.options("fp64", nn_pressure=False, stress_force=True)
+    state = 2 * 10 * 4096 * 104_857 * 8
+    assert lbnlm.workspace_bytes([spec(nx=4096, ny=104_857)], o) >= state
+    with pytest.raises(lbnlm.LbError) as e:
+        lbnlm.workspace_bytes([spec(nx=4096, ny=104_961)], o)
+    assert e.value.status == -1
+    assert lbnlm.workspace_bytes([spec(nx=4096, ny=104_961)], lbnlm.options("fp64")) > state
+
+
 def test_create_rejects_small_or_misaligned_workspace(L):
     arr = (lbnlm.LbChannel * 1)(spec().to_c())
     opt = lbnlm.options()
