@@ -1044,8 +1044,16 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
 
   auto tile = [&](int y, int tx) __attribute__((always_inline)) -> long long { return tile00 + (long long)y * tiles_row + tx; };
   // one field of this lane's NPL columns of row y
+  // The time-integrated model's cached step (state and stress about 218 MB
+  // per buffer on 4096 x 1024 FP32, near the last-level cache's 256 MB)
+  // reads its rows with nontemporal loads: the buffer it reads is dead once
+  // read, and letting it go first keeps more of what the previous step wrote
+  // (+3 points there; the same loads cost 1 point on the instantaneous
+  // model's 168 MB buffers and 6 on the streamed 10.7 GB ones).
   auto vrun = [&](int y, int p) __attribute__((always_inline)) -> V {
-    return *reinterpret_cast<const V *>(A + (tile(y, xt + lt) * kPlanes + p) * F + lo);
+    const V *src = reinterpret_cast<const V *>(A + (tile(y, xt + lt) * kPlanes + p) * F + lo);
+    if constexpr (VE && !NT && !OBS) return __builtin_nontemporal_load(src);
+    return *src;
   };
 
   // Side values of a row, by lane i < 24 (kSide* below): lanes 0..5 hold the
