@@ -679,8 +679,8 @@ __global__ void __launch_bounds__(kMainThreads) sweep_tile_kernel(SweepArgs a) {
   double f[9], fh[9], sgc[3] = {0.0, 0.0, 0.0};
   pull_local(Ac, nx, ny, wrapx(xo), clampy(yo), uw6, f);
   const double Pc = Ac[lslot(9, m)];
-  const double *__restrict__ SAc = static_cast<const double *>(a.SA) + c.off * kStressPlanes;
   if constexpr (VE) {
+    const double *__restrict__ SAc = static_cast<const double *>(a.SA) + c.off * kStressPlanes;
 #pragma unroll
     for (int p = 0; p < 3; ++p) sgc[p] = SAc[((m >> 6) * kStressPlanes + p) * kTile + (m & (kTile - 1))];
   }
