@@ -117,14 +117,21 @@ def newtonian_startup(ny, g, eta, t, kmax=2000):
     return (coef[None, :] * np.cos(np.outer(xi, mu)) * (1 - np.exp(-eta * mu[None, :] ** 2 * t))).sum(axis=1)
 
 
-def newtonian_couette_startup(ny, U, eta, t, kmax=2000, rho0=1.0):
+def couette_width(ny, top_wall="halfway"):
+    """Distance between the fixed wall at y = -1/2 and the moving wall: the
+    half link y = ny - 1/2 ("halfway") or the top node row y = ny - 1
+    ("zou_he")."""
+    return float(ny) if top_wall == "halfway" else ny - 0.5
+
+
+def newtonian_couette_startup(ny, U, eta, t, kmax=2000, rho0=1.0, top_wall="halfway"):
     """Start-up of planar Couette flow from rest (Sec. IV.B): walls at
-    y = -1/2 (at rest) and y = ny - 1/2 (moving with U from t = 0), H = ny,
-    s = (y + 1/2)/H. Steady part U s; the transient solves the diffusion
-    equation with zero wall values, starting from -U s, whose sine series has
-    coefficients -2U (-1)^(n+1) / (n pi): u = U s - (2U/pi) sum (-1)^(n+1)/n
-    sin(n pi s) exp(-(eta/rho0) (n pi/H)^2 t)."""
-    H = float(ny)
+    y = -1/2 (at rest) and y = -1/2 + H (moving with U from t = 0), H from
+    couette_width, s = (y + 1/2)/H. Steady part U s; the transient solves the
+    diffusion equation with zero wall values, starting from -U s, whose sine
+    series has coefficients -2U (-1)^(n+1) / (n pi): u = U s - (2U/pi) sum
+    (-1)^(n+1)/n sin(n pi s) exp(-(eta/rho0) (n pi/H)^2 t)."""
+    H = couette_width(ny, top_wall)
     s = (np.arange(ny) + 0.5) / H
     n = np.arange(1, kmax + 1)[:, None]
     terms = ((-1.0) ** (n + 1) / n) * np.sin(n * math.pi * s[None, :]) * np.exp(

@@ -28,7 +28,7 @@ class OrcParams(C.Structure):
     _fields_ = [("g", C.c_double), ("tau_eff", C.c_double), ("G", C.c_double),
                 ("tau", C.c_double), ("gamma_c", C.c_double), ("lam", C.c_double),
                 ("t_startup", C.c_longlong), ("nn_pressure", C.c_int), ("uw", C.c_double),
-                ("dp", C.c_double), ("ve", C.c_int), ("saf", C.c_int)]
+                ("dp", C.c_double), ("ve", C.c_int), ("saf", C.c_int), ("zh", C.c_int)]
 
 
 def lib():
@@ -38,7 +38,8 @@ def lib():
         L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         L.orc_resolve.argtypes = [C.c_double] * 6 + [C.c_double, C.c_longlong, C.c_int, C.c_double,
-                                                     C.c_double, C.c_int, C.c_int, C.POINTER(OrcParams)]
+                                                     C.c_double, C.c_int, C.c_int, C.c_int,
+                                                     C.POINTER(OrcParams)]
         L.orc_resolve.restype = C.c_int
         L.orc_equilibrium.argtypes = [C.c_double] * 3 + [dp]
         L.orc_forcing.argtypes = [C.c_double, dp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, dp]
@@ -53,6 +54,7 @@ def lib():
         L.orc_run.argtypes = [C.POINTER(OrcParams), C.c_int, C.c_int, dp, dp, dp, C.c_longlong, C.c_longlong]
         L.orc_run.restype = C.c_longlong
         L.orc_init_rest.argtypes = [C.c_int, C.c_int, dp, dp, dp]
+        L.orc_zou_he_top.argtypes = [C.POINTER(OrcParams), C.c_int, C.c_int, dp, C.c_longlong]
         L.orc_wall_drag.argtypes = [C.c_int, C.c_int, dp, C.c_double]
         L.orc_wall_drag.restype = C.c_double
         L.orc_num_fields.restype = C.c_int
@@ -112,13 +114,17 @@ def tau_M(kappa, tau, gamma_c):
     return lib().orc_tau_M(_p(k), tau, gamma_c)
 
 
+TOP_WALLS = {"halfway": 0, "zou_he": 1}
+
+
 def resolve(tau_lb, G, tau0, gamma_c, eps=0.0, visc_split=0.0, force=0.0,
             t_startup=2 ** 62, nn_pressure=True, wall_velocity=0.0, pressure_drop=0.0, viscoelastic=False,
-            stress_force=False):
+            stress_force=False, top_wall="halfway"):
     p = OrcParams()
     rc = lib().orc_resolve(tau_lb, G, tau0, gamma_c, eps, visc_split, force,
                            int(t_startup), int(bool(nn_pressure)), float(wall_velocity),
-                           float(pressure_drop), int(bool(viscoelastic)), int(bool(stress_force)), C.byref(p))
+                           float(pressure_drop), int(bool(viscoelastic)), int(bool(stress_force)),
+                           TOP_WALLS[top_wall], C.byref(p))
     if rc != 0:
         raise ValueError("invalid channel parameters")
     return p
@@ -129,9 +135,13 @@ class Channel:
 
     def __init__(self, nx, ny, force, tau_lb=1.0, G=1e-4, tau0=1e4, gamma_c=0.1,
                  eps=0.0, visc_split=0.0, t_startup=2 ** 62, nn_pressure=True, wall_velocity=0.0,
-                 pressure_gradient=0.0, viscoelastic=False, stress_force=False):
+                 pressure_gradient=0.0, viscoelastic=False, stress_force=False, top_wall="halfway"):
         """wall_velocity: x velocity of the top wall while t < t_startup
         (planar Couette flow); 0 gives the channel with two fixed walls.
+        top_wall: "halfway" (bounce-back on the half link above row ny - 1;
+        a moving wall reflects with the wall-momentum term, R9) or "zou_he"
+        (Zou and He's velocity boundary on the top node row, R13: the
+        channel spans y = -1/2 .. ny - 1).
         pressure_gradient: pressure drop per unit length G_p imposed by
         generalised periodic boundaries (R10: p+ - p- = (nx + 1) G_p between
         the virtual nodes; needs force 0 and nn_pressure False).
@@ -142,12 +152,19 @@ class Channel:
         self.nx, self.ny = int(nx), int(ny)
         self.params = resolve(tau_lb, G, tau0, gamma_c, eps, visc_split, force,
                               t_startup, nn_pressure, wall_velocity, (self.nx + 1) * pressure_gradient,
-                              viscoelastic, stress_force)
+                              viscoelastic, stress_force, top_wall)
         self.n = np.empty((9, self.ny, self.nx))
         self.P = np.empty((self.ny, self.nx))
         self.S = np.zeros((3, self.ny, self.nx))
         lib().orc_init_rest(self.nx, self.ny, _p(self.n), _p(self.P), _p(self.S))
         self.t = 0
+        self._complete_top()
+
+    def _complete_top(self):
+        """R13: the top node row's populations entering from outside the
+        lattice, completed for the current step."""
+        if self.params.zh:
+            lib().orc_zou_he_top(C.byref(self.params), self.nx, self.ny, _p(self.n), self.t)
 
     def set_state(self, n, P, t=None, S=None):
         self.n[...] = n
@@ -156,6 +173,7 @@ class Channel:
             self.S[...] = S
         if t is not None:
             self.t = int(t)
+        self._complete_top()
 
     def run(self, steps):
         bad = lib().orc_run(C.byref(self.params), self.nx, self.ny, _p(self.n), _p(self.P), _p(self.S),

@@ -98,6 +98,20 @@
  *      Sigma(ny-2) (one row: zero gradient), so that the summed force is
  *      the stress at the half-way walls. The equilibrium and forcing use
  *      u = (m + f/2)/s.
+ *   R13 the moving wall of planar Couette flow as Zou and He's velocity
+ *      boundary (Sec. II.B, last paragraph; Sec. IV.B): the top wall lies on
+ *      the node row y = ny - 1, so the channel spans L = ny - 1/2 from the
+ *      half-way wall at y = -1/2. After streaming, a node of that row lacks
+ *      the three populations that would enter from above (c_y = -1). They
+ *      follow from the six it has: no flow through the wall fixes the
+ *      density, s = n0 + n1 + n3 + 2 (n2 + n5 + n6); the normal part of the
+ *      non-equilibrium bounces back, n4 = n2; the two diagonals share what is
+ *      left of the momentum such that the node's provisional velocity
+ *      u~ = (m + f/2)/s is the wall's (u_w, 0). The node then collides like
+ *      any other. Populations it emits upwards leave the lattice. Its
+ *      velocity gradient uses the ghost mirrored through the wall node,
+ *      u~(ny) = 2 (u_w, 0) - u~(ny-2). The state held after each step has
+ *      the missing populations already completed for the next step.
  *
  * Lattice units: dx = dt = 1, rho0 = 1, c_s^2 = 1/3, d = 2.
  * Storage: populations n[i][y][x] (nine planes, x fastest), the previous
@@ -138,12 +152,14 @@ typedef struct {
   double dp;        /* pressure drop p+ - p- across the period (R10), 0: off */
   int ve;           /* 1: time-integrated stress (R11); 0: instantaneous     */
   int saf;          /* 1: stress as a force density (R12)                    */
+  int zh;           /* 1: top wall is Zou-He's velocity boundary on the top  */
+                    /*    node row (R13); 0: half-way bounce-back (R4, R9)   */
 } orc_params;
 
 /* Parameter resolution (readings R7, R8). Returns 0, or -1 for invalid input. */
 int orc_resolve(double tau_lb, double G, double tau0, double gamma_c, double eps,
                 double lam, double g, long long t_startup, int nn_pressure, double uw,
-                double dp, int ve, int saf, orc_params *out) {
+                double dp, int ve, int saf, int zh, orc_params *out) {
   if (!(tau_lb > 0.5) || !(G >= 0) || !(tau0 > 0) || !(gamma_c > 0) ||
       !(lam >= 0 && lam <= 1) || !isfinite(g) || !isfinite(eps) || !isfinite(uw) || !isfinite(dp))
     return -1;
@@ -152,6 +168,9 @@ int orc_resolve(double tau_lb, double G, double tau0, double gamma_c, double eps
   /* the stress force replaces the second-moment stress term and the
    * flow-induced density, and is defined for the instantaneous model */
   if (saf && (nn_pressure || ve || dp != 0)) return -1;
+  /* the node wall closes the channel at the top; it is not combined with the
+   * pressure drive or the stress force */
+  if (zh && (dp != 0 || saf)) return -1;
   double eta_s = (tau_lb - 0.5) / 3.0;
   double tau = tau0 * pow(10.0, fmin(eps, 0.0) / 0.05);
   double Ginf = G * (1.0 + sqrt(fmax(eps, 0.0)));
@@ -168,7 +187,40 @@ int orc_resolve(double tau_lb, double G, double tau0, double gamma_c, double eps
   out->dp = dp;
   out->ve = ve ? 1 : 0;
   out->saf = saf ? 1 : 0;
+  out->zh = zh ? 1 : 0;
   return 0;
+}
+
+/* Reading R13: completes the populations of the top node row that enter from
+ * outside the lattice (c_y = -1: 4, 7, 8) for step t, following Zou and He's
+ * velocity boundary with the wall velocity (u_w, 0) of step t. n holds nine
+ * planes of nx*ny post-streaming populations and is changed in place. */
+void orc_zou_he_top(const orc_params *p, int nx, int ny, double *n, long long t) {
+  const size_t N = (size_t)nx * ny;
+  double uw = (t < p->t_startup) ? p->uw : 0.0;
+  double fx = (t < p->t_startup) ? p->g : 0.0;
+  for (int x = 0; x < nx; ++x) {
+    size_t id = (size_t)(ny - 1) * nx + x;
+    double v[9];
+    for (int i = 0; i < 9; ++i) v[i] = n[i * N + id];
+    /* no flow through the wall: sum_i c_iy n_i = 0 with the three unknowns
+     * carrying c_y = -1, so s = (c_y = 0 populations) + 2 (c_y = +1 ones) */
+    double s = v[0] + v[1] + v[3] + 2.0 * (v[2] + v[5] + v[6]);
+    /* momentum the node must hold for u~ = (m + f/2)/s = (u_w, 0) */
+    double mx = s * uw - 0.5 * fx;
+    /* bounce-back of the non-equilibrium part normal to the wall; n4^eq and
+     * n2^eq are equal when the wall has no normal velocity */
+    double n4 = v[2];
+    /* the diagonals: n7 + n8 = n5 + n6 (no normal flow, given n4 = n2), and
+     * n8 - n7 supplies the x momentum the other six lack */
+    double sum78 = v[5] + v[6];
+    double diff87 = mx - ((v[1] - v[3]) + (v[5] - v[6]));
+    double n8 = 0.5 * (sum78 + diff87);
+    double n7 = 0.5 * (sum78 - diff87);
+    n[4 * N + id] = n4;
+    n[7 * N + id] = n7;
+    n[8 * N + id] = n8;
+  }
 }
 
 /* Second-order equilibrium n_i^eq(rho, u) = a_i rho [1 + c.u/cs2 +
@@ -332,6 +384,14 @@ int orc_step(const orc_params *p, int nx, int ny, const double *n, const double 
   double uw = (t < p->t_startup) ? p->uw : 0.0;  /* top wall velocity at step t */
   double *utx = malloc(N * sizeof(double)), *uty = malloc(N * sizeof(double));
   int bad = 0;
+  /* R13: the top node row's populations from outside, completed for step t */
+  double *nz = NULL;
+  if (p->zh) {
+    nz = malloc(9 * N * sizeof(double));
+    memcpy(nz, n, 9 * N * sizeof(double));
+    orc_zou_he_top(p, nx, ny, nz, t);
+    n = nz;
+  }
   /* pressure drive: mean density of the inlet (x = 0) and outlet (x = nx-1)
    * columns; the collision keeps every node's density and momentum then */
   double rbar_in = 0, rbar_out = 0;
@@ -377,7 +437,8 @@ int orc_step(const orc_params *p, int nx, int ny, const double *n, const double 
       double jx = mx + 0.5 * fx, jy = my + 0.5 * fy;
 
       /* kappa_ab = d_b u_a by central differences; x periodic, wall ghosts
-       * u(-1) = -u(0), u(ny) = 2 u_w - u(ny-1) (readings R4, R5, R9). */
+       * u(-1) = -u(0), u(ny) = 2 u_w - u(ny-1) (readings R4, R5, R9), or
+       * u(ny) = 2 u_w - u(ny-2) behind the node wall (R13). */
       int xm = (x - 1 + nx) % nx, xp = (x + 1) % nx;
       double uxm = utx[(size_t)y * nx + xm], uxp = utx[(size_t)y * nx + xp];
       double uym = uty[(size_t)y * nx + xm], uyp = uty[(size_t)y * nx + xp];
@@ -385,6 +446,7 @@ int orc_step(const orc_params *p, int nx, int ny, const double *n, const double 
       if (y > 0) { uxd = utx[id - nx]; uyd = uty[id - nx]; }
       else       { uxd = -utx[id];     uyd = -uty[id]; }
       if (y < ny - 1) { uxu = utx[id + nx]; uyu = uty[id + nx]; }
+      else if (p->zh) { uxu = 2.0 * uw - utx[id - nx]; uyu = -uty[id - nx]; }
       else            { uxu = 2.0 * uw - utx[id]; uyu = -uty[id]; }
       double k[2][2];
       k[0][0] = 0.5 * (uxp - uxm);  /* d_x u_x */
@@ -440,7 +502,9 @@ int orc_step(const orc_params *p, int nx, int ny, const double *n, const double 
       /* Collide (BGK + forcing) and stream; links leaving through a wall are
        * reflected back to the same node (half-way bounce-back); at the moving
        * top wall the reflected population gains the wall's momentum,
-       * -2 a_i (c_i . u_w) / cs2 with the wall density rho0 = 1 (R9). */
+       * -2 a_i (c_i . u_w) / cs2 with the wall density rho0 = 1 (R9). Behind
+       * the node wall of R13 there is no lattice: what leaves upwards is
+       * gone. */
       for (int i = 0; i < 9; ++i) {
         double post = nn[i] - (nn[i] - neq[i]) / p->tau_eff + F[i];
         int xd = (x + CX[i] + nx) % nx, yd = y + CY[i];
@@ -456,6 +520,8 @@ int orc_step(const orc_params *p, int nx, int ny, const double *n, const double 
         }
         if (yd >= 0 && yd < ny)
           n_out[i * N + (size_t)yd * nx + xd] = post;
+        else if (yd >= ny && p->zh)
+          continue;
         else if (yd >= ny)
           n_out[opposite(i) * N + id] = post - 2.0 * W[i] * (CX[i] * uw) / CS2;
         else
@@ -470,6 +536,9 @@ int orc_step(const orc_params *p, int nx, int ny, const double *n, const double 
     }
   free(utx);
   free(uty);
+  free(nz);
+  /* R13: the state handed on is complete for the next step */
+  if (p->zh && n_out) orc_zou_he_top(p, nx, ny, n_out, t + 1);
   return bad;
 }
 

@@ -1,6 +1,7 @@
-"""Pins of the FP64 network oracle: backward against central finite
-differences of its own forward, the SiLU derivative against its definition,
-the first Adam step against its closed form, and the lbml symbols."""
+"""Pins of the FP64 network oracle: the forward pass against a network
+written out by hand, backward against central finite differences of that
+forward, the SiLU derivative against its definition, the first Adam step
+against its closed form, and the lbml symbols."""
 import re
 import os
 
@@ -26,6 +27,36 @@ def test_backward_matches_finite_differences():
         e[i] = h
         fd = (mlp.loss_and_grad(p + e, DIMS, x, t)[0] - mlp.loss_and_grad(p - e, DIMS, x, t)[0]) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-9
+
+
+def test_forward_hand_computed():
+    """Forward pass of a 2-2-1 network written out by hand: layer 0 is
+    z_j = sum_k W0[j][k] x_k + b0[j] with SiLU(z) = z / (1 + e^-z), the
+    output layer is linear. W0 is square and not symmetric, so a transposed
+    weight matrix, a missing bias, a swapped row order or SiLU on the output
+    each change the numbers."""
+    import math
+    W0 = [[1.0, -2.0], [0.5, 3.0]]
+    b0 = [0.1, -0.2]
+    W1 = [[2.0, -1.0]]
+    b1 = [0.3]
+    p = np.array([W0[0][0], W0[0][1], W0[1][0], W0[1][1], b0[0], b0[1], W1[0][0], W1[0][1], b1[0]])
+    x = np.array([[1.0, 2.0], [-0.7, 0.4]])
+
+    def silu(z):
+        return z / (1.0 + math.exp(-z))
+
+    want = []
+    for row in x:
+        z0 = row[0] * W0[0][0] + row[1] * W0[0][1] + b0[0]
+        z1 = row[0] * W0[1][0] + row[1] * W0[1][1] + b0[1]
+        want.append(W1[0][0] * silu(z0) + W1[0][1] * silu(z1) + b1[0])
+    y, _ = mlp.forward(p, [2, 2, 1], x)
+    assert y.shape == (2, 1)
+    assert np.allclose(y[:, 0], want, rtol=1e-15, atol=0)
+    # first row by hand: z = (-2.9, 6.3)
+    assert y[0, 0] == pytest.approx(2 * (-2.9 / (1 + math.exp(2.9))) - 6.3 / (1 + math.exp(-6.3)) + 0.3,
+                                    rel=1e-15)
 
 
 def test_silu_derivative():

@@ -387,7 +387,8 @@ def test_cessation_below_bingham_bound(orc):
     assert t_stop is not None and t_stop < bound
 
 
-# ---- planar Couette flow: the moving top wall (reading R9)
+# ---- planar Couette flow with the half-link moving wall (reading R9, the
+# alternative to R13 below)
 
 def test_couette_newtonian_linear(orc):
     """G = 0 with the top wall moving at U: the steady profile is exactly the
@@ -451,6 +452,130 @@ def test_couette_nlm_steady(orc):
     tauM = 1.0 / (1.0 / tau + gdot / gc)
     assert np.abs(pr["sxy"] - G * gdot * tauM).max() / (G * gdot * tauM) < 1e-9
     assert np.abs(pr["sxx"] - pr["syy"] - 2 * G * gdot ** 2 * tauM ** 2).max() / (2 * G * gdot ** 2 * tauM ** 2) < 1e-9
+
+
+# ---- planar Couette flow with Zou and He's node wall (reading R13): the
+# moving wall of the paper's Couette runs (Sec. II.B, last paragraph)
+
+def zh_channel(orc, nx, ny, **kw):
+    return orc.Channel(nx, ny, kw.pop("force", 0.0), top_wall="zou_he", **kw)
+
+
+def test_zou_he_newtonian_linear(orc):
+    """G = 0, top wall on the node row y = ny - 1 moving at U: the steady
+    profile is the linear Couette profile U (y + 1/2)/(ny - 1/2) between the
+    half-way wall at y = -1/2 and the node wall, for any relaxation time,
+    with and without the delta-rho terms; u_y = 0."""
+    for tau, nnp in ((0.6, False), (0.8, True), (1.3, False)):
+        ch = zh_channel(orc, 1, 16, tau_lb=tau, G=0.0, wall_velocity=0.01, nn_pressure=nnp)
+        ch.run(int(8000 / ((tau - 0.5) / 3 / (1 / 6))))
+        pr = ch.profiles()
+        want = 0.01 * (np.arange(16) + 0.5) / 15.5
+        assert np.abs(pr["ux"] - want).max() / 0.01 < 1e-10
+        assert np.abs(pr["uy"]).max() / 0.01 < 1e-10
+
+
+def test_zou_he_wall_node_velocity(orc):
+    """The node wall imposes its velocity: at every step the provisional
+    velocity of the top row is (u_w(t), 0) to round-off, also after the wall
+    has stopped (t >= t_startup), from a random state with a force."""
+    from paper_1310_7450_amd import workloads
+    ch = zh_channel(orc, 5, 9, force=1e-6, tau_lb=0.8, G=2e-4, tau0=500.0, gamma_c=0.1,
+                    wall_velocity=0.02, t_startup=6)
+    pops, P = workloads.random_state(5, 9, seed=31)
+    ch.set_state(pops, P, t=0)
+    for _ in range(12):
+        f = ch.fields()
+        uw = 0.02 if ch.t < 6 else 0.0
+        assert np.abs(f["utx"][-1] - uw).max() < 1e-15
+        assert np.abs(f["uty"][-1]).max() < 1e-15
+        ch.run(1)
+
+
+def test_zou_he_newtonian_startup(orc):
+    """Start-up of Newtonian Couette flow between the half-way wall and the
+    node wall follows the Fourier series for the width ny - 1/2 (Sec. IV.B);
+    the series for the half-link width ny misses it."""
+    tau = 0.8
+    eta = (tau - 0.5) / 3
+    ch = zh_channel(orc, 1, 32, tau_lb=tau, G=0.0, wall_velocity=0.01)
+    for t in (100, 500, 2000):
+        ch.run(t - ch.t)
+        u = ch.profiles()["ux"]
+        want = analytic.newtonian_couette_startup(32, 0.01, eta, t, top_wall="zou_he")
+        assert np.abs(u - want).max() / 0.01 < 3e-3
+        other = analytic.newtonian_couette_startup(32, 0.01, eta, t, top_wall="halfway")
+        if t == 2000:
+            assert np.abs(u - other).max() / 0.01 > 5 * np.abs(u - want).max() / 0.01
+
+
+def zh_budget_terms(ch):
+    """Mass and x momentum of the rows below the node wall, and what crossed
+    between rows ny - 2 and ny - 1 in the step that produced the state: the
+    populations now in row ny - 1 moving up left the lower rows, the ones now
+    in row ny - 2 moving down entered them. Also the momentum handed to the
+    fixed half-way wall (reflected populations now moving up in row 0)."""
+    CXa, CYa = CX[:, None], CY[:, None]
+    n = ch.n
+    low = n[:, :-1, :]
+    mass = low.sum() + (1.5 * ch.P[:-1].sum() if ch.params.nn_pressure else 0.0)
+    mom = (CX[:, None, None] * low).sum()
+    up = (CYa == 1) * n[:, -1, :]
+    dn = (CYa == -1) * n[:, -2, :]
+    cross_mass = -up.sum() + dn.sum()
+    cross_mom = -(CXa * up).sum() + (CXa * dn).sum()
+    wall = (2.0 * (-CXa) * ((CYa == 1) * n[:, 0, :])).sum()
+    return mass, mom, cross_mass, cross_mom, wall
+
+
+@pytest.mark.parametrize("nnp", [False, True])
+def test_zou_he_mass_and_momentum_budget(orc, nnp):
+    """Collision conserves mass (with the flow-induced density: sum (s +
+    3/2 P)) and momentum up to the body force, and streaming only moves
+    them; so the rows below the node wall change exactly by what crossed into
+    the wall row, the body force and the fixed wall's reaction, through the
+    wall's switch-off."""
+    g = 1e-6
+    ch = zh_channel(orc, 3, 12, force=g, tau_lb=0.7, G=1e-4, tau0=1e3, gamma_c=0.1, wall_velocity=0.02,
+                    t_startup=40, nn_pressure=nnp)
+    nodes = ch.nx * (ch.ny - 1)
+    for _ in range(80):
+        q0, m0, _, _, _ = zh_budget_terms(ch)
+        gnow = ch.force_now()
+        ch.run(1)
+        q1, m1, cq, cm, w = zh_budget_terms(ch)
+        assert q1 - q0 - cq == pytest.approx(0, abs=2e-15 * nodes)
+        assert m1 - m0 - nodes * gnow - cm + w == pytest.approx(0, abs=2e-15 * nodes)
+
+
+def test_zou_he_nlm_steady(orc):
+    """Sec. IV.B: steady planar Couette flow has one shear rate everywhere,
+    gdot = U/(ny - 1/2) between the half-way wall and the node wall, and the
+    simple-shear stress of Sec. III.A on every row (sigma_xy = G gdot tau_M,
+    N1 = 2 G gdot^2 tau_M^2). theta = 100, Pe = 10, viscosity split 1/2
+    without the delta-rho terms."""
+    ny, U = 16, 0.0048
+    G, tau, gc = 1e-3, 10000.0 / 3.0, 0.1
+    ch = zh_channel(orc, 1, ny, tau_lb=0.6, G=G, tau0=tau, gamma_c=gc, visc_split=0.5,
+                    nn_pressure=False, wall_velocity=U)
+    ch.run(30000)
+    pr = ch.profiles()
+    L = ny - 0.5
+    gdot = U / L
+    want = U * (np.arange(ny) + 0.5) / L
+    assert np.abs(pr["ux"] - want).max() / U < 1e-9
+    assert np.abs(pr["kxy"] - gdot).max() / gdot < 1e-9
+    tauM = 1.0 / (1.0 / tau + gdot / gc)
+    assert np.abs(pr["sxy"] - G * gdot * tauM).max() / (G * gdot * tauM) < 1e-9
+    n1 = 2 * G * gdot ** 2 * tauM ** 2
+    assert np.abs(pr["sxx"] - pr["syy"] - n1).max() / n1 < 1e-9
+
+
+def test_zou_he_rejects_pressure_drive_and_stress_force(orc):
+    with pytest.raises(ValueError):
+        orc.resolve(1.0, 1e-4, 1e3, 0.1, nn_pressure=False, pressure_drop=1e-5, top_wall="zou_he")
+    with pytest.raises(ValueError):
+        orc.resolve(1.0, 1e-4, 1e3, 0.1, nn_pressure=False, stress_force=True, top_wall="zou_he")
 
 
 # ---- pressure drive by generalised periodic boundaries (reading R10)
