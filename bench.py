@@ -107,16 +107,46 @@ def run_batched(max_steps=None, verbose=True):
         wall = time.perf_counter() - t0
         steps = [int(s.observe(i, "step")) for i in range(len(chans))]
         active = [int(s.observe(i, "active")) for i in range(len(chans))]
+        ref = batched_oracle_fixture()
+        errs = {i: (linf_rel(s.observe(i, "ux"), u), linf_rel(s.observe(i, "sxy"), sx), steps[i] - t)
+                for i, (t, u, sx) in ref.items()}
     sec = e0.elapsed_time(e1) / 1e3
     updates = sum(c.nx * c.ny * n for c, n in zip(chans, steps))
     import numpy as np
     st = np.array(steps)
+    eu = np.array([e[0] for e in errs.values()])
+    es = np.array([e[1] for e in errs.values()])
     return {"workload": wl["name"], "channels": len(chans), "nodes": sum(c.nx * c.ny for c in chans),
-            "admitted": f"{len(chans)} of {wl['draws']} draws (seed {wl['seed']})", "strip_rows": sr,
+            "admitted": f"{len(chans)} of {wl['draws']} draws (seed {wl['seed']}; low-Mach rule only)",
+            "stiff_split": f"{wl['stiff']} channels with G_inf tau > 0.3 run with visc_split 1/2, no delta-rho terms",
+            "strip_rows": sr,
             "value": round(updates / sec / 1e6, 1), "unit": "MLUPS", "seconds": round(sec, 3),
             "wall_s": round(wall, 3), "converged": int(len(chans) - sum(active)),
             "steps_to_steady": {"median": int(np.median(st)), "max": int(st.max()), "min": int(st.min())},
-            "precision": "fp32_shifted", "steady_tol": wl["steady_tol"]}
+            "precision": "fp32_shifted", "steady_tol": wl["steady_tol"],
+            "error_vs_oracle": {
+                "sample": f"{len(errs)} channels (three per width decile and the four widest), FP64 oracle steady "
+                          "states from rest (tests/golden/batched_sweep_seed2_oracle.txt)",
+                "linf_rel_ux": {"median": float(np.median(eu)), "max": float(eu.max())},
+                "linf_rel_sxy": {"median": float(np.median(es)), "max": float(es.max())},
+                "steps_minus_oracle": {"min": int(min(e[2] for e in errs.values())),
+                                       "max": int(max(e[2] for e in errs.values()))}}}
+
+
+def linf_rel(a, b):
+    import numpy as np
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())
+
+
+def batched_oracle_fixture():
+    """The FP64 oracle's steady states of the batched sweep's width-stratified
+    sample, stored by tests/golden/make_batched_oracle.py (oracle only)."""
+    import importlib.util
+    path = os.path.join(ROOT, "tests", "golden", "make_batched_oracle.py")
+    spec = importlib.util.spec_from_file_location("make_batched_oracle", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.load()
 
 
 def run_transient_scale(steps=200, warmup=50):
@@ -218,7 +248,7 @@ def cpu_baseline(wl, budget_s=15.0):
 
     def channel(c):
         return orc.Channel(c.nx, c.ny, c.force, tau_lb=c.tau_lb, G=c.G, tau0=c.tau0, gamma_c=c.gamma_c,
-                           eps=c.eps, visc_split=c.visc_split)
+                           eps=c.eps, visc_split=c.visc_split, nn_pressure=c.resolved_nn_pressure())
 
     threads = orc.num_threads()
     upd, sec, n = _time_oracle(channel(spec), budget_s)

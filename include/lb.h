@@ -75,12 +75,10 @@ typedef enum {
  *              is the split of Sec. IV; lambda > 0 needs a finite tau);
  *   t_startup  first step without the body force (and without the wall
  *              motion);
- *   wall_velocity  x velocity of the top wall (y = ny - 1/2) for steps
- *              t < t_startup, 0 afterwards: planar Couette flow driven by a
- *              wall that is switched on and off (Sec. IV.B). The wall stays
- *              on the half link and reflects with the wall-momentum term
- *              -2 a_i (c_i . u_w) / c_s^2 (wall density rho0 = 1); |u_w| < 0.3
- *              (low Mach number). 0 gives two fixed walls.
+ *   wall_velocity  x velocity of the top wall for steps t < t_startup, 0
+ *              afterwards: planar Couette flow driven by a wall that is
+ *              switched on and off (Sec. IV.B); |u_w| < 0.3 (low Mach
+ *              number). How the wall acts is set by top_wall.
  *   pressure_gradient  pressure drop per unit length G_p along +x (the
  *              problem statement's Delta p / L, equivalent to force = G_p)
  *              imposed by generalised periodic boundaries (Sec. II.B): the
@@ -89,8 +87,31 @@ typedef enum {
  *              virtual nodes beside the inlet (x = 0) and outlet
  *              (x = nx - 1) columns, plus the source's non-equilibrium part;
  *              acts for t < t_startup. Needs force = 0, wall_velocity = 0,
- *              nx >= 2 and the options' nn_pressure = 0 (the forcing keeps
- *              its first line only). 0: plain periodic x.
+ *              nx >= 2, nn_pressure = 0 (the forcing keeps its first line
+ *              only) and the half-way top wall. 0: plain periodic x.
+ *   nn_pressure  1: the forcing of Eq. (bodyforce) keeps the flow-induced
+ *              density terms of Eq. (rhoplus); 0: they are dropped
+ *              (dt d(delta rho)/dt = 0), as Sec. II.B does with pressure
+ *              boundaries. Per channel, so that one batch can run stiff
+ *              channels without them (with them, the explicit stress
+ *              amplifies round-off once G_inf tau exceeds about 0.3 at
+ *              visc_split 0; without them and with visc_split 1/2 it stays
+ *              well conditioned up to G_inf tau = 10).
+ *   top_wall   LB_WALL_HALFWAY: half-way bounce-back at y = ny - 1/2 like the
+ *              bottom wall; a moving wall reflects with the wall-momentum
+ *              term -2 a_i (c_i . u_w) / c_s^2 (wall density rho0 = 1).
+ *              LB_WALL_ZOU_HE: the moving wall of the paper's Couette runs,
+ *              Zou and He's velocity boundary on the top node row y = ny - 1
+ *              (Sec. II.B, last paragraph), so the channel spans
+ *              L = ny - 1/2. After streaming, the three populations of that
+ *              row entering from above (c_y = -1) follow from the other six:
+ *              no flow through the wall, n_4 = n_2 (normal non-equilibrium
+ *              bounce-back) and the diagonals such that the node's
+ *              provisional velocity (m + f/2) / sum_i n_i is (u_w, 0); the
+ *              node then collides like any other, and what it emits upwards
+ *              leaves the lattice. Its velocity gradient uses the ghost
+ *              mirrored through the wall node, u(ny) = 2 (u_w, 0) - u(ny-2).
+ *              Needs ny >= 2, no pressure_gradient and no stress_force.
  */
 typedef struct {
   int32_t nx;
@@ -105,14 +126,16 @@ typedef struct {
   int64_t t_startup;
   double wall_velocity;
   double pressure_gradient;
+  int32_t nn_pressure;
+  int32_t top_wall;
 } lb_channel;
+
+/* Values of lb_channel.top_wall. */
+enum { LB_WALL_HALFWAY = 0, LB_WALL_ZOU_HE = 1 };
 
 /*
  * Options shared by all channels of a handle:
  *   precision    lb_precision;
- *   nn_pressure  1: full forcing of Eq. (bodyforce) including the
- *                flow-induced density terms of Eq. (rhoplus); 0: those terms
- *                are dropped (dt d(delta rho)/dt = 0);
  *   obs_every    K, the length of one block of steps (one captured graph);
  *                the convergence check and the FP32 reference move run at
  *                the block boundaries; even, >= 2 (default 1000 when 0);
@@ -142,15 +165,14 @@ typedef struct {
  *                alternative Sec. II.C names), with Sigma^nN formed at every
  *                node first, central differences for the divergence and ghost
  *                rows extrapolated linearly through the walls; there is then
- *                no flow-induced density. Needs LB_FP64, nn_pressure = 0, the
- *                instantaneous model, no pressure_gradient and channels of
- *                at most 429,496,704 nodes. Runs as one fused pass per step
- *                (u~, Sigma^nN and the collide-and-stream of a tile of nodes
- *                in one workgroup).
+ *                no flow-induced density. Needs LB_FP64, the instantaneous
+ *                model and channels with nn_pressure = 0, the half-way top
+ *                wall, no pressure_gradient and at most 429,496,704 nodes.
+ *                Runs as one fused pass per step (u~, Sigma^nN and the
+ *                collide-and-stream of a tile of nodes in one workgroup).
  */
 typedef struct {
   int32_t precision;
-  int32_t nn_pressure;
   int32_t obs_every;
   int32_t strip_rows;
   double steady_tol;
@@ -176,7 +198,11 @@ enum {
   LB_OBS_MASS = 32,     /* sum_nodes (sum_i n_i - delta rho_prev)            */
   LB_OBS_MOMX = 33,     /* sum_nodes sum_i c_ix n_i                         */
   LB_OBS_FLUX = 34,     /* sum_nodes u_x                                    */
-  LB_OBS_WALL_DRAG = 35,/* x momentum given to the walls in the last step   */
+  LB_OBS_WALL_DRAG = 35,/* x momentum given to the walls in the last step;  */
+                        /* at a Zou-He top wall: what the top row emitted  */
+                        /* upwards minus what its completion supplied (not */
+                        /* defined before the first step after            */
+                        /* lb_set_state or lb_set_profile)                */
   LB_OBS_UMID = 36,     /* x-averaged u_x at the centre line                */
   LB_OBS_RESIDUAL = 37, /* last residual R (+inf before two checks)        */
   LB_OBS_STEP = 38,     /* steps the channel has taken                      */
@@ -219,11 +245,15 @@ lb_status lb_observe(lb_handle *h, int32_t ch, int32_t what, double *host_out, s
 /* Copies the state of channel ch to host memory: the post-streaming
  * populations n_i(x, y) of the current step as pops[9][ny][nx] (velocity
  * order (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1)) and the
- * previous stress trace P[ny][nx], in FP64. Synchronises the stream. */
+ * previous stress trace P[ny][nx], in FP64. With a Zou-He top wall the three
+ * populations of row ny - 1 entering from above are the ones the boundary
+ * completes for the current step. Synchronises the stream. */
 lb_status lb_get_state(lb_handle *h, int32_t ch, double *pops, double *P);
 
 /* Overwrites the state of channel ch (same layout as lb_get_state) and sets
- * its step counter to t. Synchronises the stream. */
+ * its step counter to t. With a Zou-He top wall the three populations of row
+ * ny - 1 entering from above are not kept: the next step completes them.
+ * Synchronises the stream. */
 lb_status lb_set_state(lb_handle *h, int32_t ch, const double *pops, const double *P, int64_t t);
 
 /* Time-integrated stress of channel ch (viscoelastic option only): the
@@ -244,10 +274,11 @@ enum {
 
 /* Initialises channel ch from a predicted steady profile (a warm start):
  * u_x and N1 given at n_pts points of the set `points`. Populations are set
- * to the equilibrium at u = (u_x, 0) and rho_e = 1 - (3/2) N1 (so that the
- * hydrodynamic mass equals that of the rest state) and the previous trace to
- * N1. The step counter is kept. LB_EINVAL for an unknown point set or
- * n_pts != ny with LB_PROFILE_ROWS. */
+ * to the equilibrium at u = (u_x, 0) and rho_e = 1 - (3/2) N1 (rho_e = 1 for a
+ * channel without the flow-induced density terms), so that the conserved
+ * mass equals that of the rest state, and the previous trace to N1. The step
+ * counter is kept. LB_EINVAL for an unknown point set or n_pts != ny with
+ * LB_PROFILE_ROWS. */
 lb_status lb_set_profile(lb_handle *h, int32_t ch, const double *ux, const double *n1, int32_t n_pts,
                          int32_t points);
 

@@ -139,15 +139,16 @@ def newtonian_couette_startup(ny, U, eta, t, kmax=2000, rho0=1.0, top_wall="half
     return U * s - (2 * U / math.pi) * terms.sum(axis=0)
 
 
-def bingham_stop_bound(u_rows, eta, sigma_y, ny, rho0=1.0):
+def bingham_stop_bound(u_rows, eta, sigma_y, ny, rho0=1.0, width=None):
     """Upper bound on the stopping time of a Bingham fluid (yield stress
     sigma_y, plastic viscosity eta) released from the profile u_rows in a
-    channel of half width H = ny/2 (Sec. III.B, finite stopping time). From the
-    energy balance (rho0/2) d|u|^2/dt = -eta |u'|^2 - sigma_y |u'|_1 with
+    channel of width 2H between no-slip walls (H = ny/2 unless ``width``
+    gives 2H; Sec. III.B, finite stopping time). From the energy balance
+    (rho0/2) d|u|^2/dt = -eta |u'|^2 - sigma_y |u'|_1 with
     |u'|^2 >= lambda1 |u|^2, lambda1 = (pi/2H)^2, and |u'|_1 >= beta |u|,
     beta = sqrt(2/H): t_f <= rho0/(eta lambda1) ln(1 + eta lambda1 Y0 /(sigma_y beta)),
     Y0 = |u(0)|_2."""
-    H = ny / 2.0
+    H = (ny if width is None else width) / 2.0
     lam1 = (math.pi / (2 * H)) ** 2
     beta = math.sqrt(2.0 / H)
     Y0 = float(np.sqrt(np.sum(np.asarray(u_rows) ** 2)))

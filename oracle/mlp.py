@@ -8,6 +8,11 @@ x -> z = x W_l^T + b_l, followed by SiLU(z) = z sigmoid(z) on every layer but
 the last. Parameters are one flat vector, per layer W_l[out][in] row major and
 then b_l[out]. The loss is the mean of the squared errors over all outputs
 of the batch. Adam follows Kingma & Ba (2015) with bias-corrected moments.
+
+The network is specified with BF16 operands and FP32 accumulation. The
+optional ``operand`` argument of ``forward`` and ``backward`` is a rounding
+applied to both factors of every matrix product (for example to BF16); the
+products and sums themselves stay in FP64.
 """
 import numpy as np
 
@@ -29,13 +34,18 @@ def sigmoid(z):
     return 1.0 / (1.0 + np.exp(-z))
 
 
-def forward(p, dims, x):
+def _identity(a):
+    return a
+
+
+def forward(p, dims, x, operand=None):
     """Returns the output and the cache (pre-activations and layer inputs)."""
+    op = operand or _identity
     layers = unpack(np.asarray(p, dtype=np.float64), dims)
     h = np.asarray(x, dtype=np.float64)
     cache = []
     for l, (W, b) in enumerate(layers):
-        z = h @ W.T + b
+        z = op(h) @ op(W).T + b
         cache.append((h, z))
         h = z * sigmoid(z) if l < len(layers) - 1 else z
     return h, cache
@@ -46,18 +56,19 @@ def mse(y, t):
     return float(np.mean(d * d)), 2.0 * d / d.size
 
 
-def backward(p, dims, cache, dy):
+def backward(p, dims, cache, dy, operand=None):
     """Gradient of the loss with respect to the flat parameters, given dy =
     d loss / d output."""
+    op = operand or _identity
     layers = unpack(np.asarray(p, dtype=np.float64), dims)
     grads = [None] * len(layers)
     dz = np.asarray(dy, dtype=np.float64)
     for l in range(len(layers) - 1, -1, -1):
         W, b = layers[l]
         h, z = cache[l]
-        grads[l] = (dz.T @ h, dz.sum(axis=0))
+        grads[l] = (op(dz).T @ op(h), dz.sum(axis=0))
         if l > 0:
-            dh = dz @ W
+            dh = op(dz) @ op(W)
             zp = cache[l - 1][1]
             s = sigmoid(zp)
             dz = dh * (s * (1.0 + zp * (1.0 - s)))

@@ -50,6 +50,8 @@ struct ChanDev {
   double uw;            // top wall x velocity while t < t_startup
   double pd;            // pressure drive: p+ - p- = (nx + 1) G_p while t < t_startup
   int gpbc;             // generalised periodic boundaries in x
+  int nnp;              // keep the flow-induced density terms
+  int zh;               // top wall: Zou-He velocity boundary on row ny - 1
 };
 
 // Work unit of one wavefront: rows [y0, y1) of channel ch, starting at
@@ -69,7 +71,6 @@ struct SweepArgs {
   int n_strips;
   int n_wg;
   int k;                // step offset added to every channel's t
-  int nnp;              // keep the flow-induced density terms
   int nt;               // store the new state with nontemporal hints
   int down;             // the step marches downwards (vector sweep; flipped strips go upwards)
   const float *uref;    // FP32: reference velocity of every row (all channels)

@@ -217,6 +217,37 @@ __device__ __forceinline__ void to_row_reference(T f[9], T urd, T urc, T uru, bo
   f[8] += top ? -urc * T(1.0 / 6.0) : ref_shift(w5, T(1), uru, urc);
 }
 
+// Zou and He's velocity boundary on the top node row (Sec. II.B, the moving
+// wall of planar Couette flow): the three populations a node of row ny - 1
+// lacks after streaming (c_y = -1: 4, 7, 8) follow from the six it has. No
+// flow through the wall gives the density s = f0 + f1 + f3 + 2 (f2 + f5 +
+// f6); the normal non-equilibrium part bounces back, f4 = f2; the diagonals
+// keep f7 + f8 = f5 + f6 and supply the x momentum for which the provisional
+// velocity (m + f/2)/s is the wall's (uw, 0). With SHIFT the values are
+// relative to the equilibrium at density 1 and the row reference (ur, 0):
+// s is then the density deviation and the momentum the one beyond ur,
+// (uw - ur) + s uw - f/2, and the relations between stored values are the
+// same (the reference terms of 4 and 2, and of 7 + 8 and 5 + 6, are equal).
+template <typename T, bool SHIFT>
+__device__ __forceinline__ void zou_he_top(T f[9], T uw, T ur, T fx) {
+#pragma clang fp contract(off)
+  const T s = (f[0] + f[1] + f[3]) + T(2) * (f[2] + f[5] + f[6]);
+  const T m = SHIFT ? (uw - ur) + s * uw - T(0.5) * fx : s * uw - T(0.5) * fx;
+  const T d87 = m - ((f[1] - f[3]) + (f[5] - f[6]));
+  const T s78 = f[5] + f[6];
+  f[4] = f[2];
+  f[8] = T(0.5) * (s78 + d87);
+  f[7] = T(0.5) * (s78 - d87);
+}
+// x momentum a node of the top row gave a Zou-He wall in the previous step:
+// what it emitted upwards (its own stored 5 and 6, a5 - a6) minus what the
+// completion f supplies (f8 - f7). With SHIFT the reduction adds -ur/6 per
+// node (the reference terms of both differences).
+template <typename T>
+__device__ __forceinline__ double zh_drag(T a5, T a6, const T f[9]) {
+  return ((double)a5 - (double)a6) - ((double)f[8] - (double)f[7]);
+}
+
 // Wave-wide sum over a lane group of width GW (power of two).
 template <int GW>
 __device__ __forceinline__ double group_sum(double v) {
@@ -416,12 +447,13 @@ __device__ __forceinline__ void node_update(const T f[9], T sd, T mx, T my, T Pc
 // With the FP32 reference ur the pulled values are n_i - a_i - E_i(ur), and
 // n6 - n5 = f6 - f5 - ur/6, n7 - n8 = f7 - f8 - ur/6; the -ur/3 of each wall
 // node is added per row in the reduction.
+// At a Zou-He top wall the top row's share is ztop (zh_drag).
 template <typename T>
-__device__ __forceinline__ double wall_drag(const T f[9], int y, int ny, T uw6) {
+__device__ __forceinline__ double wall_drag(const T f[9], int y, int ny, T uw6, bool zh, double ztop) {
   double d = 0.0;
   if (y == 0) d += 2.0 * ((double)f[6] - (double)f[5]);
   // a moving top wall also received the momentum its reflection added
-  if (y == ny - 1) d += 2.0 * ((double)f[7] - (double)f[8]) + 2.0 * (double)uw6;
+  if (y == ny - 1) d += zh ? ztop : 2.0 * ((double)f[7] - (double)f[8]) + 2.0 * (double)uw6;
   return d;
 }
 
@@ -454,7 +486,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
   // moving top wall: its velocity at step t (stencil ghost) and u_w/6 of step
   // t - 1, whose reflected links step t pulls
   const T uwg = (t < c.t_startup) ? T(c.uw) : T(0);
-  const T uw6 = (t >= 1 && t - 1 < c.t_startup) ? T(c.uw / 6.0) : T(0);
+  const T uw6 = (!c.zh && t >= 1 && t - 1 < c.t_startup) ? T(c.uw / 6.0) : T(0);
   const Coef<T> q(c);
 
   int lx, ly, x, hx = 0;
@@ -494,6 +526,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
     Pv = A[slot(9, row + x)];
     ur = ref(yc);
     if constexpr (SHIFT) to_row_reference(f, ref(yc - 1), ur, ref(yc + 1), yc == 0, yc == ny - 1);
+    if (c.zh && yc == ny - 1) zou_he_top<T, SHIFT>(f, uwg, ur, fx);
   };
   auto halo_u = [&](int y) -> U2<T> {
     const int yc = clampy(y);
@@ -501,6 +534,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
     pull<T>(A, base + (long long)yc * nx, nx, ny, hx, yc, uw6, f);
     const T ur = ref(yc);
     if constexpr (SHIFT) to_row_reference(f, ref(yc - 1), ur, ref(yc + 1), yc == 0, yc == ny - 1);
+    if (c.zh && yc == ny - 1) zou_he_top<T, SHIFT>(f, uwg, ur, fx);
     moments<T>(f, sd, mx, my);
     return u_tilde<T, SHIFT>(sd, mx, my, fx, ur);
   };
@@ -562,14 +596,18 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
       if (lane == 63) rt = hr;
     }
     // no-slip ghosts behind the half-way walls, u~(-1) = -u~(0) and
-    // u~(ny) = 2 u_w - u~(ny-1); with SHIFT the ghost rows take the mirrored
+    // u~(ny) = 2 u_w - u~(ny-1), or behind a Zou-He node wall
+    // u~(ny) = 2 u_w - u~(ny-2); with SHIFT the ghost rows take the mirrored
     // references -ur and 2 u_w - ur, so their deltas are just mirrored
     if (y == 0) dn = U2<T>{-uCur.x, -uCur.y};
-    if (y == ny - 1) up = U2<T>{(SHIFT ? T(0) : T(2) * uwg) - uCur.x, -uCur.y};
+    if (y == ny - 1) {
+      const U2<T> m = c.zh ? dn : uCur;
+      up = U2<T>{(SHIFT ? T(0) : T(2) * uwg) - m.x, -m.y};
+    }
     T kref = T(0);
     if constexpr (SHIFT) {
       const T urd = (y == 0) ? -urc : ref(y - 1);
-      const T uru = (y >= ny - 1) ? T(2) * uwg - urc : ref(y + 1);
+      const T uru = (y >= ny - 1) ? T(2) * uwg - (c.zh ? urd : urc) : ref(y + 1);
       kref = T(0.5) * (uru - urd);
     }
 
@@ -578,10 +616,15 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
     const bool ok = (y < st.y1) && colok;
     T out[9], trT, sg[3];
     double obs[OF_COUNT];
-    node_update<T, SHIFT, OBS, VE>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, urc, kref, q, a.nnp, sgc, sg, out,
+    node_update<T, SHIFT, OBS, VE>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, urc, kref, q, c.nnp, sgc, sg, out,
                                    trT, obs);
     if constexpr (OBS) {
-      obs[OF_DRAG] = wall_drag<T>(fc, y, ny, uw6);
+      double ztop = 0.0;
+      if (c.zh && y == ny - 1) {
+        const long long o = base + (long long)y * nx + x;
+        ztop = zh_drag<T>(A[slot(5, o)], A[slot(6, o)], fc);
+      }
+      obs[OF_DRAG] = wall_drag<T>(fc, y, ny, uw6, c.zh, ztop);
       constexpr int GW = WIDE ? 64 : TXW;
 #pragma unroll
       for (int f = 0; f < OF_COUNT; ++f) obs[f] = group_sum<GW>(ok ? obs[f] : 0.0);
@@ -643,7 +686,7 @@ __global__ void __launch_bounds__(kMainThreads) sweep_tile_kernel(SweepArgs a) {
   const long long t = c.t + a.k;
   const double fx = (t < c.t_startup) ? c.g : 0.0;
   const double uwg = (t < c.t_startup) ? c.uw : 0.0;
-  const double uw6 = (t >= 1 && t - 1 < c.t_startup) ? c.uw / 6.0 : 0.0;
+  const double uw6 = (!c.zh && t >= 1 && t - 1 < c.t_startup) ? c.uw / 6.0 : 0.0;
   const Coef<double> q(c);
   const double *__restrict__ Ac = static_cast<const double *>(a.A) + c.off * kPlanes;
   double *__restrict__ Bc = static_cast<double *>(a.B) + c.off * kPlanes;
@@ -678,6 +721,7 @@ __global__ void __launch_bounds__(kMainThreads) sweep_tile_kernel(SweepArgs a) {
   const unsigned m = (unsigned)clampy(yo) * nx + wrapx(xo);
   double f[9], fh[9], sgc[3] = {0.0, 0.0, 0.0};
   pull_local(Ac, nx, ny, wrapx(xo), clampy(yo), uw6, f);
+  if (c.zh && clampy(yo) == ny - 1) zou_he_top<double, false>(f, uwg, 0.0, fx);
   const double Pc = Ac[lslot(9, m)];
   if constexpr (VE) {
     const double *__restrict__ SAc = static_cast<const double *>(a.SA) + c.off * kStressPlanes;
@@ -685,6 +729,7 @@ __global__ void __launch_bounds__(kMainThreads) sweep_tile_kernel(SweepArgs a) {
     for (int p = 0; p < 3; ++p) sgc[p] = SAc[((m >> 6) * kStressPlanes + p) * kTile + (m & (kTile - 1))];
   }
   if (ring) pull_local(Ac, nx, ny, wrapx(tl.x0 - 1 + hi), clampy(hy), uw6, fh);
+  if (ring && c.zh && clampy(hy) == ny - 1) zou_he_top<double, false>(fh, uwg, 0.0, fx);
   double sd, mx, my;
   moments<double>(f, sd, mx, my);
   const U2<double> uc = u_tilde<double, false>(sd, mx, my, fx, 0.0);
@@ -707,9 +752,9 @@ __global__ void __launch_bounds__(kMainThreads) sweep_tile_kernel(SweepArgs a) {
   U2<double> dn{su[0][js - 1][is], su[1][js - 1][is]};
   U2<double> up{su[0][js + 1][is], su[1][js + 1][is]};
   if (yo == 0) dn = U2<double>{-uc.x, -uc.y};
-  if (yo == ny - 1) up = U2<double>{2.0 * uwg - uc.x, -uc.y};
+  if (yo == ny - 1) up = c.zh ? U2<double>{2.0 * uwg - dn.x, -dn.y} : U2<double>{2.0 * uwg - uc.x, -uc.y};
   double out[9], trT, sg[3], obs[OF_COUNT];
-  node_update<double, false, false, VE>(f, sd, mx, my, Pc, fx, lf, rt, dn, up, 0.0, 0.0, q, a.nnp, sgc, sg, out,
+  node_update<double, false, false, VE>(f, sd, mx, my, Pc, fx, lf, rt, dn, up, 0.0, 0.0, q, c.nnp, sgc, sg, out,
                                         trT, obs);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -747,7 +792,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
   // moving top wall: its velocity at step t (stencil ghost) and u_w/6 of step
   // t - 1, whose reflected links step t pulls
   const T uwg = (t < c.t_startup) ? T(c.uw) : T(0);
-  const T uw6 = (t >= 1 && t - 1 < c.t_startup) ? T(c.uw / 6.0) : T(0);
+  const T uw6 = (!c.zh && t >= 1 && t - 1 < c.t_startup) ? T(c.uw / 6.0) : T(0);
   const Coef<T> q(c);
 
   const int tiles_row = nx >> 6;                 // tiles per row
@@ -803,6 +848,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
       f[8] = shift_up(ld(tu + dl, 63, 8), run(tu, 8));
     }
     if constexpr (SHIFT) to_row_reference(f, ref(y - 1), ref(y), ref(y + 1), bot, top);
+    if (c.zh && top) zou_he_top<T, SHIFT>(f, uwg, ref(y), fx);
   };
   // u~ of the column left of the strip (column 63 of the left tile) and of
   // the column right of it (column 0 of the right tile), from wave-uniform
@@ -853,6 +899,10 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
     if constexpr (SHIFT) {
       to_row_reference(a, ref(y - 1), urc, ref(y + 1), bot, top);
       to_row_reference(b, ref(y - 1), urc, ref(y + 1), bot, top);
+    }
+    if (c.zh && top) {
+      zou_he_top<T, SHIFT>(a, uwg, urc, fx);
+      zou_he_top<T, SHIFT>(b, uwg, urc, fx);
     }
     T sd, mx, my;
     moments<T>(a, sd, mx, my);
@@ -906,20 +956,24 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_wide64_kernel(SweepArg
     // the mirrored references -ur and 2 u_w - ur (see sweep_kernel)
     const T urc = ref(y);
     if (y == 0) dn = U2<T>{-uCur.x, -uCur.y};
-    if (y == ny - 1) up = U2<T>{(SHIFT ? T(0) : T(2) * uwg) - uCur.x, -uCur.y};
+    if (y == ny - 1) {
+      const U2<T> m = c.zh ? dn : uCur;
+      up = U2<T>{(SHIFT ? T(0) : T(2) * uwg) - m.x, -m.y};
+    }
     T kref = T(0);
     if constexpr (SHIFT) {
       const T urd = (y == 0) ? -urc : ref(y - 1);
-      const T uru = (y == ny - 1) ? T(2) * uwg - urc : ref(y + 1);
+      const T uru = (y == ny - 1) ? T(2) * uwg - (c.zh ? urd : urc) : ref(y + 1);
       kref = T(0.5) * (uru - urd);
     }
 
     T out[9], trT, sg[3];
     double obs[OF_COUNT];
-    node_update<T, SHIFT, OBS, VE>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, urc, kref, q, a.nnp, sgc, sg, out,
+    node_update<T, SHIFT, OBS, VE>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, urc, kref, q, c.nnp, sgc, sg, out,
                                    trT, obs);
     if constexpr (OBS) {
-      obs[OF_DRAG] = wall_drag<T>(fc, y, ny, uw6);
+      const double ztop = (c.zh && y == ny - 1) ? zh_drag<T>(run(tile(y), 5), run(tile(y), 6), fc) : 0.0;
+      obs[OF_DRAG] = wall_drag<T>(fc, y, ny, uw6, c.zh, ztop);
 #pragma unroll
       for (int f = 0; f < OF_COUNT; ++f) obs[f] = group_sum<64>(obs[f]);
       if (lane == 0) {
@@ -1029,7 +1083,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
   // moving top wall: its velocity at step t (stencil ghost) and u_w/6 of step
   // t - 1, whose reflected links step t pulls
   const T uwg = (t < c.t_startup) ? T(c.uw) : T(0);
-  const T uw6 = (t >= 1 && t - 1 < c.t_startup) ? T(c.uw / 6.0) : T(0);
+  const T uw6 = (!c.zh && t >= 1 && t - 1 < c.t_startup) ? T(c.uw / 6.0) : T(0);
   const Coef<T> q(c);
 
   const int tiles_row = nx >> 6;        // tiles per row
@@ -1167,6 +1221,8 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
       from_right(R.r[7], lane_value(R.side, 4), f[7]);
       from_left(R.r[8], lane_value(R.side, 5), f[8]);
     }
+    // a Zou-He top wall completes the top row's populations from above
+    const bool zhtop = top && c.zh;
     // FP32: every pulled value relative to this row's reference
     const T urd = SHIFT ? lane_value(R.side, 24) : T(0);
     const T urc = SHIFT ? lane_value(R.side, 25) : T(0);
@@ -1179,8 +1235,9 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
       T g[9];
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[i] = f[i][k];
-      if constexpr (SHIFT) {
-        to_row_reference(g, urd, urc, uru, bot, top);
+      if constexpr (SHIFT) to_row_reference(g, urd, urc, uru, bot, top);
+      if (zhtop) zou_he_top<T, SHIFT>(g, uwg, urc, fx);
+      if (SHIFT || zhtop) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i][k] = g[i];
       }
@@ -1215,6 +1272,10 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
     if constexpr (SHIFT) {
       to_row_reference(l, urd, urc, uru, bot, top);
       to_row_reference(r, urd, urc, uru, bot, top);
+    }
+    if (zhtop) {
+      zou_he_top<T, SHIFT>(l, uwg, urc, fx);
+      zou_he_top<T, SHIFT>(r, uwg, urc, fx);
     }
     T s0, m0, n0;
     moments<T>(l, s0, m0, n0);
@@ -1287,8 +1348,17 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
     T kref = T(0);
     if constexpr (SHIFT) {
       const T urd = (y == 0) ? -urc : urC[0];
-      const T uru = (y == ny - 1) ? T(2) * uwg - urc : urC[2];
+      const T uru = (y == ny - 1) ? T(2) * uwg - (c.zh ? urd : urc) : urC[2];
       kref = T(0.5) * (uru - urd);
+    }
+    // the top row's own stored 5 and 6 (what it emitted upwards), for the
+    // momentum a Zou-He wall took (observation only)
+    V a5{}, a6{};
+    if constexpr (OBS) {
+      if (c.zh && y == ny - 1) {
+        a5 = vrun(y, 5);
+        a6 = vrun(y, 6);
+      }
     }
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
@@ -1304,23 +1374,27 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
         rt = uCur[k + 1];
       }
       U2<T> dn = down ? uNext[k] : uPrev[k], up = down ? uPrev[k] : uNext[k];
-      // no-slip ghosts behind the half-way walls
+      // no-slip ghosts behind the half-way walls, or behind a Zou-He node
+      // wall mirrored through the wall row
       if (y == 0) dn = U2<T>{-uCur[k].x, -uCur[k].y};
-      if (y == ny - 1) up = U2<T>{(SHIFT ? T(0) : T(2) * uwg) - uCur[k].x, -uCur[k].y};
+      if (y == ny - 1) {
+        const U2<T> m = c.zh ? dn : uCur[k];
+        up = U2<T>{(SHIFT ? T(0) : T(2) * uwg) - m.x, -m.y};
+      }
       T g[9], o[9], tr;
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[i] = fc[i][k];
       double ob[OF_COUNT];
       const T sp[3] = {sgc[0][k], sgc[1][k], sgc[2][k]};
       T sn[3];
-      node_update<T, SHIFT, OBS, VE>(g, sdc[k], mxc[k], myc[k], Pc[k], fx, lf, rt, dn, up, urc, kref, q, a.nnp, sp,
+      node_update<T, SHIFT, OBS, VE>(g, sdc[k], mxc[k], myc[k], Pc[k], fx, lf, rt, dn, up, urc, kref, q, c.nnp, sp,
                                      sn, o, tr, ob);
       if constexpr (VE) {
 #pragma unroll
         for (int p = 0; p < 3; ++p) sgo[p][k] = sn[p];
       }
       if constexpr (OBS) {
-        ob[OF_DRAG] = wall_drag<T>(g, y, ny, uw6);
+        ob[OF_DRAG] = wall_drag<T>(g, y, ny, uw6, c.zh, zh_drag<T>(a5[k], a6[k], g));
 #pragma unroll
         for (int f = 0; f < OF_COUNT; ++f) obs[f] += ob[f];
       } else {
@@ -1420,7 +1494,7 @@ __global__ void __launch_bounds__(256) reduce_kernel(const ChanDev *ch, const do
     rs[OF_UX] += c.nx * ur;
     rs[OF_MOMX] += c.nx * ur;
     if (y == 0) rs[OF_DRAG] -= c.nx * ur / 3.0;
-    if (y == c.ny - 1) rs[OF_DRAG] -= c.nx * ur / 3.0;
+    if (y == c.ny - 1) rs[OF_DRAG] -= c.nx * ur / (c.zh ? 6.0 : 3.0);
     double *dst = prof + ((long long)c.row_off + y) * OF_COUNT;
 #pragma unroll
     for (int f = 0; f < OF_COUNT; ++f) {
@@ -1740,7 +1814,7 @@ __global__ void __launch_bounds__(kSafThreads) saf_fused_kernel(const double *__
   const long long t = c.t + k;
   const double g = (t < c.t_startup) ? c.g : 0.0;
   const double uwg = (t < c.t_startup) ? c.uw : 0.0;
-  const double uw6 = (t >= 1 && t - 1 < c.t_startup) ? c.uw / 6.0 : 0.0;
+  const double uw6 = (!c.zh && t >= 1 && t - 1 < c.t_startup) ? c.uw / 6.0 : 0.0;
   const Coef<double> cf(c);
   const double *__restrict__ Ac = A + c.off * kPlanes;
   double *__restrict__ Bc = B + c.off * kPlanes;
@@ -1896,7 +1970,7 @@ __global__ void __launch_bounds__(256) saf_observe_kernel(const double *__restri
     acc[OF_MOMX] += mx;
     acc[OF_KXY] += kxy;
     acc[OF_TRT] += Tn[n] + Tn[2 * plane + n];
-    acc[OF_DRAG] += wall_drag<double>(f, q.y, c.ny, uw6);
+    acc[OF_DRAG] += wall_drag<double>(f, q.y, c.ny, uw6, false, 0.0);
     acc[OF_KXX] += kxx;
   }
 #pragma unroll

@@ -52,15 +52,14 @@ std::string validate(const lb_channel *c, int n, const lb_options *o) {
   if (!c || n <= 0) return "no channels";
   if (!o) return "options are NULL";
   if (o->precision != LB_FP64 && o->precision != LB_FP32_SHIFTED) return "unknown precision";
-  if (o->nn_pressure != 0 && o->nn_pressure != 1) return "nn_pressure must be 0 or 1";
   if (o->obs_every < 0 || (o->obs_every > 0 && (o->obs_every < 2 || (o->obs_every & 1))))
     return "obs_every must be 0 or an even number >= 2";
   if (o->strip_rows < 0 || o->strip_rows > 4096) return "strip_rows out of range";
   if (!(o->steady_tol >= 0) || !std::isfinite(o->steady_tol)) return "steady_tol must be >= 0";
   if (o->viscoelastic != 0 && o->viscoelastic != 1) return "viscoelastic must be 0 or 1";
   if (o->stress_force != 0 && o->stress_force != 1) return "stress_force must be 0 or 1";
-  if (o->stress_force && (o->precision != LB_FP64 || o->nn_pressure || o->viscoelastic))
-    return "stress_force needs FP64, nn_pressure = 0 and the instantaneous model";
+  if (o->stress_force && (o->precision != LB_FP64 || o->viscoelastic))
+    return "stress_force needs FP64 and the instantaneous model";
   for (int i = 0; i < n; ++i) {
     const lb_channel &q = c[i];
     char buf[160];
@@ -80,9 +79,14 @@ std::string validate(const lb_channel *c, int n, const lb_options *o) {
     if (q.visc_split > 0 && std::isinf(q.tau0)) return bad("visc_split > 0 needs a finite tau0");
     if (!(std::fabs(q.wall_velocity) < 0.3)) return bad("wall_velocity must be finite with |u_w| < 0.3");
     if (!std::isfinite(q.pressure_gradient)) return bad("pressure_gradient must be finite");
-    if (q.pressure_gradient != 0 && (q.force != 0 || q.wall_velocity != 0 || q.nx < 2 || o->nn_pressure))
+    if (q.nn_pressure != 0 && q.nn_pressure != 1) return bad("nn_pressure must be 0 or 1");
+    if (q.top_wall != LB_WALL_HALFWAY && q.top_wall != LB_WALL_ZOU_HE) return bad("unknown top_wall");
+    if (q.top_wall == LB_WALL_ZOU_HE && (q.ny < 2 || q.pressure_gradient != 0 || o->stress_force))
+      return bad("a Zou-He top wall needs ny >= 2, no pressure_gradient and no stress_force");
+    if (q.pressure_gradient != 0 && (q.force != 0 || q.wall_velocity != 0 || q.nx < 2 || q.nn_pressure))
       return bad("pressure_gradient needs force = 0, wall_velocity = 0, nx >= 2 and nn_pressure = 0");
     if (q.pressure_gradient != 0 && o->stress_force) return bad("pressure_gradient is not combined with stress_force");
+    if (o->stress_force && q.nn_pressure) return bad("stress_force needs nn_pressure = 0");
     if (o->stress_force && align_up((size_t)q.nx * q.ny, kTile) * kPlanes > 0xffffffffull)
       return bad("stress_force needs nx * ny <= 429,496,704 per channel");
   }
@@ -112,15 +116,37 @@ void resolve(const lb_channel &q, ChanDev &d) {
   d.uw = q.wall_velocity;
   d.gpbc = q.pressure_gradient != 0;
   d.pd = (q.nx + 1) * q.pressure_gradient;
+  d.nnp = q.nn_pressure;
+  d.zh = q.top_wall == LB_WALL_ZOU_HE;
 }
 
 // Term the pull adds to population i of a top-row node at step t: the link
-// reflected at the moving wall during step t - 1 gained -2 a c_x u_w / cs2
-// (a and c of the outgoing population opp(i)); only i = 7, 8 are affected.
+// reflected at the moving half-way wall during step t - 1 gained
+// -2 a c_x u_w / cs2 (a and c of the outgoing population opp(i)); only i = 7,
+// 8 are affected (none at a Zou-He wall, which completes them instead).
 double wall_pull_term(const lb_channel &q, int i, long long t) {
-  const double uw = (t >= 1 && t - 1 < q.t_startup) ? q.wall_velocity : 0.0;
+  const double uw = (q.top_wall == LB_WALL_HALFWAY && t >= 1 && t - 1 < q.t_startup) ? q.wall_velocity : 0.0;
   const int o = HOPP[i];
   return -6.0 * hweight(o) * HCX[o] * uw;
+}
+
+// Zou-He completion (the kernels' zou_he_top) of the top row's populations
+// entering from above, on a host copy of a channel's state at step t:
+// no flow through the wall, n4 = n2, and the diagonals such that
+// (m + f/2)/s is the wall velocity of step t.
+void host_zou_he_top(const lb_channel &q, long long t, double *pops) {
+  const size_t N = (size_t)q.nx * q.ny;
+  const double uw = t < q.t_startup ? q.wall_velocity : 0.0, fx = t < q.t_startup ? q.force : 0.0;
+  for (int x = 0; x < q.nx; ++x) {
+    const size_t id = (size_t)(q.ny - 1) * q.nx + x;
+    double f[9];
+    for (int i = 0; i < 9; ++i) f[i] = pops[(size_t)i * N + id];
+    const double s = (f[0] + f[1] + f[3]) + 2.0 * (f[2] + f[5] + f[6]);
+    const double d87 = (s * uw - 0.5 * fx) - ((f[1] - f[3]) + (f[5] - f[6]));
+    pops[4 * N + id] = f[2];
+    pops[8 * N + id] = 0.5 * ((f[5] + f[6]) + d87);
+    pops[7 * N + id] = 0.5 * ((f[5] + f[6]) - d87);
+  }
 }
 
 int strip_rows_for(int cls, int nx, int ny, int requested) {
@@ -361,7 +387,6 @@ SweepArgs sweep_args(lb_handle *h, const Strip *strips, int begin, int count, in
   a.n_strips = count;
   a.n_wg = (count + kWaves - 1) / kWaves;
   a.k = k;
-  a.nnp = h->opt.nn_pressure;
   a.nt = (long long)kPlanes * h->L.plane * h->L.esize > kNontemporalBytes;
   a.uref = h->duref;
   a.ve = h->opt.viscoelastic;
@@ -494,11 +519,18 @@ lb_status check_steady(lb_handle *h) {
                              hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(h, hipStreamSynchronize(h->stream));
   h->obs_valid = true;
-  bool changed = false, unstable = false;
+  // NaN/Inf first: report it before anything is frozen, so that host and
+  // device keep the same active channels and step counters
+  for (int i = 0; i < h->n_ch; ++i)
+    if (h->active[i] && h->hscal[(size_t)i * CS_COUNT + CS_NAN] != 0.0) {
+      char buf[96];
+      snprintf(buf, sizeof buf, "NaN/Inf seen in channel %d during a convergence check", i);
+      return fail(h, LB_EUNSTABLE, buf);
+    }
+  bool changed = false;
   for (int i = 0; i < h->n_ch; ++i) {
     if (!h->active[i]) continue;
     const double *s = &h->hscal[(size_t)i * CS_COUNT];
-    if (s[CS_NAN] != 0.0) unstable = true;
     if (!first && s[CS_RESIDUAL] < h->opt.steady_tol) {
       h->active[i] = 0;
       h->L.ch[i].active = 0;
@@ -507,7 +539,6 @@ lb_status check_steady(lb_handle *h) {
       if (m != LB_OK) return m;
     }
   }
-  if (unstable) return fail(h, LB_EUNSTABLE, "NaN/Inf seen in a channel during a convergence check");
   if (changed) {
     // publish the active flags and the new work list, then recapture
     std::vector<ChanDev> cur(h->n_ch);
@@ -817,14 +848,24 @@ lb_status lb_get_state(lb_handle *h, int32_t ch, double *pops, double *P) {
       }
       P[id] = at(9, id);
     }
+  if (d.zh) host_zou_he_top(h->in[ch], h->t[ch], pops);
   return LB_OK;
 }
 
-lb_status lb_set_state(lb_handle *h, int32_t ch, const double *pops, const double *P, int64_t t) {
+lb_status lb_set_state(lb_handle *h, int32_t ch, const double *pops_in, const double *P, int64_t t) {
   if (!h) return LB_EINVAL;
-  if (ch < 0 || ch >= h->n_ch || !pops || !P || t < 0) return fail(h, LB_EINVAL, "bad arguments");
+  if (ch < 0 || ch >= h->n_ch || !pops_in || !P || t < 0) return fail(h, LB_EINVAL, "bad arguments");
   const ChanDev &d = h->L.ch[ch];
   const size_t N = (size_t)d.nx * d.ny;
+  // a Zou-He top wall replaces what enters its row from above (the next step
+  // completes it; completing it here keeps the FP32 row reference consistent)
+  std::vector<double> zcopy;
+  const double *pops = pops_in;
+  if (d.zh) {
+    zcopy.assign(pops_in, pops_in + 9 * N);
+    host_zou_he_top(h->in[ch], t, zcopy.data());
+    pops = zcopy.data();
+  }
   const size_t Npad = align_up(N, kTile);
   const int es = h->L.esize;
   // start from the device copy so the padding slots of the last tile keep
@@ -1000,7 +1041,9 @@ lb_status lb_set_profile(lb_handle *h, int32_t ch, const double *ux, const doubl
   const size_t N = (size_t)d.nx * d.ny;
   std::vector<double> pops(9 * N), P(N);
   for (int y = 0; y < d.ny; ++y) {
-    const double rho = 1.0 - 1.5 * q[y];
+    // with the flow-induced density the conserved mass is sum (s + 3/2 P);
+    // without it, sum s
+    const double rho = d.nnp ? 1.0 - 1.5 * q[y] : 1.0;
     const double usq = u[y] * u[y];
     for (int x = 0; x < d.nx; ++x) {
       const size_t id = (size_t)y * d.nx + x;

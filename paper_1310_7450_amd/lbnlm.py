@@ -31,17 +31,19 @@ ABI_FUNCTIONS = ["lb_workspace_bytes", "lb_create", "lb_destroy", "lb_step", "lb
                  "lb_last_error", "lb_status_string"]
 
 
+TOP_WALLS = {"halfway": 0, "zou_he": 1}
+
+
 class LbChannel(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("force", C.c_double), ("tau_lb", C.c_double),
                 ("G", C.c_double), ("tau0", C.c_double), ("gamma_c", C.c_double), ("eps", C.c_double),
                 ("visc_split", C.c_double), ("t_startup", C.c_int64), ("wall_velocity", C.c_double),
-                ("pressure_gradient", C.c_double)]
+                ("pressure_gradient", C.c_double), ("nn_pressure", C.c_int32), ("top_wall", C.c_int32)]
 
 
 class LbOptions(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("nn_pressure", C.c_int32), ("obs_every", C.c_int32),
-                ("strip_rows", C.c_int32), ("steady_tol", C.c_double), ("viscoelastic", C.c_int32),
-                ("stress_force", C.c_int32)]
+    _fields_ = [("precision", C.c_int32), ("obs_every", C.c_int32), ("strip_rows", C.c_int32),
+                ("steady_tol", C.c_double), ("viscoelastic", C.c_int32), ("stress_force", C.c_int32)]
 
 
 class LbError(RuntimeError):
@@ -85,7 +87,9 @@ def load_library():
 
 @dataclass
 class ChannelSpec:
-    """Parameters of one channel (lattice units; see ``lb_channel`` in lb.h)."""
+    """Parameters of one channel (lattice units; see ``lb_channel`` in lb.h).
+    ``nn_pressure`` None takes the Solver's default; ``top_wall`` is
+    "halfway" or "zou_he"."""
     nx: int
     ny: int
     force: float
@@ -98,11 +102,17 @@ class ChannelSpec:
     t_startup: int = 2 ** 62
     wall_velocity: float = 0.0
     pressure_gradient: float = 0.0
+    nn_pressure: Optional[bool] = None
+    top_wall: str = "halfway"
 
-    def to_c(self):
+    def resolved_nn_pressure(self, default=True):
+        return bool(default if self.nn_pressure is None else self.nn_pressure)
+
+    def to_c(self, default_nn_pressure=True):
         return LbChannel(int(self.nx), int(self.ny), float(self.force), float(self.tau_lb), float(self.G),
                          float(self.tau0), float(self.gamma_c), float(self.eps), float(self.visc_split),
-                         int(self.t_startup), float(self.wall_velocity), float(self.pressure_gradient))
+                         int(self.t_startup), float(self.wall_velocity), float(self.pressure_gradient),
+                         int(self.resolved_nn_pressure(default_nn_pressure)), TOP_WALLS[self.top_wall])
 
 
 def _dp(a):
@@ -110,17 +120,20 @@ def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def options(precision=FP64, nn_pressure=True, obs_every=1000, strip_rows=0, steady_tol=0.0, viscoelastic=False,
-            stress_force=False):
+def options(precision=FP64, obs_every=1000, strip_rows=0, steady_tol=0.0, viscoelastic=False, stress_force=False):
     if isinstance(precision, str):
         precision = {"fp64": FP64, "fp32": FP32_SHIFTED, "fp32_shifted": FP32_SHIFTED}[precision]
-    return LbOptions(int(precision), int(bool(nn_pressure)), int(obs_every), int(strip_rows), float(steady_tol),
-                     int(bool(viscoelastic)), int(bool(stress_force)))
+    return LbOptions(int(precision), int(obs_every), int(strip_rows), float(steady_tol), int(bool(viscoelastic)),
+                     int(bool(stress_force)))
 
 
-def workspace_bytes(channels: Sequence[ChannelSpec], opts: LbOptions) -> int:
+def channel_array(channels: Sequence[ChannelSpec], default_nn_pressure=True):
+    return (LbChannel * len(channels))(*[c.to_c(default_nn_pressure) for c in channels])
+
+
+def workspace_bytes(channels: Sequence[ChannelSpec], opts: LbOptions, default_nn_pressure=True) -> int:
     L = load_library()
-    arr = (LbChannel * len(channels))(*[c.to_c() for c in channels])
+    arr = channel_array(channels, default_nn_pressure)
     out = C.c_size_t(0)
     st = L.lb_workspace_bytes(arr, len(channels), C.byref(opts), C.byref(out))
     if st != 0:
@@ -130,10 +143,11 @@ def workspace_bytes(channels: Sequence[ChannelSpec], opts: LbOptions) -> int:
 
 class Solver:
     """A handle of the C library over ``channels``, on one CUDA/HIP stream.
-    ``viscoelastic`` selects the time-integrated nonlinear Maxwell stress
-    (lb_options.viscoelastic) in place of the instantaneous one;
-    ``stress_force`` makes the stress enter as the force density div Sigma^nN
-    (lb_options.stress_force; FP64, nn_pressure False)."""
+    ``nn_pressure`` is the value of lb_channel.nn_pressure for every channel
+    whose spec leaves it None. ``viscoelastic`` selects the time-integrated
+    nonlinear Maxwell stress (lb_options.viscoelastic) in place of the
+    instantaneous one; ``stress_force`` makes the stress enter as the force
+    density div Sigma^nN (lb_options.stress_force; FP64, nn_pressure False)."""
 
     def __init__(self, channels: Sequence[ChannelSpec], precision="fp64", nn_pressure=True,
                  obs_every=1000, strip_rows=0, steady_tol=0.0, stream=None, device="cuda", viscoelastic=False,
@@ -143,14 +157,15 @@ class Solver:
             raise RuntimeError("lbnlm needs a GPU; no CPU fallback exists")
         self.L = load_library()
         self.channels = list(channels)
-        self.opts = options(precision, nn_pressure, obs_every, strip_rows, steady_tol, viscoelastic, stress_force)
-        nbytes = workspace_bytes(self.channels, self.opts)
+        self.opts = options(precision, obs_every, strip_rows, steady_tol, viscoelastic, stress_force)
+        self.default_nn_pressure = bool(nn_pressure)
+        nbytes = workspace_bytes(self.channels, self.opts, self.default_nn_pressure)
         self.device = torch.device(device)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         ptr = self.workspace.data_ptr()
         aligned = (ptr + 255) // 256 * 256
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
-        arr = (LbChannel * len(self.channels))(*[c.to_c() for c in self.channels])
+        arr = channel_array(self.channels, self.default_nn_pressure)
         h = C.c_void_p()
         st = self.L.lb_create(arr, len(self.channels), C.byref(self.opts), C.c_void_p(aligned),
                               nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h))

@@ -76,32 +76,66 @@ def targets(specs, profiles):
     return Y
 
 
+# Bounds put on a prediction before it initialises a run: the batch admits
+# channels whose solvent Poiseuille velocity is at most U_SOLVENT_MAX (low
+# Mach number), and the warm density 1 - (3/2) N1 must stay close to 1.
+U_WARM_MAX = workloads.U_SOLVENT_MAX
+N1_WARM_MAX = 1e-2
+
+
 def solve_to_steady(specs, precision="fp32", max_steps=3_000_000, strip_rows=None, warm=None, tol=1e-9):
     """Runs every channel to its steady state (residual < tol) in one handle.
-    ``warm`` optionally gives (u_x, N1) at the Chebyshev points per channel;
-    ``strip_rows`` None takes the autotuner's choice for a run to steady
-    state. Returns the row profiles (u_x, sigma_xy, N1), the steps each
-    channel took and the wall time."""
+    ``warm`` optionally gives (u_x, N1) at the Chebyshev points per channel,
+    clipped to the low-Mach range before use; ``strip_rows`` None takes the
+    autotuner's choice for a run to steady state. A convergence check that
+    sees NaN/Inf (LB_EUNSTABLE) restarts the offending channels from rest in
+    the same handle; their wasted steps count with their run. Returns the row
+    profiles (u_x, sigma_xy, N1), the steps each channel took, which channels
+    froze, which were restarted from rest and the wall time."""
+    from .lbnlm import LbError
     if strip_rows is None:
         from . import autotune
         strip_rows = autotune.tune_strip_rows(specs, precision, steps=200, to_steady=True)
     t0 = time.perf_counter()
+    n = len(specs)
+    restarted = np.zeros(n, dtype=bool)
+    wasted = np.zeros(n, dtype=np.int64)
     with Solver(specs, precision=precision, obs_every=1000, steady_tol=tol, strip_rows=strip_rows) as s:
         if warm is not None:
             for i, (u, n1) in enumerate(warm):
+                u = np.clip(np.asarray(u, dtype=np.float64), -U_WARM_MAX, U_WARM_MAX)
+                n1 = np.clip(np.asarray(n1, dtype=np.float64), -N1_WARM_MAX, N1_WARM_MAX)
                 s.set_profile(i, u, n1, points="chebyshev")
-        s.step(max_steps)
-        steps = np.array([int(s.observe(i, "step")) for i in range(len(specs))])
-        frozen = np.array([s.observe(i, "active") == 0 for i in range(len(specs))])
-        prof = [(s.observe(i, "ux"), s.observe(i, "sxy"), s.observe(i, "n1")) for i in range(len(specs))]
-    return prof, steps, frozen, time.perf_counter() - t0
+        done = 0
+        while done < max_steps:
+            try:
+                s.step(max_steps - done)
+                break
+            except LbError as e:
+                if e.status != -4:  # LB_EUNSTABLE
+                    raise
+                bad = [i for i in range(n) if s.observe(i, "nan") != 0.0]
+                if not bad:
+                    raise
+                done = max(int(s.observe(i, "step")) + int(wasted[i]) for i in range(n))
+                for i in bad:
+                    c = specs[i]
+                    t_i = int(s.observe(i, "step"))
+                    wasted[i] += t_i
+                    restarted[i] = True
+                    s.set_state(i, np.broadcast_to(workloads.REST_WEIGHTS[:, None, None], (9, c.ny, c.nx)).copy(),
+                                np.zeros((c.ny, c.nx)), 0)
+        steps = np.array([int(s.observe(i, "step")) for i in range(n)]) + wasted
+        frozen = np.array([s.observe(i, "active") == 0 for i in range(n)])
+        prof = [(s.observe(i, "ux"), s.observe(i, "sxy"), s.observe(i, "n1")) for i in range(n)]
+    return prof, steps, frozen, restarted, time.perf_counter() - t0
 
 
 def generate(seeds, n_per_seed=256, verbose=True):
     specs = []
     for sd in seeds:
         specs += workloads.batched_sweep(seed=sd, n_channels=n_per_seed)["channels"]
-    prof, steps, frozen, wall = solve_to_steady(specs)
+    prof, steps, frozen, _, wall = solve_to_steady(specs)
     if verbose:
         print(f"warmstart: {len(specs)} training states, {frozen.sum()} steady, {wall:.1f} s", file=sys.stderr,
               flush=True)
@@ -179,13 +213,14 @@ def experiment(train_seeds=range(100, 116), test_seed=200, n_per_seed=256, train
     if n_test is not None:
         test = test[:n_test]
     pred = predict(net, norm, test)
-    prof_w, steps_w, frozen_w, wall_w = solve_to_steady(test, warm=[(u, n1) for u, _, n1 in pred])
-    prof_r, steps_r, frozen_r, wall_r = solve_to_steady(test)
+    prof_w, steps_w, frozen_w, restarted_w, wall_w = solve_to_steady(test, warm=[(u, n1) for u, _, n1 in pred])
+    prof_r, steps_r, frozen_r, _, wall_r = solve_to_steady(test)
     # the solver judges: warm and rest converged profiles must agree (a run
     # stopped at residual R is up to about R / (slowest decay rate) from its
-    # fixed point, 1e-4..1e-3 of u_x for the widest channels)
+    # fixed point, 1e-4..1e-3 of u_x for the widest channels); a warm run the
+    # solver had to restart from rest is a fallback too
     err = np.array([np.abs(pw[0] - pr[0]).max() / np.abs(pr[0]).max() for pw, pr in zip(prof_w, prof_r)])
-    ok = (err <= agree_tol) & frozen_w
+    ok = (err <= agree_tol) & frozen_w & ~restarted_w
     used = np.where(ok, steps_w, steps_r + steps_w)  # a fallback pays for both runs
     pred_err = []
     for c, p, pr in zip(test, pred, prof_r):
@@ -201,7 +236,7 @@ def experiment(train_seeds=range(100, 116), test_seed=200, n_per_seed=256, train
         "steps_ratio_rest_over_warm": {"median": float(np.median(ratio)),
                                        "geomean": float(np.exp(np.mean(np.log(ratio))))},
         "steps_with_fallback_total": int(used.sum()),
-        "fallbacks": int((~ok).sum()), "agree_tol": agree_tol,
+        "fallbacks": int((~ok).sum()), "restarted_unstable": int(restarted_w.sum()), "agree_tol": agree_tol,
         "final_linf_rel_ux_warm_vs_rest": {"median": float(np.median(err)), "max": float(np.max(err))},
         "seconds": {"generate": round(t_gen, 1), "train": round(t_train, 1), "warm_run": round(wall_w, 1),
                     "rest_run": round(wall_r, 1)},
@@ -209,6 +244,7 @@ def experiment(train_seeds=range(100, 116), test_seed=200, n_per_seed=256, train
     if details:
         return rep, {"test": test, "pred": pred, "prof_warm": prof_w, "prof_rest": prof_r, "steps_warm": steps_w,
                      "steps_rest": steps_r, "frozen_warm": frozen_w, "frozen_rest": frozen_r, "ok": ok,
+                     "restarted_warm": restarted_w,
                      "err_warm_vs_rest": err}
     return rep
 

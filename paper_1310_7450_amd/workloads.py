@@ -15,13 +15,15 @@ Named workloads (lattice units, rho0 = 1):
   10,000 steps from rest.
 * ``batched_sweep``: 256 channels, nx = 8, per channel in order
   ny ~ U{32..512}, log10 g ~ U(-7, -5), eps ~ U(-0.1, 0.1),
-  log10 tau0 ~ U(3, 5), from seed 2 (see the function for the admission
-  rules).
+  log10 tau0 ~ U(3, 5), from seed 2 (see the function for the low-Mach
+  rule and the conditioning policy of stiff draws); ``batched_sample``
+  picks a width-stratified sample of it.
 * ``transient_scale``: 16 channels of 8192 x 2048, 8 at eps = 0 and 8 at
   eps = +0.02, g = 2 G gamma_c / H (wp H = 2 gamma_c), 50,000 start-up steps
   then cessation.
-* ``couette_64``: planar Couette flow, 8 x 64, top wall at u0 switched on and
-  off, theta = 100 (the paper's Fig. stopshear parameters in lattice units).
+* ``couette_64``: planar Couette flow, 8 x 64, Zou and He's top wall at u0
+  switched on and off, theta = 100 (the paper's Fig. stopshear parameters in
+  lattice units).
 """
 import numpy as np
 
@@ -78,12 +80,17 @@ def random_stress(nx, ny, seed, amplitude=1e-6):
     return np.ascontiguousarray(amplitude * rng.uniform(-1, 1, size=(3, ny, nx)))
 
 
-# Admission rules of the batched sweep (input recipe; see the design notes):
-# the explicit stress is well conditioned for G_inf tau <= 0.3 at
-# visc_split 0 (a measured stability map of the scheme), and the low-Mach
-# limit asks for a solvent-viscosity Poiseuille velocity g H^2 / (2 eta_s)
-# of at most 0.1.
-GTAU_MAX = 0.3
+# Rules of the batched sweep (input recipe; see the design notes). Low Mach
+# number: a draw whose solvent-viscosity Poiseuille velocity g H^2 / (2 eta_s)
+# exceeds 0.1 is redrawn (the nlM fluid only adds viscosity, so its velocity
+# is lower still). Conditioning: the explicit stress with the flow-induced
+# density terms and visc_split 0 (the configuration as written) amplifies
+# round-off once G_inf tau exceeds about 0.3-0.5 (a measured stability map of
+# the scheme); a draw above GTAU_LITERAL_MAX runs instead with the viscosity
+# split of Sec. IV at STIFF_SPLIT and without the delta-rho terms, which the
+# same map shows well conditioned over the whole box (G_inf tau up to 13).
+GTAU_LITERAL_MAX = 0.3
+STIFF_SPLIT = 0.5
 U_SOLVENT_MAX = 0.1
 
 
@@ -94,25 +101,45 @@ def _closure(tau0, eps, G=1e-4):
 
 def batched_sweep(seed=2, n_channels=256, nx=8, tau_lb=1.0, G=1e-4, gamma_c=0.1):
     """Channels drawn in order ny ~ U{32..512}, log10 g ~ U(-7,-5),
-    eps ~ U(-0.1, 0.1), log10 tau0 ~ U(3, 5) from ``seed``; a draw is kept if
-    G_inf tau <= GTAU_MAX and g (ny/2)^2 / (2 eta_s) <= U_SOLVENT_MAX,
-    otherwise redrawn. Returns the channels and the number of draws."""
+    eps ~ U(-0.1, 0.1), log10 tau0 ~ U(3, 5) from ``seed``; a draw with
+    g (ny/2)^2 / (2 eta_s) > U_SOLVENT_MAX is redrawn. Draws with
+    G_inf tau <= GTAU_LITERAL_MAX run as written (visc_split 0, delta-rho
+    terms on), the others with visc_split STIFF_SPLIT and without the
+    delta-rho terms. Returns the channels, the number of draws and how many
+    channels run in the stiff setting."""
     rng = np.random.default_rng(seed)
     eta_s = (tau_lb - 0.5) / 3.0
-    chans, draws = [], 0
+    chans, draws, stiff = [], 0, 0
     while len(chans) < n_channels:
         ny = int(rng.integers(32, 513))
         g = 10.0 ** rng.uniform(-7.0, -5.0)
         eps = rng.uniform(-0.1, 0.1)
         tau0 = 10.0 ** rng.uniform(3.0, 5.0)
         draws += 1
-        Ginf, tau = _closure(tau0, eps, G)
-        if Ginf * tau > GTAU_MAX or g * (ny / 2.0) ** 2 / (2 * eta_s) > U_SOLVENT_MAX:
+        if g * (ny / 2.0) ** 2 / (2 * eta_s) > U_SOLVENT_MAX:
             continue
+        Ginf, tau = _closure(tau0, eps, G)
+        literal = Ginf * tau <= GTAU_LITERAL_MAX
+        stiff += not literal
         chans.append(ChannelSpec(nx=nx, ny=ny, force=g, tau_lb=tau_lb, G=G, tau0=tau0, gamma_c=gamma_c,
-                                 eps=eps, visc_split=0.0))
-    return {"name": f"batched_sweep_{n_channels}x{nx}", "channels": chans, "draws": draws, "seed": seed,
-            "steady_tol": 1e-9, "obs_every": 1000, "max_steps": 3_000_000}
+                                 eps=eps, visc_split=0.0 if literal else STIFF_SPLIT, nn_pressure=literal))
+    return {"name": f"batched_sweep_{n_channels}x{nx}", "channels": chans, "draws": draws, "stiff": stiff,
+            "seed": seed, "steady_tol": 1e-9, "obs_every": 1000, "max_steps": 3_000_000}
+
+
+def batched_sample(channels, per_decile=3, widest=4):
+    """Indices of a width-stratified sample of a batch: ``per_decile``
+    channels evenly spaced through each tenth of the channels ordered by
+    width, plus the ``widest`` widest ones (sorted, without repeats)."""
+    order = sorted(range(len(channels)), key=lambda i: (channels[i].ny, i))
+    n = len(order)
+    pick = set()
+    for d in range(10):
+        lo, hi = d * n // 10, (d + 1) * n // 10
+        for k in range(per_decile):
+            pick.add(order[lo + (2 * k + 1) * (hi - lo) // (2 * per_decile)])
+    pick.update(order[n - widest:])
+    return sorted(pick)
 
 
 def transient_scale(nx=8192, ny=2048, n_per_eps=8, eps_values=(0.0, 0.02), G=1e-4, tau0=1e4, gamma_c=0.1,
@@ -136,25 +163,35 @@ def transient_scale(nx=8192, ny=2048, n_per_eps=8, eps_values=(0.0, 0.02), G=1e-
             "cessation_cap": 200000, "stop_fraction": 1e-3, "thresholds": (1e-2, 1e-3, 1e-4)}
 
 
+def couette_width(ny, top_wall):
+    """Distance between the fixed half-way wall (y = -1/2) and the moving
+    wall: y = ny - 1/2 for the half-way wall, the node row y = ny - 1 for
+    Zou and He's wall."""
+    return float(ny) if top_wall == "halfway" else ny - 0.5
+
+
 def couette_64(nx=8, ny=64, theta=100.0, tau_lb=0.6, G=1e-3, gamma_c=0.1, wall_u_scale=1e-2, startup=60000,
-               newtonian=False):
+               newtonian=False, top_wall="zou_he"):
     """Planar Couette flow switched on and off (Sec. IV.B, Fig. stopshear):
-    the top wall moves with u0 for ``startup`` steps, then stops. The
-    paper's parameters in lattice units: theta = G tau / eta_s = 100 and
-    u0 = 1e-2 H / tau_mu with tau_mu = eta_s / G and H = ny, i.e.
-    u0 = 1e-2 H G / eta_s (0.0192 here; the wall Peclet number
+    the top wall moves with u0 for ``startup`` steps, then stops. The wall is
+    Zou and He's velocity boundary on the top node row, as in the paper
+    (``top_wall="halfway"`` gives the half-link alternative). The paper's
+    parameters in lattice units: theta = G tau / eta_s = 100 and
+    u0 = 1e-2 L / tau_mu with tau_mu = eta_s / G and L the channel width,
+    i.e. u0 = 1e-2 L G / eta_s (0.0191 here; the wall Peclet number
     gdot tau / gamma_c = 10). tau_lb = 0.6 keeps G tau = 3.3; the viscosity
-    split 1/2 without the delta-rho terms (``nn_pressure = 0`` on the handle)
-    is the well-conditioned setting for it. ``newtonian=True`` gives the
-    solvent alone (G = 0) as a reference."""
+    split 1/2 without the delta-rho terms is the well-conditioned setting for
+    it. ``newtonian=True`` gives the solvent alone (G = 0) as a reference."""
     eta_s = (tau_lb - 0.5) / 3.0
     tau0 = theta * eta_s / G
-    u0 = wall_u_scale * ny * G / eta_s
+    L = couette_width(ny, top_wall)
+    u0 = wall_u_scale * L * G / eta_s
     spec = ChannelSpec(nx=nx, ny=ny, force=0.0, tau_lb=tau_lb, G=0.0 if newtonian else G, tau0=tau0,
                        gamma_c=gamma_c, eps=0.0, visc_split=0.0 if newtonian else 0.5, t_startup=startup,
-                       wall_velocity=u0)
-    return {"name": f"couette_{nx}x{ny}" + ("_newtonian" if newtonian else ""), "channels": [spec],
-            "startup": startup, "cessation": 10000, "nn_pressure": False, "theta": theta}
+                       wall_velocity=u0, nn_pressure=False, top_wall=top_wall)
+    return {"name": f"couette_{nx}x{ny}" + ("_newtonian" if newtonian else "") +
+            ("" if top_wall == "zou_he" else "_halfway"), "channels": [spec],
+            "startup": startup, "cessation": 10000, "nn_pressure": False, "theta": theta, "width": L}
 
 
 def pressure_channel(nx=64, ny=32, pressure_gradient=2e-6, tau_lb=1.0, G=1e-4, tau0=2e3, gamma_c=0.1,

@@ -74,15 +74,44 @@ def test_invalid_options_rejected(L, kw):
         lbnlm.workspace_bytes([spec()], o)
 
 
-@pytest.mark.parametrize("kw", [dict(precision="fp32"), dict(nn_pressure=True), dict(viscoelastic=True)])
+@pytest.mark.parametrize("kw", [dict(precision="fp32"), dict(nn_pressure=True), dict(viscoelastic=True),
+                                dict(top_wall="zou_he")])
 def test_stress_force_combinations_rejected(L, kw):
-    """The stress force needs FP64, no flow-induced density and the
-    instantaneous model."""
-    args = dict(precision="fp64", nn_pressure=False, stress_force=True)
-    args.update(kw)
+    """The stress force needs FP64, no flow-induced density, the
+    instantaneous model and the half-way top wall."""
+    args = dict(precision="fp64", stress_force=True)
+    chan = dict(nn_pressure=False)
+    for k, v in kw.items():
+        (chan if k in ("nn_pressure", "top_wall") else args)[k] = v
     with pytest.raises(lbnlm.LbError) as e:
-        lbnlm.workspace_bytes([spec()], lbnlm.options(**args))
+        lbnlm.workspace_bytes([spec(**chan)], lbnlm.options(**args))
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("bad", [
+    dict(top_wall="zou_he", ny=1), dict(top_wall="zou_he", force=0.0, pressure_gradient=1e-6, nn_pressure=False),
+    dict(pressure_gradient=1e-6, force=0.0, nn_pressure=True),
+])
+def test_wall_and_drive_combinations_rejected(L, bad):
+    """A Zou-He top wall needs two rows and no pressure drive; the pressure
+    drive needs the channel's nn_pressure off."""
+    with pytest.raises(lbnlm.LbError) as e:
+        lbnlm.workspace_bytes([spec(**bad)], lbnlm.options("fp64"))
+    assert e.value.status == -1
+
+
+def test_per_channel_flags_accepted(L):
+    """nn_pressure and the top wall are per channel: one handle may mix
+    them."""
+    chans = [spec(nn_pressure=True), spec(nn_pressure=False, visc_split=0.5),
+             spec(top_wall="zou_he", wall_velocity=0.01, force=0.0), spec(top_wall="zou_he", ny=2)]
+    assert lbnlm.workspace_bytes(chans, lbnlm.options("fp32")) > 0
+    bad = spec()
+    c = bad.to_c()
+    c.top_wall = 5
+    arr = (lbnlm.LbChannel * 1)(c)
+    out = C.c_size_t(0)
+    assert L.lb_workspace_bytes(arr, 1, C.byref(lbnlm.options()), C.byref(out)) == -1
 
 
 def test_stress_force_channel_size_limit(L):
@@ -90,11 +119,11 @@ def test_stress_force_channel_size_limit(L):
     offsets: 4096 x 104,857 nodes (429,494,272) is accepted, 4096 x 104,961
     (beyond 429,496,704) is rejected; the same sizes without the stress
     force are accepted (FP64 channels beyond the limit step on strips)."""
-    o = lbnlm.options("fp64", nn_pressure=False, stress_force=True)
+    o = lbnlm.options("fp64", stress_force=True)
     state = 2 * 10 * 4096 * 104_857 * 8
-    assert lbnlm.workspace_bytes([spec(nx=4096, ny=104_857)], o) >= state
+    assert lbnlm.workspace_bytes([spec(nx=4096, ny=104_857, nn_pressure=False)], o) >= state
     with pytest.raises(lbnlm.LbError) as e:
-        lbnlm.workspace_bytes([spec(nx=4096, ny=104_961)], o)
+        lbnlm.workspace_bytes([spec(nx=4096, ny=104_961, nn_pressure=False)], o)
     assert e.value.status == -1
     assert lbnlm.workspace_bytes([spec(nx=4096, ny=104_961)], lbnlm.options("fp64")) > state
 

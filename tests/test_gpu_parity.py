@@ -37,9 +37,11 @@ def linf(a, b):
 
 
 def oracle_channel(orc, spec, nn_pressure=True):
+    nnp = spec.nn_pressure if spec.nn_pressure is not None else nn_pressure
     return orc.Channel(spec.nx, spec.ny, spec.force, tau_lb=spec.tau_lb, G=spec.G, tau0=spec.tau0,
                        gamma_c=spec.gamma_c, eps=spec.eps, visc_split=spec.visc_split,
-                       t_startup=spec.t_startup, nn_pressure=nn_pressure, wall_velocity=spec.wall_velocity)
+                       t_startup=spec.t_startup, nn_pressure=nnp, wall_velocity=spec.wall_velocity,
+                       top_wall=spec.top_wall)
 
 
 def compare_fields(s, ch, o, tol, label):
@@ -109,7 +111,8 @@ def test_poiseuille_fp32_shifted(orc):
 
 
 @pytest.mark.parametrize("nx,ny", [(1, 16), (2, 9), (4, 33), (16, 20), (64, 7), (3, 12), (100, 37), (130, 5), (63, 2),
-                                   (8, 1), (128, 9), (192, 5), (256, 3), (128, 1), (384, 2), (65, 6), (66, 3)])
+                                   (8, 1), (128, 9), (192, 5), (256, 3), (128, 1), (384, 2), (65, 6), (66, 3),
+                                   (512, 9), (768, 11)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_perturbed_state_parity(orc, nx, ny, precision):
     """Seeded random populations (every moment non-zero, x gradients present)
@@ -120,7 +123,10 @@ def test_perturbed_state_parity(orc, nx, ny, precision):
     FP64 the widths that are not powers of two run on 64 x 8 tiles: 3, 63
     and 65 wrap their halo columns by a modulo (65: a second tile of one
     column), 66 and up by one add or subtract, and 100, 130 end in a
-    partial tile."""
+    partial tile. In FP32, 512 and 768 run two and three 256-column vector
+    strips per row band, with strips of 4 rows stacked four to a workgroup
+    and every other band marching the other way, so the x halo between
+    strips and the flipped marches meet a state with x gradients."""
     spec = ChannelSpec(nx=nx, ny=ny, force=3e-6, tau_lb=0.8, G=2e-4, tau0=500.0, gamma_c=0.1,
                        eps=0.01, visc_split=0.3, t_startup=40)
     pops, P = workloads.random_state(nx, ny, seed=nx * 1000 + ny)
@@ -268,10 +274,12 @@ def test_frozen_channel_survives_odd_steps(precision, nx):
         assert np.abs(pops - pops1).max() < (1e-16 if precision == "fp64" else 1e-9)
 
 
-def test_warm_start_profile_state():
+@pytest.mark.parametrize("nnp", [True, False])
+def test_warm_start_profile_state(nnp):
     """lb_set_profile writes equilibrium populations at the given u_x with
-    rho_e = 1 - (3/2) N1 and P = N1, keeping the rest-state mass."""
-    spec = ChannelSpec(4, 24, 1e-6, 1.0, 1e-4, 1e3, 0.1)
+    rho_e = 1 - (3/2) N1 (rho_e = 1 without the flow-induced density) and
+    P = N1, keeping the rest-state mass."""
+    spec = ChannelSpec(4, 24, 1e-6, 1.0, 1e-4, 1e3, 0.1, nn_pressure=nnp)
     ux = 1e-3 * np.sin(np.linspace(0.1, 3.0, 24))
     n1 = 1e-6 * np.cos(np.linspace(0, 2, 24))
     with solver([spec], precision="fp64") as s:
@@ -279,7 +287,7 @@ def test_warm_start_profile_state():
         pops, P = s.get_state(0)
         assert np.allclose(P, n1[:, None], rtol=0, atol=1e-20)
         rho = pops.sum(axis=0)
-        assert np.allclose(rho, (1 - 1.5 * n1)[:, None], rtol=1e-14)
+        assert np.allclose(rho, ((1 - 1.5 * n1) if nnp else np.ones(24))[:, None], rtol=1e-14)
         mx = (pops[[1, 5, 8]].sum(axis=0) - pops[[3, 6, 7]].sum(axis=0))
         assert np.allclose(mx / rho, ux[:, None], rtol=1e-12, atol=1e-18)
         assert s.observe(0, "mass") == pytest.approx(96.0, rel=1e-14)
@@ -352,9 +360,11 @@ def test_batched_sweep_fp32_reaches_fp64_steady_state(orc):
     within 5e-5 of max |u_x|: a frozen profile still moves at < 1e-9 max|u|
     per step, and the slowest channel relaxes over ~4e4 steps (H^2 / (pi^2 nu),
     H = 255, nu = 1/6). FP32 resolves the slow last stretch of convergence.
-    The FP64 profiles are within 2e-3 of the analytic steady profile of
-    Sec. III.B: the lattice discretisation error, largest in the narrowest
-    channels."""
+    Channels run as configured (G tau <= 0.3) have FP64 profiles within
+    2e-3 of the analytic steady profile of Sec. III.B: the lattice
+    discretisation error, largest in the narrowest channels. Stiff channels
+    (viscosity split 1/2: relaxation times up to about 20) carry the larger
+    wall error of BGK at such relaxation times; theirs is reported."""
     from oracle import analytic
     wl = workloads.batched_sweep()
     chans = wl["channels"]
@@ -373,27 +383,53 @@ def test_batched_sweep_fp32_reaches_fp64_steady_state(orc):
         d32.append(np.abs(prof["fp32"][i] - u64).max() / np.abs(u64).max())
         e64.append(np.abs(u64 - ua).max() / np.abs(ua).max())
     d32, e64 = np.array(d32), np.array(e64)
+    lit = np.array([c.visc_split == 0.0 for c in chans])
+    print(f"FP32 vs FP64 steady: median {np.median(d32):.2e} max {d32.max():.2e}; FP64 vs analytic: "
+          f"as configured ({lit.sum()}) median {np.median(e64[lit]):.2e} max {e64[lit].max():.2e}, "
+          f"stiff ({(~lit).sum()}) median {np.median(e64[~lit]):.2e} max {e64[~lit].max():.2e}", flush=True)
     assert d32.max() < 5e-5 and np.median(d32) < 1e-6, (d32.max(), np.median(d32))
-    assert e64.max() < 2e-3 and np.median(e64) < 2e-4, (e64.max(), np.median(e64))
+    assert e64[lit].max() < 2e-3 and np.median(e64[lit]) < 2e-4, (e64[lit].max(), np.median(e64[lit]))
 
 
-def test_batched_sweep_subset_to_steady(orc):
-    """The first 24 channels of the batched sweep (nx = 8, ragged widths and
-    parameters) in one FP32 handle, each frozen at residual < 1e-9: all
-    converge, and the four narrowest match oracle runs of the same length
-    within the FP32 tolerance."""
-    import dataclasses
+def load_batched_fixture():
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_batched_oracle.py")
+    spec = importlib.util.spec_from_file_location("make_batched_oracle", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.load()
+
+
+def test_batched_sweep_per_channel_error_vs_oracle():
+    """The batched sweep as configured (256 channels of nx = 8, widths
+    32..512, forces, eps and tau0 over the whole box; stiff draws with the
+    viscosity split 1/2 and no delta-rho terms) in one FP32 handle, run until
+    every channel's residual is below 1e-9: every channel converges, and for
+    a width-stratified sample of 34 channels (three per width decile and the
+    four widest) the steady u_x and sigma_xy equal the FP64 oracle's steady
+    state from rest (tests/golden/batched_sweep_seed2_oracle.txt) within the
+    FP32 tolerance 1e-3 (L-infinity relative per channel), after the same
+    number of steps to within two checks."""
     wl = workloads.batched_sweep()
-    chans = wl["channels"][:24]
-    with solver(chans, precision="fp32", obs_every=1000, steady_tol=1e-9, strip_rows=64) as s:
+    chans = wl["channels"]
+    ref = load_batched_fixture()
+    assert sorted(ref) == workloads.batched_sample(chans)
+    with solver(chans, precision="fp32", obs_every=1000, steady_tol=1e-9, strip_rows=16) as s:
         s.step(3_000_000)
         steps = [int(s.observe(i, "step")) for i in range(len(chans))]
         assert all(s.observe(i, "active") == 0 for i in range(len(chans))), steps
-        order = np.argsort([c.ny for c in chans])[:4]
-        for i in order:
-            o = oracle_channel(orc, dataclasses.replace(chans[i], nx=1))
-            o.run(steps[i])
-            compare_fields(s, int(i), o, FP32_TOL, f"batched ny={chans[i].ny} steps={steps[i]}")
+        eu, es = [], []
+        for i, (t_o, u_o, s_o) in sorted(ref.items()):
+            u, sx = s.observe(i, "ux"), s.observe(i, "sxy")
+            eu.append(linf(u, u_o))
+            es.append(linf(sx, s_o))
+            print(f"channel {i} ny {chans[i].ny} split {chans[i].visc_split}: steps {steps[i]} (oracle {t_o}); "
+                  f"u_x {eu[-1]:.2e} sigma_xy {es[-1]:.2e}", flush=True)
+            assert abs(steps[i] - t_o) <= 2000
+    print(f"per-channel L-inf vs oracle: u_x median {np.median(eu):.2e} max {np.max(eu):.2e}; "
+          f"sigma_xy median {np.median(es):.2e} max {np.max(es):.2e}", flush=True)
+    assert max(eu) <= FP32_TOL and max(es) <= FP32_TOL
 
 
 @pytest.mark.parametrize("ny,path", [(104_857, "tiles"), (104_961, "strips")])
@@ -415,3 +451,43 @@ def test_fp64_channel_at_the_tile_offset_limit(orc, ny, path):
         # the two wall rows mirror each other up to the rounding of their
         # different bounce-back terms (3e-12 of max u_x measured)
         assert np.all(np.isfinite(ux)) and abs(ux[-1] - ux[0]) < 1e-10 * abs(ux).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_nan_reported_before_freezing(orc, precision):
+    """Failure detection: a NaN set into one channel of a two-channel handle
+    makes the next convergence check return LB_EUNSTABLE with the channel's
+    'nan' observable set, before the check freezes anything: the other
+    channel, at rest and so converged at that check, stays active. After the
+    bad channel is reset, the handle carries on: the rest channel freezes at
+    the next check, and the reset channel follows the oracle through its
+    force switch-off, so host and device agree on every step counter."""
+    from paper_1310_7450_amd.lbnlm import LbError
+    K = 16
+    specs = [ChannelSpec(8, 16, 2e-6, 0.8, 2e-4, 500.0, 0.1, t_startup=40),
+             ChannelSpec(8, 12, 0.0, 1.0, 1e-4, 1e3, 0.1)]
+    with solver(specs, precision=precision, obs_every=K, steady_tol=1e-9) as s:
+        s.step(K)
+        pops, P = s.get_state(0)
+        pops[3, 5, 2] = np.nan
+        s.set_state(0, pops, P, K)
+        with pytest.raises(LbError) as e:
+            s.step(K)
+        assert e.value.status == -4
+        assert s.observe(0, "nan") == 1.0
+        assert s.observe(1, "nan") == 0.0
+        assert s.observe(1, "active") == 1.0 and s.observe(0, "active") == 1.0
+        assert s.observe(0, "step") == 2 * K and s.observe(1, "step") == 2 * K
+        # reset channel 0 to rest at t = 2K; the force stays on until t = 40
+        rest = np.broadcast_to(workloads.REST_WEIGHTS[:, None, None], (9, 16, 8)).copy()
+        s.set_state(0, rest, np.zeros((16, 8)), 2 * K)
+        s.step(3 * K)
+        assert s.observe(1, "active") == 0.0 and s.observe(1, "step") == 3 * K
+        assert s.observe(0, "step") == 5 * K
+        o = oracle_channel(orc, specs[0])
+        o.set_state(rest, np.zeros((16, 8)), t=2 * K)
+        o.run(3 * K)
+        g_pops, _ = s.get_state(0)
+        err = np.abs(g_pops - o.n).max() / np.abs(o.n - workloads.REST_WEIGHTS[:, None, None]).max()
+        print(f"{precision}: after the reset, state {err:.2e}", flush=True)
+        assert err < (1e-9 if precision == "fp64" else 1e-4)

@@ -34,7 +34,8 @@ def oracle_channel(orc, spec, nn_pressure=True):
     return orc.Channel(spec.nx, spec.ny, spec.force, tau_lb=spec.tau_lb, G=spec.G, tau0=spec.tau0,
                        gamma_c=spec.gamma_c, eps=spec.eps, visc_split=spec.visc_split,
                        t_startup=spec.t_startup, viscoelastic=True, nn_pressure=nn_pressure,
-                       wall_velocity=spec.wall_velocity, pressure_gradient=spec.pressure_gradient)
+                       wall_velocity=spec.wall_velocity, pressure_gradient=spec.pressure_gradient,
+                       top_wall=spec.top_wall)
 
 
 def linf(a, b):
@@ -54,7 +55,7 @@ def compare_profiles(s, ch, o, tol, label):
 
 
 @pytest.mark.parametrize("nx,ny", [(1, 16), (4, 33), (64, 7), (100, 37), (130, 5), (8, 1), (128, 9), (192, 5),
-                                   (256, 3), (384, 2)])
+                                   (256, 3), (384, 2), (512, 9), (768, 11)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_perturbed_state_parity(orc, nx, ny, precision):
     """Seeded random populations, trace and stress on narrow, aligned-wide,
@@ -124,18 +125,23 @@ def test_large_channel_sampled_rows(orc, precision):
         assert np.abs(s.observe(0, "kxx")).max() == 0.0
 
 
-@pytest.mark.parametrize("drive", ["couette", "pressure"])
+@pytest.mark.parametrize("drive", ["couette", "couette_zou_he", "couette_zou_he_strips", "pressure"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_other_drives_state_parity(orc, drive, precision):
     """The time-integrated stress with a moving top wall (planar Couette
-    flow) and with the pressure drive of generalised periodic boundaries:
-    random populations and stress match the oracle after 1, 2 and 57 steps,
-    across the switch-off at t = 40."""
-    nx, ny = (64, 9) if drive == "couette" else (100, 13)
-    kw = dict(wall_velocity=2e-3) if drive == "couette" else dict(force=0.0, pressure_gradient=2e-6)
+    flow: the half-link wall, and Zou and He's node wall on 64-wide and
+    512-wide lattices) and with the pressure drive of generalised periodic
+    boundaries: random populations and stress match the oracle after 1, 2
+    and 57 steps, across the switch-off at t = 40."""
+    nx, ny = {"couette": (64, 9), "couette_zou_he": (64, 9), "couette_zou_he_strips": (512, 9),
+              "pressure": (100, 13)}[drive]
+    if drive.startswith("couette"):
+        kw = dict(wall_velocity=2e-3, top_wall="zou_he" if "zou_he" in drive else "halfway")
+    else:
+        kw = dict(force=0.0, pressure_gradient=2e-6)
     spec = ChannelSpec(nx=nx, ny=ny, force=kw.pop("force", 0.0), tau_lb=0.8, G=2e-4, tau0=500.0, gamma_c=0.1,
                        eps=0.01, visc_split=0.3, t_startup=40, **kw)
-    nnp = drive == "couette"
+    nnp = drive.startswith("couette")
     pops, P = workloads.random_state(nx, ny, seed=nx + ny)
     sig = workloads.random_stress(nx, ny, seed=nx + ny + 1)
     o = oracle_channel(orc, spec, nn_pressure=nnp)

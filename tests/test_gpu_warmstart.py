@@ -17,7 +17,8 @@ def test_warm_start_cuts_steps_to_steady(orc):
     at most 15% fall back to the rest run because the converged profiles
     disagree by more than 5e-3; and for the four narrowest held-out channels
     the warm-started steady profile equals an oracle run from rest for the
-    same number of steps as the GPU rest run, within the same 5e-3."""
+    same number of steps as the GPU rest run within 1e-3, the FP32
+    tolerance."""
     from paper_1310_7450_amd import warmstart
     rep, d = warmstart.experiment(train_seeds=range(100, 104), test_seed=200, train_steps=3000, details=True)
     print({k: rep[k] for k in ("steps_ratio_rest_over_warm", "fallbacks", "prediction_linf_rel_ux",
@@ -30,9 +31,33 @@ def test_warm_start_cuts_steps_to_steady(orc):
     for i in np.argsort([c.ny for c in test])[:4]:
         c = test[i]
         o = orc.Channel(1, c.ny, c.force, tau_lb=c.tau_lb, G=c.G, tau0=c.tau0, gamma_c=c.gamma_c, eps=c.eps,
-                        visc_split=c.visc_split)
+                        visc_split=c.visc_split, nn_pressure=c.nn_pressure)
         o.run(int(d["steps_rest"][i]))
         uo = o.profiles()["ux"]
         e = np.abs(d["prof_warm"][i][0] - uo).max() / np.abs(uo).max()
         print(f"channel {i} (ny {c.ny}): warm steady u_x vs oracle {e:.2e}", flush=True)
-        assert e <= 5e-3
+        assert e <= 1e-3
+
+
+def test_unstable_warm_channel_restarts_from_rest():
+    """The solver judges and falls back: a prediction that makes a channel
+    blow up (NaN here) is caught by the convergence check (LB_EUNSTABLE), the
+    channel is restarted from rest in the same handle and counted, and it
+    converges to the same steady profile as a run from rest; a prediction
+    beyond the low-Mach range is clipped before use."""
+    from paper_1310_7450_amd import warmstart, workloads
+    chans = sorted(workloads.batched_sweep()["channels"], key=lambda c: c.ny)[:3]
+    warm = []
+    for c in chans:
+        u = np.full(warmstart.N_PTS, 1e-4)
+        warm.append((u, np.zeros(warmstart.N_PTS)))
+    warm[1] = (np.full(warmstart.N_PTS, np.nan), np.zeros(warmstart.N_PTS))
+    warm[2] = (np.full(warmstart.N_PTS, 5.0), np.zeros(warmstart.N_PTS))
+    prof_w, steps_w, frozen_w, restarted_w, _ = warmstart.solve_to_steady(chans, warm=warm, strip_rows=16)
+    prof_r, steps_r, frozen_r, restarted_r, _ = warmstart.solve_to_steady(chans, strip_rows=16)
+    print(f"restarted {restarted_w.tolist()}, steps warm {steps_w.tolist()} rest {steps_r.tolist()}", flush=True)
+    assert restarted_w.tolist() == [False, True, False] and not restarted_r.any()
+    assert frozen_w.all() and frozen_r.all()
+    assert steps_w[1] > steps_r[1]  # the wasted steps count
+    for pw, pr in zip(prof_w, prof_r):
+        assert np.abs(pw[0] - pr[0]).max() / np.abs(pr[0]).max() < 1e-3
