@@ -158,3 +158,65 @@ def test_startup_cessation_fp32(orc, oracle_at_switch_off):
         assert e[2] <= FLUX_TOL + FP32_RESOLUTION
         if pe >= 10 and r["t_stop"][1e-2] is not None:
             assert r["t_stop"][1e-2] <= bound
+
+
+def stop_times(observe_umid, step, t_s, cap, every=10, thresholds=(1e-2, 1e-3, 1e-4)):
+    """Cessation from the current state (the switch-off step t_s): u_mid every
+    ``every`` steps until it falls below the smallest threshold times its
+    value at the switch-off, or ``cap`` steps; first crossing time of each
+    threshold."""
+    u0 = observe_umid()
+    stop = {q: None for q in thresholds}
+    t = 0
+    while t < cap:
+        step(every)
+        t += every
+        u = observe_umid()
+        for q in thresholds:
+            if stop[q] is None and u <= q * u0:
+                stop[q] = t
+        if stop[min(thresholds)] is not None:
+            break
+    return u0, stop
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_finite_stopping_time_strongly_yielded(orc, precision):
+    """Sec. III.B / IV.B, the finite stopping time on the GPU in the paper's
+    own regime: theta = G tau / eta_s = 100, the viscosity split of Sec. IV
+    with tau_LB matched to the low-shear viscosity (tau_eff = 0.9), the wall
+    stress twice the yield stress at the switch-off (wall Pe >> 1). An 8 x 32
+    channel, 60,000 start-up steps, then cessation with u_mid sampled every
+    10 steps. The state at the switch-off equals the oracle's node for node;
+    the times at which u_mid falls below 1e-2, 1e-3 and 1e-4 of its
+    switch-off value equal the oracle's (FP32: within one sample); and the
+    1e-2 time lies below the Bingham energy bound (plastic viscosity eta_s,
+    yield stress G gamma_c)."""
+    from oracle import analytic
+    from paper_1310_7450_amd.lbnlm import ChannelSpec
+    eta_s = 1.32e-3
+    G, gc, ny = 1e-5, 0.1, 32
+    tau = 0.132 / G
+    g = 2 * G * gc / (ny / 2)
+    T_s = 60000
+    spec = ChannelSpec(nx=8, ny=ny, force=g, tau_lb=0.5 + 3 * eta_s, G=G, tau0=tau, gamma_c=gc, visc_split=1.0,
+                       t_startup=T_s)
+    o = orc.Channel(1, ny, g, tau_lb=spec.tau_lb, G=G, tau0=tau, gamma_c=gc, visc_split=1.0, t_startup=T_s)
+    o.run(T_s)
+    u_o = o.profiles()["ux"]
+    bound = analytic.bingham_stop_bound(u_o, eta_s, G * gc, ny)
+    pe = abs(o.fields()["kxy"][0, 0]) * tau / gc
+    with solver([spec], precision=precision, obs_every=1000) as s:
+        s.step(T_s)
+        pops, P = s.get_state(0)
+        err = np.abs(pops - o.n[:, :, :1]).max() / np.abs(o.n - workloads.REST_WEIGHTS[:, None, None]).max()
+        print(f"{precision}: state at the switch-off vs oracle {err:.2e}; wall Pe {pe:.1f}", flush=True)
+        assert err < (1e-9 if precision == "fp64" else 1e-4)
+        u0g, st_g = stop_times(lambda: s.observe(0, "umid"), s.step, T_s, 30000)
+    u0o, st_o = stop_times(lambda: float(o.profiles()["ux"][ny // 2 - 1:ny // 2 + 1].mean()), o.run, T_s, 30000)
+    print(f"{precision}: t_stop GPU {st_g} oracle {st_o}; Bingham bound {bound:.0f}", flush=True)
+    assert pe >= 10
+    for q in st_o:
+        assert st_o[q] is not None and st_g[q] is not None
+        assert abs(st_g[q] - st_o[q]) <= (0 if precision == "fp64" else 10)
+    assert st_g[1e-2] <= bound
