@@ -15,6 +15,7 @@ of the widest eighth of the channels.
 """
 import json
 import os
+import sys
 from typing import Iterable, Optional, Sequence
 
 from .lbnlm import ChannelSpec, Solver
@@ -77,7 +78,7 @@ def tune_strip_rows(channels: Sequence[ChannelSpec], precision: str = "fp32",
         else:
             times[sr] = time_candidate(channels, precision, sr, steps, nn_pressure)
         if verbose:
-            print(f"autotune {key}: strip_rows={sr} {times[sr] * 1e3:.1f} us/step", flush=True)
+            print(f"autotune {key}: strip_rows={sr} {times[sr] * 1e3:.1f} us/step", file=sys.stderr, flush=True)
     best = min(times, key=times.get)
     cache[key] = {"strip_rows": best, "ms_per_step": times}
     if cache_path:
