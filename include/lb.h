@@ -242,6 +242,22 @@ lb_status lb_step(lb_handle *h, int64_t n_steps);
  * (n doubles available). Synchronises the stream. */
 lb_status lb_observe(lb_handle *h, int32_t ch, int32_t what, double *host_out, size_t n);
 
+/* lb_observe for callers that cannot allocate memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. Returns the
+ * same values as lb_observe (arguments likewise), but the observation's
+ * scratch (per-strip partials, per-row profiles, per-channel scalars and the
+ * gathered result) lives in a 16 MiB device array that the library keeps on
+ * each GPU for the life of the process, not in the handle's workspace, and
+ * the call allocates nothing. Every call on one GPU shares that array and
+ * finds the last call's contents in it: calls that overlap on one GPU (from
+ * other host threads, or other handles on other streams) race and must be
+ * serialised by the caller. LB_EINVAL when the handle's observation needs
+ * more than 16 MiB (about 96 bytes per row of every channel and per row and
+ * x strip, about 170,000 of them together), and for a stress-force handle
+ * (whose observation needs scratch per node); lb_observe serves both. Does
+ * not refresh what lb_observe caches. Synchronises the stream. */
+lb_status lb_observe_noalloc(lb_handle *h, int32_t ch, int32_t what, double *host_out, size_t n);
+
 /* Copies the state of channel ch to host memory: the post-streaming
  * populations n_i(x, y) of the current step as pops[9][ny][nx] (velocity
  * order (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1)) and the

@@ -9,11 +9,20 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 using namespace lbnlm;
+
+// Scratch of the allocation-free observation (lb_observe_noalloc): the
+// per-strip partials, per-row profiles and per-channel scalars of one
+// observation and the gathered result live in this file-scope device array
+// instead of the handle's workspace. Each GPU the library runs on holds its
+// own copy until the process ends; every call on that GPU shares it.
+constexpr size_t kNoallocScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) double scratch[kNoallocScratchBytes / sizeof(double)];
 
 namespace {
 
@@ -310,6 +319,9 @@ struct lb_handle {
   int n_checks = 0;
   int since_block = 0;       // steps since the last block boundary (handle clock)
   bool any_gpbc = false;     // some channel has the pressure drive
+  int device = -1;           // the GPU current at lb_create
+  double *noalloc = nullptr; // that GPU's copy of `scratch` (device address)
+  hipError_t noalloc_err = hipSuccess;
   std::string err;
 };
 
@@ -423,19 +435,28 @@ lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s) {
   return LB_OK;
 }
 
-lb_status enqueue_observe(lb_handle *h, int update_residual, int steps_since) {
+// The observation of the current state: per-row, per-strip partials into
+// part, then the per-channel reduction into prof and scal (and, with
+// update_residual, the residual history in the workspace).
+lb_status enqueue_observe_into(lb_handle *h, double *part, double *prof, double *scal, int update_residual,
+                               int steps_since) {
   if (h->opt.stress_force) {
     HIPCHECK(h, launch_saf_observe(static_cast<const double *>(h->buf[h->cur]), h->dch, h->n_ch, h->L.plane,
-                                   h->L.total_rows, h->saf_u, h->saf_t, h->dpart, h->stream));
+                                   h->L.total_rows, h->saf_u, h->saf_t, part, h->stream));
   }
   for (int c = 0; c < kClasses && !h->opt.stress_force; ++c) {
     if (!h->all_count[c]) continue;
     SweepArgs a = sweep_args(h, h->dall, h->all_begin[c], h->all_count[c], h->cur, 0);
+    a.part = part;
     HIPCHECK(h, launch_sweep(h->opt.precision == LB_FP32_SHIFTED, c, true, a, h->stream));
   }
-  HIPCHECK(h, launch_reduce(h->dch, h->n_ch, h->dpart, h->dprof, h->dprev, h->dscal, h->duref,
-                            update_residual, steps_since, h->stream));
+  HIPCHECK(h, launch_reduce(h->dch, h->n_ch, part, prof, h->dprev, scal, h->duref, update_residual, steps_since,
+                            h->stream));
   return LB_OK;
+}
+
+lb_status enqueue_observe(lb_handle *h, int update_residual, int steps_since) {
+  return enqueue_observe_into(h, h->dpart, h->dprof, h->dscal, update_residual, steps_since);
 }
 
 void drop_graphs(lb_handle *h) {
@@ -577,6 +598,69 @@ double href_eq(int i, double u) {
 
 lb_status fill_rest(lb_handle *h, int which);
 
+// Device address of `scratch` on GPU dev, looked up once per device (with
+// that device current, as the caller of lb_create leaves it) and kept for
+// the life of the process. In host code the array's name is only a stand-in
+// for the symbol: kernels and copies take this address.
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+double *g_noalloc[kMaxDevices] = {};
+
+hipError_t noalloc_scratch(int dev, double **out) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_noalloc[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_noalloc[dev] = static_cast<double *>(p);
+  }
+  *out = g_noalloc[dev];
+  return hipSuccess;
+}
+
+// Observable `what` of channel c as lb_observe reports it, from the reduced
+// profiles (prof, [row][OF_COUNT]) or scalars (scal, [channel][CS_COUNT]),
+// into out (ny doubles, or one). One thread per row.
+__global__ void gather_observable_kernel(const ChanDev *ch, int c, int what, const double *prof,
+                                         const double *scal, double *out) {
+  const ChanDev d = ch[c];
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (what >= 32) {
+    if (y != 0) return;
+    const double *s = scal + (long long)c * CS_COUNT;
+    double v = 0.0;
+    switch (what) {
+      case LB_OBS_MASS: v = (double)((long long)d.nx * d.ny) + s[CS_MASS_DEV]; break;
+      case LB_OBS_MOMX: v = s[CS_MOMX]; break;
+      case LB_OBS_FLUX: v = s[CS_FLUX]; break;
+      case LB_OBS_WALL_DRAG: v = s[CS_DRAG]; break;
+      case LB_OBS_UMID: v = s[CS_UMID]; break;
+      case LB_OBS_NAN: v = s[CS_NAN]; break;
+      default: break;
+    }
+    out[0] = v;
+    return;
+  }
+  if (y >= d.ny) return;
+  const double *r = prof + ((long long)d.row_off + y) * OF_COUNT;
+  double v = 0.0;
+  switch (what) {
+    case LB_OBS_UX: v = r[OF_UX]; break;
+    case LB_OBS_UY: v = r[OF_UY]; break;
+    case LB_OBS_SXX: v = r[OF_SXX]; break;
+    case LB_OBS_SXY: v = r[OF_SXY]; break;
+    case LB_OBS_SYY: v = r[OF_SYY]; break;
+    case LB_OBS_N1: v = r[OF_SXX] - r[OF_SYY]; break;
+    case LB_OBS_PRESSURE: v = (1.0 + r[OF_RHOE_DEV]) / 3.0; break;
+    case LB_OBS_KXY: v = r[OF_KXY]; break;
+    case LB_OBS_TRT: v = r[OF_TRT]; break;
+    case LB_OBS_KXX: v = r[OF_KXX]; break;
+    default: break;
+  }
+  out[y] = v;
+}
+
 }  // namespace
 
 extern "C" {
@@ -681,6 +765,10 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
         hipMemsetAsync(h->sbuf[b], 0, (size_t)kStressPlanes * h->L.plane * h->L.esize, h->stream) != hipSuccess)
       return bail(LB_EHIP);
   if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(LB_EHIP);
+  // the allocation-free observation's scratch on this GPU (a failure here
+  // is reported by lb_observe_noalloc, not by lb_create)
+  h->noalloc_err = hipGetDevice(&h->device);
+  if (h->noalloc_err == hipSuccess) h->noalloc_err = noalloc_scratch(h->device, &h->noalloc);
   *out = h;
   return LB_OK;
 }
@@ -803,6 +891,57 @@ lb_status lb_observe(lb_handle *h, int32_t ch, int32_t what, double *out, size_t
     }
     out[y] = v;
   }
+  return LB_OK;
+}
+
+lb_status lb_observe_noalloc(lb_handle *h, int32_t ch, int32_t what, double *out, size_t n) {
+  if (!h) return LB_EINVAL;
+  if (ch < 0 || ch >= h->n_ch || !out) return fail(h, LB_EINVAL, "bad channel or output");
+  const ChanDev &d = h->L.ch[ch];
+  if (what == LB_OBS_STEP || what == LB_OBS_ACTIVE) {
+    if (n < 1) return fail(h, LB_EINVAL, "output too small");
+    out[0] = what == LB_OBS_STEP ? (double)h->t[ch] : (double)h->active[ch];
+    return LB_OK;
+  }
+  const bool scalar = what >= 32;
+  const bool known = scalar ? (what >= LB_OBS_MASS && what <= LB_OBS_NAN) : (what >= LB_OBS_UX && what <= LB_OBS_KXX);
+  if (!known) return fail(h, LB_EINVAL, "unknown observable");
+  const size_t count = scalar ? 1 : (size_t)d.ny;
+  if (n < count) return fail(h, LB_EINVAL, scalar ? "output too small" : "output shorter than ny");
+  if (what == LB_OBS_RESIDUAL) {
+    // the residual of the last convergence check, kept in the workspace
+    if (h->n_checks < 2) {
+      out[0] = INFINITY;
+      return LB_OK;
+    }
+    HIPCHECK(h, hipMemcpyAsync(out, h->dscal + (size_t)ch * CS_COUNT + CS_RESIDUAL, sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    return LB_OK;
+  }
+  if (h->opt.stress_force)
+    return fail(h, LB_EINVAL, "lb_observe_noalloc: the stress-force observation needs per-node scratch (use lb_observe)");
+  if (!h->noalloc) return hipfail(h, h->noalloc_err, "lb_observe_noalloc: scratch address");
+  // partials, profiles, scalars and the gathered result, 256-byte aligned
+  auto chunk = [](size_t doubles) { return align_up(doubles, kAlign / sizeof(double)); };
+  const size_t n_part = chunk((size_t)OF_COUNT * h->L.total_part), n_prof = chunk((size_t)OF_COUNT * h->L.total_rows);
+  const size_t n_scal = chunk((size_t)CS_COUNT * h->n_ch), n_out = chunk(count);
+  const size_t need = (n_part + n_prof + n_scal + n_out) * sizeof(double);
+  if (need > kNoallocScratchBytes) {
+    char buf[200];
+    snprintf(buf, sizeof buf,
+             "lb_observe_noalloc: this handle's observation needs %zu bytes of scratch, more than its %zu "
+             "(use lb_observe)", need, kNoallocScratchBytes);
+    return fail(h, LB_EINVAL, buf);
+  }
+  double *part = h->noalloc, *prof = part + n_part, *scal = prof + n_prof, *res = scal + n_scal;
+  lb_status st = enqueue_observe_into(h, part, prof, scal, 0, 0);
+  if (st != LB_OK) return st;
+  hipLaunchKernelGGL(gather_observable_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, h->stream,
+                     h->dch, ch, what, prof, scal, res);
+  HIPCHECK(h, hipGetLastError());
+  HIPCHECK(h, hipMemcpyAsync(out, res, count * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
   return LB_OK;
 }
 

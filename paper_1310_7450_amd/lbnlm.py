@@ -26,7 +26,7 @@ SCALARS = {"mass": 32, "momx": 33, "flux": 34, "wall_drag": 35, "umid": 36,
 STATUS = {0: "LB_OK", -1: "LB_EINVAL", -2: "LB_ENOMEM", -3: "LB_EHIP", -4: "LB_EUNSTABLE", -5: "LB_ESTATE"}
 
 # Names of every function include/lb.h declares.
-ABI_FUNCTIONS = ["lb_workspace_bytes", "lb_create", "lb_destroy", "lb_step", "lb_observe",
+ABI_FUNCTIONS = ["lb_workspace_bytes", "lb_create", "lb_destroy", "lb_step", "lb_observe", "lb_observe_noalloc",
                  "lb_get_state", "lb_set_state", "lb_get_stress", "lb_set_stress", "lb_set_profile",
                  "lb_last_error", "lb_status_string"]
 
@@ -69,6 +69,7 @@ def load_library():
     L.lb_destroy.argtypes = [vp]
     L.lb_step.argtypes = [vp, C.c_int64]
     L.lb_observe.argtypes = [vp, C.c_int32, C.c_int32, dp, sz]
+    L.lb_observe_noalloc.argtypes = [vp, C.c_int32, C.c_int32, dp, sz]
     L.lb_get_state.argtypes = [vp, C.c_int32, dp, dp]
     L.lb_set_state.argtypes = [vp, C.c_int32, dp, dp, C.c_int64]
     L.lb_get_stress.argtypes = [vp, C.c_int32, dp]
@@ -78,7 +79,7 @@ def load_library():
     L.lb_last_error.restype = C.c_char_p
     L.lb_status_string.argtypes = [C.c_int32]
     L.lb_status_string.restype = C.c_char_p
-    for name in ["lb_workspace_bytes", "lb_create", "lb_destroy", "lb_step", "lb_observe",
+    for name in ["lb_workspace_bytes", "lb_create", "lb_destroy", "lb_step", "lb_observe", "lb_observe_noalloc",
                  "lb_get_state", "lb_set_state", "lb_get_stress", "lb_set_stress", "lb_set_profile"]:
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -190,6 +191,17 @@ class Solver:
         ny = self.channels[ch].ny
         out = np.zeros(ny)
         self._check(self.L.lb_observe(self.h, ch, PROFILES[what], _dp(out), ny))
+        return out
+
+    def observe_noalloc(self, ch: int, what: str):
+        """lb_observe_noalloc: the same values as observe(), computed in the
+        library's per-GPU static scratch (no allocation on the call)."""
+        if what in SCALARS:
+            out = np.zeros(1)
+            self._check(self.L.lb_observe_noalloc(self.h, ch, SCALARS[what], _dp(out), 1))
+            return float(out[0])
+        out = np.zeros(self.channels[ch].ny)
+        self._check(self.L.lb_observe_noalloc(self.h, ch, PROFILES[what], _dp(out), len(out)))
         return out
 
     def profiles(self, ch: int):
