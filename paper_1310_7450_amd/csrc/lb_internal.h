@@ -57,8 +57,9 @@ struct ChanDev {
 // Work unit of one wavefront: rows [y0, y1) of channel ch, starting at
 // column x0 (wide mode: first interior column; narrow mode: 0). flip: the
 // vector sweep marches this strip against the step's direction (odd bands).
+// x1: the two-step sweep stores columns [x0, x1) (at most 248 of them).
 struct Strip {
-  int ch, x0, y0, y1, flip;
+  int ch, x0, y0, y1, flip, x1;
 };
 
 struct SweepArgs {
@@ -77,6 +78,7 @@ struct SweepArgs {
   const void *SA;       // viscoelastic model: stress read (3 planes)
   void *SB;             // viscoelastic model: stress written (3 planes)
   int ve;               // time-integrated stress in place of the instantaneous one
+  int zh;               // some channel of the handle has a Zou-He top wall
 };
 // A state buffer larger than this is written with nontemporal stores: it
 // cannot stay in the 256 MB last-level cache (MALL) until the next step reads
@@ -155,5 +157,12 @@ hipError_t launch_saf_observe(const double *A, const ChanDev *ch, int n_ch, long
                               double *U, double *Tn, double *part, hipStream_t s);
 hipError_t launch_rereference(float *A, const ChanDev *ch, int n_ch, int total_rows, const double *prof,
                               float *uref, hipStream_t s);
+// Two steps per launch on strips of at most kTwoStepCols stored columns
+// (FP32 storage, instantaneous model, vector-class channels with fixed
+// half-way walls and no pressure drive); SweepArgs.strips holds the strips,
+// n_strips their number; the state goes from A to B over steps k and k+1.
+constexpr int kTwoStepCols = 248;
+constexpr int kTwoStepWaves = 2;
+hipError_t launch_two_step(const SweepArgs &a, hipStream_t s);
 
 }  // namespace lbnlm

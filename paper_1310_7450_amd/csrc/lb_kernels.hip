@@ -1066,7 +1066,7 @@ constexpr int kSideTop[25] = {
 // the nine pulled populations of each neighbour column, for its u~) come in
 // one lane-indexed vector load, lane i holding value i, so that they complete
 // in order with the row's other loads; they are read out with readlane.
-template <typename T, bool SHIFT, bool OBS, int NPL, bool NT, bool VE>
+template <typename T, bool SHIFT, bool OBS, int NPL, bool NT, bool VE, bool ZH>
 __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a) {
   typedef typename Vec<T, NPL>::type V;
   constexpr int LPT = 64 / NPL;  // lanes per tile
@@ -1221,8 +1221,10 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
       from_right(R.r[7], lane_value(R.side, 4), f[7]);
       from_left(R.r[8], lane_value(R.side, 5), f[8]);
     }
-    // a Zou-He top wall completes the top row's populations from above
-    const bool zhtop = top && c.zh;
+    // a Zou-He top wall completes the top row's populations from above (a
+    // variant of its own: the completion's registers cost the plain sweep
+    // about a fifth of a point of occupancy headroom)
+    const bool zhtop = ZH && top && c.zh;
     // FP32: every pulled value relative to this row's reference
     const T urd = SHIFT ? lane_value(R.side, 24) : T(0);
     const T urc = SHIFT ? lane_value(R.side, 25) : T(0);
@@ -1354,7 +1356,7 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
     // the top row's own stored 5 and 6 (what it emitted upwards), for the
     // momentum a Zou-He wall took (observation only)
     V a5{}, a6{};
-    if constexpr (OBS) {
+    if constexpr (OBS && ZH) {
       if (c.zh && y == ny - 1) {
         a5 = vrun(y, 5);
         a6 = vrun(y, 6);
@@ -1470,6 +1472,403 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
     for (int j = 0; j < D; ++j)
       if (j == 0 || i + j < nrows) row_step(yfirst + dir * (i + j), S[j], S[(j + 1) % D]);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Two steps per launch. For FP32 storage relative to the row references,
+// the instantaneous model, vector-class channels (nx a multiple of 256) with
+// fixed half-way walls and no pressure drive, one wavefront takes an output
+// strip of at most 248 columns [x0, x1) and rows [y0, y1) through steps t
+// and t+1 without writing step t to memory:
+//  * the window is the 256 columns starting four columns left of x0 (four
+//    per lane, wrapped periodically), with one column beside it on either
+//    side as the vector sweep has;
+//  * stage A (step t) is the vector sweep's row machine over the window for
+//    rows max(y0-2, 0) .. min(y1+2, ny)-1, read from the state; each row's
+//    post-collision populations and trace go into a ring of four rows in
+//    LDS instead of memory;
+//  * stage B (step t+1) is the same machine reading its rows from that ring,
+//    two rows behind stage A, and stores rows y0 .. y1-1 of lanes 1..62
+//    to the other buffer.
+// After step t the window's two outermost columns on each side lack valid
+// neighbours for step t+1; lanes 0 and 63 hold them and store nothing, so
+// every stored node saw only values of the exact step-t state. Per node the
+// arithmetic is the vector sweep's (same helpers, same pull, reference
+// shifts and collision), so the result equals two one-step sweeps to the
+// rounding of the FP32 operations.
+constexpr int kV2Ring = 4;
+
+// Side values of stage A's rows, by lane i < 24: (row offset, column offset
+// from the window start, field), with the wall rows' bounce-back sources;
+// the same meaning as kSideIn/kSideBot/kSideTop for the columns beside a
+// window that need not start on a tile. Lanes 24..26 carry the row
+// references.
+struct SideEntry {
+  int dy, dc, p;
+};
+// interior rows, packed as (dy + 1) | (dc + 2) << 2 | p << 12
+#define V2SIDE(dy, dc, p) ((dy) + 1 | ((dc) + 2) << 2 | (p) << 12)
+constexpr int kV2Side[24] = {
+    V2SIDE(0, -1, 1),   V2SIDE(0, 256, 3),  V2SIDE(-1, -1, 5), V2SIDE(-1, 256, 6), V2SIDE(1, 256, 7),
+    V2SIDE(1, -1, 8),   V2SIDE(0, -1, 0),   V2SIDE(0, -2, 1),  V2SIDE(0, 0, 3),    V2SIDE(-1, -1, 2),
+    V2SIDE(-1, -2, 5),  V2SIDE(-1, 0, 6),   V2SIDE(1, -1, 4),  V2SIDE(1, 0, 7),    V2SIDE(1, -2, 8),
+    V2SIDE(0, 256, 0),  V2SIDE(0, 255, 1),  V2SIDE(0, 257, 3), V2SIDE(-1, 256, 2), V2SIDE(-1, 255, 5),
+    V2SIDE(-1, 257, 6), V2SIDE(1, 256, 4),  V2SIDE(1, 257, 7), V2SIDE(1, 255, 8)};
+#undef V2SIDE
+__device__ __forceinline__ SideEntry v2_side(int i, bool bot, bool top) {
+  const int code = kV2Side[i];
+  SideEntry e{(code & 3) - 1, ((code >> 2) & 1023) - 2, code >> 12};
+  if (bot && e.dy < 0) {
+    // entries 2, 3: edge values of pulls the wall row takes from its own
+    // node (unused); the side columns' pops 2, 5, 6 bounce back from 4, 7, 8
+    const bool edge = (i == 2 || i == 3);
+    const int col = (i < 15) ? -1 : 256;
+    const int back = e.p == 2 ? 4 : (e.p == 5 ? 7 : 8);
+    e = edge ? SideEntry{0, 0, 0} : SideEntry{0, col, back};
+  }
+  if (top && e.dy > 0) {
+    const bool edge = (i == 4 || i == 5);
+    const int col = (i < 15) ? -1 : 256;
+    const int back = e.p == 4 ? 2 : (e.p == 7 ? 5 : 6);
+    e = edge ? SideEntry{0, 0, 0} : SideEntry{0, col, back};
+  }
+  return e;
+}
+
+template <bool NT>
+__global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArgs a) {
+  typedef float T;
+  constexpr bool SHIFT = true;
+  constexpr int NPL = 4;
+  typedef typename Vec<T, NPL>::type V;
+  __shared__ V ring_lds[kTwoStepWaves][kV2Ring][kPlanes][64];  // 80 KB per workgroup
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int sidx = xcd_item(blockIdx.x, a.n_wg) * kTwoStepWaves + wave;
+  if (sidx >= a.n_strips) return;  // no workgroup barriers: each wavefront uses its own LDS
+  V(*ring)[kPlanes][64] = ring_lds[wave];
+  const Strip st = a.strips[sidx];
+  const ChanDev c = a.ch[st.ch];
+  const T *__restrict__ A = static_cast<const T *>(a.A);
+  T *__restrict__ B = static_cast<T *>(a.B);
+  const int nx = c.nx, ny = c.ny;
+  const long long t = c.t + a.k;
+  const T fxA = (t < c.t_startup) ? T(c.g) : T(0);
+  const T fxB = (t + 1 < c.t_startup) ? T(c.g) : T(0);
+  const Coef<T> q(c);
+  constexpr int F = kTile;
+  const long long tile00 = c.off >> 6;
+  const int tiles_row = nx >> 6;
+  const long long row_stride = (long long)tiles_row * kPlanes * F;
+  auto rowbase = [&](int y) __attribute__((always_inline)) { return (tile00 + (long long)y * tiles_row) * (kPlanes * F); };
+  // column of window offset dc, wrapped, as an element offset inside a row
+  const int w0 = st.x0 - 4;
+  auto colpart = [&](int dc) __attribute__((always_inline)) -> long long {
+    int col = w0 + dc;
+    col += (col < 0) ? nx : 0;
+    col -= (col >= nx) ? nx : 0;
+    return (long long)(col >> 6) * (kPlanes * F) + (col & 63);
+  };
+  const long long lcol = colpart(4 * lane);
+  auto clampy = [&](int y) __attribute__((always_inline)) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
+
+  // ---- stage A: raw loads of a row of the state (window and side values)
+  struct Raw {
+    V r[10];
+    T side;
+  };
+  const int li = lane < 24 ? lane : 0;
+  // element offset of this lane's side value relative to the row (decoded
+  // again on wall rows: a choice between precomputed offsets would keep them
+  // in scratch memory)
+  auto side_offset = [&](bool bot, bool top) __attribute__((always_inline)) -> long long {
+    const SideEntry e = v2_side(li, bot, top);
+    return (lane < 24) ? (long long)e.dy * row_stride + colpart(e.dc) + (long long)e.p * F : lcol;
+  };
+  const long long o_in = side_offset(false, false);
+  auto load_raw = [&](int y, Raw &R) __attribute__((always_inline)) {
+    const bool bot = (y == 0), top = (y == ny - 1);
+    const long long rb = rowbase(y);
+    const long long rd = bot ? rb : rb - row_stride, ru = top ? rb : rb + row_stride;
+    auto run = [&](long long base, int p) __attribute__((always_inline)) {
+      return *reinterpret_cast<const V *>(A + base + lcol + (long long)p * F);
+    };
+    R.r[0] = run(rb, 0);
+    R.r[1] = run(rb, 1);
+    R.r[3] = run(rb, 3);
+    R.r[9] = run(rb, 9);
+    R.r[2] = run(rd, bot ? 4 : 2);
+    R.r[5] = run(rd, bot ? 7 : 5);
+    R.r[6] = run(rd, bot ? 8 : 6);
+    R.r[4] = run(ru, top ? 2 : 4);
+    R.r[7] = run(ru, top ? 5 : 7);
+    R.r[8] = run(ru, top ? 6 : 8);
+    long long o = o_in;
+    if (bot || top) o = side_offset(bot, top);  // wall rows only
+    const T *ps = A + rb + o;
+    const int yr = y + lane - 25;
+    const T *pu = a.uref + c.row_off + (yr < 0 ? 0 : (yr >= ny ? ny - 1 : yr));
+    ps = (lane >= 24 && lane <= 26) ? pu : ps;
+    R.side = *ps;
+  };
+  // ---- stage B: the same row from the LDS ring of step-t rows (side
+  // values: only the row references are meaningful; lanes 0 and 63, which
+  // would use the others, store nothing)
+  T uring = T(0);  // lane s: reference velocity of the row in ring slot s
+  auto load_lds = [&](int y, Raw &R) __attribute__((always_inline)) {
+    const bool bot = (y == 0), top = (y == ny - 1);
+    const int sc = y & (kV2Ring - 1), sd = bot ? sc : ((y - 1) & (kV2Ring - 1)), su = top ? sc : ((y + 1) & (kV2Ring - 1));
+    R.r[0] = ring[sc][0][lane];
+    R.r[1] = ring[sc][1][lane];
+    R.r[3] = ring[sc][3][lane];
+    R.r[9] = ring[sc][9][lane];
+    R.r[2] = ring[sd][bot ? 4 : 2][lane];
+    R.r[5] = ring[sd][bot ? 7 : 5][lane];
+    R.r[6] = ring[sd][bot ? 8 : 6][lane];
+    R.r[4] = ring[su][top ? 2 : 4][lane];
+    R.r[7] = ring[su][top ? 5 : 7][lane];
+    R.r[8] = ring[su][top ? 6 : 8][lane];
+    const T ud = lane_value(uring, sd), uc = lane_value(uring, sc), uu = lane_value(uring, su);
+    R.side = lane == 24 ? ud : (lane == 25 ? uc : (lane == 26 ? uu : T(0)));
+  };
+
+  // Pulled populations, P, moments and u~ of the window's columns of row y,
+  // and u~ of the two columns beside it (the vector sweep's assembly, fixed
+  // walls).
+  auto assemble = [&](int y, const Raw &R, T fx, T f[9][NPL], T P[NPL], T sd[NPL], T mx[NPL], T my[NPL],
+                      U2<T> u[NPL], U2<T> &uL, U2<T> &uR, T ur3[3]) __attribute__((always_inline)) {
+    const bool bot = (y == 0), top = (y == ny - 1);
+    auto from_left = [&](const V &r, T edge, T out[NPL]) __attribute__((always_inline)) {
+      out[0] = shift_up(edge, r[NPL - 1]);
+#pragma unroll
+      for (int k = 1; k < NPL; ++k) out[k] = r[k - 1];
+    };
+    auto from_right = [&](const V &r, T edge, T out[NPL]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int k = 0; k < NPL - 1; ++k) out[k] = r[k + 1];
+      out[NPL - 1] = shift_down(edge, r[0]);
+    };
+    auto split = [&](const V &r, T out[NPL]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) out[k] = r[k];
+    };
+    split(R.r[0], f[0]);
+    from_left(R.r[1], lane_value(R.side, 0), f[1]);
+    from_right(R.r[3], lane_value(R.side, 1), f[3]);
+    split(R.r[9], P);
+    split(R.r[2], f[2]);
+    split(R.r[4], f[4]);
+    if (bot) {
+      split(R.r[5], f[5]);
+      split(R.r[6], f[6]);
+    } else {
+      from_left(R.r[5], lane_value(R.side, 2), f[5]);
+      from_right(R.r[6], lane_value(R.side, 3), f[6]);
+    }
+    if (top) {
+      split(R.r[7], f[7]);
+      split(R.r[8], f[8]);
+    } else {
+      from_right(R.r[7], lane_value(R.side, 4), f[7]);
+      from_left(R.r[8], lane_value(R.side, 5), f[8]);
+    }
+    const T urd = lane_value(R.side, 24), urc = lane_value(R.side, 25), uru = lane_value(R.side, 26);
+    ur3[0] = urd;
+    ur3[1] = urc;
+    ur3[2] = uru;
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      T g[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) g[i] = f[i][k];
+      to_row_reference(g, urd, urc, uru, bot, top);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i][k] = g[i];
+      moments<T>(g, sd[k], mx[k], my[k]);
+      u[k] = u_tilde<T, SHIFT>(sd[k], mx[k], my[k], fx, urc);
+    }
+    T l[9], r[9];
+    l[0] = lane_value(R.side, 6);
+    l[1] = lane_value(R.side, 7);
+    l[3] = lane_value(R.side, 8);
+    l[2] = lane_value(R.side, 9);
+    l[5] = lane_value(R.side, 10);
+    l[6] = lane_value(R.side, 11);
+    l[4] = lane_value(R.side, 12);
+    l[7] = lane_value(R.side, 13);
+    l[8] = lane_value(R.side, 14);
+    r[0] = lane_value(R.side, 15);
+    r[1] = lane_value(R.side, 16);
+    r[3] = lane_value(R.side, 17);
+    r[2] = lane_value(R.side, 18);
+    r[5] = lane_value(R.side, 19);
+    r[6] = lane_value(R.side, 20);
+    r[4] = lane_value(R.side, 21);
+    r[7] = lane_value(R.side, 22);
+    r[8] = lane_value(R.side, 23);
+    to_row_reference(l, urd, urc, uru, bot, top);
+    to_row_reference(r, urd, urc, uru, bot, top);
+    T s0, m0, n0;
+    moments<T>(l, s0, m0, n0);
+    uL = u_tilde<T, SHIFT>(s0, m0, n0, fx, urc);
+    moments<T>(r, s0, m0, n0);
+    uR = u_tilde<T, SHIFT>(s0, m0, n0, fx, urc);
+  };
+
+  // Update of row y from its assembled state (fc ..., uCur, side u~, the
+  // references) and u~ of the rows below and above; out and trT receive
+  // the new populations and trace.
+  auto update = [&](int y, T fx, T fc[9][NPL], const T Pc[NPL], const T sdc[NPL], const T mxc[NPL],
+                    const T myc[NPL], const U2<T> uPrev[NPL], const U2<T> uCur[NPL], const U2<T> uNext[NPL],
+                    U2<T> uLc, U2<T> uRc, const T urC[3], V out[kPlanes]) __attribute__((always_inline)) {
+    const T urc = urC[1];
+    const T urd = (y == 0) ? -urc : urC[0];
+    const T uru = (y == ny - 1) ? -urc : urC[2];
+    const T kref = T(0.5) * (uru - urd);
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      U2<T> lf, rt;
+      if (k == 0) lf = U2<T>{shift_up(uLc.x, uCur[NPL - 1].x), shift_up(uLc.y, uCur[NPL - 1].y)};
+      else lf = uCur[k - 1];
+      if (k == NPL - 1) rt = U2<T>{shift_down(uRc.x, uCur[0].x), shift_down(uRc.y, uCur[0].y)};
+      else rt = uCur[k + 1];
+      U2<T> dn = uPrev[k], up = uNext[k];
+      if (y == 0) dn = U2<T>{-uCur[k].x, -uCur[k].y};
+      if (y == ny - 1) up = U2<T>{-uCur[k].x, -uCur[k].y};
+      T g[9], o[9], tr, sn[3];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) g[i] = fc[i][k];
+      const T sp[3] = {T(0), T(0), T(0)};
+      double ob[OF_COUNT];
+      node_update<T, SHIFT, false, false>(g, sdc[k], mxc[k], myc[k], Pc[k], fx, lf, rt, dn, up, urc, kref, q, c.nnp,
+                                          sp, sn, o, tr, ob);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) out[i][k] = o[i];
+      out[9][k] = tr;
+    }
+  };
+
+  // ---- rows of the two stages
+  const int A0 = st.y0 - 2 < 0 ? 0 : st.y0 - 2, A1 = st.y1 + 2 > ny ? ny : st.y1 + 2;
+  const int R0 = st.y0 - 1 < 0 ? 0 : st.y0 - 1, R1 = st.y1 + 1 > ny ? ny : st.y1 + 1;
+  const int iend = (A1 - 1 > st.y1 + 1 ? A1 - 1 : st.y1 + 1) + 1;  // iterations [A0, iend)
+  // stage B's stores: lanes whose four columns lie in [x0, x1)
+  const bool store_lane = lane >= 1 && 4 * (lane - 1) < st.x1 - st.x0;
+
+  // stage A state (the vector sweep's pipeline, ring depth 2)
+  constexpr int D = 2;
+  auto ring_row = [&](int y) __attribute__((always_inline)) { return clampy(y < A0 - 1 ? A0 - 1 : (y > A1 ? A1 : y)); };
+  T fc[9][NPL], Pc[NPL], sdc[NPL], mxc[NPL], myc[NPL];
+  U2<T> uPrev[NPL], uCur[NPL], uLc, uRc;
+  T urC[3];
+  Raw S[D];
+  {
+    Raw Rp, Rf;
+    const int yp = clampy(A0 - 1);
+    load_raw(yp, Rp);
+    load_raw(A0, Rf);
+#pragma unroll
+    for (int k = 1; k < D; ++k) load_raw(ring_row(A0 + k), S[k]);
+    T ftmp[9][NPL], Ptmp[NPL], s0[NPL], m0[NPL], n0[NPL], ur_unused[3];
+    U2<T> hl, hr;
+    assemble(yp, Rp, fxA, ftmp, Ptmp, s0, m0, n0, uPrev, hl, hr, ur_unused);
+    assemble(A0, Rf, fxA, fc, Pc, sdc, mxc, myc, uCur, uLc, uRc, urC);
+  }
+  // stage B state: the assembled row i-2 and u~ of rows i-3 and i-1
+  T fB[9][NPL], PB[NPL], sdB[NPL], mxB[NPL], myB[NPL], urB[3];
+  U2<T> uBp[NPL], uBc[NPL], uBLc, uBRc;
+
+  auto stage_a = [&](int y, Raw &Rload, const Raw &Rasm) __attribute__((always_inline)) {
+    load_raw(ring_row(y + D), Rload);
+    T fn[9][NPL], Pn[NPL], sdn[NPL], mxn[NPL], myn[NPL], urN[3];
+    U2<T> uNext[NPL], uLn, uRn;
+    assemble(clampy(y + 1), Rasm, fxA, fn, Pn, sdn, mxn, myn, uNext, uLn, uRn, urN);
+    V out[kPlanes];
+    update(y, fxA, fc, Pc, sdc, mxc, myc, uPrev, uCur, uNext, uLc, uRc, urC, out);
+    const int slot = y & (kV2Ring - 1);
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) ring[slot][p][lane] = out[p];
+    uring = (lane == slot) ? urC[1] : uring;
+    uLc = uLn;
+    uRc = uRn;
+    urC[0] = urN[0];
+    urC[1] = urN[1];
+    urC[2] = urN[2];
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      uPrev[k] = uCur[k];
+      uCur[k] = uNext[k];
+      Pc[k] = Pn[k];
+      sdc[k] = sdn[k];
+      mxc[k] = mxn[k];
+      myc[k] = myn[k];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) fc[i][k] = fn[i][k];
+    }
+  };
+
+  auto stage_b = [&](int i) __attribute__((always_inline)) {
+    const int r = i - 1, y = i - 2;
+    T fn[9][NPL], Pn[NPL], sdn[NPL], mxn[NPL], myn[NPL], urN[3];
+    U2<T> uNext[NPL], uLn, uRn;
+    if (r >= R0 && r < R1) {
+      Raw R;
+      load_lds(r, R);
+      assemble(r, R, fxB, fn, Pn, sdn, mxn, myn, uNext, uLn, uRn, urN);
+    } else {
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        uNext[k] = U2<T>{T(0), T(0)};
+        Pn[k] = sdn[k] = mxn[k] = myn[k] = T(0);
+#pragma unroll
+        for (int j = 0; j < 9; ++j) fn[j][k] = T(0);
+      }
+      uLn = uRn = U2<T>{T(0), T(0)};
+      urN[0] = urN[1] = urN[2] = T(0);
+    }
+    if (y >= st.y0 && y < st.y1) {
+      V out[kPlanes];
+      update(y, fxB, fB, PB, sdB, mxB, myB, uBp, uBc, uNext, uBLc, uBRc, urB, out);
+      if (store_lane) {
+        T *w = B + rowbase(y) + lcol;
+#pragma unroll
+        for (int p = 0; p < kPlanes; ++p) {
+          if constexpr (NT) __builtin_nontemporal_store(out[p], reinterpret_cast<V *>(w + (long long)p * F));
+          else *reinterpret_cast<V *>(w + (long long)p * F) = out[p];
+        }
+      }
+    }
+    uBLc = uLn;
+    uBRc = uRn;
+    urB[0] = urN[0];
+    urB[1] = urN[1];
+    urB[2] = urN[2];
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      uBp[k] = uBc[k];
+      uBc[k] = uNext[k];
+      PB[k] = Pn[k];
+      sdB[k] = sdn[k];
+      mxB[k] = mxn[k];
+      myB[k] = myn[k];
+#pragma unroll
+      for (int j = 0; j < 9; ++j) fB[j][k] = fn[j][k];
+    }
+  };
+
+  // stage A rows [A0, A1) unrolled D times (fixed ring registers), each
+  // followed by stage B's iteration; then stage B drains
+#pragma unroll 1
+  for (int i = A0; i < A1; i += D) {
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j == 0 || i + j < A1) {
+        stage_a(i + j, S[j], S[(j + 1) % D]);
+        stage_b(i + j);
+      }
+  }
+#pragma unroll 1
+  for (int i = A1; i < iend; ++i) stage_b(i);
 }
 
 __global__ void __launch_bounds__(256) reduce_kernel(const ChanDev *ch, const double *part,
@@ -2018,11 +2417,15 @@ hipError_t launch_vec(bool observe, const SweepArgs &a, hipStream_t s) {
   constexpr int NPL = sizeof(T) == 4 ? LB_VEC_NPL32 : LB_VEC_NPL64;
   dim3 grid(a.n_wg), block(64 * LB_WG_WAVES);
   if (observe)
-    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, true, NPL, false, VE>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, true, NPL, false, VE, true>), grid, block, 0, s, a);
+  else if (a.zh && a.nt)
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, true, VE, true>), grid, block, 0, s, a);
+  else if (a.zh)
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, false, VE, true>), grid, block, 0, s, a);
   else if (a.nt)
-    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, true, VE>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, true, VE, false>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, false, VE>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((sweep_vec_kernel<T, SHIFT, false, NPL, false, VE, false>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
@@ -2088,6 +2491,14 @@ hipError_t launch_gpbc(int fp32, void *B, const ChanDev *ch, int n_ch, int k, co
   else
     hipLaunchKernelGGL((gpbc_kernel<double, false>), dim3(n_ch), dim3(256), 0, s, static_cast<double *>(B), ch,
                        k, uref);
+  return hipGetLastError();
+}
+
+hipError_t launch_two_step(const SweepArgs &a, hipStream_t s) {
+  if (a.n_strips == 0) return hipSuccess;
+  const dim3 grid(a.n_wg), block(64 * kTwoStepWaves);
+  if (a.nt) hipLaunchKernelGGL(sweep_vec2_kernel<true>, grid, block, 0, s, a);
+  else hipLaunchKernelGGL(sweep_vec2_kernel<false>, grid, block, 0, s, a);
   return hipGetLastError();
 }
 

@@ -54,6 +54,10 @@ struct Layout {
   size_t off_stress[2] = {0, 0};  // viscoelastic model only
   size_t off_saf_u = 0, off_saf_t = 0;  // stress-as-force scratch (u~, Sigma^nN)
   size_t off_tiles = 0;                 // tiles of the tiled step
+  // two steps per launch: strips of the other channels for captured blocks
+  // (and their reverse), and the two-step strips
+  size_t off_bstrips = 0, off_brstrips = 0, off_tstrips = 0;
+  int max_two = 0;
   std::vector<ChanDev> ch;
 };
 
@@ -67,6 +71,7 @@ std::string validate(const lb_channel *c, int n, const lb_options *o) {
   if (!(o->steady_tol >= 0) || !std::isfinite(o->steady_tol)) return "steady_tol must be >= 0";
   if (o->viscoelastic != 0 && o->viscoelastic != 1) return "viscoelastic must be 0 or 1";
   if (o->stress_force != 0 && o->stress_force != 1) return "stress_force must be 0 or 1";
+  if (o->steps_per_sweep < 0 || o->steps_per_sweep > 2) return "steps_per_sweep must be 0, 1 or 2";
   if (o->stress_force && (o->precision != LB_FP64 || o->viscoelastic))
     return "stress_force needs FP64 and the instantaneous model";
   for (int i = 0; i < n; ++i) {
@@ -197,6 +202,52 @@ void add_strips(int ci, const ChanDev &d, int esize, int srows, bool stack, std:
       out.push_back(Strip{ci, xs * w, b * srows, std::min((b + 1) * srows, d.ny), 0});
 }
 
+// Two steps per launch (sweep_vec2_kernel) for the blocks of captured steps:
+// FP32 storage, the instantaneous model and the force only (no moving wall,
+// no pressure drive) on vector-class channels, with blocks a multiple of
+// four steps (a block is then an even number of two-step launches and
+// returns the state to its buffer, as one-step launches do).
+bool two_step_handle(const lb_options *o, int K) {
+  return o->steps_per_sweep != 1 && o->precision == LB_FP32_SHIFTED && !o->viscoelastic && !o->stress_force &&
+         K % 4 == 0;
+}
+bool two_step_channel(const lb_channel &c) {
+  return width_class(c.nx, 4) == kVecClass && c.top_wall == LB_WALL_HALFWAY && c.wall_velocity == 0 &&
+         c.pressure_gradient == 0;
+}
+// Stored columns of the two-step strips of a width: at most kTwoStepCols,
+// multiples of four, as even as possible.
+std::vector<int> two_step_cuts(int nx) {
+  const int quads = nx / 4, m = (nx + kTwoStepCols - 1) / kTwoStepCols;
+  std::vector<int> x(1, 0);
+  for (int i = 0; i < m; ++i) x.push_back(x.back() + 4 * (quads / m + (i < quads % m)));
+  return x;
+}
+// Rows per two-step strip: whole rounds of resident wavefronts (one per
+// SIMD) cost each strip's rows plus its four extra rows of step t and about
+// two rows of start-up, so the height minimises rounds x (rows + 6) over
+// 16..32 rows.
+int two_step_rows(const std::vector<lb_channel> &chans, int slots) {
+  int best = 16;
+  double best_cost = 1e300;
+  for (int H = 16; H <= 32; ++H) {
+    long long S = 0;
+    for (const lb_channel &c : chans) S += (long long)(two_step_cuts(c.nx).size() - 1) * ((c.ny + H - 1) / H);
+    const double cost = (double)((S + slots - 1) / std::max(slots, 1)) * (H + 6);
+    if (S > 0 && cost < best_cost) {
+      best_cost = cost;
+      best = H;
+    }
+  }
+  return best;
+}
+void add_two_step_strips(int ci, const lb_channel &c, int H, std::vector<Strip> &out) {
+  const std::vector<int> x = two_step_cuts(c.nx);
+  for (int y0 = 0; y0 < c.ny; y0 += H)
+    for (size_t s = 0; s + 1 < x.size(); ++s)
+      out.push_back(Strip{ci, x[s], y0, std::min(y0 + H, c.ny), 0, x[s + 1]});
+}
+
 // The tiled step: the fused stress-force kernel for every channel of a
 // stress-force handle; the FP64 tile sweep for FP64 channels of the strip
 // classes whose slots fit 32-bit offsets (the others keep the strip sweeps).
@@ -282,6 +333,12 @@ Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
   for (int i = 0; i < n; ++i)
     if (tiled(o, c[i])) L.n_tiles += ((c[i].nx + ts.tx - 1) / ts.tx) * ((c[i].ny + ts.ty - 1) / ts.ty);
   L.off_tiles = take(sizeof(Strip) * L.n_tiles);
+  L.off_bstrips = take(sizeof(Strip) * strips);
+  L.off_brstrips = take(sizeof(Strip) * strips);
+  for (int i = 0; i < n && two_step_handle(o, o->obs_every > 0 ? o->obs_every : kDefaultK); ++i)
+    if (two_step_channel(c[i]))
+      L.max_two += (int)(two_step_cuts(c[i].nx).size() - 1) * ((c[i].ny + 15) / 16);
+  L.off_tstrips = take(sizeof(Strip) * std::max(L.max_two, 1));
   L.bytes = at;
   return L;
 }
@@ -308,6 +365,12 @@ struct lb_handle {
   // strips grouped by width class: [begin, begin + count) in the arrays
   int all_begin[kClasses] = {0}, all_count[kClasses] = {0};
   int act_begin[kClasses] = {0}, act_count[kClasses] = {0};
+  Strip *dbact = nullptr, *dbact_rev = nullptr;  // captured blocks: active channels without two-step strips
+  Strip *dtwo = nullptr;                        // two-step strips of the active channels
+  int bact_begin[kClasses] = {0}, bact_count[kClasses] = {0};
+  int two_count = 0;
+  bool two_step = false;     // captured blocks pair their steps where eligible
+  int slots = 1024;          // resident wavefronts at one per SIMD
   int cur = 0;               // buffer holding the current state
   hipStream_t stream = nullptr, cap = nullptr;
   bool own_stream = false;
@@ -319,6 +382,7 @@ struct lb_handle {
   int n_checks = 0;
   int since_block = 0;       // steps since the last block boundary (handle clock)
   bool any_gpbc = false;     // some channel has the pressure drive
+  bool any_zh = false;       // some channel has a Zou-He top wall
   int device = -1;           // the GPU current at lb_create
   double *noalloc = nullptr; // that GPU's copy of `scratch` (device address)
   hipError_t noalloc_err = hipSuccess;
@@ -380,6 +444,39 @@ lb_status upload_strips(lb_handle *h, bool all) {
       HIPCHECK(h, hipMemcpyAsync(h->dact_rev, rev.data(), rev.size() * sizeof(Strip), hipMemcpyHostToDevice,
                                  h->stream));
     }
+    // captured blocks: two-step strips for the eligible active channels, the
+    // one-step strips of the others
+    std::vector<Strip> braw, bgrouped, two;
+    if (h->two_step) {
+      std::vector<lb_channel> elig;
+      for (int i = 0; i < h->n_ch; ++i)
+        if (h->active[i] && two_step_channel(h->in[i])) elig.push_back(h->in[i]);
+      const int H = two_step_rows(elig, h->slots);
+      for (int i = 0; i < h->n_ch; ++i) {
+        if (!h->active[i] || tiled(&h->opt, h->in[i])) continue;
+        if (two_step_channel(h->in[i])) {
+          add_two_step_strips(i, h->in[i], H, two);
+        } else {
+          const ChanDev &d = h->L.ch[i];
+          add_strips(i, d, h->L.esize,
+                     strip_rows_for(width_class(d.nx, h->L.esize), d.nx, d.ny, h->opt.strip_rows), stack, braw);
+        }
+      }
+    }
+    group_strips(braw, h->L.ch, h->L.esize, bgrouped, h->bact_begin, h->bact_count);
+    std::vector<Strip> brev(bgrouped);
+    for (int c = 0; c < kClasses; ++c)
+      std::reverse(brev.begin() + h->bact_begin[c], brev.begin() + h->bact_begin[c] + h->bact_count[c]);
+    if (!bgrouped.empty()) {
+      HIPCHECK(h, hipMemcpyAsync(h->dbact, bgrouped.data(), bgrouped.size() * sizeof(Strip), hipMemcpyHostToDevice,
+                                 h->stream));
+      HIPCHECK(h, hipMemcpyAsync(h->dbact_rev, brev.data(), brev.size() * sizeof(Strip), hipMemcpyHostToDevice,
+                                 h->stream));
+    }
+    if ((int)two.size() > h->L.max_two) return fail(h, LB_ENOMEM, "two-step strip list exceeds its workspace");
+    h->two_count = (int)two.size();
+    if (!two.empty())
+      HIPCHECK(h, hipMemcpyAsync(h->dtwo, two.data(), two.size() * sizeof(Strip), hipMemcpyHostToDevice, h->stream));
     // the host vectors die here: make the copies complete first
     HIPCHECK(h, hipStreamSynchronize(h->stream));
   }
@@ -402,13 +499,15 @@ SweepArgs sweep_args(lb_handle *h, const Strip *strips, int begin, int count, in
   a.nt = (long long)kPlanes * h->L.plane * h->L.esize > kNontemporalBytes;
   a.uref = h->duref;
   a.ve = h->opt.viscoelastic;
+  a.zh = h->any_zh;
   a.SA = h->sbuf[src];
   a.SB = h->sbuf[src ^ 1];
   return a;
 }
 
-// Enqueues the sweeps of one step (source buffer src, step offset k).
-lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s) {
+// Enqueues the sweeps of one step (source buffer src, step offset k), over
+// every active channel or (block) over those without two-step strips.
+lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s, bool block = false) {
   if (h->opt.stress_force) {
     HIPCHECK(h, launch_saf_fused(static_cast<const double *>(h->buf[src]), static_cast<double *>(h->buf[src ^ 1]),
                                  h->dch, h->tiles, h->L.n_tiles, k,
@@ -416,14 +515,16 @@ lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s) {
     return LB_OK;
   }
   if (h->L.n_tiles) HIPCHECK(h, launch_tiles(sweep_args(h, h->tiles, 0, h->L.n_tiles, src, k), s));
+  const int *begin = block ? h->bact_begin : h->act_begin, *count = block ? h->bact_count : h->act_count;
+  Strip *fwd = block ? h->dbact : h->dact, *rev = block ? h->dbact_rev : h->dact_rev;
   for (int c = 0; c < kClasses; ++c) {
-    if (!h->act_count[c]) continue;
+    if (!count[c]) continue;
     // Serpentine order: steps reading buffer 0 take the strips in order and
     // march them upwards, steps reading buffer 1 take them in reverse and
     // march downwards (flipped strips of a stack the other way in both), so
     // that every step starts on what the previous step wrote last, the
     // likeliest to still sit in the last-level cache (MALL).
-    SweepArgs a = sweep_args(h, src == 0 ? h->dact : h->dact_rev, h->act_begin[c], h->act_count[c], src, k);
+    SweepArgs a = sweep_args(h, src == 0 ? fwd : rev, begin[c], count[c], src, k);
     a.down = (src == 1);
     HIPCHECK(h, launch_sweep(h->opt.precision == LB_FP32_SHIFTED, c, false, a, s));
   }
@@ -473,7 +574,23 @@ lb_status capture(lb_handle *h, int src) {
   hipGraph_t g = nullptr;
   HIPCHECK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed));
   lb_status st = LB_OK;
-  for (int k = 0; k < h->K && st == LB_OK; ++k) st = enqueue_step(h, src ^ (k & 1), k, h->cap);
+  if (h->two_step) {
+    // pairs of steps: one two-step launch for the eligible channels (its
+    // j-th launch reads buffer src ^ (j & 1) and writes the other one), and
+    // the one-step launches of the others
+    for (int k = 0; k < h->K && st == LB_OK; k += 2) {
+      if (h->two_count) {
+        SweepArgs a = sweep_args(h, h->dtwo, 0, h->two_count, src ^ ((k / 2) & 1), k);
+        a.n_wg = (h->two_count + kTwoStepWaves - 1) / kTwoStepWaves;
+        hipError_t e = launch_two_step(a, h->cap);
+        if (e != hipSuccess) st = hipfail(h, e, "launch_two_step");
+      }
+      if (st == LB_OK) st = enqueue_step(h, src, k, h->cap, true);
+      if (st == LB_OK) st = enqueue_step(h, src ^ 1, k + 1, h->cap, true);
+    }
+  } else {
+    for (int k = 0; k < h->K && st == LB_OK; ++k) st = enqueue_step(h, src ^ (k & 1), k, h->cap);
+  }
   if (st == LB_OK) {
     hipError_t e = launch_advance(h->dch, h->n_ch, h->K, h->cap);
     if (e != hipSuccess) st = hipfail(h, e, "launch_advance");
@@ -701,7 +818,10 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
   }
   h->opt = *o;
   h->n_ch = n;
-  for (int i = 0; i < n; ++i) h->any_gpbc = h->any_gpbc || h->L.ch[i].gpbc;
+  for (int i = 0; i < n; ++i) {
+    h->any_gpbc = h->any_gpbc || h->L.ch[i].gpbc;
+    h->any_zh = h->any_zh || h->L.ch[i].zh;
+  }
   h->K = o->obs_every > 0 ? o->obs_every : kDefaultK;
   h->in.assign(c, c + n);
   h->ws = static_cast<char *>(ws);
@@ -712,6 +832,10 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
   h->dall = reinterpret_cast<Strip *>(h->ws + h->L.off_strips);
   h->dact = reinterpret_cast<Strip *>(h->ws + h->L.off_astrips);
   h->dact_rev = reinterpret_cast<Strip *>(h->ws + h->L.off_rstrips);
+  h->dbact = reinterpret_cast<Strip *>(h->ws + h->L.off_bstrips);
+  h->dbact_rev = reinterpret_cast<Strip *>(h->ws + h->L.off_brstrips);
+  h->dtwo = reinterpret_cast<Strip *>(h->ws + h->L.off_tstrips);
+  h->two_step = two_step_handle(o, h->K) && h->L.max_two > 0;
   h->dpart = reinterpret_cast<double *>(h->ws + h->L.off_part);
   h->dprof = reinterpret_cast<double *>(h->ws + h->L.off_prof);
   h->dprev = reinterpret_cast<double *>(h->ws + h->L.off_prev);
@@ -751,6 +875,14 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
   if (hipMemcpyAsync(h->duref, zrows.data(), sizeof(float) * h->L.total_rows, hipMemcpyHostToDevice, h->stream) !=
       hipSuccess)
     return bail(LB_EHIP);
+  {
+    // resident wavefronts of the two-step sweep: one per SIMD, four per CU
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return bail(LB_EHIP);
+    h->slots = 4 * std::max(cus, 1);
+  }
   if (upload_strips(h, true) != LB_OK || upload_strips(h, false) != LB_OK) return bail(LB_EHIP);
   std::vector<Strip> tiles;  // kept until the synchronisation below
   for (int i = 0; i < n; ++i)

@@ -43,7 +43,8 @@ class LbChannel(C.Structure):
 
 class LbOptions(C.Structure):
     _fields_ = [("precision", C.c_int32), ("obs_every", C.c_int32), ("strip_rows", C.c_int32),
-                ("steady_tol", C.c_double), ("viscoelastic", C.c_int32), ("stress_force", C.c_int32)]
+                ("steady_tol", C.c_double), ("viscoelastic", C.c_int32), ("stress_force", C.c_int32),
+                ("steps_per_sweep", C.c_int32)]
 
 
 class LbError(RuntimeError):
@@ -121,11 +122,12 @@ def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def options(precision=FP64, obs_every=1000, strip_rows=0, steady_tol=0.0, viscoelastic=False, stress_force=False):
+def options(precision=FP64, obs_every=1000, strip_rows=0, steady_tol=0.0, viscoelastic=False, stress_force=False,
+            steps_per_sweep=0):
     if isinstance(precision, str):
         precision = {"fp64": FP64, "fp32": FP32_SHIFTED, "fp32_shifted": FP32_SHIFTED}[precision]
     return LbOptions(int(precision), int(obs_every), int(strip_rows), float(steady_tol), int(bool(viscoelastic)),
-                     int(bool(stress_force)))
+                     int(bool(stress_force)), int(steps_per_sweep))
 
 
 def channel_array(channels: Sequence[ChannelSpec], default_nn_pressure=True):
@@ -148,17 +150,20 @@ class Solver:
     whose spec leaves it None. ``viscoelastic`` selects the time-integrated
     nonlinear Maxwell stress (lb_options.viscoelastic) in place of the
     instantaneous one; ``stress_force`` makes the stress enter as the force
-    density div Sigma^nN (lb_options.stress_force; FP64, nn_pressure False)."""
+    density div Sigma^nN (lb_options.stress_force; FP64, nn_pressure False).
+    ``steps_per_sweep`` is lb_options.steps_per_sweep (0: two steps per pass
+    where eligible, 1: one)."""
 
     def __init__(self, channels: Sequence[ChannelSpec], precision="fp64", nn_pressure=True,
                  obs_every=1000, strip_rows=0, steady_tol=0.0, stream=None, device="cuda", viscoelastic=False,
-                 stress_force=False):
+                 stress_force=False, steps_per_sweep=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("lbnlm needs a GPU; no CPU fallback exists")
         self.L = load_library()
         self.channels = list(channels)
-        self.opts = options(precision, obs_every, strip_rows, steady_tol, viscoelastic, stress_force)
+        self.opts = options(precision, obs_every, strip_rows, steady_tol, viscoelastic, stress_force,
+                            steps_per_sweep)
         self.default_nn_pressure = bool(nn_pressure)
         nbytes = workspace_bytes(self.channels, self.opts, self.default_nn_pressure)
         self.device = torch.device(device)

@@ -145,3 +145,13 @@ def test_solver_refuses_without_gpu():
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError):
         lbnlm.Solver([spec()])
+
+
+def test_steps_per_sweep_values():
+    """lb_options.steps_per_sweep takes 0, 1 or 2; other values are rejected
+    before any allocation."""
+    for v in (0, 1, 2):
+        assert lbnlm.workspace_bytes([spec(nx=512, ny=8)], lbnlm.options("fp32", steps_per_sweep=v)) > 0
+    for v in (-1, 3):
+        with pytest.raises(lbnlm.LbError):
+            lbnlm.workspace_bytes([spec(nx=512, ny=8)], lbnlm.options("fp32", steps_per_sweep=v))
