@@ -38,7 +38,8 @@ BYTES_PER_NODE_SAF = 160
 def measured_traffic(key):
     """HBM bytes per sweep launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size) for
-    'fp32', 'fp64' (4096 x 1024) or 'transient_fp32' (16 x 8192 x 2048), or
+    'fp32' (two steps per launch), 'fp32_one' (one step), 'fp64' (4096 x 1024)
+    or 'transient_fp32' (16 x 8192 x 2048, two steps per launch), or
     None when the kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic_sweep_vec.json")
     if not os.path.exists(path):
@@ -53,13 +54,14 @@ def measured_traffic(key):
     return None if k is None else round(k["traffic_bytes"])
 
 
-def time_solver(precision, wl, steps, warmup, strip_rows=0, viscoelastic=False, stress_force=False):
+def time_solver(precision, wl, steps, warmup, strip_rows=0, viscoelastic=False, stress_force=False,
+                steps_per_sweep=0):
     import torch
     from paper_1310_7450_amd import Solver
     spec = wl["channels"][0]
     nodes = spec.nx * spec.ny
     with Solver([spec], precision=precision, obs_every=1000, strip_rows=strip_rows, viscoelastic=viscoelastic,
-                stress_force=stress_force, nn_pressure=not stress_force) as s:
+                stress_force=stress_force, nn_pressure=not stress_force, steps_per_sweep=steps_per_sweep) as s:
         s.step(warmup)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -149,7 +151,7 @@ def batched_oracle_fixture():
     return mod.load()
 
 
-def run_transient_scale(steps=200, warmup=50):
+def run_transient_scale(steps=200, warmup=100):
     """Throughput of the start-up/cessation workload at full size: 16
     channels of 8192 x 2048 (268M nodes), FP32 shifted, from rest with the
     force on. The protocol itself (250,000 steps, stopping times) runs on the
@@ -159,7 +161,9 @@ def run_transient_scale(steps=200, warmup=50):
     wl = workloads.transient_scale()
     chans = wl["channels"]
     nodes = sum(c.nx * c.ny for c in chans)
-    with Solver(chans, precision="fp32", obs_every=1000) as s:
+    # blocks of 100 steps, so that the timed steps are whole captured blocks
+    # (two steps per pass)
+    with Solver(chans, precision="fp32", obs_every=100) as s:
         s.step(warmup)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -172,8 +176,27 @@ def run_transient_scale(steps=200, warmup=50):
     achieved = BYTES_PER_NODE["fp32"] * nodes * steps / sec / 1e9
     return {"workload": wl["name"], "nodes": nodes, "steps": steps, "value": round(nodes * steps / sec / 1e6, 1),
             "unit": "MLUPS", "ms_per_step": round(sec * 1e3 / steps, 4),
-            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("transient_fp32")}}
+            "roofline": two_step_roofline(achieved, nodes, sec / steps, measured_traffic("transient_fp32"))}
+
+
+def two_step_roofline(achieved, nodes, sec_per_step, traffic):
+    """Roofline of the FP32 two-step sweep (sweep_vec2_kernel): one launch
+    performs two node updates per node, so at 80 B per node update its
+    algorithmic bytes are 160 B per node and launch; the state itself is read
+    and written once per launch (80 B per node), which state_GBs reports
+    beside the counters' traffic per launch."""
+    state = BYTES_PER_NODE["fp32"] * nodes / (2 * sec_per_step) / 1e9
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+           "kernel": "sweep_vec2_kernel", "node_updates_per_launch": 2 * nodes,
+           "bytes_per_node_update": BYTES_PER_NODE["fp32"],
+           "algorithmic_bytes_per_launch": 2 * BYTES_PER_NODE["fp32"] * nodes,
+           "state_bytes_per_launch": BYTES_PER_NODE["fp32"] * nodes, "state_GBs": round(state, 1),
+           "state_frac": round(state / HBM_PEAK_GBS, 4)}
+    if traffic is not None:
+        out["traffic_GBs"] = round(traffic / (2 * sec_per_step) / 1e9, 1)
+    return out
 
 
 def run_viscoelastic(steps=2000, warmup=1000):
@@ -324,6 +347,9 @@ def main():
           file=sys.stderr, flush=True)
     r32 = time_solver("fp32", wl, args.steps, args.warmup, args.strip_rows)
     print(f"bench: fp32 {r32['mlups']:.0f} MLUPS, {r32['achieved_GBs']:.0f} GB/s", file=sys.stderr, flush=True)
+    r32one = time_solver("fp32", wl, min(args.steps, 4000), min(args.warmup, 1000), args.strip_rows,
+                         steps_per_sweep=1)
+    print(f"bench: fp32 one step per pass {r32one['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     r64 = None
     if not args.no_fp64:
         r64 = time_solver("fp64", wl, args.steps, args.warmup, args.strip_rows)
@@ -376,9 +402,13 @@ def main():
                    "force": spec.force, "eps": spec.eps, "tau_lb": spec.tau_lb, "G": spec.G,
                    "tau0": spec.tau0, "gamma_c": spec.gamma_c, "precision": "fp32_shifted",
                    "nn_pressure": 1, "start": "rest"},
-        "roofline": {"bound": "hbm", "achieved": round(r32["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(r32["frac"], 4), "traffic": measured_traffic("fp32"),
-                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"},
+        "roofline": two_step_roofline(r32["achieved_GBs"], spec.nx * spec.ny, r32["ms_per_step"] / 1e3,
+                                      measured_traffic("fp32")),
+        "fp32_one_step_per_pass": {
+            "value": round(r32one["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r32one["ms_per_step"], 5),
+            "roofline": {"bound": "hbm", "achieved": round(r32one["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(r32one["frac"], 4), "traffic": measured_traffic("fp32_one"),
+                         "kernel": "sweep_vec_kernel"}},
         "fp64": None if r64 is None else {
             "value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 5),
             "roofline": {"bound": "hbm", "achieved": round(r64["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,

@@ -139,7 +139,9 @@ enum { LB_WALL_HALFWAY = 0, LB_WALL_ZOU_HE = 1 };
  *   obs_every    K, the length of one block of steps (one captured graph);
  *                the convergence check and the FP32 reference move run at
  *                the block boundaries; even, >= 2 (default 1000 when 0);
- *   strip_rows   rows per wavefront strip of the sweep (0: tuned default);
+ *   strip_rows   rows per wavefront strip of the sweep, also of the
+ *                two-step sweep below (0: tuned default; the two-step
+ *                default fills whole rounds of one wavefront per SIMD);
  *                FP64 channels whose width is not a power of two up to 64
  *                (and whose nx * ny is at most 429,496,704) step on tiles of
  *                64 x 8 nodes instead and do not use it;

@@ -64,6 +64,13 @@ __device__ __forceinline__ T recip(T v) {
   if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(v);
   return T(1) / v;
 }
+// Square root: FP32 takes the hardware instruction (1 ulp, like the
+// reciprocal above) instead of the correctly rounded sequence.
+template <typename T>
+__device__ __forceinline__ T root(T v) {
+  if constexpr (sizeof(T) == 4) return __builtin_amdgcn_sqrtf(v);
+  return sqrt(v);
+}
 
 // Lane moves across the whole wavefront: shift_up gives lane i the value of
 // lane i-1 (lane 0 gets `edge`), shift_down gives lane i the value of lane
@@ -270,15 +277,18 @@ struct Coef {
 // gradient k_ab = d_b u_a: tau_M from the shear rate, then the steady sum
 // through the relation it satisfies by Eq. (smalld),
 // sigma - tau_M (kappa sigma + sigma kappa^T) = G tau_M D, solved in closed
-// form (Cramer) for (sigma_xx, sigma_xy, sigma_yy). Leaves the outputs
-// untouched when the relaxation rate vanishes (tau = inf and D = 0).
+// form (Cramer) for (sigma_xx, sigma_xy, sigma_yy). The relaxation rate
+// vanishes only for tau = inf and D = 0; any finite tau_M then gives the
+// right sigma = 0 (every right-hand side is zero), so tau_M = 1 is taken
+// there instead of a branch.
 template <typename T>
 __device__ __forceinline__ void inlm_stress(T kxx, T kxy, T kyx, T kyy, const Coef<T> &q, T &sxx, T &sxy,
                                             T &syy) {
   const T Dxx = T(2) * kxx, Dxy = kxy + kyx, Dyy = T(2) * kyy;
   const T II = T(0.5) * (Dxx * Dxx + T(2) * Dxy * Dxy + Dyy * Dyy);
-  const T rate = q.inv_tau + sqrt(II) * q.inv_gc;
-  if (rate > T(0)) {
+  const T r0 = q.inv_tau + root(II) * q.inv_gc;
+  const T rate = r0 > T(0) ? r0 : T(1);
+  {
     const T tM = recip<T>(rate);
     const T ka = tM * kxx, kb = tM * kxy, kc = tM * kyx, kd = tM * kyy;
     const T gt = q.G * tM;
@@ -331,7 +341,7 @@ __device__ __forceinline__ void node_update(const T f[9], T sd, T mx, T my, T Pc
     // G D] / (1 + 1/tau_M), written as sigma plus its increment so that FP32
     // rounds only the increment.
     const T II = T(0.5) * (Dxx * Dxx + T(2) * Dxy * Dxy + Dyy * Dyy);
-    const T rate = q.inv_tau + sqrt(II) * q.inv_gc;  // 1 / tau_M
+    const T rate = q.inv_tau + root(II) * q.inv_gc;  // 1 / tau_M
     const T d = recip<T>(T(1) + rate);
     const T cxx = T(2) * (kxx * sp[0] + kxy * sp[1]);
     const T cxy = kxx * sp[1] + kxy * sp[2] + kyx * sp[0] + kyy * sp[1];
@@ -1488,8 +1498,10 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
 //    post-collision populations and trace go into a ring of four rows in
 //    LDS instead of memory;
 //  * stage B (step t+1) is the same machine reading its rows from that ring,
-//    two rows behind stage A, and stores rows y0 .. y1-1 of lanes 1..62
-//    to the other buffer.
+//    three rows behind stage A, and stores rows y0 .. y1-1 of lanes 1..62
+//    to the other buffer. Each iteration issues the loads of stage A's next
+//    row first, runs stage B from LDS while they are in flight, then
+//    assembles that row and updates stage A's current one.
 // After step t the window's two outermost columns on each side lack valid
 // neighbours for step t+1; lanes 0 and 63 hold them and store nothing, so
 // every stored node saw only values of the exact step-t state. Per node the
@@ -1635,8 +1647,12 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArg
   // Pulled populations, P, moments and u~ of the window's columns of row y,
   // and u~ of the two columns beside it (the vector sweep's assembly, fixed
   // walls).
-  auto assemble = [&](int y, const Raw &R, T fx, T f[9][NPL], T P[NPL], T sd[NPL], T mx[NPL], T my[NPL],
-                      U2<T> u[NPL], U2<T> &uL, U2<T> &uR, T ur3[3]) __attribute__((always_inline)) {
+  // With sides false (stage B) the values beside the window are not formed:
+  // only lanes 0 and 63 would use them, and those store nothing.
+  auto assemble = [&](auto sides, int y, const Raw &R, T fx, T f[9][NPL], T P[NPL], T sd[NPL], T mx[NPL],
+                      T my[NPL], U2<T> u[NPL], U2<T> &uL, U2<T> &uR, T ur3[3]) __attribute__((always_inline)) {
+    constexpr bool SIDES = decltype(sides)::value;
+    auto edge = [&](int i) __attribute__((always_inline)) { return SIDES ? lane_value(R.side, i) : T(0); };
     const bool bot = (y == 0), top = (y == ny - 1);
     auto from_left = [&](const V &r, T edge, T out[NPL]) __attribute__((always_inline)) {
       out[0] = shift_up(edge, r[NPL - 1]);
@@ -1653,8 +1669,8 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArg
       for (int k = 0; k < NPL; ++k) out[k] = r[k];
     };
     split(R.r[0], f[0]);
-    from_left(R.r[1], lane_value(R.side, 0), f[1]);
-    from_right(R.r[3], lane_value(R.side, 1), f[3]);
+    from_left(R.r[1], edge(0), f[1]);
+    from_right(R.r[3], edge(1), f[3]);
     split(R.r[9], P);
     split(R.r[2], f[2]);
     split(R.r[4], f[4]);
@@ -1662,15 +1678,15 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArg
       split(R.r[5], f[5]);
       split(R.r[6], f[6]);
     } else {
-      from_left(R.r[5], lane_value(R.side, 2), f[5]);
-      from_right(R.r[6], lane_value(R.side, 3), f[6]);
+      from_left(R.r[5], edge(2), f[5]);
+      from_right(R.r[6], edge(3), f[6]);
     }
     if (top) {
       split(R.r[7], f[7]);
       split(R.r[8], f[8]);
     } else {
-      from_right(R.r[7], lane_value(R.side, 4), f[7]);
-      from_left(R.r[8], lane_value(R.side, 5), f[8]);
+      from_right(R.r[7], edge(4), f[7]);
+      from_left(R.r[8], edge(5), f[8]);
     }
     const T urd = lane_value(R.side, 24), urc = lane_value(R.side, 25), uru = lane_value(R.side, 26);
     ur3[0] = urd;
@@ -1686,6 +1702,10 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArg
       for (int i = 0; i < 9; ++i) f[i][k] = g[i];
       moments<T>(g, sd[k], mx[k], my[k]);
       u[k] = u_tilde<T, SHIFT>(sd[k], mx[k], my[k], fx, urc);
+    }
+    if constexpr (!SIDES) {
+      uL = uR = U2<T>{T(0), T(0)};
+      return;
     }
     T l[9], r[9];
     l[0] = lane_value(R.side, 6);
@@ -1751,38 +1771,33 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArg
   // ---- rows of the two stages
   const int A0 = st.y0 - 2 < 0 ? 0 : st.y0 - 2, A1 = st.y1 + 2 > ny ? ny : st.y1 + 2;
   const int R0 = st.y0 - 1 < 0 ? 0 : st.y0 - 1, R1 = st.y1 + 1 > ny ? ny : st.y1 + 1;
-  const int iend = (A1 - 1 > st.y1 + 1 ? A1 - 1 : st.y1 + 1) + 1;  // iterations [A0, iend)
+  const int iend = st.y1 + 3;  // iterations [A0, iend): stage B updates row i - 3
   // stage B's stores: lanes whose four columns lie in [x0, x1)
   const bool store_lane = lane >= 1 && 4 * (lane - 1) < st.x1 - st.x0;
 
-  // stage A state (the vector sweep's pipeline, ring depth 2)
-  constexpr int D = 2;
-  auto ring_row = [&](int y) __attribute__((always_inline)) { return clampy(y < A0 - 1 ? A0 - 1 : (y > A1 ? A1 : y)); };
+  // stage A state: the assembled row i and u~ of rows i-1 and i
   T fc[9][NPL], Pc[NPL], sdc[NPL], mxc[NPL], myc[NPL];
   U2<T> uPrev[NPL], uCur[NPL], uLc, uRc;
   T urC[3];
-  Raw S[D];
   {
     Raw Rp, Rf;
     const int yp = clampy(A0 - 1);
     load_raw(yp, Rp);
     load_raw(A0, Rf);
-#pragma unroll
-    for (int k = 1; k < D; ++k) load_raw(ring_row(A0 + k), S[k]);
     T ftmp[9][NPL], Ptmp[NPL], s0[NPL], m0[NPL], n0[NPL], ur_unused[3];
     U2<T> hl, hr;
-    assemble(yp, Rp, fxA, ftmp, Ptmp, s0, m0, n0, uPrev, hl, hr, ur_unused);
-    assemble(A0, Rf, fxA, fc, Pc, sdc, mxc, myc, uCur, uLc, uRc, urC);
+    assemble(std::true_type{}, yp, Rp, fxA, ftmp, Ptmp, s0, m0, n0, uPrev, hl, hr, ur_unused);
+    assemble(std::true_type{}, A0, Rf, fxA, fc, Pc, sdc, mxc, myc, uCur, uLc, uRc, urC);
   }
-  // stage B state: the assembled row i-2 and u~ of rows i-3 and i-1
+  // stage B state: the assembled row i-3 and u~ of rows i-4 and i-3
   T fB[9][NPL], PB[NPL], sdB[NPL], mxB[NPL], myB[NPL], urB[3];
   U2<T> uBp[NPL], uBc[NPL], uBLc, uBRc;
 
-  auto stage_a = [&](int y, Raw &Rload, const Raw &Rasm) __attribute__((always_inline)) {
-    load_raw(ring_row(y + D), Rload);
+  // stage A's update of row y, with row y+1 assembled from Rasm
+  auto stage_a = [&](int y, const Raw &Rasm) __attribute__((always_inline)) {
     T fn[9][NPL], Pn[NPL], sdn[NPL], mxn[NPL], myn[NPL], urN[3];
     U2<T> uNext[NPL], uLn, uRn;
-    assemble(clampy(y + 1), Rasm, fxA, fn, Pn, sdn, mxn, myn, uNext, uLn, uRn, urN);
+    assemble(std::true_type{}, clampy(y + 1), Rasm, fxA, fn, Pn, sdn, mxn, myn, uNext, uLn, uRn, urN);
     V out[kPlanes];
     update(y, fxA, fc, Pc, sdc, mxc, myc, uPrev, uCur, uNext, uLc, uRc, urC, out);
     const int slot = y & (kV2Ring - 1);
@@ -1808,13 +1823,13 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArg
   };
 
   auto stage_b = [&](int i) __attribute__((always_inline)) {
-    const int r = i - 1, y = i - 2;
+    const int r = i - 2, y = i - 3;
     T fn[9][NPL], Pn[NPL], sdn[NPL], mxn[NPL], myn[NPL], urN[3];
     U2<T> uNext[NPL], uLn, uRn;
     if (r >= R0 && r < R1) {
       Raw R;
       load_lds(r, R);
-      assemble(r, R, fxB, fn, Pn, sdn, mxn, myn, uNext, uLn, uRn, urN);
+      assemble(std::false_type{}, r, R, fxB, fn, Pn, sdn, mxn, myn, uNext, uLn, uRn, urN);
     } else {
 #pragma unroll
       for (int k = 0; k < NPL; ++k) {
@@ -1856,15 +1871,20 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArg
     }
   };
 
-  // stage A rows [A0, A1) unrolled D times (fixed ring registers), each
-  // followed by stage B's iteration; then stage B drains
+  // Stage B's iteration i assembles row i-2 and updates row i-3. Iteration
+  // i: the loads of row i+1 (row A1 at the last, in the lattice or clamped
+  // to its top row), stage B, then stage A's row i; stage A's rows [A0, A1)
+  // unrolled twice (the two-deep state swaps stay in fixed registers), then
+  // stage B drains.
 #pragma unroll 1
-  for (int i = A0; i < A1; i += D) {
+  for (int i = A0; i < A1; i += 2) {
 #pragma unroll
-    for (int j = 0; j < D; ++j)
+    for (int j = 0; j < 2; ++j)
       if (j == 0 || i + j < A1) {
-        stage_a(i + j, S[j], S[(j + 1) % D]);
+        Raw R;
+        load_raw(clampy(i + j + 1), R);
         stage_b(i + j);
+        stage_a(i + j, R);
       }
   }
 #pragma unroll 1

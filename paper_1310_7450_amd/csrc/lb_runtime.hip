@@ -335,9 +335,10 @@ Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
   L.off_tiles = take(sizeof(Strip) * L.n_tiles);
   L.off_bstrips = take(sizeof(Strip) * strips);
   L.off_brstrips = take(sizeof(Strip) * strips);
+  const int min_rows = o->strip_rows > 0 ? std::min(o->strip_rows, 16) : 16;
   for (int i = 0; i < n && two_step_handle(o, o->obs_every > 0 ? o->obs_every : kDefaultK); ++i)
     if (two_step_channel(c[i]))
-      L.max_two += (int)(two_step_cuts(c[i].nx).size() - 1) * ((c[i].ny + 15) / 16);
+      L.max_two += (int)(two_step_cuts(c[i].nx).size() - 1) * ((c[i].ny + min_rows - 1) / min_rows);
   L.off_tstrips = take(sizeof(Strip) * std::max(L.max_two, 1));
   L.bytes = at;
   return L;
@@ -451,7 +452,7 @@ lb_status upload_strips(lb_handle *h, bool all) {
       std::vector<lb_channel> elig;
       for (int i = 0; i < h->n_ch; ++i)
         if (h->active[i] && two_step_channel(h->in[i])) elig.push_back(h->in[i]);
-      const int H = two_step_rows(elig, h->slots);
+      const int H = h->opt.strip_rows > 0 ? h->opt.strip_rows : two_step_rows(elig, h->slots);
       for (int i = 0; i < h->n_ch; ++i) {
         if (!h->active[i] || tiled(&h->opt, h->in[i])) continue;
         if (two_step_channel(h->in[i])) {
