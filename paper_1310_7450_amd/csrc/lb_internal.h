@@ -162,7 +162,8 @@ hipError_t launch_rereference(float *A, const ChanDev *ch, int n_ch, int total_r
 // half-way walls and no pressure drive); SweepArgs.strips holds the strips,
 // n_strips their number; the state goes from A to B over steps k and k+1.
 constexpr int kTwoStepCols = 248;
-constexpr int kTwoStepWaves = 2;
+// wavefronts per strip (one per stage) and the most rows a strip may have
+constexpr int kTwoStepWaves = 2, kTwoStepMaxRows = 56;
 hipError_t launch_two_step(const SweepArgs &a, hipStream_t s);
 
 }  // namespace lbnlm

@@ -1487,21 +1487,23 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
 // ---------------------------------------------------------------------------
 // Two steps per launch. For FP32 storage relative to the row references,
 // the instantaneous model, vector-class channels (nx a multiple of 256) with
-// fixed half-way walls and no pressure drive, one wavefront takes an output
-// strip of at most 248 columns [x0, x1) and rows [y0, y1) through steps t
-// and t+1 without writing step t to memory:
+// fixed half-way walls and no pressure drive, one workgroup of two
+// wavefronts takes an output strip of at most 248 columns [x0, x1) and rows
+// [y0, y1) through steps t and t+1 without writing step t to memory:
 //  * the window is the 256 columns starting four columns left of x0 (four
 //    per lane, wrapped periodically), with one column beside it on either
 //    side as the vector sweep has;
-//  * stage A (step t) is the vector sweep's row machine over the window for
-//    rows max(y0-2, 0) .. min(y1+2, ny)-1, read from the state; each row's
-//    post-collision populations and trace go into a ring of four rows in
-//    LDS instead of memory;
-//  * stage B (step t+1) is the same machine reading its rows from that ring,
-//    three rows behind stage A, and stores rows y0 .. y1-1 of lanes 1..62
-//    to the other buffer. Each iteration issues the loads of stage A's next
-//    row first, runs stage B from LDS while they are in flight, then
-//    assembles that row and updates stage A's current one.
+//  * wavefront 0 runs stage A (step t): the vector sweep's row machine over
+//    the window for rows max(y0-2, 0) .. min(y1+2, ny)-1, read from the
+//    state; each row's post-collision populations and trace go into a ring
+//    of four rows in LDS instead of memory;
+//  * wavefront 1 runs stage B (step t+1): the same machine reading its rows
+//    from that ring, three rows behind stage A, and stores rows y0 .. y1-1
+//    of lanes 1..62 to the other buffer.
+// The two stages share one loop with one barrier per row. Splitting them
+// over two wavefronts halves what each keeps in registers (240 VGPRs), so
+// that two wavefronts fit a SIMD and one's arithmetic covers the other's
+// waits; four strips (40 KB of LDS each) share a CU.
 // After step t the window's two outermost columns on each side lack valid
 // neighbours for step t+1; lanes 0 and 63 hold them and store nothing, so
 // every stored node saw only values of the exact step-t state. Per node the
@@ -1548,17 +1550,17 @@ __device__ __forceinline__ SideEntry v2_side(int i, bool bot, bool top) {
 }
 
 template <bool NT>
-__global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArgs a) {
+__global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_kernel(SweepArgs a) {
   typedef float T;
   constexpr bool SHIFT = true;
   constexpr int NPL = 4;
   typedef typename Vec<T, NPL>::type V;
-  __shared__ V ring_lds[kTwoStepWaves][kV2Ring][kPlanes][64];  // 80 KB per workgroup
+  __shared__ V ring[kV2Ring][kPlanes][64];  // 40 KB per workgroup
   const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int sidx = xcd_item(blockIdx.x, a.n_wg) * kTwoStepWaves + wave;
-  if (sidx >= a.n_strips) return;  // no workgroup barriers: each wavefront uses its own LDS
-  V(*ring)[kPlanes][64] = ring_lds[wave];
+  // wave 0 runs stage A, wave 1 stage B of the same strip
+  const bool isA = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0;
+  const int sidx = xcd_item(blockIdx.x, a.n_wg);
+  if (sidx >= a.n_strips) return;  // the whole workgroup, before any barrier
   const Strip st = a.strips[sidx];
   const ChanDev c = a.ch[st.ch];
   const T *__restrict__ A = static_cast<const T *>(a.A);
@@ -1567,6 +1569,7 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArg
   const long long t = c.t + a.k;
   const T fxA = (t < c.t_startup) ? T(c.g) : T(0);
   const T fxB = (t + 1 < c.t_startup) ? T(c.g) : T(0);
+  const T fx = isA ? fxA : fxB;
   const Coef<T> q(c);
   constexpr int F = kTile;
   const long long tile00 = c.off >> 6;
@@ -1583,6 +1586,18 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArg
   };
   const long long lcol = colpart(4 * lane);
   auto clampy = [&](int y) __attribute__((always_inline)) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
+
+  // ---- rows of the two stages
+  const int A0 = st.y0 - 2 < 0 ? 0 : st.y0 - 2, A1 = st.y1 + 2 > ny ? ny : st.y1 + 2;
+  const int R0 = st.y0 - 1 < 0 ? 0 : st.y0 - 1, R1 = st.y1 + 1 > ny ? ny : st.y1 + 1;
+  const int iend = st.y1 + 3;  // iterations [A0, iend): stage B updates row i - 3
+  // stage B's stores: lanes whose four columns lie in [x0, x1)
+  const bool store_lane = lane >= 1 && 4 * (lane - 1) < st.x1 - st.x0;
+  // row references of rows A0-1 .. A0+62 (clamped), lane j holding row
+  // A0-1+j: stage B reads those of its rows from here (strips have at most
+  // 56 rows, so rows A0-1 .. A1 fit)
+  const T uall = a.uref[c.row_off + clampy(A0 - 1 + lane)];
+  auto ref = [&](int y) __attribute__((always_inline)) { return lane_value(uall, clampy(y) - (A0 - 1)); };
 
   // ---- stage A: raw loads of a row of the state (window and side values)
   struct Raw {
@@ -1623,10 +1638,8 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArg
     ps = (lane >= 24 && lane <= 26) ? pu : ps;
     R.side = *ps;
   };
-  // ---- stage B: the same row from the LDS ring of step-t rows (side
-  // values: only the row references are meaningful; lanes 0 and 63, which
-  // would use the others, store nothing)
-  T uring = T(0);  // lane s: reference velocity of the row in ring slot s
+  // ---- stage B: the same row from the LDS ring of step-t rows (no side
+  // values: lanes 0 and 63, which would use them, store nothing)
   auto load_lds = [&](int y, Raw &R) __attribute__((always_inline)) {
     const bool bot = (y == 0), top = (y == ny - 1);
     const int sc = y & (kV2Ring - 1), sd = bot ? sc : ((y - 1) & (kV2Ring - 1)), su = top ? sc : ((y + 1) & (kV2Ring - 1));
@@ -1640,19 +1653,14 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArg
     R.r[4] = ring[su][top ? 2 : 4][lane];
     R.r[7] = ring[su][top ? 5 : 7][lane];
     R.r[8] = ring[su][top ? 6 : 8][lane];
-    const T ud = lane_value(uring, sd), uc = lane_value(uring, sc), uu = lane_value(uring, su);
-    R.side = lane == 24 ? ud : (lane == 25 ? uc : (lane == 26 ? uu : T(0)));
+    R.side = T(0);
   };
 
   // Pulled populations, P, moments and u~ of the window's columns of row y,
-  // and u~ of the two columns beside it (the vector sweep's assembly, fixed
-  // walls).
-  // With sides false (stage B) the values beside the window are not formed:
-  // only lanes 0 and 63 would use them, and those store nothing.
-  auto assemble = [&](auto sides, int y, const Raw &R, T fx, T f[9][NPL], T P[NPL], T sd[NPL], T mx[NPL],
-                      T my[NPL], U2<T> u[NPL], U2<T> &uL, U2<T> &uR, T ur3[3]) __attribute__((always_inline)) {
-    constexpr bool SIDES = decltype(sides)::value;
-    auto edge = [&](int i) __attribute__((always_inline)) { return SIDES ? lane_value(R.side, i) : T(0); };
+  // and (stage A) u~ of the two columns beside it (the vector sweep's
+  // assembly, fixed walls), with the row references urd, urc, uru.
+  auto assemble = [&](int y, const Raw &R, T urd, T urc, T uru, T f[9][NPL], T P[NPL], T sd[NPL], T mx[NPL],
+                      T my[NPL], U2<T> u[NPL], U2<T> &uL, U2<T> &uR) __attribute__((always_inline)) {
     const bool bot = (y == 0), top = (y == ny - 1);
     auto from_left = [&](const V &r, T edge, T out[NPL]) __attribute__((always_inline)) {
       out[0] = shift_up(edge, r[NPL - 1]);
@@ -1669,8 +1677,8 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArg
       for (int k = 0; k < NPL; ++k) out[k] = r[k];
     };
     split(R.r[0], f[0]);
-    from_left(R.r[1], edge(0), f[1]);
-    from_right(R.r[3], edge(1), f[3]);
+    from_left(R.r[1], lane_value(R.side, 0), f[1]);
+    from_right(R.r[3], lane_value(R.side, 1), f[3]);
     split(R.r[9], P);
     split(R.r[2], f[2]);
     split(R.r[4], f[4]);
@@ -1678,20 +1686,16 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArg
       split(R.r[5], f[5]);
       split(R.r[6], f[6]);
     } else {
-      from_left(R.r[5], edge(2), f[5]);
-      from_right(R.r[6], edge(3), f[6]);
+      from_left(R.r[5], lane_value(R.side, 2), f[5]);
+      from_right(R.r[6], lane_value(R.side, 3), f[6]);
     }
     if (top) {
       split(R.r[7], f[7]);
       split(R.r[8], f[8]);
     } else {
-      from_right(R.r[7], edge(4), f[7]);
-      from_left(R.r[8], edge(5), f[8]);
+      from_right(R.r[7], lane_value(R.side, 4), f[7]);
+      from_left(R.r[8], lane_value(R.side, 5), f[8]);
     }
-    const T urd = lane_value(R.side, 24), urc = lane_value(R.side, 25), uru = lane_value(R.side, 26);
-    ur3[0] = urd;
-    ur3[1] = urc;
-    ur3[2] = uru;
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       T g[9];
@@ -1703,44 +1707,43 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArg
       moments<T>(g, sd[k], mx[k], my[k]);
       u[k] = u_tilde<T, SHIFT>(sd[k], mx[k], my[k], fx, urc);
     }
-    if constexpr (!SIDES) {
-      uL = uR = U2<T>{T(0), T(0)};
-      return;
+    uL = uR = U2<T>{T(0), T(0)};
+    if (isA) {
+      T l[9], r[9];
+      l[0] = lane_value(R.side, 6);
+      l[1] = lane_value(R.side, 7);
+      l[3] = lane_value(R.side, 8);
+      l[2] = lane_value(R.side, 9);
+      l[5] = lane_value(R.side, 10);
+      l[6] = lane_value(R.side, 11);
+      l[4] = lane_value(R.side, 12);
+      l[7] = lane_value(R.side, 13);
+      l[8] = lane_value(R.side, 14);
+      r[0] = lane_value(R.side, 15);
+      r[1] = lane_value(R.side, 16);
+      r[3] = lane_value(R.side, 17);
+      r[2] = lane_value(R.side, 18);
+      r[5] = lane_value(R.side, 19);
+      r[6] = lane_value(R.side, 20);
+      r[4] = lane_value(R.side, 21);
+      r[7] = lane_value(R.side, 22);
+      r[8] = lane_value(R.side, 23);
+      to_row_reference(l, urd, urc, uru, bot, top);
+      to_row_reference(r, urd, urc, uru, bot, top);
+      T s0, m0, n0;
+      moments<T>(l, s0, m0, n0);
+      uL = u_tilde<T, SHIFT>(s0, m0, n0, fx, urc);
+      moments<T>(r, s0, m0, n0);
+      uR = u_tilde<T, SHIFT>(s0, m0, n0, fx, urc);
     }
-    T l[9], r[9];
-    l[0] = lane_value(R.side, 6);
-    l[1] = lane_value(R.side, 7);
-    l[3] = lane_value(R.side, 8);
-    l[2] = lane_value(R.side, 9);
-    l[5] = lane_value(R.side, 10);
-    l[6] = lane_value(R.side, 11);
-    l[4] = lane_value(R.side, 12);
-    l[7] = lane_value(R.side, 13);
-    l[8] = lane_value(R.side, 14);
-    r[0] = lane_value(R.side, 15);
-    r[1] = lane_value(R.side, 16);
-    r[3] = lane_value(R.side, 17);
-    r[2] = lane_value(R.side, 18);
-    r[5] = lane_value(R.side, 19);
-    r[6] = lane_value(R.side, 20);
-    r[4] = lane_value(R.side, 21);
-    r[7] = lane_value(R.side, 22);
-    r[8] = lane_value(R.side, 23);
-    to_row_reference(l, urd, urc, uru, bot, top);
-    to_row_reference(r, urd, urc, uru, bot, top);
-    T s0, m0, n0;
-    moments<T>(l, s0, m0, n0);
-    uL = u_tilde<T, SHIFT>(s0, m0, n0, fx, urc);
-    moments<T>(r, s0, m0, n0);
-    uR = u_tilde<T, SHIFT>(s0, m0, n0, fx, urc);
   };
 
   // Update of row y from its assembled state (fc ..., uCur, side u~, the
   // references) and u~ of the rows below and above; out and trT receive
   // the new populations and trace.
-  auto update = [&](int y, T fx, T fc[9][NPL], const T Pc[NPL], const T sdc[NPL], const T mxc[NPL],
-                    const T myc[NPL], const U2<T> uPrev[NPL], const U2<T> uCur[NPL], const U2<T> uNext[NPL],
-                    U2<T> uLc, U2<T> uRc, const T urC[3], V out[kPlanes]) __attribute__((always_inline)) {
+  auto update = [&](int y, T fc[9][NPL], const T Pc[NPL], const T sdc[NPL], const T mxc[NPL], const T myc[NPL],
+                    const U2<T> uPrev[NPL], const U2<T> uCur[NPL], const U2<T> uNext[NPL], U2<T> uLc, U2<T> uRc,
+                    const T urC[3], V out[kPlanes]) __attribute__((always_inline)) {
     const T urc = urC[1];
     const T urd = (y == 0) ? -urc : urC[0];
     const T uru = (y == ny - 1) ? -urc : urC[2];
@@ -1768,42 +1771,88 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArg
     }
   };
 
-  // ---- rows of the two stages
-  const int A0 = st.y0 - 2 < 0 ? 0 : st.y0 - 2, A1 = st.y1 + 2 > ny ? ny : st.y1 + 2;
-  const int R0 = st.y0 - 1 < 0 ? 0 : st.y0 - 1, R1 = st.y1 + 1 > ny ? ny : st.y1 + 1;
-  const int iend = st.y1 + 3;  // iterations [A0, iend): stage B updates row i - 3
-  // stage B's stores: lanes whose four columns lie in [x0, x1)
-  const bool store_lane = lane >= 1 && 4 * (lane - 1) < st.x1 - st.x0;
-
-  // stage A state: the assembled row i and u~ of rows i-1 and i
-  T fc[9][NPL], Pc[NPL], sdc[NPL], mxc[NPL], myc[NPL];
+  // The state each wave carries from one iteration to the next: its
+  // assembled current row and u~ of the rows below and at it (stage A: row
+  // i and the raw loads of row i+1; stage B: row i-3).
+  T fc[9][NPL], Pc[NPL], sdc[NPL], mxc[NPL], myc[NPL], urC[3];
   U2<T> uPrev[NPL], uCur[NPL], uLc, uRc;
-  T urC[3];
-  {
-    Raw Rp, Rf;
+  Raw R;
+  if (isA) {
+    Raw Rp;
     const int yp = clampy(A0 - 1);
     load_raw(yp, Rp);
-    load_raw(A0, Rf);
-    T ftmp[9][NPL], Ptmp[NPL], s0[NPL], m0[NPL], n0[NPL], ur_unused[3];
+    load_raw(A0, R);
+    T ftmp[9][NPL], Ptmp[NPL], s0[NPL], m0[NPL], n0[NPL];
     U2<T> hl, hr;
-    assemble(std::true_type{}, yp, Rp, fxA, ftmp, Ptmp, s0, m0, n0, uPrev, hl, hr, ur_unused);
-    assemble(std::true_type{}, A0, Rf, fxA, fc, Pc, sdc, mxc, myc, uCur, uLc, uRc, urC);
+    assemble(yp, Rp, lane_value(Rp.side, 24), lane_value(Rp.side, 25), lane_value(Rp.side, 26), ftmp, Ptmp, s0,
+             m0, n0, uPrev, hl, hr);
+    urC[0] = lane_value(R.side, 24);
+    urC[1] = lane_value(R.side, 25);
+    urC[2] = lane_value(R.side, 26);
+    assemble(A0, R, urC[0], urC[1], urC[2], fc, Pc, sdc, mxc, myc, uCur, uLc, uRc);
+    load_raw(clampy(A0 + 1), R);
+  } else {
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      uPrev[k] = uCur[k] = U2<T>{T(0), T(0)};
+      Pc[k] = sdc[k] = mxc[k] = myc[k] = T(0);
+#pragma unroll
+      for (int j = 0; j < 9; ++j) fc[j][k] = T(0);
+    }
+    uLc = uRc = U2<T>{T(0), T(0)};
+    urC[0] = urC[1] = urC[2] = T(0);
+#pragma unroll
+    for (int j = 0; j < 10; ++j) R.r[j] = V{};
+    R.side = T(0);
   }
-  // stage B state: the assembled row i-3 and u~ of rows i-4 and i-3
-  T fB[9][NPL], PB[NPL], sdB[NPL], mxB[NPL], myB[NPL], urB[3];
-  U2<T> uBp[NPL], uBc[NPL], uBLc, uBRc;
 
-  // stage A's update of row y, with row y+1 assembled from Rasm
-  auto stage_a = [&](int y, const Raw &Rasm) __attribute__((always_inline)) {
+  // Iteration i. Stage A (rows [A0, A1)): assembles row i+1 from the loads
+  // issued in the previous iteration, updates row i into ring slot i mod 4,
+  // then issues the loads of row i+2. Stage B: assembles row i-2 from the
+  // ring (rows [R0, R1)), updates row i-3 and stores it (rows [y0, y1)).
+  // One barrier per iteration orders stage A's ring writes before stage B's
+  // reads three iterations later, and stage B's reads before the slot is
+  // written again; both waves run every iteration.
+  auto iteration = [&](int i) __attribute__((always_inline)) {
+    const int r = isA ? i + 1 : i - 2, y = isA ? i : i - 3;
+    const bool do_asm = isA ? (i < A1) : (r >= R0 && r < R1);
+    const bool do_upd = isA ? (i < A1) : (y >= st.y0 && y < st.y1);
     T fn[9][NPL], Pn[NPL], sdn[NPL], mxn[NPL], myn[NPL], urN[3];
     U2<T> uNext[NPL], uLn, uRn;
-    assemble(std::true_type{}, clampy(y + 1), Rasm, fxA, fn, Pn, sdn, mxn, myn, uNext, uLn, uRn, urN);
-    V out[kPlanes];
-    update(y, fxA, fc, Pc, sdc, mxc, myc, uPrev, uCur, uNext, uLc, uRc, urC, out);
-    const int slot = y & (kV2Ring - 1);
+    if (do_asm) {
+      if (!isA) load_lds(r, R);
+      const int rr = clampy(r);
+      urN[0] = isA ? lane_value(R.side, 24) : ref(rr - 1);
+      urN[1] = isA ? lane_value(R.side, 25) : ref(rr);
+      urN[2] = isA ? lane_value(R.side, 26) : ref(rr + 1);
+      assemble(rr, R, urN[0], urN[1], urN[2], fn, Pn, sdn, mxn, myn, uNext, uLn, uRn);
+    } else {
 #pragma unroll
-    for (int p = 0; p < kPlanes; ++p) ring[slot][p][lane] = out[p];
-    uring = (lane == slot) ? urC[1] : uring;
+      for (int k = 0; k < NPL; ++k) {
+        uNext[k] = U2<T>{T(0), T(0)};
+        Pn[k] = sdn[k] = mxn[k] = myn[k] = T(0);
+#pragma unroll
+        for (int j = 0; j < 9; ++j) fn[j][k] = T(0);
+      }
+      uLn = uRn = U2<T>{T(0), T(0)};
+      urN[0] = urN[1] = urN[2] = T(0);
+    }
+    if (do_upd) {
+      V out[kPlanes];
+      update(y, fc, Pc, sdc, mxc, myc, uPrev, uCur, uNext, uLc, uRc, urC, out);
+      if (isA) {
+        const int slot = y & (kV2Ring - 1);
+#pragma unroll
+        for (int p = 0; p < kPlanes; ++p) ring[slot][p][lane] = out[p];
+      } else if (store_lane) {
+        T *w = B + rowbase(y) + lcol;
+#pragma unroll
+        for (int p = 0; p < kPlanes; ++p) {
+          if constexpr (NT) __builtin_nontemporal_store(out[p], reinterpret_cast<V *>(w + (long long)p * F));
+          else *reinterpret_cast<V *>(w + (long long)p * F) = out[p];
+        }
+      }
+    }
     uLc = uLn;
     uRc = uRn;
     urC[0] = urN[0];
@@ -1818,77 +1867,21 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves) sweep_vec2_kernel(SweepArg
       mxc[k] = mxn[k];
       myc[k] = myn[k];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) fc[i][k] = fn[i][k];
+      for (int j = 0; j < 9; ++j) fc[j][k] = fn[j][k];
     }
+    // the loads of row i+2 (clamped to the lattice), in flight across the
+    // barrier
+    if (isA && i + 1 < A1) load_raw(clampy(i + 2), R);
+    __syncthreads();
   };
-
-  auto stage_b = [&](int i) __attribute__((always_inline)) {
-    const int r = i - 2, y = i - 3;
-    T fn[9][NPL], Pn[NPL], sdn[NPL], mxn[NPL], myn[NPL], urN[3];
-    U2<T> uNext[NPL], uLn, uRn;
-    if (r >= R0 && r < R1) {
-      Raw R;
-      load_lds(r, R);
-      assemble(std::false_type{}, r, R, fxB, fn, Pn, sdn, mxn, myn, uNext, uLn, uRn, urN);
-    } else {
-#pragma unroll
-      for (int k = 0; k < NPL; ++k) {
-        uNext[k] = U2<T>{T(0), T(0)};
-        Pn[k] = sdn[k] = mxn[k] = myn[k] = T(0);
-#pragma unroll
-        for (int j = 0; j < 9; ++j) fn[j][k] = T(0);
-      }
-      uLn = uRn = U2<T>{T(0), T(0)};
-      urN[0] = urN[1] = urN[2] = T(0);
-    }
-    if (y >= st.y0 && y < st.y1) {
-      V out[kPlanes];
-      update(y, fxB, fB, PB, sdB, mxB, myB, uBp, uBc, uNext, uBLc, uBRc, urB, out);
-      if (store_lane) {
-        T *w = B + rowbase(y) + lcol;
-#pragma unroll
-        for (int p = 0; p < kPlanes; ++p) {
-          if constexpr (NT) __builtin_nontemporal_store(out[p], reinterpret_cast<V *>(w + (long long)p * F));
-          else *reinterpret_cast<V *>(w + (long long)p * F) = out[p];
-        }
-      }
-    }
-    uBLc = uLn;
-    uBRc = uRn;
-    urB[0] = urN[0];
-    urB[1] = urN[1];
-    urB[2] = urN[2];
-#pragma unroll
-    for (int k = 0; k < NPL; ++k) {
-      uBp[k] = uBc[k];
-      uBc[k] = uNext[k];
-      PB[k] = Pn[k];
-      sdB[k] = sdn[k];
-      mxB[k] = mxn[k];
-      myB[k] = myn[k];
-#pragma unroll
-      for (int j = 0; j < 9; ++j) fB[j][k] = fn[j][k];
-    }
-  };
-
-  // Stage B's iteration i assembles row i-2 and updates row i-3. Iteration
-  // i: the loads of row i+1 (row A1 at the last, in the lattice or clamped
-  // to its top row), stage B, then stage A's row i; stage A's rows [A0, A1)
-  // unrolled twice (the two-deep state swaps stay in fixed registers), then
-  // stage B drains.
+  // unrolled twice: the two-deep state swaps stay in fixed registers (the
+  // trip count is the same for both wavefronts, so they pass the same
+  // barriers)
 #pragma unroll 1
-  for (int i = A0; i < A1; i += 2) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-      if (j == 0 || i + j < A1) {
-        Raw R;
-        load_raw(clampy(i + j + 1), R);
-        stage_b(i + j);
-        stage_a(i + j, R);
-      }
+  for (int i = A0; i < iend; i += 2) {
+    iteration(i);
+    if (i + 1 < iend) iteration(i + 1);
   }
-#pragma unroll 1
-  for (int i = A1; i < iend; ++i) stage_b(i);
 }
 
 __global__ void __launch_bounds__(256) reduce_kernel(const ChanDev *ch, const double *part,

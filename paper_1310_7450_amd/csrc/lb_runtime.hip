@@ -452,7 +452,8 @@ lb_status upload_strips(lb_handle *h, bool all) {
       std::vector<lb_channel> elig;
       for (int i = 0; i < h->n_ch; ++i)
         if (h->active[i] && two_step_channel(h->in[i])) elig.push_back(h->in[i]);
-      const int H = h->opt.strip_rows > 0 ? h->opt.strip_rows : two_step_rows(elig, h->slots);
+      const int H = h->opt.strip_rows > 0 ? std::min(h->opt.strip_rows, kTwoStepMaxRows)
+                                          : two_step_rows(elig, h->slots);
       for (int i = 0; i < h->n_ch; ++i) {
         if (!h->active[i] || tiled(&h->opt, h->in[i])) continue;
         if (two_step_channel(h->in[i])) {
@@ -582,7 +583,7 @@ lb_status capture(lb_handle *h, int src) {
     for (int k = 0; k < h->K && st == LB_OK; k += 2) {
       if (h->two_count) {
         SweepArgs a = sweep_args(h, h->dtwo, 0, h->two_count, src ^ ((k / 2) & 1), k);
-        a.n_wg = (h->two_count + kTwoStepWaves - 1) / kTwoStepWaves;
+        a.n_wg = h->two_count;  // one strip per workgroup (a wavefront per stage)
         hipError_t e = launch_two_step(a, h->cap);
         if (e != hipSuccess) st = hipfail(h, e, "launch_two_step");
       }
