@@ -172,16 +172,17 @@ enum { LB_WALL_HALFWAY = 0, LB_WALL_ZOU_HE = 1 };
  *                wall, no pressure_gradient and at most 429,496,704 nodes.
  *                Runs as one fused pass per step (u~, Sigma^nN and the
  *                collide-and-stream of a tile of nodes in one workgroup);
- *   steps_per_sweep 0 (default) or 2: with LB_FP32_SHIFTED, the instantaneous
- *                model, no stress_force and K a multiple of 4, the blocks of
- *                K steps advance the channels whose width is a multiple of
- *                256 columns with the half-way top wall, no wall velocity
- *                and no pressure_gradient two steps per pass over the state
- *                (a strip's rows of step t are kept on chip for step t+1);
+ *   steps_per_sweep 0 (default) or 2: with the instantaneous model, no
+ *                stress_force and K a multiple of 4, the blocks of K steps
+ *                advance the vector-class channels (width a multiple of 256
+ *                in LB_FP32_SHIFTED, of 64 in LB_FP64, not a power of two up
+ *                to 64) with the half-way top wall, no wall velocity and no
+ *                pressure_gradient two steps per pass over the state (a
+ *                strip's rows of step t are kept on chip for step t+1);
  *                other channels, other handles and steps outside whole
  *                blocks run one step per pass. Each node update is the
  *                arithmetic of the one-step pass; states agree with it to
- *                FP32 round-off; 1: one step per pass always.
+ *                round-off; 1: one step per pass always.
  */
 typedef struct {
   int32_t precision;

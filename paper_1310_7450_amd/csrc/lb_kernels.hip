@@ -1515,8 +1515,10 @@ constexpr int kV2Ring = 4;
 // Side values of stage A's rows, by lane i < 24: (row offset, column offset
 // from the window start, field), with the wall rows' bounce-back sources;
 // the same meaning as kSideIn/kSideBot/kSideTop for the columns beside a
-// window that need not start on a tile. Lanes 24..26 carry the row
-// references.
+// window that need not start on a tile. The table is written for a window
+// of 256 columns (offsets 255..257 on the right); v2_side<W> moves the
+// right side to a window of W columns. Lanes 24..26 carry the row
+// references (FP32 storage).
 struct SideEntry {
   int dy, dc, p;
 };
@@ -1529,33 +1531,37 @@ constexpr int kV2Side[24] = {
     V2SIDE(0, 256, 0),  V2SIDE(0, 255, 1),  V2SIDE(0, 257, 3), V2SIDE(-1, 256, 2), V2SIDE(-1, 255, 5),
     V2SIDE(-1, 257, 6), V2SIDE(1, 256, 4),  V2SIDE(1, 257, 7), V2SIDE(1, 255, 8)};
 #undef V2SIDE
+template <int W>
 __device__ __forceinline__ SideEntry v2_side(int i, bool bot, bool top) {
   const int code = kV2Side[i];
   SideEntry e{(code & 3) - 1, ((code >> 2) & 1023) - 2, code >> 12};
+  if (e.dc >= 255) e.dc += W - 256;
   if (bot && e.dy < 0) {
     // entries 2, 3: edge values of pulls the wall row takes from its own
     // node (unused); the side columns' pops 2, 5, 6 bounce back from 4, 7, 8
     const bool edge = (i == 2 || i == 3);
-    const int col = (i < 15) ? -1 : 256;
+    const int col = (i < 15) ? -1 : W;
     const int back = e.p == 2 ? 4 : (e.p == 5 ? 7 : 8);
     e = edge ? SideEntry{0, 0, 0} : SideEntry{0, col, back};
   }
   if (top && e.dy > 0) {
     const bool edge = (i == 4 || i == 5);
-    const int col = (i < 15) ? -1 : 256;
+    const int col = (i < 15) ? -1 : W;
     const int back = e.p == 4 ? 2 : (e.p == 7 ? 5 : 6);
     e = edge ? SideEntry{0, 0, 0} : SideEntry{0, col, back};
   }
   return e;
 }
 
-template <bool NT>
+template <typename T, int NPL, bool NT>
 __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_kernel(SweepArgs a) {
-  typedef float T;
-  constexpr bool SHIFT = true;
-  constexpr int NPL = 4;
+  // FP32: storage relative to the row references, four nodes per lane;
+  // FP64: plain storage, one node per lane
+  constexpr bool SHIFT = sizeof(T) == 4;
+  constexpr int W = 64 * NPL;                 // window columns
+  constexpr int HL = (2 + NPL - 1) / NPL;     // lanes per side without valid step t+1
   typedef typename Vec<T, NPL>::type V;
-  __shared__ V ring[kV2Ring][kPlanes][64];  // 40 KB per workgroup
+  __shared__ V ring[kV2Ring][kPlanes][64];  // 40 KB (FP32) or 20 KB (FP64) per workgroup
   const int lane = threadIdx.x & 63;
   // wave 0 runs stage A, wave 1 stage B of the same strip
   const bool isA = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0;
@@ -1577,27 +1583,30 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
   const long long row_stride = (long long)tiles_row * kPlanes * F;
   auto rowbase = [&](int y) __attribute__((always_inline)) { return (tile00 + (long long)y * tiles_row) * (kPlanes * F); };
   // column of window offset dc, wrapped, as an element offset inside a row
-  const int w0 = st.x0 - 4;
+  const int w0 = st.x0 - HL * NPL;
   auto colpart = [&](int dc) __attribute__((always_inline)) -> long long {
     int col = w0 + dc;
     col += (col < 0) ? nx : 0;
     col -= (col >= nx) ? nx : 0;
     return (long long)(col >> 6) * (kPlanes * F) + (col & 63);
   };
-  const long long lcol = colpart(4 * lane);
+  const long long lcol = colpart(NPL * lane);
   auto clampy = [&](int y) __attribute__((always_inline)) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
 
   // ---- rows of the two stages
   const int A0 = st.y0 - 2 < 0 ? 0 : st.y0 - 2, A1 = st.y1 + 2 > ny ? ny : st.y1 + 2;
   const int R0 = st.y0 - 1 < 0 ? 0 : st.y0 - 1, R1 = st.y1 + 1 > ny ? ny : st.y1 + 1;
   const int iend = st.y1 + 3;  // iterations [A0, iend): stage B updates row i - 3
-  // stage B's stores: lanes whose four columns lie in [x0, x1)
-  const bool store_lane = lane >= 1 && 4 * (lane - 1) < st.x1 - st.x0;
-  // row references of rows A0-1 .. A0+62 (clamped), lane j holding row
-  // A0-1+j: stage B reads those of its rows from here (strips have at most
-  // 56 rows, so rows A0-1 .. A1 fit)
-  const T uall = a.uref[c.row_off + clampy(A0 - 1 + lane)];
-  auto ref = [&](int y) __attribute__((always_inline)) { return lane_value(uall, clampy(y) - (A0 - 1)); };
+  // stage B's stores: lanes whose columns lie in [x0, x1)
+  const bool store_lane = lane >= HL && NPL * (lane - HL) < st.x1 - st.x0;
+  // FP32: row references of rows A0-1 .. A0+62 (clamped), lane j holding
+  // row A0-1+j: stage B reads those of its rows from here (strips have at
+  // most 56 rows, so rows A0-1 .. A1 fit)
+  T uall = T(0);
+  if constexpr (SHIFT) uall = a.uref[c.row_off + clampy(A0 - 1 + lane)];
+  auto ref = [&](int y) __attribute__((always_inline)) {
+    return SHIFT ? lane_value(uall, clampy(y) - (A0 - 1)) : T(0);
+  };
 
   // ---- stage A: raw loads of a row of the state (window and side values)
   struct Raw {
@@ -1609,7 +1618,7 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
   // again on wall rows: a choice between precomputed offsets would keep them
   // in scratch memory)
   auto side_offset = [&](bool bot, bool top) __attribute__((always_inline)) -> long long {
-    const SideEntry e = v2_side(li, bot, top);
+    const SideEntry e = v2_side<W>(li, bot, top);
     return (lane < 24) ? (long long)e.dy * row_stride + colpart(e.dc) + (long long)e.p * F : lcol;
   };
   const long long o_in = side_offset(false, false);
@@ -1633,9 +1642,11 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
     long long o = o_in;
     if (bot || top) o = side_offset(bot, top);  // wall rows only
     const T *ps = A + rb + o;
-    const int yr = y + lane - 25;
-    const T *pu = a.uref + c.row_off + (yr < 0 ? 0 : (yr >= ny ? ny - 1 : yr));
-    ps = (lane >= 24 && lane <= 26) ? pu : ps;
+    if constexpr (SHIFT) {
+      const int yr = y + lane - 25;
+      const T *pu = a.uref + c.row_off + (yr < 0 ? 0 : (yr >= ny ? ny - 1 : yr));
+      ps = (lane >= 24 && lane <= 26) ? pu : ps;
+    }
     R.side = *ps;
   };
   // ---- stage B: the same row from the LDS ring of step-t rows (no side
@@ -1701,7 +1712,7 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
       T g[9];
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[i] = f[i][k];
-      to_row_reference(g, urd, urc, uru, bot, top);
+      if constexpr (SHIFT) to_row_reference(g, urd, urc, uru, bot, top);
 #pragma unroll
       for (int i = 0; i < 9; ++i) f[i][k] = g[i];
       moments<T>(g, sd[k], mx[k], my[k]);
@@ -1728,8 +1739,10 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
       r[4] = lane_value(R.side, 21);
       r[7] = lane_value(R.side, 22);
       r[8] = lane_value(R.side, 23);
-      to_row_reference(l, urd, urc, uru, bot, top);
-      to_row_reference(r, urd, urc, uru, bot, top);
+      if constexpr (SHIFT) {
+        to_row_reference(l, urd, urc, uru, bot, top);
+        to_row_reference(r, urd, urc, uru, bot, top);
+      }
       T s0, m0, n0;
       moments<T>(l, s0, m0, n0);
       uL = u_tilde<T, SHIFT>(s0, m0, n0, fx, urc);
@@ -1784,11 +1797,15 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
     load_raw(A0, R);
     T ftmp[9][NPL], Ptmp[NPL], s0[NPL], m0[NPL], n0[NPL];
     U2<T> hl, hr;
-    assemble(yp, Rp, lane_value(Rp.side, 24), lane_value(Rp.side, 25), lane_value(Rp.side, 26), ftmp, Ptmp, s0,
-             m0, n0, uPrev, hl, hr);
-    urC[0] = lane_value(R.side, 24);
-    urC[1] = lane_value(R.side, 25);
-    urC[2] = lane_value(R.side, 26);
+    // row references (FP32; zero in FP64, which stores plain populations)
+    auto refs = [&](const Raw &Q, T u[3]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) u[j] = SHIFT ? lane_value(Q.side, 24 + j) : T(0);
+    };
+    T urp[3];
+    refs(Rp, urp);
+    assemble(yp, Rp, urp[0], urp[1], urp[2], ftmp, Ptmp, s0, m0, n0, uPrev, hl, hr);
+    refs(R, urC);
     assemble(A0, R, urC[0], urC[1], urC[2], fc, Pc, sdc, mxc, myc, uCur, uLc, uRc);
     load_raw(clampy(A0 + 1), R);
   } else {
@@ -1822,9 +1839,8 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
     if (do_asm) {
       if (!isA) load_lds(r, R);
       const int rr = clampy(r);
-      urN[0] = isA ? lane_value(R.side, 24) : ref(rr - 1);
-      urN[1] = isA ? lane_value(R.side, 25) : ref(rr);
-      urN[2] = isA ? lane_value(R.side, 26) : ref(rr + 1);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) urN[j] = !SHIFT ? T(0) : (isA ? lane_value(R.side, 24 + j) : ref(rr - 1 + j));
       assemble(rr, R, urN[0], urN[1], urN[2], fn, Pn, sdn, mxn, myn, uNext, uLn, uRn);
     } else {
 #pragma unroll
@@ -2507,12 +2523,26 @@ hipError_t launch_gpbc(int fp32, void *B, const ChanDev *ch, int n_ch, int k, co
   return hipGetLastError();
 }
 
-hipError_t launch_two_step(const SweepArgs &a, hipStream_t s) {
+hipError_t launch_two_step(bool fp32, const SweepArgs &a, hipStream_t s) {
   if (a.n_strips == 0) return hipSuccess;
   const dim3 grid(a.n_wg), block(64 * kTwoStepWaves);
-  if (a.nt) hipLaunchKernelGGL(sweep_vec2_kernel<true>, grid, block, 0, s, a);
-  else hipLaunchKernelGGL(sweep_vec2_kernel<false>, grid, block, 0, s, a);
+  if (fp32) {
+    if (a.nt) hipLaunchKernelGGL((sweep_vec2_kernel<float, 4, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((sweep_vec2_kernel<float, 4, false>), grid, block, 0, s, a);
+  } else {
+    if (a.nt) hipLaunchKernelGGL((sweep_vec2_kernel<double, 1, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((sweep_vec2_kernel<double, 1, false>), grid, block, 0, s, a);
+  }
   return hipGetLastError();
+}
+
+int two_step_blocks_per_cu(bool fp32) {
+  int n = 0;
+  const hipError_t e =
+      fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<float, 4, false>, 64 * kTwoStepWaves, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<double, 1, false>, 64 * kTwoStepWaves,
+                                                          0);
+  return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 hipError_t launch_rereference(float *A, const ChanDev *ch, int n_ch, int total_rows, const double *prof,

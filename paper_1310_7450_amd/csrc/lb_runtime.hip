@@ -57,6 +57,7 @@ struct Layout {
   // two steps per launch: strips of the other channels for captured blocks
   // (and their reverse), and the two-step strips
   size_t off_bstrips = 0, off_brstrips = 0, off_tstrips = 0;
+  size_t off_btiles = 0;  // tiles of the tiled channels without two-step strips
   int max_two = 0;
   std::vector<ChanDev> ch;
 };
@@ -203,36 +204,36 @@ void add_strips(int ci, const ChanDev &d, int esize, int srows, bool stack, std:
 }
 
 // Two steps per launch (sweep_vec2_kernel) for the blocks of captured steps:
-// FP32 storage, the instantaneous model and the force only (no moving wall,
-// no pressure drive) on vector-class channels, with blocks a multiple of
-// four steps (a block is then an even number of two-step launches and
-// returns the state to its buffer, as one-step launches do).
+// the instantaneous model and the force only (no moving wall, no pressure
+// drive) on vector-class channels, with blocks a multiple of four steps (a
+// block is then an even number of two-step launches and returns the state
+// to its buffer, as one-step launches do).
 bool two_step_handle(const lb_options *o, int K) {
-  return o->steps_per_sweep != 1 && o->precision == LB_FP32_SHIFTED && !o->viscoelastic && !o->stress_force &&
-         K % 4 == 0;
+  return o->steps_per_sweep != 1 && !o->viscoelastic && !o->stress_force && K % 4 == 0;
 }
-bool two_step_channel(const lb_channel &c) {
-  return width_class(c.nx, 4) == kVecClass && c.top_wall == LB_WALL_HALFWAY && c.wall_velocity == 0 &&
+bool two_step_channel(const lb_channel &c, int esize) {
+  return width_class(c.nx, esize) == kVecClass && c.top_wall == LB_WALL_HALFWAY && c.wall_velocity == 0 &&
          c.pressure_gradient == 0;
 }
-// Stored columns of the two-step strips of a width: at most kTwoStepCols,
-// multiples of four, as even as possible.
-std::vector<int> two_step_cuts(int nx) {
-  const int quads = nx / 4, m = (nx + kTwoStepCols - 1) / kTwoStepCols;
+// Stored columns of the two-step strips of a width: at most 248 (FP32, four
+// nodes per lane) or 60 (FP64, one), in multiples of the nodes per lane, as
+// even as possible.
+std::vector<int> two_step_cuts(int nx, int esize) {
+  const int npl = vec_nodes(esize), cols = esize == 4 ? kTwoStepCols32 : kTwoStepCols64;
+  const int units = nx / npl, m = (nx + cols - 1) / cols;
   std::vector<int> x(1, 0);
-  for (int i = 0; i < m; ++i) x.push_back(x.back() + 4 * (quads / m + (i < quads % m)));
+  for (int i = 0; i < m; ++i) x.push_back(x.back() + npl * (units / m + (i < units % m)));
   return x;
 }
-// Rows per two-step strip: whole rounds of resident wavefronts (one per
-// SIMD) cost each strip's rows plus its four extra rows of step t and about
-// two rows of start-up, so the height minimises rounds x (rows + 6) over
-// 16..32 rows.
-int two_step_rows(const std::vector<lb_channel> &chans, int slots) {
+// Rows per two-step strip: whole rounds of resident strips cost each
+// strip's rows plus its four extra rows of step t and about two rows of
+// start-up, so the height minimises rounds x (rows + 6) over 16..56 rows.
+int two_step_rows(const std::vector<lb_channel> &chans, int esize, int slots) {
   int best = 16;
   double best_cost = 1e300;
-  for (int H = 16; H <= 32; ++H) {
+  for (int H = 16; H <= kTwoStepMaxRows; ++H) {
     long long S = 0;
-    for (const lb_channel &c : chans) S += (long long)(two_step_cuts(c.nx).size() - 1) * ((c.ny + H - 1) / H);
+    for (const lb_channel &c : chans) S += (long long)(two_step_cuts(c.nx, esize).size() - 1) * ((c.ny + H - 1) / H);
     const double cost = (double)((S + slots - 1) / std::max(slots, 1)) * (H + 6);
     if (S > 0 && cost < best_cost) {
       best_cost = cost;
@@ -241,8 +242,8 @@ int two_step_rows(const std::vector<lb_channel> &chans, int slots) {
   }
   return best;
 }
-void add_two_step_strips(int ci, const lb_channel &c, int H, std::vector<Strip> &out) {
-  const std::vector<int> x = two_step_cuts(c.nx);
+void add_two_step_strips(int ci, const lb_channel &c, int esize, int H, std::vector<Strip> &out) {
+  const std::vector<int> x = two_step_cuts(c.nx, esize);
   for (int y0 = 0; y0 < c.ny; y0 += H)
     for (size_t s = 0; s + 1 < x.size(); ++s)
       out.push_back(Strip{ci, x[s], y0, std::min(y0 + H, c.ny), 0, x[s + 1]});
@@ -337,8 +338,9 @@ Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
   L.off_brstrips = take(sizeof(Strip) * strips);
   const int min_rows = o->strip_rows > 0 ? std::min(o->strip_rows, 16) : 16;
   for (int i = 0; i < n && two_step_handle(o, o->obs_every > 0 ? o->obs_every : kDefaultK); ++i)
-    if (two_step_channel(c[i]))
-      L.max_two += (int)(two_step_cuts(c[i].nx).size() - 1) * ((c[i].ny + min_rows - 1) / min_rows);
+    if (two_step_channel(c[i], L.esize))
+      L.max_two += (int)(two_step_cuts(c[i].nx, L.esize).size() - 1) * ((c[i].ny + min_rows - 1) / min_rows);
+  L.off_btiles = take(sizeof(Strip) * std::max(L.n_tiles, 1));
   L.off_tstrips = take(sizeof(Strip) * std::max(L.max_two, 1));
   L.bytes = at;
   return L;
@@ -370,8 +372,10 @@ struct lb_handle {
   Strip *dtwo = nullptr;                        // two-step strips of the active channels
   int bact_begin[kClasses] = {0}, bact_count[kClasses] = {0};
   int two_count = 0;
+  Strip *btiles = nullptr;  // captured blocks: tiles of the tiled channels without two-step strips
+  int n_btiles = 0;
   bool two_step = false;     // captured blocks pair their steps where eligible
-  int slots = 1024;          // resident wavefronts at one per SIMD
+  int slots = 1024;          // two-step strips resident at once on the GPU
   int cur = 0;               // buffer holding the current state
   hipStream_t stream = nullptr, cap = nullptr;
   bool own_stream = false;
@@ -449,16 +453,17 @@ lb_status upload_strips(lb_handle *h, bool all) {
     // one-step strips of the others
     std::vector<Strip> braw, bgrouped, two;
     if (h->two_step) {
+      const int es = h->L.esize;
       std::vector<lb_channel> elig;
       for (int i = 0; i < h->n_ch; ++i)
-        if (h->active[i] && two_step_channel(h->in[i])) elig.push_back(h->in[i]);
+        if (h->active[i] && two_step_channel(h->in[i], es)) elig.push_back(h->in[i]);
       const int H = h->opt.strip_rows > 0 ? std::min(h->opt.strip_rows, kTwoStepMaxRows)
-                                          : two_step_rows(elig, h->slots);
+                                          : two_step_rows(elig, es, h->slots);
       for (int i = 0; i < h->n_ch; ++i) {
-        if (!h->active[i] || tiled(&h->opt, h->in[i])) continue;
-        if (two_step_channel(h->in[i])) {
-          add_two_step_strips(i, h->in[i], H, two);
-        } else {
+        if (!h->active[i]) continue;
+        if (two_step_channel(h->in[i], es)) {
+          add_two_step_strips(i, h->in[i], es, H, two);
+        } else if (!tiled(&h->opt, h->in[i])) {
           const ChanDev &d = h->L.ch[i];
           add_strips(i, d, h->L.esize,
                      strip_rows_for(width_class(d.nx, h->L.esize), d.nx, d.ny, h->opt.strip_rows), stack, braw);
@@ -516,7 +521,9 @@ lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s, bool block =
                                  (long long)kPlanes * h->L.plane * h->L.esize > kNontemporalBytes, s));
     return LB_OK;
   }
-  if (h->L.n_tiles) HIPCHECK(h, launch_tiles(sweep_args(h, h->tiles, 0, h->L.n_tiles, src, k), s));
+  Strip *tl = block ? h->btiles : h->tiles;
+  const int ntl = block ? h->n_btiles : h->L.n_tiles;
+  if (ntl) HIPCHECK(h, launch_tiles(sweep_args(h, tl, 0, ntl, src, k), s));
   const int *begin = block ? h->bact_begin : h->act_begin, *count = block ? h->bact_count : h->act_count;
   Strip *fwd = block ? h->dbact : h->dact, *rev = block ? h->dbact_rev : h->dact_rev;
   for (int c = 0; c < kClasses; ++c) {
@@ -584,7 +591,7 @@ lb_status capture(lb_handle *h, int src) {
       if (h->two_count) {
         SweepArgs a = sweep_args(h, h->dtwo, 0, h->two_count, src ^ ((k / 2) & 1), k);
         a.n_wg = h->two_count;  // one strip per workgroup (a wavefront per stage)
-        hipError_t e = launch_two_step(a, h->cap);
+        hipError_t e = launch_two_step(h->opt.precision == LB_FP32_SHIFTED, a, h->cap);
         if (e != hipSuccess) st = hipfail(h, e, "launch_two_step");
       }
       if (st == LB_OK) st = enqueue_step(h, src, k, h->cap, true);
@@ -837,6 +844,7 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
   h->dbact = reinterpret_cast<Strip *>(h->ws + h->L.off_bstrips);
   h->dbact_rev = reinterpret_cast<Strip *>(h->ws + h->L.off_brstrips);
   h->dtwo = reinterpret_cast<Strip *>(h->ws + h->L.off_tstrips);
+  h->btiles = reinterpret_cast<Strip *>(h->ws + h->L.off_btiles);
   h->two_step = two_step_handle(o, h->K) && h->L.max_two > 0;
   h->dpart = reinterpret_cast<double *>(h->ws + h->L.off_part);
   h->dprof = reinterpret_cast<double *>(h->ws + h->L.off_prof);
@@ -878,19 +886,26 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
       hipSuccess)
     return bail(LB_EHIP);
   {
-    // resident wavefronts of the two-step sweep: one per SIMD, four per CU
+    // strips of the two-step sweep resident at once
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return bail(LB_EHIP);
-    h->slots = 4 * std::max(cus, 1);
+    h->slots = two_step_blocks_per_cu(o->precision == LB_FP32_SHIFTED) * std::max(cus, 1);
   }
   if (upload_strips(h, true) != LB_OK || upload_strips(h, false) != LB_OK) return bail(LB_EHIP);
-  std::vector<Strip> tiles;  // kept until the synchronisation below
+  std::vector<Strip> tiles, btiles;  // kept until the synchronisation below
   for (int i = 0; i < n; ++i)
-    if (tiled(o, c[i])) add_tiles(i, c[i], tile_shape(o), tiles);
+    if (tiled(o, c[i])) {
+      add_tiles(i, c[i], tile_shape(o), tiles);
+      if (!h->two_step || !two_step_channel(c[i], h->L.esize)) add_tiles(i, c[i], tile_shape(o), btiles);
+    }
   if (!tiles.empty() && hipMemcpyAsync(h->tiles, tiles.data(), sizeof(Strip) * tiles.size(),
                                        hipMemcpyHostToDevice, h->stream) != hipSuccess)
+    return bail(LB_EHIP);
+  h->n_btiles = (int)btiles.size();
+  if (!btiles.empty() && hipMemcpyAsync(h->btiles, btiles.data(), sizeof(Strip) * btiles.size(),
+                                        hipMemcpyHostToDevice, h->stream) != hipSuccess)
     return bail(LB_EHIP);
   if (fill_rest(h, 0) != LB_OK || fill_rest(h, 1) != LB_OK) return bail(LB_EHIP);
   // zero stress at rest (outside any graph)

@@ -1,17 +1,19 @@
-"""Two steps per pass over the state (FP32 storage, captured blocks of K
-steps, K a multiple of 4) against one step per pass and against the FP64
-oracle.
+"""Two steps per pass over the state (captured blocks of K steps, K a
+multiple of 4) against one step per pass and against the FP64 oracle, in
+FP32 (reference-shifted storage, four nodes per lane) and FP64 (one node per
+lane).
 
 The two-step sweep keeps a strip's rows of step t on chip and applies step
 t+1 to them; each node update is the one-step sweep's arithmetic, so the
-states agree with one step per pass to FP32 round-off (and, where the
-compiler contracts the same products into the same fused operations, bit for
-bit). Shapes cover one, two, three and many column strips per row (two-step
-strips are at most 248 columns, split as evenly as the width allows in
-multiples of 4), ragged row bands, one- and two-row channels, the periodic
-wrap of the window around the channel, and handles that mix eligible
-channels with others (moving wall, Zou-He top, pressure drive, narrow
-widths) whose steps still run one per pass inside the same block."""
+states agree with one step per pass to round-off (and, where the compiler
+contracts the same products into the same fused operations, bit for bit).
+Shapes cover one, two, three and many column strips per row (two-step strips
+are at most 248 columns in FP32 and 60 in FP64, split as evenly as the width
+allows in multiples of the nodes per lane), ragged row bands, one- and
+two-row channels, the periodic wrap of the window around the channel, and
+handles that mix eligible channels with others (moving wall, Zou-He top,
+pressure drive, narrow widths) whose steps still run one per pass inside the
+same block (in FP64 on the tile sweep)."""
 import numpy as np
 import pytest
 
@@ -32,14 +34,15 @@ def spec(nx, ny, **kw):
     return ChannelSpec(nx=nx, ny=ny, **base)
 
 
-def run_pair(chans, steps, obs_every, seed=0, strip_rows=0):
+def run_pair(chans, steps, obs_every, seed=0, strip_rows=0, precision="fp32"):
     """The same seeded random states advanced by a two-step handle and a
     one-step handle; returns [(state2, state1)] per channel."""
     out = []
     states = [workloads.random_state(c.nx, c.ny, seed=seed + 17 * i) for i, c in enumerate(chans)]
     res = []
     for sps in (0, 1):
-        with solver(chans, precision="fp32", obs_every=obs_every, strip_rows=strip_rows, steps_per_sweep=sps) as s:
+        with solver(chans, precision=precision, obs_every=obs_every, strip_rows=strip_rows,
+                    steps_per_sweep=sps) as s:
             for i, (pops, P) in enumerate(states):
                 s.set_state(i, pops, P, 0)
             for n in steps:
@@ -55,50 +58,56 @@ def state_diff(a, b, pops0):
     return np.abs(a[0] - b[0]).max() / dev, np.abs(a[1] - b[1]).max() / max(np.abs(b[1]).max(), 1e-30)
 
 
-# a few FP32 units of the populations (2.6e-8 each near 0.44) relative to the
-# state's deviation from rest (~1e-3); a wrong column, row or wall
-# substitution gives O(1)
-TOL = 2e-4
+# FP32: a few units of the populations (2.6e-8 each near 0.44) relative to
+# the state's deviation from rest (~1e-3); FP64: the same in FP64 units. A
+# wrong column, row or wall substitution gives O(1)
+TOL = {"fp32": (2e-4, 1e-3), "fp64": (1e-11, 1e-9)}
+
+SHAPES = {"fp32": [(256, 1), (256, 2), (512, 3), (512, 37), (768, 16), (1024, 65), (2048, 33), (4096, 24)],
+          "fp64": [(128, 1), (128, 2), (192, 3), (320, 37), (256, 16), (1024, 65), (4096, 24)]}
 
 
-@pytest.mark.parametrize("nx,ny", [(256, 1), (256, 2), (512, 3), (512, 37), (768, 16), (1024, 65), (2048, 33),
-                                   (4096, 24)])
-def test_two_step_matches_one_step(nx, ny):
+@pytest.mark.parametrize("precision,nx,ny", [(p, nx, ny) for p in SHAPES for nx, ny in SHAPES[p]])
+def test_two_step_matches_one_step(precision, nx, ny):
     """Random x-varying states, 2 blocks of 8 steps plus 3 single steps:
     the two-step handle's populations and traces equal the one-step
-    handle's to FP32 round-off (bitwise equality reported)."""
-    pairs, st = run_pair([spec(nx, ny)], [16, 3], obs_every=8, seed=nx + ny)
+    handle's to round-off (bitwise equality reported)."""
+    pairs, st = run_pair([spec(nx, ny)], [16, 3], obs_every=8, seed=nx + ny, precision=precision)
     (a, b), = pairs
     e, ep = state_diff(a, b, st[0][0])
     same = np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
-    print(f"{nx}x{ny}: two-step vs one-step state {e:.2e} P {ep:.2e} bitwise {same}", flush=True)
-    assert e < TOL and ep < 1e-3
+    print(f"{precision} {nx}x{ny}: two-step vs one-step state {e:.2e} P {ep:.2e} bitwise {same}", flush=True)
+    assert e < TOL[precision][0] and ep < TOL[precision][1]
 
 
-def test_two_step_mixed_handle():
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_two_step_mixed_handle(precision):
     """Eligible channels beside channels that stay one step per pass
-    (moving wall, Zou-He top, pressure drive, widths 64, 300 and 192) in one
-    handle: every channel equals its one-step run."""
+    (moving wall, Zou-He top, pressure drive, widths 64, 300 and 192 in
+    FP32; 64 and 300 are narrow or tiled in FP64) in one handle: every
+    channel equals its one-step run."""
     chans = [spec(512, 20), spec(512, 12, wall_velocity=1e-3), spec(768, 9, top_wall="zou_he", nn_pressure=False),
              spec(256, 7, force=0.0, pressure_gradient=1e-6, nn_pressure=False), spec(64, 10), spec(300, 6),
              spec(1024, 30), spec(192, 5)]
-    pairs, st = run_pair(chans, [8, 8, 5], obs_every=8, seed=3)
+    pairs, st = run_pair(chans, [8, 8, 5], obs_every=8, seed=3, precision=precision)
     for i, (a, b) in enumerate(pairs):
         e, ep = state_diff(a, b, st[i][0])
-        print(f"channel {i} ({chans[i].nx}x{chans[i].ny}): state {e:.2e} P {ep:.2e}", flush=True)
-        assert e < TOL and ep < 1e-3
+        print(f"{precision} channel {i} ({chans[i].nx}x{chans[i].ny}): state {e:.2e} P {ep:.2e}", flush=True)
+        assert e < TOL[precision][0] and ep < TOL[precision][1]
 
 
-def test_two_step_matches_oracle(orc):
-    """Against the FP64 oracle node by node after 1 + 2 blocks of 4 steps
-    (the first step one per pass, the blocks two per pass) on a 512 x 13
-    channel with x gradients."""
-    c = spec(512, 13)
-    pops, P = workloads.random_state(512, 13, seed=5)
-    o = orc.Channel(512, 13, c.force, tau_lb=c.tau_lb, G=c.G, tau0=c.tau0, gamma_c=c.gamma_c, eps=c.eps,
+@pytest.mark.parametrize("precision,nx", [("fp32", 512), ("fp64", 320)])
+def test_two_step_matches_oracle(orc, precision, nx):
+    """Against the FP64 oracle node by node after 3 single steps and 3
+    blocks of 4 (the blocks two steps per pass) on a channel of 13 rows
+    with x gradients."""
+    c = spec(nx, 13)
+    pops, P = workloads.random_state(nx, 13, seed=5)
+    o = orc.Channel(nx, 13, c.force, tau_lb=c.tau_lb, G=c.G, tau0=c.tau0, gamma_c=c.gamma_c, eps=c.eps,
                     visc_split=c.visc_split, t_startup=c.t_startup, nn_pressure=True)
     o.set_state(pops, P, t=0)
-    with solver([c], precision="fp32", obs_every=4) as s:
+    tol = (1e-4, 1e-3) if precision == "fp32" else (1e-11, 1e-9)
+    with solver([c], precision=precision, obs_every=4) as s:
         s.set_state(0, pops, P, 0)
         for n in [3, 8, 4]:
             s.step(n)
@@ -106,16 +115,17 @@ def test_two_step_matches_oracle(orc):
             g, gP = s.get_state(0)
             err = np.abs(g - o.n).max() / np.abs(o.n - workloads.REST_WEIGHTS[:, None, None]).max()
             perr = np.abs(gP - o.P).max() / np.abs(o.P).max()
-            print(f"t={o.t}: state {err:.2e} P {perr:.2e}", flush=True)
-            assert err < 1e-4 and perr < 1e-3
+            print(f"{precision} t={o.t}: state {err:.2e} P {perr:.2e}", flush=True)
+            assert err < tol[0] and perr < tol[1]
 
 
-@pytest.mark.parametrize("nx", [256, 768, 4096])
-def test_two_step_x_uniform_stays_bitwise_uniform(nx):
+@pytest.mark.parametrize("precision,nx", [("fp32", 256), ("fp32", 768), ("fp32", 4096), ("fp64", 128),
+                                          ("fp64", 320), ("fp64", 4096)])
+def test_two_step_x_uniform_stays_bitwise_uniform(precision, nx):
     """From rest, 3 blocks of 100 steps (with the reference moves between
-    blocks): every column of every row stays identical, so every lane of
-    every window and every strip boundary computes the same values."""
-    with solver([spec(nx, 21, t_startup=2 ** 62)], precision="fp32", obs_every=100) as s:
+    blocks in FP32): every column of every row stays identical, so every lane
+    of every window and every strip boundary computes the same values."""
+    with solver([spec(nx, 21, t_startup=2 ** 62)], precision=precision, obs_every=100) as s:
         s.step(300)
         pops, P = s.get_state(0)
         assert np.array_equal(pops, np.broadcast_to(pops[:, :, :1], pops.shape))
