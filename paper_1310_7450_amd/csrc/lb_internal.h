@@ -161,7 +161,8 @@ hipError_t launch_rereference(float *A, const ChanDev *ch, int n_ch, int total_r
 // (FP32 storage, instantaneous model, vector-class channels with fixed
 // half-way walls and no pressure drive); SweepArgs.strips holds the strips,
 // n_strips their number; the state goes from A to B over steps k and k+1.
-constexpr int kTwoStepCols32 = 248, kTwoStepCols64 = 60;
+constexpr int kTwoStepNpl64 = 2;  // FP64 nodes per lane
+constexpr int kTwoStepCols32 = 248, kTwoStepCols64 = kTwoStepNpl64 == 1 ? 60 : 124;
 // wavefronts per strip (one per stage) and the most rows a strip may have
 constexpr int kTwoStepWaves = 2, kTwoStepMaxRows = 56;
 hipError_t launch_two_step(bool fp32, const SweepArgs &a, hipStream_t s);

@@ -1556,12 +1556,12 @@ __device__ __forceinline__ SideEntry v2_side(int i, bool bot, bool top) {
 template <typename T, int NPL, bool NT>
 __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_kernel(SweepArgs a) {
   // FP32: storage relative to the row references, four nodes per lane;
-  // FP64: plain storage, one node per lane
+  // FP64: plain storage, two nodes per lane
   constexpr bool SHIFT = sizeof(T) == 4;
   constexpr int W = 64 * NPL;                 // window columns
   constexpr int HL = (2 + NPL - 1) / NPL;     // lanes per side without valid step t+1
   typedef typename Vec<T, NPL>::type V;
-  __shared__ V ring[kV2Ring][kPlanes][64];  // 40 KB (FP32) or 20 KB (FP64) per workgroup
+  __shared__ V ring[kV2Ring][kPlanes][64];  // 40 KB per workgroup
   const int lane = threadIdx.x & 63;
   // wave 0 runs stage A, wave 1 stage B of the same strip
   const bool isA = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0;
@@ -2530,8 +2530,8 @@ hipError_t launch_two_step(bool fp32, const SweepArgs &a, hipStream_t s) {
     if (a.nt) hipLaunchKernelGGL((sweep_vec2_kernel<float, 4, true>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((sweep_vec2_kernel<float, 4, false>), grid, block, 0, s, a);
   } else {
-    if (a.nt) hipLaunchKernelGGL((sweep_vec2_kernel<double, 1, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((sweep_vec2_kernel<double, 1, false>), grid, block, 0, s, a);
+    if (a.nt) hipLaunchKernelGGL((sweep_vec2_kernel<double, kTwoStepNpl64, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((sweep_vec2_kernel<double, kTwoStepNpl64, false>), grid, block, 0, s, a);
   }
   return hipGetLastError();
 }
@@ -2540,7 +2540,7 @@ int two_step_blocks_per_cu(bool fp32) {
   int n = 0;
   const hipError_t e =
       fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<float, 4, false>, 64 * kTwoStepWaves, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<double, 1, false>, 64 * kTwoStepWaves,
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<double, kTwoStepNpl64, false>, 64 * kTwoStepWaves,
                                                           0);
   return (e == hipSuccess && n > 0) ? n : 1;
 }

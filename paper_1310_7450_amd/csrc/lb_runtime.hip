@@ -216,10 +216,10 @@ bool two_step_channel(const lb_channel &c, int esize) {
          c.pressure_gradient == 0;
 }
 // Stored columns of the two-step strips of a width: at most 248 (FP32, four
-// nodes per lane) or 60 (FP64, one), in multiples of the nodes per lane, as
+// nodes per lane) or 124 (FP64, two), in multiples of the nodes per lane, as
 // even as possible.
 std::vector<int> two_step_cuts(int nx, int esize) {
-  const int npl = vec_nodes(esize), cols = esize == 4 ? kTwoStepCols32 : kTwoStepCols64;
+  const int npl = esize == 4 ? vec_nodes(esize) : kTwoStepNpl64, cols = esize == 4 ? kTwoStepCols32 : kTwoStepCols64;
   const int units = nx / npl, m = (nx + cols - 1) / cols;
   std::vector<int> x(1, 0);
   for (int i = 0; i < m; ++i) x.push_back(x.back() + npl * (units / m + (i < units % m)));

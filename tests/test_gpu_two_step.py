@@ -1,6 +1,6 @@
 """Two steps per pass over the state (captured blocks of K steps, K a
 multiple of 4) against one step per pass and against the FP64 oracle, in
-FP32 (reference-shifted storage, four nodes per lane) and FP64 (one node per
+FP32 (reference-shifted storage, four nodes per lane) and FP64 (two nodes per
 lane).
 
 The two-step sweep keeps a strip's rows of step t on chip and applies step
@@ -8,7 +8,7 @@ t+1 to them; each node update is the one-step sweep's arithmetic, so the
 states agree with one step per pass to round-off (and, where the compiler
 contracts the same products into the same fused operations, bit for bit).
 Shapes cover one, two, three and many column strips per row (two-step strips
-are at most 248 columns in FP32 and 60 in FP64, split as evenly as the width
+are at most 248 columns in FP32 and 124 in FP64, split as evenly as the width
 allows in multiples of the nodes per lane), ragged row bands, one- and
 two-row channels, the periodic wrap of the window around the channel, and
 handles that mix eligible channels with others (moving wall, Zou-He top,
