@@ -38,8 +38,9 @@ BYTES_PER_NODE_SAF = 160
 def measured_traffic(key):
     """HBM bytes per sweep launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size) for
-    'fp32' (two steps per launch), 'fp32_one' (one step), 'fp64' (4096 x 1024)
-    or 'transient_fp32' (16 x 8192 x 2048, two steps per launch), or
+    'fp32' / 'fp64' (4096 x 1024, two steps per launch), 'fp32_one' /
+    'fp64_one' (one step per launch), 'transient_fp32' (16 x 8192 x 2048, two
+    steps per launch) and the other legs' keys, or
     None when the kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic_sweep_vec.json")
     if not os.path.exists(path):
@@ -179,20 +180,21 @@ def run_transient_scale(steps=200, warmup=100):
             "roofline": two_step_roofline(achieved, nodes, sec / steps, measured_traffic("transient_fp32"))}
 
 
-def two_step_roofline(achieved, nodes, sec_per_step, traffic):
-    """Roofline of the FP32 two-step sweep (sweep_vec2_kernel): one launch
-    performs two node updates per node, so at 80 B per node update its
-    algorithmic bytes are 160 B per node and launch; the state itself is read
-    and written once per launch (80 B per node), which state_GBs reports
-    beside the counters' traffic per launch."""
-    state = BYTES_PER_NODE["fp32"] * nodes / (2 * sec_per_step) / 1e9
+def two_step_roofline(achieved, nodes, sec_per_step, traffic, precision="fp32"):
+    """Roofline of the two-step sweep (sweep_vec2_kernel): one launch
+    performs two node updates per node, so at B bytes per node update (80 in
+    FP32, 160 in FP64) its algorithmic bytes are 2 B per node and launch; the
+    state itself is read and written once per launch (B per node), which
+    state_GBs reports beside the counters' traffic per launch. The kernel is
+    limited by instruction issue, not by HBM (state_frac)."""
+    bpn = BYTES_PER_NODE[precision]
+    state = bpn * nodes / (2 * sec_per_step) / 1e9
     out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
            "kernel": "sweep_vec2_kernel", "node_updates_per_launch": 2 * nodes,
-           "bytes_per_node_update": BYTES_PER_NODE["fp32"],
-           "algorithmic_bytes_per_launch": 2 * BYTES_PER_NODE["fp32"] * nodes,
-           "state_bytes_per_launch": BYTES_PER_NODE["fp32"] * nodes, "state_GBs": round(state, 1),
+           "bytes_per_node_update": bpn, "algorithmic_bytes_per_launch": 2 * bpn * nodes,
+           "state_bytes_per_launch": bpn * nodes, "state_GBs": round(state, 1),
            "state_frac": round(state / HBM_PEAK_GBS, 4)}
     if traffic is not None:
         out["traffic_GBs"] = round(traffic / (2 * sec_per_step) / 1e9, 1)
@@ -354,6 +356,9 @@ def main():
     if not args.no_fp64:
         r64 = time_solver("fp64", wl, args.steps, args.warmup, args.strip_rows)
         print(f"bench: fp64 {r64['mlups']:.0f} MLUPS, {r64['achieved_GBs']:.0f} GB/s", file=sys.stderr, flush=True)
+        r64one = time_solver("fp64", wl, min(args.steps, 4000), min(args.warmup, 1000), args.strip_rows,
+                             steps_per_sweep=1)
+        print(f"bench: fp64 one step per pass {r64one['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     batched = None
     if not args.no_batched:
         batched = run_batched()
@@ -411,8 +416,13 @@ def main():
                          "kernel": "sweep_vec_kernel"}},
         "fp64": None if r64 is None else {
             "value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 5),
-            "roofline": {"bound": "hbm", "achieved": round(r64["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(r64["frac"], 4), "traffic": measured_traffic("fp64")}},
+            "roofline": two_step_roofline(r64["achieved_GBs"], spec.nx * spec.ny, r64["ms_per_step"] / 1e3,
+                                          measured_traffic("fp64"), "fp64"),
+            "one_step_per_pass": {
+                "value": round(r64one["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64one["ms_per_step"], 5),
+                "roofline": {"bound": "hbm", "achieved": round(r64one["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(r64one["frac"], 4),
+                             "traffic": measured_traffic("fp64_one"), "kernel": "sweep_tile_kernel"}}},
         "batched": batched,
         "transient_scale": transient,
         "viscoelastic": ve,
