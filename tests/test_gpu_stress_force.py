@@ -39,13 +39,16 @@ def linf(a, b):
 
 
 @pytest.mark.parametrize("nx,ny,uw", [(1, 16, 0.0), (4, 33, 0.0), (64, 7, 0.0), (100, 37, 0.0), (8, 1, 0.0),
-                                      (8, 2, 0.0), (256, 3, 0.0), (16, 12, 1e-3), (67, 5, 0.0), (68, 4, 0.0)])
+                                      (8, 2, 0.0), (256, 3, 0.0), (16, 12, 1e-3), (67, 5, 0.0), (68, 4, 0.0),
+                                      (128, 37, 0.0), (192, 16, 1e-3), (512, 9, 0.0), (128, 1, 0.0),
+                                      (128, 2, 1e-3), (64, 40, 1e-3)])
 def test_perturbed_state_parity(orc, nx, ny, uw):
     """Seeded random populations on narrow, wide, odd, one- and two-row
-    lattices (and one with a moving top wall): after 1, 2 and 57 steps the
+    lattices (and some with a moving top wall): after 1, 2 and 57 steps the
     populations equal the oracle's node by node. The fused kernel's 64 x 8
     tiles wrap their two-node halo columns by a modulo below nx = 68 (67: a
-    second tile of three columns) and by one add or subtract from 68 on."""
+    second tile of three columns) and by one add or subtract from 68 on;
+    128 and wider run several tiles per row band and several bands."""
     spec = ChannelSpec(nx=nx, ny=ny, force=3e-6, tau_lb=0.8, G=2e-4, tau0=500.0, gamma_c=0.1, eps=0.01,
                        visc_split=0.3, t_startup=40, wall_velocity=uw)
     pops, P = workloads.random_state(nx, ny, seed=nx * 1000 + ny + 3)
