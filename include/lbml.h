@@ -55,8 +55,8 @@ lbml_status lbml_set_params(lbml_net *net, const float *host_params, size_t n);
 lbml_status lbml_get_params(lbml_net *net, float *host_params, size_t n);
 
 /* Forward pass of `batch` rows (1 <= batch <= max_batch): dev_x[batch][dims[0]]
- * FP32 in, dev_y[batch][dims[n_layers]] FP32 out. The activations are kept for
- * lbml_backward; dev_x must stay unchanged until then. Asynchronous. */
+ * FP32 in, dev_y[batch][dims[n_layers]] FP32 out. The activations (and a BF16
+ * copy of the input) are kept for lbml_backward. Asynchronous. */
 lbml_status lbml_forward(lbml_net *net, const float *dev_x, int32_t batch, float *dev_y);
 
 /* Mean-squared error of dev_y against dev_target (both [batch][dims[n_layers]],
@@ -76,6 +76,17 @@ lbml_status lbml_get_grads(lbml_net *net, float *host_grads, size_t n);
  * (t = 1, 2, ... the update count, for bias correction), then refreshes the
  * BF16 weights. Asynchronous. */
 lbml_status lbml_adam_step(lbml_net *net, float lr, float beta1, float beta2, float eps, int32_t t);
+/* One training step on a minibatch gathered on the device: rows
+ * dev_idx[0..batch) (int32, caller-owned; each in [0, n), not checked) of
+ * the inputs dev_X[n][dims[0]] and the targets dev_Y[n][dims[n_layers]] (FP32,
+ * caller-owned), then the forward pass, the mean-squared error, the backward
+ * pass and one Adam update (t as in lbml_adam_step); the same arithmetic as
+ * those calls on the gathered rows, in one call. If host_loss is not NULL
+ * the batch loss before the update is returned there (synchronises);
+ * asynchronous otherwise. The gradients remain readable with lbml_get_grads. */
+lbml_status lbml_train_step(lbml_net *net, const float *dev_X, const float *dev_Y, const int32_t *dev_idx,
+                            int32_t batch, float lr, float beta1, float beta2, float eps, int32_t t,
+                            double *host_loss);
 
 const char *lbml_last_error(const lbml_net *net);
 

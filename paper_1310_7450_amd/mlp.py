@@ -13,7 +13,7 @@ from .lbnlm import load_library
 
 LBML_FUNCTIONS = ["lbml_workspace_bytes", "lbml_param_count", "lbml_create", "lbml_destroy", "lbml_set_params",
                   "lbml_get_params", "lbml_forward", "lbml_mse", "lbml_backward", "lbml_get_grads",
-                  "lbml_adam_step", "lbml_last_error"]
+                  "lbml_adam_step", "lbml_train_step", "lbml_last_error"]
 
 _bound = False
 
@@ -35,6 +35,8 @@ def _lib():
         L.lbml_mse.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
         L.lbml_backward.argtypes = [vp, vp, C.c_int32]
         L.lbml_adam_step.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32]
+        L.lbml_train_step.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float,
+                                      C.c_int32, C.POINTER(C.c_double)]
         L.lbml_last_error.argtypes = [vp]
         L.lbml_last_error.restype = C.c_char_p
         for n in LBML_FUNCTIONS[:-1]:
@@ -140,6 +142,21 @@ class Net:
     def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         self.t += 1
         self._check(self.L.lbml_adam_step(self.h, lr, beta1, beta2, eps, self.t))
+
+    def train_step(self, X_dev, Y_dev, idx_dev, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, want_loss=False):
+        """lbml_train_step: forward, MSE, backward and Adam on rows idx_dev
+        (int32 CUDA tensor) of X_dev / Y_dev (float32 CUDA tensors), in one
+        call; returns the batch loss before the update if want_loss."""
+        import torch
+        assert X_dev.dtype == torch.float32 and X_dev.is_contiguous() and X_dev.shape[1] == self.dims[0]
+        assert Y_dev.dtype == torch.float32 and Y_dev.is_contiguous() and Y_dev.shape[1] == self.dims[-1]
+        assert idx_dev.dtype == torch.int32 and idx_dev.is_contiguous() and idx_dev.numel() <= self.max_batch
+        self.t += 1
+        loss = C.c_double(0.0)
+        self._check(self.L.lbml_train_step(self.h, C.c_void_p(X_dev.data_ptr()), C.c_void_p(Y_dev.data_ptr()),
+                                           C.c_void_p(idx_dev.data_ptr()), idx_dev.numel(), lr, beta1, beta2, eps,
+                                           self.t, C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

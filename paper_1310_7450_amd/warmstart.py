@@ -163,19 +163,17 @@ def train(X, Y, steps=4000, batch=256, lr=1e-3, seed=0, verbose=True):
     net = Net(DIMS, max_batch=batch)
     net.set_params(init_params(DIMS, seed=seed))
     rng = np.random.default_rng(seed)
-    dy = torch.empty((batch, DIMS[-1]), dtype=torch.float32, device="cuda")
     hist = []
     n = X.shape[0]
+    # every minibatch's rows, drawn up front and copied once; the library
+    # gathers them on the device (lbml_train_step)
+    idx_all = torch.from_numpy(np.stack([rng.choice(n, batch, replace=n < batch) for _ in range(steps)])
+                               .astype(np.int32)).cuda()
     for it in range(steps):
-        idx = torch.from_numpy(rng.choice(n, batch, replace=n < batch)).cuda()
-        xb = Xn.index_select(0, idx).contiguous()
-        yb = Yd.index_select(0, idx).contiguous()
-        y = net.forward(xb)
         want = (it % 500 == 0) or it == steps - 1
-        loss = net.mse(y, yb, dy, want_loss=want)
-        net.backward(dy)
         # cosine decay of the learning rate
-        net.adam_step(lr=lr * 0.5 * (1 + math.cos(math.pi * it / steps)) + 1e-5)
+        loss = net.train_step(Xn, Yd, idx_all[it], lr=lr * 0.5 * (1 + math.cos(math.pi * it / steps)) + 1e-5,
+                              want_loss=want)
         if want:
             hist.append((it, loss))
             if verbose and (it % 5000 == 0 or it == steps - 1):

@@ -226,3 +226,34 @@ def test_training_reduces_loss():
         net.adam_step(lr=2e-3)
     print(f"loss {first:.4e} -> {loss:.4e}", flush=True)
     assert loss < first / 10
+
+
+def test_train_step_equals_separate_calls():
+    """lbml_train_step (rows gathered on the device, one call) gives the same
+    loss, gradients and updated parameters, bit for bit, as forward, mse,
+    backward and adam_step on the same rows gathered by torch; two steps in a
+    row, the second with a smaller batch."""
+    import torch
+    from paper_1310_7450_amd import mlp
+    rng = np.random.default_rng(21)
+    X = torch.from_numpy(rng.standard_normal((300, DIMS[0])).astype(np.float32)).cuda()
+    Y = torch.from_numpy((0.3 * rng.standard_normal((300, DIMS[-1]))).astype(np.float32)).cuda()
+    p0 = mlp.init_params(DIMS, seed=6)
+    a, b = mlp.Net(DIMS, max_batch=128), mlp.Net(DIMS, max_batch=128)
+    a.set_params(p0)
+    b.set_params(p0)
+    for batch in (100, 37):
+        idx = torch.from_numpy(rng.choice(300, batch, replace=False).astype(np.int32)).cuda()
+        la = a.train_step(X, Y, idx, lr=1e-3, want_loss=True)
+        xb = X.index_select(0, idx.long()).contiguous()
+        yb = Y.index_select(0, idx.long()).contiguous()
+        y = b.forward(xb)
+        dy = torch.empty_like(y)
+        lb = b.mse(y, yb, dy, want_loss=True)
+        b.backward(dy)
+        b.adam_step(lr=1e-3)
+        torch.cuda.synchronize()
+        print(f"batch {batch}: loss {la:.6e} vs {lb:.6e}", flush=True)
+        assert la == lb
+        assert np.array_equal(a.get_grads(), b.get_grads())
+        assert np.array_equal(a.get_params(), b.get_params())
