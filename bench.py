@@ -180,14 +180,14 @@ def run_transient_scale(steps=200, warmup=100):
             "roofline": two_step_roofline(achieved, nodes, sec / steps, measured_traffic("transient_fp32"))}
 
 
-def two_step_roofline(achieved, nodes, sec_per_step, traffic, precision="fp32"):
+def two_step_roofline(achieved, nodes, sec_per_step, traffic, precision="fp32", bpn=None):
     """Roofline of the two-step sweep (sweep_vec2_kernel): one launch
     performs two node updates per node, so at B bytes per node update (80 in
     FP32, 160 in FP64) its algorithmic bytes are 2 B per node and launch; the
     state itself is read and written once per launch (B per node), which
     state_GBs reports beside the counters' traffic per launch. The kernel is
     limited by instruction issue, not by HBM (state_frac)."""
-    bpn = BYTES_PER_NODE[precision]
+    bpn = BYTES_PER_NODE[precision] if bpn is None else bpn
     state = bpn * nodes / (2 * sec_per_step) / 1e9
     out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -208,13 +208,19 @@ def run_viscoelastic(steps=2000, warmup=1000):
     from paper_1310_7450_amd import workloads
     wl = workloads.large_channel()
     out = {"workload": wl["name"] + "_viscoelastic", "steps": steps}
+    nodes = wl["channels"][0].nx * wl["channels"][0].ny
     for prec in ("fp32", "fp64"):
         r = time_solver(prec, wl, steps, warmup, viscoelastic=True)
+        one = time_solver(prec, wl, steps, warmup, viscoelastic=True, steps_per_sweep=1)
         out[prec] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
                      "bytes_per_node": BYTES_PER_NODE_VE[prec],
-                     "roofline": {"bound": "hbm", "achieved": round(r["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
-                                  "unit": "GB/s", "frac": round(r["frac"], 4),
-                                  "traffic": measured_traffic("ve_" + prec)}}
+                     "roofline": two_step_roofline(r["achieved_GBs"], nodes, r["ms_per_step"] / 1e3,
+                                                   measured_traffic("ve_" + prec), prec, BYTES_PER_NODE_VE[prec]),
+                     "one_step_per_pass": {
+                         "value": round(one["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(one["ms_per_step"], 5),
+                         "roofline": {"bound": "hbm", "achieved": round(one["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
+                                      "unit": "GB/s", "frac": round(one["frac"], 4),
+                                      "traffic": measured_traffic("ve_" + prec + "_one")}}}
     return out
 
 

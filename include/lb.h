@@ -172,7 +172,7 @@ enum { LB_WALL_HALFWAY = 0, LB_WALL_ZOU_HE = 1 };
  *                wall, no pressure_gradient and at most 429,496,704 nodes.
  *                Runs as one fused pass per step (u~, Sigma^nN and the
  *                collide-and-stream of a tile of nodes in one workgroup);
- *   steps_per_sweep 0 (default) or 2: with the instantaneous model, no
+ *   steps_per_sweep 0 (default) or 2: with either stress model, no
  *                stress_force and K a multiple of 4, the blocks of K steps
  *                advance the vector-class channels (width a multiple of 256
  *                in LB_FP32_SHIFTED, of 64 in LB_FP64, not a power of two up

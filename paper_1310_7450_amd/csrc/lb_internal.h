@@ -167,6 +167,6 @@ constexpr int kTwoStepCols32 = 248, kTwoStepCols64 = kTwoStepNpl64 == 1 ? 60 : 1
 constexpr int kTwoStepWaves = 2, kTwoStepMaxRows = 56;
 hipError_t launch_two_step(bool fp32, const SweepArgs &a, hipStream_t s);
 // workgroups of the two-step kernel one CU holds at once
-int two_step_blocks_per_cu(bool fp32);
+int two_step_blocks_per_cu(bool fp32, bool ve);
 
 }  // namespace lbnlm

@@ -1553,15 +1553,18 @@ __device__ __forceinline__ SideEntry v2_side(int i, bool bot, bool top) {
   return e;
 }
 
-template <typename T, int NPL, bool NT>
-__global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_kernel(SweepArgs a) {
+template <typename T, int NPL, bool NT, bool VE>
+__global__ void __launch_bounds__(64 * kTwoStepWaves, VE ? 1 : kTwoStepWaves) sweep_vec2_kernel(SweepArgs a) {
   // FP32: storage relative to the row references, four nodes per lane;
   // FP64: plain storage, two nodes per lane
   constexpr bool SHIFT = sizeof(T) == 4;
   constexpr int W = 64 * NPL;                 // window columns
   constexpr int HL = (2 + NPL - 1) / NPL;     // lanes per side without valid step t+1
   typedef typename Vec<T, NPL>::type V;
-  __shared__ V ring[kV2Ring][kPlanes][64];  // 40 KB per workgroup
+  // the ring of step-t rows: populations and trace, and with VE the stress
+  // sigma(t) (40 KB per workgroup, 52 KB with VE)
+  constexpr int RP = kPlanes + (VE ? kStressPlanes : 0);
+  __shared__ V ring[kV2Ring][RP][64];
   const int lane = threadIdx.x & 63;
   // wave 0 runs stage A, wave 1 stage B of the same strip
   const bool isA = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0;
@@ -1591,6 +1594,14 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
     return (long long)(col >> 6) * (kPlanes * F) + (col & 63);
   };
   const long long lcol = colpart(NPL * lane);
+  // VE: the stress fields, three planes per tile of 64 nodes
+  const T *__restrict__ SA = static_cast<const T *>(a.SA);
+  T *__restrict__ SB = static_cast<T *>(a.SB);
+  auto srow = [&](int y) __attribute__((always_inline)) {
+    return (tile00 + (long long)y * tiles_row) * (kStressPlanes * F);
+  };
+  const long long scol = (long long)(((w0 + NPL * lane + nx) % nx) >> 6) * (kStressPlanes * F) +
+                         ((w0 + NPL * lane + nx) % nx & 63);
   auto clampy = [&](int y) __attribute__((always_inline)) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
 
   // ---- rows of the two stages
@@ -1611,6 +1622,7 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
   // ---- stage A: raw loads of a row of the state (window and side values)
   struct Raw {
     V r[10];
+    V sg[VE ? 3 : 1];  // VE: the stress of the previous step at the row's own nodes
     T side;
   };
   const int li = lane < 24 ? lane : 0;
@@ -1642,6 +1654,10 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
     long long o = o_in;
     if (bot || top) o = side_offset(bot, top);  // wall rows only
     const T *ps = A + rb + o;
+    if constexpr (VE) {
+#pragma unroll
+      for (int p = 0; p < 3; ++p) R.sg[p] = *reinterpret_cast<const V *>(SA + srow(y) + scol + (long long)p * F);
+    }
     if constexpr (SHIFT) {
       const int yr = y + lane - 25;
       const T *pu = a.uref + c.row_off + (yr < 0 ? 0 : (yr >= ny ? ny - 1 : yr));
@@ -1664,6 +1680,10 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
     R.r[4] = ring[su][top ? 2 : 4][lane];
     R.r[7] = ring[su][top ? 5 : 7][lane];
     R.r[8] = ring[su][top ? 6 : 8][lane];
+    if constexpr (VE) {
+#pragma unroll
+      for (int p = 0; p < 3; ++p) R.sg[p] = ring[sc][kPlanes + p][lane];
+    }
     R.side = T(0);
   };
 
@@ -1756,7 +1776,7 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
   // the new populations and trace.
   auto update = [&](int y, T fc[9][NPL], const T Pc[NPL], const T sdc[NPL], const T mxc[NPL], const T myc[NPL],
                     const U2<T> uPrev[NPL], const U2<T> uCur[NPL], const U2<T> uNext[NPL], U2<T> uLc, U2<T> uRc,
-                    const T urC[3], V out[kPlanes]) __attribute__((always_inline)) {
+                    const T urC[3], const T sgc[VE ? 3 : 1][NPL], V out[RP]) __attribute__((always_inline)) {
     const T urc = urC[1];
     const T urd = (y == 0) ? -urc : urC[0];
     const T uru = (y == ny - 1) ? -urc : urC[2];
@@ -1774,22 +1794,33 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
       T g[9], o[9], tr, sn[3];
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[i] = fc[i][k];
-      const T sp[3] = {T(0), T(0), T(0)};
+      const T sp[3] = {VE ? sgc[0][k] : T(0), VE ? sgc[VE ? 1 : 0][k] : T(0), VE ? sgc[VE ? 2 : 0][k] : T(0)};
       double ob[OF_COUNT];
-      node_update<T, SHIFT, false, false>(g, sdc[k], mxc[k], myc[k], Pc[k], fx, lf, rt, dn, up, urc, kref, q, c.nnp,
-                                          sp, sn, o, tr, ob);
+      node_update<T, SHIFT, false, VE>(g, sdc[k], mxc[k], myc[k], Pc[k], fx, lf, rt, dn, up, urc, kref, q, c.nnp, sp,
+                                       sn, o, tr, ob);
 #pragma unroll
       for (int i = 0; i < 9; ++i) out[i][k] = o[i];
       out[9][k] = tr;
+      if constexpr (VE) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) out[kPlanes + p][k] = sn[p];
+      }
     }
   };
 
   // The state each wave carries from one iteration to the next: its
   // assembled current row and u~ of the rows below and at it (stage A: row
   // i and the raw loads of row i+1; stage B: row i-3).
-  T fc[9][NPL], Pc[NPL], sdc[NPL], mxc[NPL], myc[NPL], urC[3];
+  T fc[9][NPL], Pc[NPL], sdc[NPL], mxc[NPL], myc[NPL], urC[3], sgc[VE ? 3 : 1][NPL];
   U2<T> uPrev[NPL], uCur[NPL], uLc, uRc;
   Raw R;
+  // VE: the stress of the previous step at a row's nodes, from its loads
+  auto take_sigma = [&](const Raw &Q, T sg[VE ? 3 : 1][NPL]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int p = 0; p < (VE ? 3 : 1); ++p)
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) sg[p][k] = VE ? Q.sg[p][k] : T(0);
+  };
   if (isA) {
     Raw Rp;
     const int yp = clampy(A0 - 1);
@@ -1807,6 +1838,7 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
     assemble(yp, Rp, urp[0], urp[1], urp[2], ftmp, Ptmp, s0, m0, n0, uPrev, hl, hr);
     refs(R, urC);
     assemble(A0, R, urC[0], urC[1], urC[2], fc, Pc, sdc, mxc, myc, uCur, uLc, uRc);
+    take_sigma(R, sgc);
     load_raw(clampy(A0 + 1), R);
   } else {
 #pragma unroll
@@ -1820,7 +1852,10 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
     urC[0] = urC[1] = urC[2] = T(0);
 #pragma unroll
     for (int j = 0; j < 10; ++j) R.r[j] = V{};
+#pragma unroll
+    for (int j = 0; j < (VE ? 3 : 1); ++j) R.sg[j] = V{};
     R.side = T(0);
+    take_sigma(R, sgc);
   }
 
   // Iteration i. Stage A (rows [A0, A1)): assembles row i+1 from the loads
@@ -1834,7 +1869,7 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
     const int r = isA ? i + 1 : i - 2, y = isA ? i : i - 3;
     const bool do_asm = isA ? (i < A1) : (r >= R0 && r < R1);
     const bool do_upd = isA ? (i < A1) : (y >= st.y0 && y < st.y1);
-    T fn[9][NPL], Pn[NPL], sdn[NPL], mxn[NPL], myn[NPL], urN[3];
+    T fn[9][NPL], Pn[NPL], sdn[NPL], mxn[NPL], myn[NPL], urN[3], sgn[VE ? 3 : 1][NPL];
     U2<T> uNext[NPL], uLn, uRn;
     if (do_asm) {
       if (!isA) load_lds(r, R);
@@ -1842,7 +1877,12 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
 #pragma unroll
       for (int j = 0; j < 3; ++j) urN[j] = !SHIFT ? T(0) : (isA ? lane_value(R.side, 24 + j) : ref(rr - 1 + j));
       assemble(rr, R, urN[0], urN[1], urN[2], fn, Pn, sdn, mxn, myn, uNext, uLn, uRn);
+      take_sigma(R, sgn);
     } else {
+#pragma unroll
+      for (int p = 0; p < (VE ? 3 : 1); ++p)
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) sgn[p][k] = T(0);
 #pragma unroll
       for (int k = 0; k < NPL; ++k) {
         uNext[k] = U2<T>{T(0), T(0)};
@@ -1854,18 +1894,26 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
       urN[0] = urN[1] = urN[2] = T(0);
     }
     if (do_upd) {
-      V out[kPlanes];
-      update(y, fc, Pc, sdc, mxc, myc, uPrev, uCur, uNext, uLc, uRc, urC, out);
+      V out[RP];
+      update(y, fc, Pc, sdc, mxc, myc, uPrev, uCur, uNext, uLc, uRc, urC, sgc, out);
       if (isA) {
         const int slot = y & (kV2Ring - 1);
 #pragma unroll
-        for (int p = 0; p < kPlanes; ++p) ring[slot][p][lane] = out[p];
+        for (int p = 0; p < RP; ++p) ring[slot][p][lane] = out[p];
       } else if (store_lane) {
         T *w = B + rowbase(y) + lcol;
 #pragma unroll
         for (int p = 0; p < kPlanes; ++p) {
           if constexpr (NT) __builtin_nontemporal_store(out[p], reinterpret_cast<V *>(w + (long long)p * F));
           else *reinterpret_cast<V *>(w + (long long)p * F) = out[p];
+        }
+        if constexpr (VE) {
+          T *ws = SB + srow(y) + scol;
+#pragma unroll
+          for (int p = 0; p < 3; ++p) {
+            if constexpr (NT) __builtin_nontemporal_store(out[kPlanes + p], reinterpret_cast<V *>(ws + (long long)p * F));
+            else *reinterpret_cast<V *>(ws + (long long)p * F) = out[kPlanes + p];
+          }
         }
       }
     }
@@ -1874,6 +1922,10 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, kTwoStepWaves) sweep_vec2_
     urC[0] = urN[0];
     urC[1] = urN[1];
     urC[2] = urN[2];
+#pragma unroll
+    for (int p = 0; p < (VE ? 3 : 1); ++p)
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) sgc[p][k] = sgn[p][k];
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       uPrev[k] = uCur[k];
@@ -2523,24 +2575,36 @@ hipError_t launch_gpbc(int fp32, void *B, const ChanDev *ch, int n_ch, int k, co
   return hipGetLastError();
 }
 
+template <typename T, int NPL, bool VE>
+void launch_two_step_t(const SweepArgs &a, hipStream_t s) {
+  const dim3 grid(a.n_wg), block(64 * kTwoStepWaves);
+  if (a.nt) hipLaunchKernelGGL((sweep_vec2_kernel<T, NPL, true, VE>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((sweep_vec2_kernel<T, NPL, false, VE>), grid, block, 0, s, a);
+}
+
 hipError_t launch_two_step(bool fp32, const SweepArgs &a, hipStream_t s) {
   if (a.n_strips == 0) return hipSuccess;
-  const dim3 grid(a.n_wg), block(64 * kTwoStepWaves);
+  if (a.ve && (!a.SA || !a.SB)) return hipErrorInvalidValue;
   if (fp32) {
-    if (a.nt) hipLaunchKernelGGL((sweep_vec2_kernel<float, 4, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((sweep_vec2_kernel<float, 4, false>), grid, block, 0, s, a);
+    if (a.ve) launch_two_step_t<float, 4, true>(a, s);
+    else launch_two_step_t<float, 4, false>(a, s);
   } else {
-    if (a.nt) hipLaunchKernelGGL((sweep_vec2_kernel<double, kTwoStepNpl64, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((sweep_vec2_kernel<double, kTwoStepNpl64, false>), grid, block, 0, s, a);
+    if (a.ve) launch_two_step_t<double, kTwoStepNpl64, true>(a, s);
+    else launch_two_step_t<double, kTwoStepNpl64, false>(a, s);
   }
   return hipGetLastError();
 }
 
-int two_step_blocks_per_cu(bool fp32) {
+int two_step_blocks_per_cu(bool fp32, bool ve) {
   int n = 0;
-  const hipError_t e =
-      fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<float, 4, false>, 64 * kTwoStepWaves, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<double, kTwoStepNpl64, false>, 64 * kTwoStepWaves,
+  constexpr int b = 64 * kTwoStepWaves;
+  hipError_t e;
+  if (fp32)
+    e = ve ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<float, 4, false, true>, b, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<float, 4, false, false>, b, 0);
+  else
+    e = ve ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<double, kTwoStepNpl64, false, true>, b, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<double, kTwoStepNpl64, false, false>, b,
                                                           0);
   return (e == hipSuccess && n > 0) ? n : 1;
 }

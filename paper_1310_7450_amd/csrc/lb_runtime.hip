@@ -204,12 +204,12 @@ void add_strips(int ci, const ChanDev &d, int esize, int srows, bool stack, std:
 }
 
 // Two steps per launch (sweep_vec2_kernel) for the blocks of captured steps:
-// the instantaneous model and the force only (no moving wall, no pressure
-// drive) on vector-class channels, with blocks a multiple of four steps (a
+// the force only (no moving wall, no pressure drive) on vector-class
+// channels, with either stress model, with blocks a multiple of four steps (a
 // block is then an even number of two-step launches and returns the state
 // to its buffer, as one-step launches do).
 bool two_step_handle(const lb_options *o, int K) {
-  return o->steps_per_sweep != 1 && !o->viscoelastic && !o->stress_force && K % 4 == 0;
+  return o->steps_per_sweep != 1 && !o->stress_force && K % 4 == 0;
 }
 bool two_step_channel(const lb_channel &c, int esize) {
   return width_class(c.nx, esize) == kVecClass && c.top_wall == LB_WALL_HALFWAY && c.wall_velocity == 0 &&
@@ -891,7 +891,7 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return bail(LB_EHIP);
-    h->slots = two_step_blocks_per_cu(o->precision == LB_FP32_SHIFTED) * std::max(cus, 1);
+    h->slots = two_step_blocks_per_cu(o->precision == LB_FP32_SHIFTED, o->viscoelastic) * std::max(cus, 1);
   }
   if (upload_strips(h, true) != LB_OK || upload_strips(h, false) != LB_OK) return bail(LB_EHIP);
   std::vector<Strip> tiles, btiles;  // kept until the synchronisation below

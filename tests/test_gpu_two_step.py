@@ -132,3 +132,30 @@ def test_two_step_x_uniform_stays_bitwise_uniform(precision, nx):
         assert np.array_equal(P, np.broadcast_to(P[:, :1], P.shape))
         assert np.abs(pops - workloads.REST_WEIGHTS[:, None, None]).max() > 0
 
+
+
+@pytest.mark.parametrize("precision,nx,ny", [("fp32", 512, 19), ("fp32", 256, 2), ("fp32", 1024, 40),
+                                             ("fp64", 192, 19), ("fp64", 128, 1), ("fp64", 512, 40)])
+def test_two_step_viscoelastic_matches_one_step(precision, nx, ny):
+    """The time-integrated stress: the stored stress sigma(t) rides in the
+    ring beside the populations. From seeded random populations and a seeded
+    random stress, 2 blocks of 8 steps plus 3 single steps: populations,
+    traces and stresses equal the one-step handle's to round-off."""
+    c = spec(nx, ny, G=1e-4, tau0=1e3)
+    pops, P = workloads.random_state(nx, ny, seed=nx + 3 * ny)
+    rng = np.random.default_rng(nx * ny)
+    sig = 1e-6 * rng.standard_normal((3, ny, nx))
+    res = []
+    for sps in (0, 1):
+        with solver([c], precision=precision, obs_every=8, steps_per_sweep=sps, viscoelastic=True) as s:
+            s.set_state(0, pops, P, 0)
+            s.set_stress(0, sig)
+            s.step(16)
+            s.step(3)
+            res.append((s.get_state(0), s.get_stress(0)))
+    (a, sa), (b, sb) = res
+    e, ep = state_diff(a, b, pops)
+    es = np.abs(sa - sb).max() / np.abs(sb).max()
+    print(f"{precision} VE {nx}x{ny}: state {e:.2e} P {ep:.2e} stress {es:.2e}", flush=True)
+    assert e < TOL[precision][0] and ep < TOL[precision][1]
+    assert es < (1e-4 if precision == "fp32" else 1e-11)
