@@ -176,8 +176,8 @@ enum { LB_WALL_HALFWAY = 0, LB_WALL_ZOU_HE = 1 };
  *                stress_force and K a multiple of 4, the blocks of K steps
  *                advance the vector-class channels (width a multiple of 256
  *                in LB_FP32_SHIFTED, of 64 in LB_FP64, not a power of two up
- *                to 64) with the half-way top wall, no wall velocity and no
- *                pressure_gradient two steps per pass over the state (a
+ *                to 64) without pressure_gradient (any top wall) two
+ *                steps per pass over the state (a
  *                strip's rows of step t are kept on chip for step t+1);
  *                other channels, other handles and steps outside whole
  *                blocks run one step per pass. Each node update is the

@@ -79,6 +79,7 @@ struct SweepArgs {
   void *SB;             // viscoelastic model: stress written (3 planes)
   int ve;               // time-integrated stress in place of the instantaneous one
   int zh;               // some channel of the handle has a Zou-He top wall
+  int wall;             // two-step sweep: some strip's channel has a moving or Zou-He top wall
 };
 // A state buffer larger than this is written with nontemporal stores: it
 // cannot stay in the 256 MB last-level cache (MALL) until the next step reads

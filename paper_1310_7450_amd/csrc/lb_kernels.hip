@@ -1553,7 +1553,7 @@ __device__ __forceinline__ SideEntry v2_side(int i, bool bot, bool top) {
   return e;
 }
 
-template <typename T, int NPL, bool NT, bool VE>
+template <typename T, int NPL, bool NT, bool VE, bool WALL>
 __global__ void __launch_bounds__(64 * kTwoStepWaves, VE ? 1 : kTwoStepWaves) sweep_vec2_kernel(SweepArgs a) {
   // FP32: storage relative to the row references, four nodes per lane;
   // FP64: plain storage, two nodes per lane
@@ -1579,6 +1579,12 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, VE ? 1 : kTwoStepWaves) sw
   const T fxA = (t < c.t_startup) ? T(c.g) : T(0);
   const T fxB = (t + 1 < c.t_startup) ? T(c.g) : T(0);
   const T fx = isA ? fxA : fxB;
+  // WALL: a moving top wall at this stage's step ts: its velocity (stencil
+  // ghost) and, for the half-way wall, u_w/6 of step ts - 1, whose reflected
+  // links step ts pulls; or the Zou-He completion of the top row
+  const long long ts = isA ? t : t + 1;
+  const T uwg = (WALL && ts < c.t_startup) ? T(c.uw) : T(0);
+  const T uw6 = (WALL && !c.zh && ts >= 1 && ts - 1 < c.t_startup) ? T(c.uw / 6.0) : T(0);
   const Coef<T> q(c);
   constexpr int F = kTile;
   const long long tile00 = c.off >> 6;
@@ -1723,16 +1729,25 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, VE ? 1 : kTwoStepWaves) sw
     if (top) {
       split(R.r[7], f[7]);
       split(R.r[8], f[8]);
+      if constexpr (WALL) {
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) {
+          f[7][k] -= uw6;
+          f[8][k] += uw6;
+        }
+      }
     } else {
       from_right(R.r[7], lane_value(R.side, 4), f[7]);
       from_left(R.r[8], lane_value(R.side, 5), f[8]);
     }
+    const bool zhtop = WALL && top && c.zh;
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       T g[9];
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[i] = f[i][k];
       if constexpr (SHIFT) to_row_reference(g, urd, urc, uru, bot, top);
+      if (zhtop) zou_he_top<T, SHIFT>(g, uwg, urc, fx);
 #pragma unroll
       for (int i = 0; i < 9; ++i) f[i][k] = g[i];
       moments<T>(g, sd[k], mx[k], my[k]);
@@ -1759,9 +1774,20 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, VE ? 1 : kTwoStepWaves) sw
       r[4] = lane_value(R.side, 21);
       r[7] = lane_value(R.side, 22);
       r[8] = lane_value(R.side, 23);
+      if constexpr (WALL) {
+        const T wc = top ? uw6 : T(0);
+        l[7] -= wc;
+        l[8] += wc;
+        r[7] -= wc;
+        r[8] += wc;
+      }
       if constexpr (SHIFT) {
         to_row_reference(l, urd, urc, uru, bot, top);
         to_row_reference(r, urd, urc, uru, bot, top);
+      }
+      if (zhtop) {
+        zou_he_top<T, SHIFT>(l, uwg, urc, fx);
+        zou_he_top<T, SHIFT>(r, uwg, urc, fx);
       }
       T s0, m0, n0;
       moments<T>(l, s0, m0, n0);
@@ -1779,8 +1805,10 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, VE ? 1 : kTwoStepWaves) sw
                     const T urC[3], const T sgc[VE ? 3 : 1][NPL], V out[RP]) __attribute__((always_inline)) {
     const T urc = urC[1];
     const T urd = (y == 0) ? -urc : urC[0];
-    const T uru = (y == ny - 1) ? -urc : urC[2];
-    const T kref = T(0.5) * (uru - urd);
+    const T uru = (y == ny - 1) ? T(2) * uwg - (WALL && c.zh ? urd : urc) : urC[2];
+    // FP32: the references' share of d_y u_x (ghost rows mirrored); FP64
+    // stores plain populations and has none
+    const T kref = SHIFT ? T(0.5) * (uru - urd) : T(0);
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       U2<T> lf, rt;
@@ -1790,7 +1818,12 @@ __global__ void __launch_bounds__(64 * kTwoStepWaves, VE ? 1 : kTwoStepWaves) sw
       else rt = uCur[k + 1];
       U2<T> dn = uPrev[k], up = uNext[k];
       if (y == 0) dn = U2<T>{-uCur[k].x, -uCur[k].y};
-      if (y == ny - 1) up = U2<T>{-uCur[k].x, -uCur[k].y};
+      // no-slip ghosts behind the half-way walls (moving at u_w above), or
+      // behind a Zou-He node wall mirrored through the wall row
+      if (y == ny - 1) {
+        const U2<T> m = (WALL && c.zh) ? dn : uCur[k];
+        up = U2<T>{(SHIFT ? T(0) : T(2) * uwg) - m.x, -m.y};
+      }
       T g[9], o[9], tr, sn[3];
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[i] = fc[i][k];
@@ -2578,8 +2611,13 @@ hipError_t launch_gpbc(int fp32, void *B, const ChanDev *ch, int n_ch, int k, co
 template <typename T, int NPL, bool VE>
 void launch_two_step_t(const SweepArgs &a, hipStream_t s) {
   const dim3 grid(a.n_wg), block(64 * kTwoStepWaves);
-  if (a.nt) hipLaunchKernelGGL((sweep_vec2_kernel<T, NPL, true, VE>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((sweep_vec2_kernel<T, NPL, false, VE>), grid, block, 0, s, a);
+  if (a.wall) {
+    if (a.nt) hipLaunchKernelGGL((sweep_vec2_kernel<T, NPL, true, VE, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((sweep_vec2_kernel<T, NPL, false, VE, true>), grid, block, 0, s, a);
+  } else {
+    if (a.nt) hipLaunchKernelGGL((sweep_vec2_kernel<T, NPL, true, VE, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((sweep_vec2_kernel<T, NPL, false, VE, false>), grid, block, 0, s, a);
+  }
 }
 
 hipError_t launch_two_step(bool fp32, const SweepArgs &a, hipStream_t s) {
@@ -2600,11 +2638,11 @@ int two_step_blocks_per_cu(bool fp32, bool ve) {
   constexpr int b = 64 * kTwoStepWaves;
   hipError_t e;
   if (fp32)
-    e = ve ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<float, 4, false, true>, b, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<float, 4, false, false>, b, 0);
+    e = ve ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<float, 4, false, true, false>, b, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<float, 4, false, false, false>, b, 0);
   else
-    e = ve ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<double, kTwoStepNpl64, false, true>, b, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<double, kTwoStepNpl64, false, false>, b,
+    e = ve ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<double, kTwoStepNpl64, false, true, false>, b, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<double, kTwoStepNpl64, false, false, false>, b,
                                                           0);
   return (e == hipSuccess && n > 0) ? n : 1;
 }

@@ -204,17 +204,17 @@ void add_strips(int ci, const ChanDev &d, int esize, int srows, bool stack, std:
 }
 
 // Two steps per launch (sweep_vec2_kernel) for the blocks of captured steps:
-// the force only (no moving wall, no pressure drive) on vector-class
-// channels, with either stress model, with blocks a multiple of four steps (a
+// vector-class channels without the pressure drive (whose column pass runs
+// between steps), with either stress model and any top wall, with blocks a multiple of four steps (a
 // block is then an even number of two-step launches and returns the state
 // to its buffer, as one-step launches do).
 bool two_step_handle(const lb_options *o, int K) {
   return o->steps_per_sweep != 1 && !o->stress_force && K % 4 == 0;
 }
 bool two_step_channel(const lb_channel &c, int esize) {
-  return width_class(c.nx, esize) == kVecClass && c.top_wall == LB_WALL_HALFWAY && c.wall_velocity == 0 &&
-         c.pressure_gradient == 0;
+  return width_class(c.nx, esize) == kVecClass && c.pressure_gradient == 0;
 }
+bool two_step_wall(const lb_channel &c) { return c.top_wall == LB_WALL_ZOU_HE || c.wall_velocity != 0; }
 // Stored columns of the two-step strips of a width: at most 248 (FP32, four
 // nodes per lane) or 124 (FP64, two), in multiples of the nodes per lane, as
 // even as possible.
@@ -372,6 +372,7 @@ struct lb_handle {
   Strip *dtwo = nullptr;                        // two-step strips of the active channels
   int bact_begin[kClasses] = {0}, bact_count[kClasses] = {0};
   int two_count = 0;
+  bool two_wall = false;  // some two-step strip's channel has a moving or Zou-He top wall
   Strip *btiles = nullptr;  // captured blocks: tiles of the tiled channels without two-step strips
   int n_btiles = 0;
   bool two_step = false;     // captured blocks pair their steps where eligible
@@ -452,6 +453,7 @@ lb_status upload_strips(lb_handle *h, bool all) {
     // captured blocks: two-step strips for the eligible active channels, the
     // one-step strips of the others
     std::vector<Strip> braw, bgrouped, two;
+    bool wall = false;
     if (h->two_step) {
       const int es = h->L.esize;
       std::vector<lb_channel> elig;
@@ -463,6 +465,7 @@ lb_status upload_strips(lb_handle *h, bool all) {
         if (!h->active[i]) continue;
         if (two_step_channel(h->in[i], es)) {
           add_two_step_strips(i, h->in[i], es, H, two);
+          wall = wall || two_step_wall(h->in[i]);
         } else if (!tiled(&h->opt, h->in[i])) {
           const ChanDev &d = h->L.ch[i];
           add_strips(i, d, h->L.esize,
@@ -482,6 +485,7 @@ lb_status upload_strips(lb_handle *h, bool all) {
     }
     if ((int)two.size() > h->L.max_two) return fail(h, LB_ENOMEM, "two-step strip list exceeds its workspace");
     h->two_count = (int)two.size();
+    h->two_wall = wall;
     if (!two.empty())
       HIPCHECK(h, hipMemcpyAsync(h->dtwo, two.data(), two.size() * sizeof(Strip), hipMemcpyHostToDevice, h->stream));
     // the host vectors die here: make the copies complete first
@@ -590,6 +594,7 @@ lb_status capture(lb_handle *h, int src) {
     for (int k = 0; k < h->K && st == LB_OK; k += 2) {
       if (h->two_count) {
         SweepArgs a = sweep_args(h, h->dtwo, 0, h->two_count, src ^ ((k / 2) & 1), k);
+        a.wall = h->two_wall;
         a.n_wg = h->two_count;  // one strip per workgroup (a wavefront per stage)
         hipError_t e = launch_two_step(h->opt.precision == LB_FP32_SHIFTED, a, h->cap);
         if (e != hipSuccess) st = hipfail(h, e, "launch_two_step");

@@ -13,7 +13,9 @@ allows in multiples of the nodes per lane), ragged row bands, one- and
 two-row channels, the periodic wrap of the window around the channel, and
 handles that mix eligible channels with others (moving wall, Zou-He top,
 pressure drive, narrow widths) whose steps still run one per pass inside the
-same block (in FP64 on the tile sweep)."""
+same block (in FP64 on the tile sweep). Moving half-way walls and Zou-He
+tops run two steps per pass too, with the wall switched off between the two
+steps of a launch."""
 import numpy as np
 import pytest
 
@@ -82,10 +84,10 @@ def test_two_step_matches_one_step(precision, nx, ny):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_two_step_mixed_handle(precision):
-    """Eligible channels beside channels that stay one step per pass
-    (moving wall, Zou-He top, pressure drive, widths 64, 300 and 192 in
-    FP32; 64 and 300 are narrow or tiled in FP64) in one handle: every
-    channel equals its one-step run."""
+    """Two-step channels (plain, with a moving wall, with a Zou-He top)
+    beside channels that stay one step per pass (pressure drive, widths 64,
+    300 and 192 in FP32; 64 and 300 are narrow or tiled in FP64) in one
+    handle: every channel equals its one-step run."""
     chans = [spec(512, 20), spec(512, 12, wall_velocity=1e-3), spec(768, 9, top_wall="zou_he", nn_pressure=False),
              spec(256, 7, force=0.0, pressure_gradient=1e-6, nn_pressure=False), spec(64, 10), spec(300, 6),
              spec(1024, 30), spec(192, 5)]
@@ -159,3 +161,34 @@ def test_two_step_viscoelastic_matches_one_step(precision, nx, ny):
     print(f"{precision} VE {nx}x{ny}: state {e:.2e} P {ep:.2e} stress {es:.2e}", flush=True)
     assert e < TOL[precision][0] and ep < TOL[precision][1]
     assert es < (1e-4 if precision == "fp32" else 1e-11)
+
+
+@pytest.mark.parametrize("precision,nx", [("fp32", 512), ("fp64", 192)])
+@pytest.mark.parametrize("wall", ["moving", "zou_he"])
+def test_two_step_walls_match_one_step_and_oracle(orc, precision, nx, wall):
+    """A moving top wall (half-way, u_w = 1e-3) or a Zou-He top moving at
+    u_w, switched off at t = 19 (inside a launch: step 18 with the wall, 19
+    without): the two-step handle equals the one-step handle to round-off
+    and the FP64 oracle within the FP32 or FP64 tolerance, node by node."""
+    kw = dict(wall_velocity=1e-3, t_startup=19, nn_pressure=False)
+    if wall == "zou_he":
+        kw["top_wall"] = "zou_he"
+    c = spec(nx, 15, **kw)
+    pops, P = workloads.random_state(nx, 15, seed=nx + len(wall))
+    res = []
+    for sps in (0, 1):
+        with solver([c], precision=precision, obs_every=8, steps_per_sweep=sps) as s:
+            s.set_state(0, pops, P, 0)
+            s.step(24)
+            s.step(3)
+            res.append(s.get_state(0))
+    e, ep = state_diff(res[0], res[1], pops)
+    o = orc.Channel(nx, 15, c.force, tau_lb=c.tau_lb, G=c.G, tau0=c.tau0, gamma_c=c.gamma_c, eps=c.eps,
+                    visc_split=c.visc_split, t_startup=c.t_startup, nn_pressure=False, wall_velocity=c.wall_velocity,
+                    top_wall=c.top_wall)
+    o.set_state(pops, P, t=0)
+    o.run(27)
+    eo = np.abs(res[0][0] - o.n).max() / np.abs(o.n - workloads.REST_WEIGHTS[:, None, None]).max()
+    print(f"{precision} {wall} {nx}: two-step vs one-step {e:.2e} (P {ep:.2e}), vs oracle {eo:.2e}", flush=True)
+    assert e < TOL[precision][0] and ep < TOL[precision][1]
+    assert eo < (1e-4 if precision == "fp32" else 1e-11)
