@@ -247,5 +247,31 @@ def experiment(train_seeds=range(100, 116), test_seed=200, n_per_seed=256, train
     return rep
 
 
+def time_training(steps=2000, batch=512, seed=0):
+    """Wall time per training step of the network on seeded synthetic data
+    (X ~ N(0, 1) of shape 4096 x 5, Y = sin(X A) with a seeded 5 x 192
+    matrix A), after 50 warm-up steps: the cost of the training loop alone."""
+    import torch
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((4096, DIMS[0]))
+    Y = np.sin(X @ rng.standard_normal((DIMS[0], DIMS[-1])))
+    train(X, Y, steps=50, batch=batch, lr=2e-3, verbose=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, hist = train(X, Y, steps=steps, batch=batch, lr=2e-3, verbose=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"steps": steps, "batch": batch, "seconds": round(dt, 4), "us_per_step": round(dt / steps * 1e6, 1),
+            "final_loss": hist[-1][1]}
+
+
 if __name__ == "__main__":
-    print(json.dumps(experiment()), flush=True)
+    import argparse
+    ap = argparse.ArgumentParser(description="the learned warm-start experiment, or the training loop's timing")
+    ap.add_argument("--time-training", type=int, default=0, metavar="STEPS",
+                    help="time STEPS training steps on synthetic data instead of running the experiment")
+    args = ap.parse_args()
+    if args.time_training:
+        print(json.dumps(time_training(args.time_training)), flush=True)
+    else:
+        print(json.dumps(experiment()), flush=True)
