@@ -141,7 +141,11 @@ enum { LB_WALL_HALFWAY = 0, LB_WALL_ZOU_HE = 1 };
  *                the block boundaries; even, >= 2 (default 1000 when 0);
  *   strip_rows   rows per wavefront strip of the sweep, also of the
  *                two-step sweep below (0: tuned default; the two-step
- *                default fills whole rounds of one wavefront per SIMD);
+ *                default fills whole rounds of resident strips). While
+ *                the active channels make fewer one-step strips than the
+ *                GPU has SIMDs, their heights are divided alike (down to
+ *                4 rows, or a narrow kernel's row group) to spread them
+ *                over the GPU; results do not depend on strip heights;
  *                FP64 channels whose width is not a power of two up to 64
  *                (and whose nx * ny is at most 429,496,704) step on tiles of
  *                64 x 8 nodes instead and do not use it;

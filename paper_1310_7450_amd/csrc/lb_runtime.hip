@@ -58,6 +58,7 @@ struct Layout {
   // (and their reverse), and the two-step strips
   size_t off_bstrips = 0, off_brstrips = 0, off_tstrips = 0;
   size_t off_btiles = 0;  // tiles of the tiled channels without two-step strips
+  int strip_cap = 0;      // entries of each one-step strip list
   int max_two = 0;
   std::vector<ChanDev> ch;
 };
@@ -299,6 +300,10 @@ Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
     const int srows = strip_rows_for(cls, c[i].nx, c[i].ny, o->strip_rows);
     strips += d.nxs * ((c[i].ny + srows - 1) / srows);
   }
+  // room for the active set's smaller strips when few channels are left
+  // (fewer than twice the SIMDs of any GPU this runs on, see upload_strips)
+  strips = std::max(strips, 4096 + 2 * n);
+  L.strip_cap = strips;
   L.plane = (long long)align_up((size_t)std::max<long long>(node, kTile), kTile);
   L.total_rows = rows;
   L.total_part = part;
@@ -377,6 +382,7 @@ struct lb_handle {
   int n_btiles = 0;
   bool two_step = false;     // captured blocks pair their steps where eligible
   int slots = 1024;          // two-step strips resident at once on the GPU
+  int simds = 1024;          // SIMDs of the GPU (four per CU)
   int cur = 0;               // buffer holding the current state
   hipStream_t stream = nullptr, cap = nullptr;
   bool own_stream = false;
@@ -428,10 +434,48 @@ lb_status upload_strips(lb_handle *h, bool all) {
   // stacks while a state buffer fits the last-level cache (the stores are
   // then cached, see sweep_args)
   const bool stack = (long long)kPlanes * h->L.plane * h->L.esize <= kNontemporalBytes;
+  // Strip heights of the active set: the requested (or default) ones, all
+  // divided alike while the active channels make fewer strips than the GPU
+  // has SIMDs (down to a kernel's row group for the narrow widths, 4 rows
+  // otherwise), so that a few small channels left still spread over the
+  // GPU. A node's arithmetic does not depend on the strip it falls in.
+  int div = 1;
+  auto rows_of = [&](int i) {
+    const ChanDev &d = h->L.ch[i];
+    const int cls = width_class(d.nx, h->L.esize);
+    const int base = strip_rows_for(cls, d.nx, d.ny, h->opt.strip_rows);
+    if (is_strip_class(cls)) return std::max(std::min(base, 4), base / div);
+    const int tyw = 64 / d.nx;
+    const int r = std::max(tyw, base / div);
+    return (r + tyw - 1) / tyw * tyw;
+  };
+  if (!all) {
+    auto count = [&]() {
+      long long S = 0;
+      for (int i = 0; i < h->n_ch; ++i) {
+        if (!h->active[i] || tiled(&h->opt, h->in[i])) continue;
+        const ChanDev &d = h->L.ch[i];
+        const int cls = width_class(d.nx, h->L.esize);
+        const int w = strip_cols(cls, h->L.esize);
+        S += (long long)(is_strip_class(cls) ? (d.nx + w - 1) / w : 1) * ((d.ny + rows_of(i) - 1) / rows_of(i));
+      }
+      return S;
+    };
+    for (long long S = count(); S > 0 && S < h->simds && div < 64;) {
+      div *= 2;
+      const long long S2 = count();
+      if (S2 == S || S2 > h->L.strip_cap) {  // every channel at its smallest height, or no room
+        div /= 2;
+        break;
+      }
+      S = S2;
+    }
+  }
   for (int i = 0; i < h->n_ch; ++i) {
     if (!all && (!h->active[i] || tiled(&h->opt, h->in[i]))) continue;
     const ChanDev &d = h->L.ch[i];
-    add_strips(i, d, h->L.esize, strip_rows_for(width_class(d.nx, h->L.esize), d.nx, d.ny, h->opt.strip_rows),
+    add_strips(i, d, h->L.esize,
+               all ? strip_rows_for(width_class(d.nx, h->L.esize), d.nx, d.ny, h->opt.strip_rows) : rows_of(i),
                stack, raw);
   }
   if (all) {
@@ -468,8 +512,7 @@ lb_status upload_strips(lb_handle *h, bool all) {
           wall = wall || two_step_wall(h->in[i]);
         } else if (!tiled(&h->opt, h->in[i])) {
           const ChanDev &d = h->L.ch[i];
-          add_strips(i, d, h->L.esize,
-                     strip_rows_for(width_class(d.nx, h->L.esize), d.nx, d.ny, h->opt.strip_rows), stack, braw);
+          add_strips(i, d, h->L.esize, rows_of(i), stack, braw);
         }
       }
     }
@@ -897,6 +940,7 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return bail(LB_EHIP);
     h->slots = two_step_blocks_per_cu(o->precision == LB_FP32_SHIFTED, o->viscoelastic) * std::max(cus, 1);
+    h->simds = 4 * std::max(cus, 1);
   }
   if (upload_strips(h, true) != LB_OK || upload_strips(h, false) != LB_OK) return bail(LB_EHIP);
   std::vector<Strip> tiles, btiles;  // kept until the synchronisation below
