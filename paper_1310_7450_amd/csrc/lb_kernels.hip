@@ -528,12 +528,23 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
     if constexpr (SHIFT) return a.uref[c.row_off + clampy(y)];
     return T(0);
   };
-  // pulled populations of row y relative to that row's reference ur
-  auto pull_row = [&](int y, T f[9], T &Pv, T &ur) {
+  // a row's loads (the pulled populations and P), then the populations
+  // relative to that row's reference ur: split so that the loads of several
+  // rows can be in flight before any is used
+  struct RowLoad {
+    T f[9], P;
+  };
+  auto load_row = [&](int y, RowLoad &L) {
     const int yc = clampy(y);
     const long long row = base + (long long)yc * nx;
-    pull<T>(A, row, nx, ny, x, yc, uw6, f);
-    Pv = A[slot(9, row + x)];
+    pull<T>(A, row, nx, ny, x, yc, uw6, L.f);
+    L.P = A[slot(9, row + x)];
+  };
+  auto finish_row = [&](int y, const RowLoad &L, T f[9], T &Pv, T &ur) {
+    const int yc = clampy(y);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = L.f[i];
+    Pv = L.P;
     ur = ref(yc);
     if constexpr (SHIFT) to_row_reference(f, ref(yc - 1), ur, ref(yc + 1), yc == 0, yc == ny - 1);
     if (c.zh && yc == ny - 1) zou_he_top<T, SHIFT>(f, uwg, ur, fx);
@@ -563,14 +574,20 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
 
   T fc[9], fn[9], Pc, Pn, urc, urn, sgc[3], sgn[3];
   U2<T> uPrev, uCur, uNext, uhCur = {T(0), T(0)}, uhNext = {T(0), T(0)};
+  // the loads of the row groups below the strip, at its start and after it
+  // (the first one the loop takes) go out together
+  RowLoad Lp, Lc, Ln;
+  load_row(st.y0 - TYW + ly, Lp);
+  load_row(st.y0 + ly, Lc);
+  load_row(st.y0 + TYW + ly, Ln);
   {
     T ftmp[9], Ptmp, sd, mx, my, urp;
-    pull_row(st.y0 - TYW + ly, ftmp, Ptmp, urp);
+    finish_row(st.y0 - TYW + ly, Lp, ftmp, Ptmp, urp);
     moments<T>(ftmp, sd, mx, my);
     uPrev = u_tilde<T, SHIFT>(sd, mx, my, fx, urp);
   }
   T sdc, mxc, myc;
-  pull_row(st.y0 + ly, fc, Pc, urc);
+  finish_row(st.y0 + ly, Lc, fc, Pc, urc);
   load_sigma(st.y0 + ly, sgc);
   moments<T>(fc, sdc, mxc, myc);
   uCur = u_tilde<T, SHIFT>(sdc, mxc, myc, fx, urc);
@@ -579,7 +596,8 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
 #pragma unroll 1
   for (int yb = st.y0; yb < st.y1; yb += TYW) {
     T sdn, mxn, myn;
-    pull_row(yb + TYW + ly, fn, Pn, urn);
+    if (yb != st.y0) load_row(yb + TYW + ly, Ln);
+    finish_row(yb + TYW + ly, Ln, fn, Pn, urn);
     load_sigma(yb + TYW + ly, sgn);
     if (WIDE) uhNext = halo_u(yb + TYW);
     moments<T>(fn, sdn, mxn, myn);
