@@ -183,6 +183,8 @@ enum { LB_WALL_HALFWAY = 0, LB_WALL_ZOU_HE = 1 };
  *                to 64) without pressure_gradient (any top wall) two
  *                steps per pass over the state (a
  *                strip's rows of step t are kept on chip for step t+1);
+ *                without the viscoelastic option the narrow channels (width
+ *                1, 2, 4, ..., 64) without pressure_gradient do too;
  *                other channels, other handles and steps outside whole
  *                blocks run one step per pass. Each node update is the
  *                arithmetic of the one-step pass; states agree with it to

@@ -167,6 +167,10 @@ constexpr int kTwoStepCols32 = 248, kTwoStepCols64 = kTwoStepNpl64 == 1 ? 60 : 1
 // wavefronts per strip (one per stage) and the most rows a strip may have
 constexpr int kTwoStepWaves = 2, kTwoStepMaxRows = 56;
 hipError_t launch_two_step(bool fp32, const SweepArgs &a, hipStream_t s);
+// Two steps per launch for the narrow widths (nx a power of two up to 64,
+// the instantaneous model): one workgroup of two wavefronts per strip of
+// rows, the strips of one width in SweepArgs.strips, n_wg = n_strips.
+hipError_t launch_narrow_two_step(bool fp32, int nx, const SweepArgs &a, hipStream_t s);
 // workgroups of the two-step kernel one CU holds at once
 int two_step_blocks_per_cu(bool fp32, bool ve);
 

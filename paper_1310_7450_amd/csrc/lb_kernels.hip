@@ -691,6 +691,199 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
   }
 }
 
+// Two steps per launch for the narrow widths (nx = 1, 2, ..., 64: a row
+// fits TXW = nx lanes and a wavefront holds TYW = 64 / nx rows), for the
+// instantaneous model. A workgroup of two wavefronts takes the strip of rows
+// [y0, y1) of one channel through steps t and t+1 with the narrow sweep's
+// row machine in both:
+//  * wavefront 0 (stage A, step t) marches groups of TYW rows from
+//    max(y0 - 2, 0) to min(y1 + 2, ny), reading the state, and writes each
+//    group's post-collision populations and trace into a ring of groups in
+//    LDS;
+//  * wavefront 1 (stage B, step t+1) marches the groups of [y0, y1), pulling
+//    from the ring (any row of the last few groups, by index), and stores.
+// A row of the channel is whole in one group, so no column beyond it is
+// needed. Stage B starts its march L - 1 iterations after stage A (L = 3,
+// or 4 and 5 when a group holds 2 and 1 rows) so that every group it reads
+// is in the ring; one barrier per iteration orders the ring's writes and
+// reads. Per node the arithmetic is the narrow sweep's.
+constexpr int kN2Ring = 8;  // groups in the ring
+template <typename T, bool SHIFT, int TXW>
+__global__ void __launch_bounds__(128) sweep_narrow2_kernel(SweepArgs a) {
+  constexpr int TYW = 64 / TXW;
+  constexpr int L = 3 + 2 / TYW;  // stage B's lag in iterations
+  static_assert(L <= kN2Ring, "the ring must hold the groups stage B reads");
+  __shared__ T ring[kN2Ring][kPlanes][64];
+  const int lane = threadIdx.x & 63;
+  const bool isA = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0;
+  const int sidx = xcd_item(blockIdx.x, a.n_wg);
+  if (sidx >= a.n_strips) return;  // the whole workgroup, before any barrier
+  const Strip st = a.strips[sidx];
+  const ChanDev c = a.ch[st.ch];
+  const T *__restrict__ A = static_cast<const T *>(a.A);
+  T *__restrict__ B = static_cast<T *>(a.B);
+  const int nx = c.nx, ny = c.ny;
+  const long long t = c.t + a.k, ts = isA ? t : t + 1;  // this stage's step
+  const T fx = (ts < c.t_startup) ? T(c.g) : T(0);
+  const T uwg = (ts < c.t_startup) ? T(c.uw) : T(0);
+  const T uw6 = (!c.zh && ts >= 1 && ts - 1 < c.t_startup) ? T(c.uw / 6.0) : T(0);
+  const Coef<T> q(c);
+  const int lx = lane & (TXW - 1), ly = lane / TXW, x = lx;
+  const int left_src = ly * TXW + ((lx + TXW - 1) & (TXW - 1));
+  const int right_src = ly * TXW + ((lx + 1) & (TXW - 1));
+  const long long base = c.off;
+  auto clampy = [&](int y) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
+  auto ref = [&](int y) -> T {
+    if constexpr (SHIFT) return a.uref[c.row_off + clampy(y)];
+    return T(0);
+  };
+  // the groups of the two stages
+  const int yA0 = st.y0 - 2 < 0 ? 0 : st.y0 - 2, yA1 = st.y1 + 2 > ny ? ny : st.y1 + 2;
+  const int nA = (yA1 - yA0 + TYW - 1) / TYW, nB = (st.y1 - st.y0 + TYW - 1) / TYW;
+  const int ys = isA ? yA0 : st.y0;  // this stage's first group
+
+  // stage A's source: the state (the narrow sweep's pull)
+  auto pull_mem = [&](int y, T f[9], T &Pv) {
+    const int yc = clampy(y);
+    const long long row = base + (long long)yc * nx;
+    pull<T>(A, row, nx, ny, x, yc, uw6, f);
+    Pv = A[slot(9, row + x)];
+  };
+  // stage B's source: row r, column col of step t from the ring (rows
+  // outside stage A's range read a row inside it; their values are unused)
+  auto at = [&](int r, int p, int col) -> T {
+    const int rr = (r < yA0 ? yA0 : (r >= yA1 ? yA1 - 1 : r)) - yA0;
+    const int g = rr / TYW;
+    return ring[g & (kN2Ring - 1)][p][(rr - g * TYW) * TXW + col];
+  };
+  auto pull_ring = [&](int y, T f[9], T &Pv) {
+    const int yc = clampy(y);
+    const bool bot = (yc == 0), top = (yc == ny - 1);
+    const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+    f[0] = at(yc, 0, x);
+    f[1] = at(yc, 1, xm);
+    f[3] = at(yc, 3, xp);
+    f[2] = bot ? at(yc, 4, x) : at(yc - 1, 2, x);
+    f[5] = bot ? at(yc, 7, x) : at(yc - 1, 5, xm);
+    f[6] = bot ? at(yc, 8, x) : at(yc - 1, 6, xp);
+    f[4] = top ? at(yc, 2, x) : at(yc + 1, 4, x);
+    f[7] = top ? at(yc, 5, x) - uw6 : at(yc + 1, 7, xp);
+    f[8] = top ? at(yc, 6, x) + uw6 : at(yc + 1, 8, xm);
+    Pv = at(yc, 9, x);
+  };
+  // a row's pulled populations and P (split from the rest so that stage A
+  // can have the loads of several groups in flight), then the populations
+  // relative to the row's reference, moments and u~
+  struct RowLoad {
+    T f[9], P;
+  };
+  auto fetch = [&](int y, RowLoad &L) {
+    if (isA) pull_mem(y, L.f, L.P);
+    else pull_ring(y, L.f, L.P);
+  };
+  auto finish = [&](int y, const RowLoad &L, T f[9], T &Pv, T &ur, T &sd, T &mx, T &my, U2<T> &u) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = L.f[i];
+    Pv = L.P;
+    const int yc = clampy(y);
+    ur = ref(yc);
+    if constexpr (SHIFT) to_row_reference(f, ref(yc - 1), ur, ref(yc + 1), yc == 0, yc == ny - 1);
+    if (c.zh && yc == ny - 1) zou_he_top<T, SHIFT>(f, uwg, ur, fx);
+    moments<T>(f, sd, mx, my);
+    u = u_tilde<T, SHIFT>(sd, mx, my, fx, ur);
+  };
+
+  T fc[9], Pc, urc, sdc, mxc, myc;
+  U2<T> uPrev, uCur;
+  RowLoad Ln;
+  // the group below this stage's first and the first; stage A also fetches
+  // the second (stage B cannot yet: stage A has not written all its rows)
+  auto start = [&]() {
+    RowLoad Lp, Lc;
+    fetch(ys - TYW + ly, Lp);
+    fetch(ys + ly, Lc);
+    if (isA) fetch(ys + TYW + ly, Ln);
+    T ftmp[9], Ptmp, urp, sd, mx, my;
+    finish(ys - TYW + ly, Lp, ftmp, Ptmp, urp, sd, mx, my, uPrev);
+    finish(ys + ly, Lc, fc, Pc, urc, sdc, mxc, myc, uCur);
+  };
+  // group g of this stage: fetch and finish the next group, update this one
+  auto group = [&](int g) {
+    const int yb = ys + g * TYW;
+    T fn[9], Pn, urn, sdn, mxn, myn;
+    U2<T> uNext;
+    if (g != 0 || !isA) fetch(yb + TYW + ly, Ln);
+    finish(yb + TYW + ly, Ln, fn, Pn, urn, sdn, mxn, myn, uNext);
+    const int y = yb + ly;
+    U2<T> dn, up;
+    if (TYW == 1) {
+      dn = uPrev;
+      up = uNext;
+    } else {
+      const U2<T> dc = shfl2(uCur, lane - TXW < 0 ? 0 : lane - TXW);
+      const U2<T> dp = shfl2(uPrev, lane + (TYW - 1) * TXW > 63 ? 63 : lane + (TYW - 1) * TXW);
+      const U2<T> uc = shfl2(uCur, lane + TXW > 63 ? 63 : lane + TXW);
+      const U2<T> un = shfl2(uNext, lane - (TYW - 1) * TXW < 0 ? 0 : lane - (TYW - 1) * TXW);
+      dn = (ly > 0) ? dc : dp;
+      up = (ly < TYW - 1) ? uc : un;
+    }
+    const U2<T> lf = shfl2(uCur, left_src), rt = shfl2(uCur, right_src);
+    if (y == 0) dn = U2<T>{-uCur.x, -uCur.y};
+    if (y == ny - 1) {
+      const U2<T> m = c.zh ? dn : uCur;
+      up = U2<T>{(SHIFT ? T(0) : T(2) * uwg) - m.x, -m.y};
+    }
+    T kref = T(0);
+    if constexpr (SHIFT) {
+      const T urd = (y == 0) ? -urc : ref(y - 1);
+      const T uru = (y >= ny - 1) ? T(2) * uwg - (c.zh ? urd : urc) : ref(y + 1);
+      kref = T(0.5) * (uru - urd);
+    }
+    T out[9], trT, sg[3];
+    const T sp[3] = {T(0), T(0), T(0)};
+    double obs[OF_COUNT];
+    node_update<T, SHIFT, false, false>(fc, sdc, mxc, myc, Pc, fx, lf, rt, dn, up, urc, kref, q, c.nnp, sp, sg, out,
+                                        trT, obs);
+    if (isA) {
+      // the whole group goes into the ring (rows past stage A's range are
+      // never read)
+      T *slotp = &ring[g & (kN2Ring - 1)][0][0];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) slotp[i * 64 + lane] = out[i];
+      slotp[9 * 64 + lane] = trT;
+    } else if (y < st.y1 && y < ny) {
+      const long long o = base + (long long)y * nx + x;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) B[slot(i, o)] = out[i];
+      B[slot(9, o)] = trT;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fc[i] = fn[i];
+    Pc = Pn;
+    urc = urn;
+    sdc = sdn;
+    mxc = mxn;
+    myc = myn;
+    uPrev = uCur;
+    uCur = uNext;
+  };
+
+  // Iteration j: stage A runs group j (after starting at j = 0); stage B
+  // starts at j = L - 1 and runs group j - L; one barrier per iteration.
+  const int niter = (nA > nB + L) ? nA : nB + L;
+  if (isA) start();
+#pragma unroll 1
+  for (int j = 0; j < niter; ++j) {
+    if (isA) {
+      if (j < nA) group(j);
+    } else {
+      if (j == L - 1) start();
+      if (j >= L && j - L < nB) group(j - L);
+    }
+    __syncthreads();
+  }
+}
+
 // FP64 step of the instantaneous or time-integrated model over tiles of
 // kMainTileX x kMainTileY nodes, one workgroup per tile and one thread per
 // node. Each thread pulls its node and keeps the populations; u~ of the tile
@@ -2636,6 +2829,31 @@ void launch_two_step_t(const SweepArgs &a, hipStream_t s) {
     if (a.nt) hipLaunchKernelGGL((sweep_vec2_kernel<T, NPL, true, VE, false>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((sweep_vec2_kernel<T, NPL, false, VE, false>), grid, block, 0, s, a);
   }
+}
+
+hipError_t launch_narrow_two_step(bool fp32, int nx, const SweepArgs &a, hipStream_t s) {
+  if (a.n_strips == 0) return hipSuccess;
+  const dim3 grid(a.n_wg), block(128);
+#define LB_N2(TT, SH, W) hipLaunchKernelGGL((sweep_narrow2_kernel<TT, SH, W>), grid, block, 0, s, a)
+#define LB_N2_ALL(TT, SH)  \
+  switch (nx) {            \
+    case 1: LB_N2(TT, SH, 1); break;   \
+    case 2: LB_N2(TT, SH, 2); break;   \
+    case 4: LB_N2(TT, SH, 4); break;   \
+    case 8: LB_N2(TT, SH, 8); break;   \
+    case 16: LB_N2(TT, SH, 16); break; \
+    case 32: LB_N2(TT, SH, 32); break; \
+    case 64: LB_N2(TT, SH, 64); break; \
+    default: return hipErrorInvalidValue; \
+  }
+  if (fp32) {
+    LB_N2_ALL(float, true)
+  } else {
+    LB_N2_ALL(double, false)
+  }
+#undef LB_N2_ALL
+#undef LB_N2
+  return hipGetLastError();
 }
 
 hipError_t launch_two_step(bool fp32, const SweepArgs &a, hipStream_t s) {

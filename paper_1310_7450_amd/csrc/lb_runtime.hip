@@ -215,6 +215,11 @@ bool two_step_handle(const lb_options *o, int K) {
 bool two_step_channel(const lb_channel &c, int esize) {
   return width_class(c.nx, esize) == kVecClass && c.pressure_gradient == 0;
 }
+// The narrow widths (nx = 1, 2, ..., 64) of the instantaneous model take
+// two steps per launch too (sweep_narrow2_kernel), without the pressure drive.
+bool narrow_two_step_channel(const lb_options *o, const lb_channel &c, int esize) {
+  return !o->viscoelastic && !is_strip_class(width_class(c.nx, esize)) && c.pressure_gradient == 0;
+}
 bool two_step_wall(const lb_channel &c) { return c.top_wall == LB_WALL_ZOU_HE || c.wall_velocity != 0; }
 // Stored columns of the two-step strips of a width: at most 248 (FP32, four
 // nodes per lane) or 124 (FP64, two), in multiples of the nodes per lane, as
@@ -376,6 +381,9 @@ struct lb_handle {
   Strip *dbact = nullptr, *dbact_rev = nullptr;  // captured blocks: active channels without two-step strips
   Strip *dtwo = nullptr;                        // two-step strips of the active channels
   int bact_begin[kClasses] = {0}, bact_count[kClasses] = {0};
+  // captured blocks: the narrow two-step strips of each width, after the
+  // others in dbact
+  int n2_begin[kClasses] = {0}, n2_count[kClasses] = {0};
   int two_count = 0;
   bool two_wall = false;  // some two-step strip's channel has a moving or Zou-He top wall
   Strip *btiles = nullptr;  // captured blocks: tiles of the tiled channels without two-step strips
@@ -496,7 +504,7 @@ lb_status upload_strips(lb_handle *h, bool all) {
     }
     // captured blocks: two-step strips for the eligible active channels, the
     // one-step strips of the others
-    std::vector<Strip> braw, bgrouped, two;
+    std::vector<Strip> braw, bgrouped, two, n2raw, n2grouped;
     bool wall = false;
     if (h->two_step) {
       const int es = h->L.esize;
@@ -510,6 +518,8 @@ lb_status upload_strips(lb_handle *h, bool all) {
         if (two_step_channel(h->in[i], es)) {
           add_two_step_strips(i, h->in[i], es, H, two);
           wall = wall || two_step_wall(h->in[i]);
+        } else if (narrow_two_step_channel(&h->opt, h->in[i], es)) {
+          add_strips(i, h->L.ch[i], es, rows_of(i), stack, n2raw);
         } else if (!tiled(&h->opt, h->in[i])) {
           const ChanDev &d = h->L.ch[i];
           add_strips(i, d, h->L.esize, rows_of(i), stack, braw);
@@ -520,6 +530,12 @@ lb_status upload_strips(lb_handle *h, bool all) {
     std::vector<Strip> brev(bgrouped);
     for (int c = 0; c < kClasses; ++c)
       std::reverse(brev.begin() + h->bact_begin[c], brev.begin() + h->bact_begin[c] + h->bact_count[c]);
+    // the narrow two-step strips follow in dbact (their heights are the
+    // active set's one-step ones, so both lists together fit its room)
+    group_strips(n2raw, h->L.ch, h->L.esize, n2grouped, h->n2_begin, h->n2_count);
+    for (int c = 0; c < kClasses; ++c) h->n2_begin[c] += (int)bgrouped.size();
+    bgrouped.insert(bgrouped.end(), n2grouped.begin(), n2grouped.end());
+    if ((long long)bgrouped.size() > h->L.strip_cap) return fail(h, LB_ENOMEM, "block strip list exceeds its workspace");
     if (!bgrouped.empty()) {
       HIPCHECK(h, hipMemcpyAsync(h->dbact, bgrouped.data(), bgrouped.size() * sizeof(Strip), hipMemcpyHostToDevice,
                                  h->stream));
@@ -641,6 +657,13 @@ lb_status capture(lb_handle *h, int src) {
         a.n_wg = h->two_count;  // one strip per workgroup (a wavefront per stage)
         hipError_t e = launch_two_step(h->opt.precision == LB_FP32_SHIFTED, a, h->cap);
         if (e != hipSuccess) st = hipfail(h, e, "launch_two_step");
+      }
+      for (int c = 0; c < kClasses && st == LB_OK; ++c) {
+        if (!h->n2_count[c]) continue;
+        SweepArgs a = sweep_args(h, h->dbact, h->n2_begin[c], h->n2_count[c], src ^ ((k / 2) & 1), k);
+        a.n_wg = h->n2_count[c];  // one strip per workgroup (a wavefront per stage)
+        hipError_t e = launch_narrow_two_step(h->opt.precision == LB_FP32_SHIFTED, 1 << c, a, h->cap);
+        if (e != hipSuccess) st = hipfail(h, e, "launch_narrow_two_step");
       }
       if (st == LB_OK) st = enqueue_step(h, src, k, h->cap, true);
       if (st == LB_OK) st = enqueue_step(h, src ^ 1, k + 1, h->cap, true);
@@ -893,7 +916,9 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
   h->dbact_rev = reinterpret_cast<Strip *>(h->ws + h->L.off_brstrips);
   h->dtwo = reinterpret_cast<Strip *>(h->ws + h->L.off_tstrips);
   h->btiles = reinterpret_cast<Strip *>(h->ws + h->L.off_btiles);
-  h->two_step = two_step_handle(o, h->K) && h->L.max_two > 0;
+  h->two_step = false;
+  for (int i = 0; i < n && two_step_handle(o, h->K); ++i)
+    h->two_step = h->two_step || two_step_channel(c[i], h->L.esize) || narrow_two_step_channel(o, c[i], h->L.esize);
   h->dpart = reinterpret_cast<double *>(h->ws + h->L.off_part);
   h->dprof = reinterpret_cast<double *>(h->ws + h->L.off_prof);
   h->dprev = reinterpret_cast<double *>(h->ws + h->L.off_prev);
