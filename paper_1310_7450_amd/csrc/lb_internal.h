@@ -57,7 +57,7 @@ struct ChanDev {
 // Work unit of one wavefront: rows [y0, y1) of channel ch, starting at
 // column x0 (wide mode: first interior column; narrow mode: 0). flip: the
 // vector sweep marches this strip against the step's direction (odd bands).
-// x1: the two-step sweep stores columns [x0, x1) (at most 248 of them).
+// x1: the two-step sweep stores columns [x0, x1) (at most two_step_cols).
 struct Strip {
   int ch, x0, y0, y1, flip, x1;
 };
@@ -158,12 +158,17 @@ hipError_t launch_saf_observe(const double *A, const ChanDev *ch, int n_ch, long
                               double *U, double *Tn, double *part, hipStream_t s);
 hipError_t launch_rereference(float *A, const ChanDev *ch, int n_ch, int total_rows, const double *prof,
                               float *uref, hipStream_t s);
-// Two steps per launch on strips of at most kTwoStepCols stored columns
-// (FP32 storage, instantaneous model, vector-class channels with fixed
-// half-way walls and no pressure drive); SweepArgs.strips holds the strips,
-// n_strips their number; the state goes from A to B over steps k and k+1.
-constexpr int kTwoStepNpl64 = 2;  // FP64 nodes per lane
-constexpr int kTwoStepCols32 = 248, kTwoStepCols64 = kTwoStepNpl64 == 1 ? 60 : 124;
+// Two steps per launch (sweep_vec2_kernel) on strips of vector-class
+// channels without the pressure drive: NPL nodes per lane, four for FP32
+// states streamed from HBM with the instantaneous model (16-byte loads keep
+// more bytes in flight), two otherwise (fewer registers: three wavefronts
+// per SIMD in FP32), in windows of 64 NPL columns of which
+// two_step_cols(NPL) are stored (the rest is the halo step t+1 needs).
+// SweepArgs.strips holds the strips, n_strips their number; the state (with
+// the viscoelastic model also the stress) goes from A to B over steps k and
+// k+1.
+inline int two_step_npl(bool fp32, bool nt, bool ve) { return (fp32 && nt && !ve) ? 4 : 2; }
+inline int two_step_cols(int npl) { return 64 * npl - 2 * npl * ((2 + npl - 1) / npl); }
 // wavefronts per strip (one per stage) and the most rows a strip may have
 constexpr int kTwoStepWaves = 2, kTwoStepMaxRows = 56;
 hipError_t launch_two_step(bool fp32, const SweepArgs &a, hipStream_t s);
@@ -172,6 +177,6 @@ hipError_t launch_two_step(bool fp32, const SweepArgs &a, hipStream_t s);
 // rows, the strips of one width in SweepArgs.strips, n_wg = n_strips.
 hipError_t launch_narrow_two_step(bool fp32, int nx, const SweepArgs &a, hipStream_t s);
 // workgroups of the two-step kernel one CU holds at once
-int two_step_blocks_per_cu(bool fp32, bool ve);
+int two_step_blocks_per_cu(bool fp32, bool nt, bool ve);
 
 }  // namespace lbnlm

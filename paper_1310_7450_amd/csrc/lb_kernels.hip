@@ -1696,31 +1696,34 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_vec_kernel(SweepArgs a
 }
 
 // ---------------------------------------------------------------------------
-// Two steps per launch. For FP32 storage relative to the row references,
-// the instantaneous model, vector-class channels (nx a multiple of 256) with
-// fixed half-way walls and no pressure drive, one workgroup of two
-// wavefronts takes an output strip of at most 248 columns [x0, x1) and rows
-// [y0, y1) through steps t and t+1 without writing step t to memory:
-//  * the window is the 256 columns starting four columns left of x0 (four
-//    per lane, wrapped periodically), with one column beside it on either
-//    side as the vector sweep has;
+// Two steps per launch for vector-class channels without the pressure
+// drive (either stress model, any top wall; FP32 storage relative to the
+// row references or plain FP64). One workgroup of two wavefronts takes an
+// output strip of columns [x0, x1) and rows [y0, y1) through steps t and
+// t+1 without writing step t to memory; each lane holds NPL adjacent nodes
+// of a row (two, or four for streamed FP32 states of the instantaneous
+// model):
+//  * the window is the 64 NPL columns starting HL NPL columns left of x0
+//    (HL = ceil(2 / NPL) lanes, wrapped periodically), with one column
+//    beside it on either side as the vector sweep has;
 //  * wavefront 0 runs stage A (step t): the vector sweep's row machine over
 //    the window for rows max(y0-2, 0) .. min(y1+2, ny)-1, read from the
-//    state; each row's post-collision populations and trace go into a ring
-//    of four rows in LDS instead of memory;
+//    state; each row's post-collision populations and trace (and with the
+//    time-integrated model the stress sigma(t)) go into a ring of four rows
+//    in LDS instead of memory;
 //  * wavefront 1 runs stage B (step t+1): the same machine reading its rows
 //    from that ring, three rows behind stage A, and stores rows y0 .. y1-1
-//    of lanes 1..62 to the other buffer.
+//    of lanes HL .. 63-HL to the other buffer.
 // The two stages share one loop with one barrier per row. Splitting them
-// over two wavefronts halves what each keeps in registers (240 VGPRs), so
-// that two wavefronts fit a SIMD and one's arithmetic covers the other's
-// waits; four strips (40 KB of LDS each) share a CU.
+// over two wavefronts halves what each keeps in registers, so that two or
+// three wavefronts fit a SIMD and one's arithmetic covers the other's waits.
 // After step t the window's two outermost columns on each side lack valid
-// neighbours for step t+1; lanes 0 and 63 hold them and store nothing, so
-// every stored node saw only values of the exact step-t state. Per node the
+// neighbours for step t+1; the lanes holding them store nothing, so every
+// stored node saw only values of the exact step-t state. Per node the
 // arithmetic is the vector sweep's (same helpers, same pull, reference
 // shifts and collision), so the result equals two one-step sweeps to the
-// rounding of the FP32 operations.
+// rounding of the operations. A moving top wall takes each stage's own
+// step's velocity.
 constexpr int kV2Ring = 4;
 
 // Side values of stage A's rows, by lane i < 24: (row offset, column offset
@@ -1766,14 +1769,13 @@ __device__ __forceinline__ SideEntry v2_side(int i, bool bot, bool top) {
 
 template <typename T, int NPL, bool NT, bool VE, bool WALL>
 __global__ void __launch_bounds__(64 * kTwoStepWaves, VE ? 1 : kTwoStepWaves) sweep_vec2_kernel(SweepArgs a) {
-  // FP32: storage relative to the row references, four nodes per lane;
-  // FP64: plain storage, two nodes per lane
+  // FP32: storage relative to the row references; FP64: plain storage
   constexpr bool SHIFT = sizeof(T) == 4;
   constexpr int W = 64 * NPL;                 // window columns
   constexpr int HL = (2 + NPL - 1) / NPL;     // lanes per side without valid step t+1
   typedef typename Vec<T, NPL>::type V;
   // the ring of step-t rows: populations and trace, and with VE the stress
-  // sigma(t) (40 KB per workgroup, 52 KB with VE)
+  // sigma(t) (sizeof(T) x NPL x 5 KB per workgroup, x 6.5 KB with VE)
   constexpr int RP = kPlanes + (VE ? kStressPlanes : 0);
   __shared__ V ring[kV2Ring][RP][64];
   const int lane = threadIdx.x & 63;
@@ -2859,27 +2861,31 @@ hipError_t launch_narrow_two_step(bool fp32, int nx, const SweepArgs &a, hipStre
 hipError_t launch_two_step(bool fp32, const SweepArgs &a, hipStream_t s) {
   if (a.n_strips == 0) return hipSuccess;
   if (a.ve && (!a.SA || !a.SB)) return hipErrorInvalidValue;
-  if (fp32) {
-    if (a.ve) launch_two_step_t<float, 4, true>(a, s);
-    else launch_two_step_t<float, 4, false>(a, s);
+  const int npl = two_step_npl(fp32, a.nt, a.ve);
+  if (fp32 && npl == 4) {
+    launch_two_step_t<float, 4, false>(a, s);
+  } else if (fp32) {
+    if (a.ve) launch_two_step_t<float, 2, true>(a, s);
+    else launch_two_step_t<float, 2, false>(a, s);
   } else {
-    if (a.ve) launch_two_step_t<double, kTwoStepNpl64, true>(a, s);
-    else launch_two_step_t<double, kTwoStepNpl64, false>(a, s);
+    if (a.ve) launch_two_step_t<double, 2, true>(a, s);
+    else launch_two_step_t<double, 2, false>(a, s);
   }
   return hipGetLastError();
 }
 
-int two_step_blocks_per_cu(bool fp32, bool ve) {
+int two_step_blocks_per_cu(bool fp32, bool nt, bool ve) {
   int n = 0;
   constexpr int b = 64 * kTwoStepWaves;
   hipError_t e;
-  if (fp32)
-    e = ve ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<float, 4, false, true, false>, b, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<float, 4, false, false, false>, b, 0);
+  if (fp32 && two_step_npl(fp32, nt, ve) == 4)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<float, 4, true, false, false>, b, 0);
+  else if (fp32)
+    e = ve ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<float, 2, false, true, false>, b, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<float, 2, false, false, false>, b, 0);
   else
-    e = ve ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<double, kTwoStepNpl64, false, true, false>, b, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<double, kTwoStepNpl64, false, false, false>, b,
-                                                          0);
+    e = ve ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<double, 2, false, true, false>, b, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_vec2_kernel<double, 2, false, false, false>, b, 0);
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 

@@ -221,11 +221,11 @@ bool narrow_two_step_channel(const lb_options *o, const lb_channel &c, int esize
   return !o->viscoelastic && !is_strip_class(width_class(c.nx, esize)) && c.pressure_gradient == 0;
 }
 bool two_step_wall(const lb_channel &c) { return c.top_wall == LB_WALL_ZOU_HE || c.wall_velocity != 0; }
-// Stored columns of the two-step strips of a width: at most 248 (FP32, four
-// nodes per lane) or 124 (FP64, two), in multiples of the nodes per lane, as
-// even as possible.
-std::vector<int> two_step_cuts(int nx, int esize) {
-  const int npl = esize == 4 ? vec_nodes(esize) : kTwoStepNpl64, cols = esize == 4 ? kTwoStepCols32 : kTwoStepCols64;
+// Stored columns of the two-step strips of a width at npl nodes per lane:
+// at most two_step_cols(npl) (248 at four, 124 at two), in multiples of
+// npl, as even as possible.
+std::vector<int> two_step_cuts(int nx, int npl) {
+  const int cols = two_step_cols(npl);
   const int units = nx / npl, m = (nx + cols - 1) / cols;
   std::vector<int> x(1, 0);
   for (int i = 0; i < m; ++i) x.push_back(x.back() + npl * (units / m + (i < units % m)));
@@ -234,12 +234,12 @@ std::vector<int> two_step_cuts(int nx, int esize) {
 // Rows per two-step strip: whole rounds of resident strips cost each
 // strip's rows plus its four extra rows of step t and about two rows of
 // start-up, so the height minimises rounds x (rows + 6) over 16..56 rows.
-int two_step_rows(const std::vector<lb_channel> &chans, int esize, int slots) {
+int two_step_rows(const std::vector<lb_channel> &chans, int npl, int slots) {
   int best = 16;
   double best_cost = 1e300;
   for (int H = 16; H <= kTwoStepMaxRows; ++H) {
     long long S = 0;
-    for (const lb_channel &c : chans) S += (long long)(two_step_cuts(c.nx, esize).size() - 1) * ((c.ny + H - 1) / H);
+    for (const lb_channel &c : chans) S += (long long)(two_step_cuts(c.nx, npl).size() - 1) * ((c.ny + H - 1) / H);
     const double cost = (double)((S + slots - 1) / std::max(slots, 1)) * (H + 6);
     if (S > 0 && cost < best_cost) {
       best_cost = cost;
@@ -248,8 +248,8 @@ int two_step_rows(const std::vector<lb_channel> &chans, int esize, int slots) {
   }
   return best;
 }
-void add_two_step_strips(int ci, const lb_channel &c, int esize, int H, std::vector<Strip> &out) {
-  const std::vector<int> x = two_step_cuts(c.nx, esize);
+void add_two_step_strips(int ci, const lb_channel &c, int npl, int H, std::vector<Strip> &out) {
+  const std::vector<int> x = two_step_cuts(c.nx, npl);
   for (int y0 = 0; y0 < c.ny; y0 += H)
     for (size_t s = 0; s + 1 < x.size(); ++s)
       out.push_back(Strip{ci, x[s], y0, std::min(y0 + H, c.ny), 0, x[s + 1]});
@@ -283,6 +283,10 @@ void add_tiles(int i, const lb_channel &c, TileShape ts, std::vector<Strip> &out
       for (int cx = g * cols / 8; cx < (g + 1) * cols / 8; ++cx)
         out.push_back(Strip{i, cx * ts.tx, y0, std::min(y0 + ts.ty, c.ny), 0});
 }
+
+// A state buffer larger than the last-level cache: the sweeps stream it
+// (nontemporal stores)
+bool streamed(const Layout &L) { return (long long)kPlanes * L.plane * L.esize > kNontemporalBytes; }
 
 Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
   Layout L;
@@ -347,9 +351,10 @@ Layout make_layout(const lb_channel *c, int n, const lb_options *o) {
   L.off_bstrips = take(sizeof(Strip) * strips);
   L.off_brstrips = take(sizeof(Strip) * strips);
   const int min_rows = o->strip_rows > 0 ? std::min(o->strip_rows, 16) : 16;
+  const int npl = two_step_npl(L.esize == 4, streamed(L), o->viscoelastic);
   for (int i = 0; i < n && two_step_handle(o, o->obs_every > 0 ? o->obs_every : kDefaultK); ++i)
     if (two_step_channel(c[i], L.esize))
-      L.max_two += (int)(two_step_cuts(c[i].nx, L.esize).size() - 1) * ((c[i].ny + min_rows - 1) / min_rows);
+      L.max_two += (int)(two_step_cuts(c[i].nx, npl).size() - 1) * ((c[i].ny + min_rows - 1) / min_rows);
   L.off_btiles = take(sizeof(Strip) * std::max(L.n_tiles, 1));
   L.off_tstrips = take(sizeof(Strip) * std::max(L.max_two, 1));
   L.bytes = at;
@@ -441,7 +446,7 @@ lb_status upload_strips(lb_handle *h, bool all) {
   std::vector<Strip> raw, grouped;
   // stacks while a state buffer fits the last-level cache (the stores are
   // then cached, see sweep_args)
-  const bool stack = (long long)kPlanes * h->L.plane * h->L.esize <= kNontemporalBytes;
+  const bool stack = !streamed(h->L);
   // Strip heights of the active set: the requested (or default) ones, all
   // divided alike while the active channels make fewer strips than the GPU
   // has SIMDs (down to a kernel's row group for the narrow widths, 4 rows
@@ -511,12 +516,13 @@ lb_status upload_strips(lb_handle *h, bool all) {
       std::vector<lb_channel> elig;
       for (int i = 0; i < h->n_ch; ++i)
         if (h->active[i] && two_step_channel(h->in[i], es)) elig.push_back(h->in[i]);
+      const int npl = two_step_npl(es == 4, streamed(h->L), h->opt.viscoelastic);
       const int H = h->opt.strip_rows > 0 ? std::min(h->opt.strip_rows, kTwoStepMaxRows)
-                                          : two_step_rows(elig, es, h->slots);
+                                          : two_step_rows(elig, npl, h->slots);
       for (int i = 0; i < h->n_ch; ++i) {
         if (!h->active[i]) continue;
         if (two_step_channel(h->in[i], es)) {
-          add_two_step_strips(i, h->in[i], es, H, two);
+          add_two_step_strips(i, h->in[i], npl, H, two);
           wall = wall || two_step_wall(h->in[i]);
         } else if (narrow_two_step_channel(&h->opt, h->in[i], es)) {
           add_strips(i, h->L.ch[i], es, rows_of(i), stack, n2raw);
@@ -566,7 +572,7 @@ SweepArgs sweep_args(lb_handle *h, const Strip *strips, int begin, int count, in
   a.n_strips = count;
   a.n_wg = (count + kWaves - 1) / kWaves;
   a.k = k;
-  a.nt = (long long)kPlanes * h->L.plane * h->L.esize > kNontemporalBytes;
+  a.nt = streamed(h->L);
   a.uref = h->duref;
   a.ve = h->opt.viscoelastic;
   a.zh = h->any_zh;
@@ -581,7 +587,7 @@ lb_status enqueue_step(lb_handle *h, int src, int k, hipStream_t s, bool block =
   if (h->opt.stress_force) {
     HIPCHECK(h, launch_saf_fused(static_cast<const double *>(h->buf[src]), static_cast<double *>(h->buf[src ^ 1]),
                                  h->dch, h->tiles, h->L.n_tiles, k,
-                                 (long long)kPlanes * h->L.plane * h->L.esize > kNontemporalBytes, s));
+                                 streamed(h->L), s));
     return LB_OK;
   }
   Strip *tl = block ? h->btiles : h->tiles;
@@ -964,7 +970,8 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return bail(LB_EHIP);
-    h->slots = two_step_blocks_per_cu(o->precision == LB_FP32_SHIFTED, o->viscoelastic) * std::max(cus, 1);
+    h->slots = two_step_blocks_per_cu(o->precision == LB_FP32_SHIFTED, streamed(h->L), o->viscoelastic) *
+               std::max(cus, 1);
     h->simds = 4 * std::max(cus, 1);
   }
   if (upload_strips(h, true) != LB_OK || upload_strips(h, false) != LB_OK) return bail(LB_EHIP);

@@ -1,15 +1,17 @@
 """Two steps per pass over the state (captured blocks of K steps, K a
 multiple of 4) against one step per pass and against the FP64 oracle, in
-FP32 (reference-shifted storage, four nodes per lane) and FP64 (two nodes per
-lane).
+FP32 (reference-shifted storage) and FP64, at two nodes per lane and, for
+FP32 states larger than the last-level cache (streamed with nontemporal
+stores) with the instantaneous stress, four.
 
 The two-step sweep keeps a strip's rows of step t on chip and applies step
 t+1 to them; each node update is the one-step sweep's arithmetic, so the
 states agree with one step per pass to round-off (and, where the compiler
 contracts the same products into the same fused operations, bit for bit).
 Shapes cover one, two, three and many column strips per row (two-step strips
-are at most 248 columns in FP32 and 124 in FP64, split as evenly as the width
-allows in multiples of the nodes per lane), ragged row bands, one- and
+are at most 124 columns at two nodes per lane and 248 at four, split as
+evenly as the width allows in multiples of the nodes per lane), ragged row
+bands, states of either size, one- and
 two-row channels, the periodic wrap of the window around the channel, and
 handles that mix eligible channels with others (pressure drive, other
 widths) whose steps still run one per pass inside the same block (in FP64 on
@@ -73,8 +75,11 @@ TOL = {"fp32": (2e-4, 1e-3), "fp64": (1e-11, 1e-9)}
 # parity bound (random states amplify round-off over a few tens of steps)
 ORACLE_TOL = {"fp32": (1e-4, 1e-3), "fp64": (5e-11, 1e-9)}
 
-SHAPES = {"fp32": [(256, 1), (256, 2), (512, 3), (512, 37), (768, 16), (1024, 65), (2048, 33), (4096, 24)],
-          "fp64": [(128, 1), (128, 2), (192, 3), (320, 37), (256, 16), (1024, 65), (4096, 24)]}
+# (1024, 6600) in FP32 and (1024, 3300) in FP64 exceed 256 MB per state
+# buffer: streamed, FP32 at four nodes per lane
+SHAPES = {"fp32": [(256, 1), (256, 2), (512, 3), (512, 37), (768, 16), (1024, 65), (2048, 33), (4096, 24),
+                   (1024, 6600)],
+          "fp64": [(128, 1), (128, 2), (192, 3), (320, 37), (256, 16), (1024, 65), (4096, 24), (1024, 3300)]}
 NARROW = [(1, 40), (1, 3), (2, 33), (4, 17), (8, 511), (8, 1), (8, 6), (16, 9), (16, 200), (32, 70), (32, 2),
           (64, 5), (64, 130)]
 
@@ -133,7 +138,8 @@ def test_two_step_matches_oracle(orc, precision, nx):
 
 
 @pytest.mark.parametrize("precision,nx", [("fp32", 256), ("fp32", 768), ("fp32", 4096), ("fp64", 128),
-                                          ("fp64", 320), ("fp64", 4096), ("fp32", 8), ("fp64", 64)])
+                                          ("fp64", 320), ("fp64", 4096), ("fp32", 8), ("fp64", 64),
+                                          ("fp32", 327680)])
 def test_two_step_x_uniform_stays_bitwise_uniform(precision, nx):
     """From rest, 3 blocks of 100 steps (with the reference moves between
     blocks in FP32): every column of every row stays identical, so every lane
@@ -148,7 +154,8 @@ def test_two_step_x_uniform_stays_bitwise_uniform(precision, nx):
 
 
 @pytest.mark.parametrize("precision,nx,ny", [("fp32", 512, 19), ("fp32", 256, 2), ("fp32", 1024, 40),
-                                             ("fp64", 192, 19), ("fp64", 128, 1), ("fp64", 512, 40)])
+                                             ("fp32", 1024, 6600), ("fp64", 192, 19), ("fp64", 128, 1),
+                                             ("fp64", 512, 40)])
 def test_two_step_viscoelastic_matches_one_step(precision, nx, ny):
     """The time-integrated stress: the stored stress sigma(t) rides in the
     ring beside the populations. From seeded random populations and a seeded
