@@ -145,7 +145,10 @@ enum { LB_WALL_HALFWAY = 0, LB_WALL_ZOU_HE = 1 };
  *                the active channels make fewer one-step strips than the
  *                GPU has SIMDs, their heights are divided alike (down to
  *                4 rows, or a narrow kernel's row group) to spread them
- *                over the GPU; results do not depend on strip heights;
+ *                over the GPU. The narrow widths' two-step strips take
+ *                the smallest power of two of rows (at most strip_rows
+ *                when it is set) whose strips the GPU holds all at once.
+ *                Results do not depend on strip heights;
  *                FP64 channels whose width is not a power of two up to 64
  *                (and whose nx * ny is at most 429,496,704) step on tiles of
  *                64 x 8 nodes instead and do not use it;

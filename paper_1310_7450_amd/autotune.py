@@ -7,11 +7,11 @@ device name, the precision and the shape of the batch (the width classes,
 the node count and the row-count range).
 
 For a batch run to steady state (``to_steady``) the time per step of the
-whole batch is the wrong target. A channel relaxes over ~H^2/nu steps, so the
-widest channels converge last and spend much of the run alone: with widths
-spread evenly, about half the run has at most a quarter of the channels
-active. The objective is then the mean time per step of the widest half and
-of the widest eighth of the channels.
+whole batch alone is the wrong target. A channel relaxes over ~H^2/nu steps,
+so the widest channels converge last and spend much of the run alone: with
+widths spread evenly, about half the run has at most a quarter of the
+channels active. The objective is then the mean time per step of the whole
+batch, of its widest half and of its widest eighth.
 """
 import json
 import os
@@ -20,7 +20,9 @@ from typing import Iterable, Optional, Sequence
 
 from .lbnlm import ChannelSpec, Solver
 
-DEFAULT_CANDIDATES = (4, 8, 16, 24, 32, 64)
+# 0: the library's own heights (for the narrow widths' two-step strips,
+# chosen from the number of active channels)
+DEFAULT_CANDIDATES = (0, 4, 8, 16, 24, 32, 64)
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lbnlm_autotune.json")
 
 
@@ -73,8 +75,9 @@ def tune_strip_rows(channels: Sequence[ChannelSpec], precision: str = "fp32",
     times = {}
     for sr in candidates:
         if to_steady:
-            times[sr] = 0.5 * (time_candidate(widest(channels, 0.5), precision, sr, steps, nn_pressure) +
-                               time_candidate(widest(channels, 0.125), precision, sr, steps, nn_pressure))
+            times[sr] = (time_candidate(channels, precision, sr, steps, nn_pressure) +
+                         time_candidate(widest(channels, 0.5), precision, sr, steps, nn_pressure) +
+                         time_candidate(widest(channels, 0.125), precision, sr, steps, nn_pressure)) / 3
         else:
             times[sr] = time_candidate(channels, precision, sr, steps, nn_pressure)
         if verbose:

@@ -176,6 +176,9 @@ hipError_t launch_two_step(bool fp32, const SweepArgs &a, hipStream_t s);
 // the instantaneous model): one workgroup of two wavefronts per strip of
 // rows, the strips of one width in SweepArgs.strips, n_wg = n_strips.
 hipError_t launch_narrow_two_step(bool fp32, int nx, const SweepArgs &a, hipStream_t s);
+// workgroups of the narrow two-step kernel one CU holds at once (the fewest
+// over the widths)
+int narrow_two_step_blocks_per_cu(bool fp32);
 // workgroups of the two-step kernel one CU holds at once
 int two_step_blocks_per_cu(bool fp32, bool nt, bool ve);
 

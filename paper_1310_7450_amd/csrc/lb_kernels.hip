@@ -2858,6 +2858,27 @@ hipError_t launch_narrow_two_step(bool fp32, int nx, const SweepArgs &a, hipStre
   return hipGetLastError();
 }
 
+template <typename T, bool SH>
+int narrow2_blocks_per_cu() {
+  int lo = 1 << 30;
+  auto q = [&](const void *f) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 128, 0) == hipSuccess && n > 0) lo = std::min(lo, n);
+  };
+  q(reinterpret_cast<const void *>(sweep_narrow2_kernel<T, SH, 1>));
+  q(reinterpret_cast<const void *>(sweep_narrow2_kernel<T, SH, 2>));
+  q(reinterpret_cast<const void *>(sweep_narrow2_kernel<T, SH, 4>));
+  q(reinterpret_cast<const void *>(sweep_narrow2_kernel<T, SH, 8>));
+  q(reinterpret_cast<const void *>(sweep_narrow2_kernel<T, SH, 16>));
+  q(reinterpret_cast<const void *>(sweep_narrow2_kernel<T, SH, 32>));
+  q(reinterpret_cast<const void *>(sweep_narrow2_kernel<T, SH, 64>));
+  return lo == (1 << 30) ? 1 : lo;
+}
+
+int narrow_two_step_blocks_per_cu(bool fp32) {
+  return fp32 ? narrow2_blocks_per_cu<float, true>() : narrow2_blocks_per_cu<double, false>();
+}
+
 hipError_t launch_two_step(bool fp32, const SweepArgs &a, hipStream_t s) {
   if (a.n_strips == 0) return hipSuccess;
   if (a.ve && (!a.SA || !a.SB)) return hipErrorInvalidValue;

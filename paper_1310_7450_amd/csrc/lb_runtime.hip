@@ -248,6 +248,30 @@ int two_step_rows(const std::vector<lb_channel> &chans, int npl, int slots) {
   }
   return best;
 }
+// Rows per narrow two-step strip: a power of two R (a channel's strips take
+// at least its row group), the same for every narrow channel: the smallest
+// whose strips all fit the GPU's resident workgroups at once (slots), so
+// that the strips are as short as one round allows; not above the
+// requested height when one is given; within the room left in the strip
+// list. (Measured on 8-wide channels of 32..512 rows, 16 to 256 of them:
+// this height was the fastest in every case; a second round, or strips
+// twice as tall, cost 10-55% per step.)
+int narrow_two_step_rows(const std::vector<lb_channel> &chans, long long slots, int requested, long long room) {
+  int last_fit = 0;  // the tallest height so far within the room
+  for (int k = 0; k <= 30; ++k) {
+    const int R = 1 << k;
+    if (requested > 0 && R > requested && last_fit > 0) return last_fit;
+    long long S = 0;
+    for (const lb_channel &c : chans) {
+      const int rows = std::max(R, 64 / c.nx);
+      S += (c.ny + rows - 1) / rows;
+    }
+    if (S > room) continue;
+    if (S <= slots) return R;
+    last_fit = R;
+  }
+  return last_fit > 0 ? last_fit : 1 << 30;
+}
 void add_two_step_strips(int ci, const lb_channel &c, int npl, int H, std::vector<Strip> &out) {
   const std::vector<int> x = two_step_cuts(c.nx, npl);
   for (int y0 = 0; y0 < c.ny; y0 += H)
@@ -396,6 +420,7 @@ struct lb_handle {
   bool two_step = false;     // captured blocks pair their steps where eligible
   int slots = 1024;          // two-step strips resident at once on the GPU
   int simds = 1024;          // SIMDs of the GPU (four per CU)
+  long long n2slots = 1536;  // narrow two-step strips resident at once
   int cur = 0;               // buffer holding the current state
   hipStream_t stream = nullptr, cap = nullptr;
   bool own_stream = false;
@@ -513,9 +538,12 @@ lb_status upload_strips(lb_handle *h, bool all) {
     bool wall = false;
     if (h->two_step) {
       const int es = h->L.esize;
-      std::vector<lb_channel> elig;
-      for (int i = 0; i < h->n_ch; ++i)
-        if (h->active[i] && two_step_channel(h->in[i], es)) elig.push_back(h->in[i]);
+      std::vector<lb_channel> elig, nelig;
+      for (int i = 0; i < h->n_ch; ++i) {
+        if (!h->active[i]) continue;
+        if (two_step_channel(h->in[i], es)) elig.push_back(h->in[i]);
+        else if (narrow_two_step_channel(&h->opt, h->in[i], es)) nelig.push_back(h->in[i]);
+      }
       const int npl = two_step_npl(es == 4, streamed(h->L), h->opt.viscoelastic);
       const int H = h->opt.strip_rows > 0 ? std::min(h->opt.strip_rows, kTwoStepMaxRows)
                                           : two_step_rows(elig, npl, h->slots);
@@ -524,20 +552,24 @@ lb_status upload_strips(lb_handle *h, bool all) {
         if (two_step_channel(h->in[i], es)) {
           add_two_step_strips(i, h->in[i], npl, H, two);
           wall = wall || two_step_wall(h->in[i]);
-        } else if (narrow_two_step_channel(&h->opt, h->in[i], es)) {
-          add_strips(i, h->L.ch[i], es, rows_of(i), stack, n2raw);
-        } else if (!tiled(&h->opt, h->in[i])) {
-          const ChanDev &d = h->L.ch[i];
-          add_strips(i, d, h->L.esize, rows_of(i), stack, braw);
+        } else if (!narrow_two_step_channel(&h->opt, h->in[i], es) && !tiled(&h->opt, h->in[i])) {
+          add_strips(i, h->L.ch[i], es, rows_of(i), stack, braw);
         }
+      }
+      // the narrow ones, in what room the list has left
+      if (!nelig.empty()) {
+        const int R2 = narrow_two_step_rows(nelig, h->n2slots, h->opt.strip_rows,
+                                            h->L.strip_cap - (long long)braw.size());
+        for (int i = 0; i < h->n_ch; ++i)
+          if (h->active[i] && narrow_two_step_channel(&h->opt, h->in[i], es))
+            add_strips(i, h->L.ch[i], es, std::max(R2, 64 / h->in[i].nx), stack, n2raw);
       }
     }
     group_strips(braw, h->L.ch, h->L.esize, bgrouped, h->bact_begin, h->bact_count);
     std::vector<Strip> brev(bgrouped);
     for (int c = 0; c < kClasses; ++c)
       std::reverse(brev.begin() + h->bact_begin[c], brev.begin() + h->bact_begin[c] + h->bact_count[c]);
-    // the narrow two-step strips follow in dbact (their heights are the
-    // active set's one-step ones, so both lists together fit its room)
+    // the narrow two-step strips follow in dbact
     group_strips(n2raw, h->L.ch, h->L.esize, n2grouped, h->n2_begin, h->n2_count);
     for (int c = 0; c < kClasses; ++c) h->n2_begin[c] += (int)bgrouped.size();
     bgrouped.insert(bgrouped.end(), n2grouped.begin(), n2grouped.end());
@@ -973,6 +1005,7 @@ lb_status lb_create(const lb_channel *c, int32_t n, const lb_options *o, void *w
     h->slots = two_step_blocks_per_cu(o->precision == LB_FP32_SHIFTED, streamed(h->L), o->viscoelastic) *
                std::max(cus, 1);
     h->simds = 4 * std::max(cus, 1);
+    h->n2slots = (long long)narrow_two_step_blocks_per_cu(o->precision == LB_FP32_SHIFTED) * std::max(cus, 1);
   }
   if (upload_strips(h, true) != LB_OK || upload_strips(h, false) != LB_OK) return bail(LB_EHIP);
   std::vector<Strip> tiles, btiles;  // kept until the synchronisation below
