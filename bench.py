@@ -180,6 +180,28 @@ def run_transient_scale(steps=200, warmup=100):
             "roofline": two_step_roofline(achieved, nodes, sec / steps, measured_traffic("transient_fp32"))}
 
 
+def copy_bandwidth(reps=5):
+    """Measured device copy rate (GB/s, bytes read plus bytes written): a
+    plain copy of 1 GiB, timed with HIP events after two untimed copies."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * 4 * n * reps / sec / 1e9
+
+
 def two_step_roofline(achieved, nodes, sec_per_step, traffic, precision="fp32", bpn=None):
     """Roofline of the two-step sweep (sweep_vec2_kernel): one launch
     performs two node updates per node, so at B bytes per node update (80 in
@@ -351,6 +373,8 @@ def main():
                       f"({100 * r['frac']:.1f}%)", flush=True)
         return
     spec = wl["channels"][0]
+    copy_gbs = copy_bandwidth()
+    print(f"bench: device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     print(f"bench: {wl['name']} g={spec.force:.3e} eps={spec.eps:+.4f}, fp32 {args.steps} steps",
           file=sys.stderr, flush=True)
     r32 = time_solver("fp32", wl, args.steps, args.warmup, args.strip_rows)
@@ -413,13 +437,14 @@ def main():
                    "force": spec.force, "eps": spec.eps, "tau_lb": spec.tau_lb, "G": spec.G,
                    "tau0": spec.tau0, "gamma_c": spec.gamma_c, "precision": "fp32_shifted",
                    "nn_pressure": 1, "start": "rest"},
-        "roofline": two_step_roofline(r32["achieved_GBs"], spec.nx * spec.ny, r32["ms_per_step"] / 1e3,
-                                      measured_traffic("fp32")),
+        "roofline": dict(two_step_roofline(r32["achieved_GBs"], spec.nx * spec.ny, r32["ms_per_step"] / 1e3,
+                                           measured_traffic("fp32")),
+                         copy_GBs=round(copy_gbs, 1), frac_of_copy=round(r32["achieved_GBs"] / copy_gbs, 4)),
         "fp32_one_step_per_pass": {
             "value": round(r32one["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r32one["ms_per_step"], 5),
             "roofline": {"bound": "hbm", "achieved": round(r32one["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(r32one["frac"], 4), "traffic": measured_traffic("fp32_one"),
-                         "kernel": "sweep_vec_kernel"}},
+                         "kernel": "sweep_vec_kernel", "frac_of_copy": round(r32one["achieved_GBs"] / copy_gbs, 4)}},
         "fp64": None if r64 is None else {
             "value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 5),
             "roofline": two_step_roofline(r64["achieved_GBs"], spec.nx * spec.ny, r64["ms_per_step"] / 1e3,
@@ -428,7 +453,8 @@ def main():
                 "value": round(r64one["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64one["ms_per_step"], 5),
                 "roofline": {"bound": "hbm", "achieved": round(r64one["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
                              "unit": "GB/s", "frac": round(r64one["frac"], 4),
-                             "traffic": measured_traffic("fp64_one"), "kernel": "sweep_tile_kernel"}}},
+                             "traffic": measured_traffic("fp64_one"), "kernel": "sweep_tile_kernel",
+                             "frac_of_copy": round(r64one["achieved_GBs"] / copy_gbs, 4)}}},
         "batched": batched,
         "transient_scale": transient,
         "viscoelastic": ve,

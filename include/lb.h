@@ -146,7 +146,8 @@ enum { LB_WALL_HALFWAY = 0, LB_WALL_ZOU_HE = 1 };
  *                GPU has SIMDs, their heights are divided alike (down to
  *                4 rows, or a narrow kernel's row group) to spread them
  *                over the GPU. The narrow widths' two-step strips take
- *                the smallest power of two of rows (at most strip_rows
+ *                the smallest height among 1, 2, 4, the multiples of 8 up
+ *                to 64 and the powers of two beyond (at most strip_rows
  *                when it is set) whose strips the GPU holds all at once.
  *                Results do not depend on strip heights;
  *                FP64 channels whose width is not a power of two up to 64

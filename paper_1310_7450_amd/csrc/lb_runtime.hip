@@ -248,22 +248,37 @@ int two_step_rows(const std::vector<lb_channel> &chans, int npl, int slots) {
   }
   return best;
 }
-// Rows per narrow two-step strip: a power of two R (a channel's strips take
-// at least its row group), the same for every narrow channel: the smallest
-// whose strips all fit the GPU's resident workgroups at once (slots), so
-// that the strips are as short as one round allows; not above the
-// requested height when one is given; within the room left in the strip
-// list. (Measured on 8-wide channels of 32..512 rows, 16 to 256 of them:
-// this height was the fastest in every case; a second round, or strips
-// twice as tall, cost 10-55% per step.)
+// Rows per narrow two-step strip: one height R for every narrow channel
+// (1, 2, 4, a multiple of 8 up to 64, or a power of two; a channel's
+// strips take it rounded up to its row group), the smallest whose strips
+// all fit the GPU's resident workgroups at once (slots), so that the strips
+// are as short as one round allows; not above the requested height when
+// one is given; within the room left in the strip list. (Measured on
+// 8-wide channels of 32..512 rows, 16 to 256 of them: among powers of two
+// this height was the fastest in every case, a second round or strips
+// twice as tall costing 10-55% per step; the multiples of 8 gained a
+// further 14% with all 256 channels active, at 48 rows against 64, and
+// lost 2% with 64 active, at 24 rows against 32.)
+// a channel's rows per strip for height R: R rounded up to its row group
+int narrow_rows(int R, int nx) {
+  const int g = 64 / nx;
+  return (std::max(R, g) + g - 1) / g * g;
+}
 int narrow_two_step_rows(const std::vector<lb_channel> &chans, long long slots, int requested, long long room) {
+  // candidate heights: 1, 2, 4, every multiple of 8 up to 64, then powers
+  // of two
+  std::vector<int> cand = {1, 2, 4};
+  for (int m = 8; m <= 64; m += 8) cand.push_back(m);
+  for (int R = 128; R <= (1 << 30); R *= 2) {
+    cand.push_back(R);
+    if (R == (1 << 30)) break;
+  }
   int last_fit = 0;  // the tallest height so far within the room
-  for (int k = 0; k <= 30; ++k) {
-    const int R = 1 << k;
+  for (const int R : cand) {
     if (requested > 0 && R > requested && last_fit > 0) return last_fit;
     long long S = 0;
     for (const lb_channel &c : chans) {
-      const int rows = std::max(R, 64 / c.nx);
+      const int rows = narrow_rows(R, c.nx);
       S += (c.ny + rows - 1) / rows;
     }
     if (S > room) continue;
@@ -562,7 +577,7 @@ lb_status upload_strips(lb_handle *h, bool all) {
                                             h->L.strip_cap - (long long)braw.size());
         for (int i = 0; i < h->n_ch; ++i)
           if (h->active[i] && narrow_two_step_channel(&h->opt, h->in[i], es))
-            add_strips(i, h->L.ch[i], es, std::max(R2, 64 / h->in[i].nx), stack, n2raw);
+            add_strips(i, h->L.ch[i], es, narrow_rows(R2, h->in[i].nx), stack, n2raw);
       }
     }
     group_strips(braw, h->L.ch, h->L.esize, bgrouped, h->bact_begin, h->bact_count);
