@@ -234,13 +234,22 @@ std::vector<int> two_step_cuts(int nx, int npl) {
 // Rows per two-step strip: whole rounds of resident strips cost each
 // strip's rows plus its four extra rows of step t and about two rows of
 // start-up, so the height minimises rounds x (rows + 6) over 16..56 rows.
+// From four rounds on, workgroups that finish early let the next ones
+// start, so the cost is the strips' rows (each plus 6) over the slots (the
+// tallest strips then win: 16 x 8192 x 2048 at 56 rows 108.7-108.9k MLUPS,
+// at 50 rows, the whole-round choice, 107.3k).
 int two_step_rows(const std::vector<lb_channel> &chans, int npl, int slots) {
   int best = 16;
   double best_cost = 1e300;
   for (int H = 16; H <= kTwoStepMaxRows; ++H) {
-    long long S = 0;
-    for (const lb_channel &c : chans) S += (long long)(two_step_cuts(c.nx, npl).size() - 1) * ((c.ny + H - 1) / H);
-    const double cost = (double)((S + slots - 1) / std::max(slots, 1)) * (H + 6);
+    long long S = 0, work = 0;
+    for (const lb_channel &c : chans) {
+      const long long cuts = (long long)(two_step_cuts(c.nx, npl).size() - 1), full = c.ny / H, rem = c.ny % H;
+      S += cuts * (full + (rem > 0));
+      work += cuts * (full * (H + 6) + (rem > 0 ? rem + 6 : 0));
+    }
+    const double r = (double)S / std::max(slots, 1);
+    const double cost = r < 4.0 ? std::ceil(r) * (H + 6) : (double)work / std::max(slots, 1);
     if (S > 0 && cost < best_cost) {
       best_cost = cost;
       best = H;
