@@ -141,12 +141,13 @@ hipError_t launch_gpbc(int fp32, void *B, const ChanDev *ch, int n_ch, int k, co
 constexpr int kMainTileX = LB_MAIN_TX, kMainTileY = LB_MAIN_TY, kMainThreads = LB_MAIN_THREADS;
 hipError_t launch_tiles(const SweepArgs &a, hipStream_t s);
 // Fused stress-force step: tiles of kSafTileX x kSafTileY output nodes
-// (x0, y0, y1 of a Strip), one workgroup each.
+// (x0, y0, y1 of a Strip), one workgroup each; each of the kSafThreads
+// threads takes a column of kSafTileX * kSafTileY / kSafThreads nodes.
 #ifndef LB_SAF_TX
 #define LB_SAF_TX 64
 #endif
 #ifndef LB_SAF_TY
-#define LB_SAF_TY 8
+#define LB_SAF_TY 16
 #endif
 #ifndef LB_SAF_THREADS
 #define LB_SAF_THREADS 512

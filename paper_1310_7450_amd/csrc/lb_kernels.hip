@@ -2508,21 +2508,26 @@ __device__ __forceinline__ void saf_force(const double *__restrict__ Tn, long lo
 }
 
 // One step of the stress-force path fused in one kernel, one workgroup per
-// tile of kSafTX x kSafTY output nodes and one thread per output node. Each
-// XCD takes a contiguous run of the tile list, which the host orders so that
-// a run is a block of neighbouring tiles: adjacent tiles share the halo
-// populations they pull and then find them in that XCD's L2. Each
-// thread pulls its node and keeps the populations; u~ of the tile and of a
-// ring of two nodes around it go to LDS, then Sigma^nN of the tile and a ring
-// of one node, then each thread collides its node with div Sigma^nN from
-// LDS. Columns wrap (x periodic; narrow channels repeat columns); rows
+// tile of kSafTX x kSafTY output nodes, each thread taking a column of
+// kSafNPT of them (kSafRows rows apart): the taller tile repeats less of
+// the ring work per node than one node per thread would, at the same
+// number of wavefronts per CU. Each XCD takes a contiguous run of the tile
+// list, which the host orders so that a run is a block of neighbouring
+// tiles: adjacent tiles share the halo populations they pull and then find
+// them in that XCD's L2. Each thread pulls its nodes and keeps the
+// populations; u~ of the tile and of a ring of two nodes around it go to
+// LDS, then Sigma^nN of the tile and a ring of one node, then each thread
+// collides its nodes with div Sigma^nN from LDS. Columns wrap (x periodic; narrow channels repeat columns); rows
 // outside the channel are the wall ghosts of saf_kappa and saf_force. The
 // arithmetic is that of the three separate passes.
 constexpr int kSafTX = kSafTileX, kSafTY = kSafTileY;
+constexpr int kSafRows = kSafThreads / kSafTX;            // rows of threads
+constexpr int kSafNPT = kSafTY / kSafRows;                // output nodes per thread
 constexpr int kSafUX = kSafTX + 4, kSafUY = kSafTY + 4;  // u~ region
 constexpr int kSafSX = kSafTX + 2, kSafSY = kSafTY + 2;  // Sigma^nN region
 constexpr int kSafRing = 4 * kSafUX + 4 * kSafTY;       // u~ region minus the tile
-static_assert(kSafTX * kSafTY == kSafThreads, "one output node per thread");
+static_assert(kSafRows * kSafTX == kSafThreads && kSafNPT * kSafRows == kSafTY,
+              "a whole column of output nodes per thread");
 static_assert(kSafRing <= kSafThreads, "at most one ring node per thread");
 
 template <bool NT>
@@ -2551,13 +2556,14 @@ __global__ void __launch_bounds__(kSafThreads) saf_fused_kernel(const double *__
     return r < 0 ? r + nx : r;
   };
   auto clampy = [&](int y) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
-  // This thread's node, whose populations it keeps to the collision, and
-  // (threads below kSafRing) one node of the ring of two around the tile:
-  // two rows below, two above, two columns on either side. Both are pulled
-  // before either is used, so that their loads overlap; rows outside the
-  // channel pull a row inside and store nothing.
+  // This thread's nodes (a column of kSafNPT, kSafRows rows apart), whose
+  // populations it keeps to the collision, and (threads below kSafRing) one
+  // node of the ring of two around the tile: two rows below, two above, two
+  // columns on either side. All are pulled before any is used, so that
+  // their loads overlap; rows outside the channel pull a row inside and
+  // store nothing.
   const int jo = threadIdx.x / kSafTX, io = threadIdx.x - jo * kSafTX;
-  const int yo = tl.y0 + jo, xo = tl.x0 + io;
+  const int xo = tl.x0 + io, xw = wrapx(xo);
   const int h = threadIdx.x;
   int hj, hi;
   if (h < 2 * kSafUX) {
@@ -2574,18 +2580,26 @@ __global__ void __launch_bounds__(kSafThreads) saf_fused_kernel(const double *__
   }
   const int hy = tl.y0 - 2 + hj;
   const bool ring = h < kSafRing;
-  const unsigned m = (unsigned)clampy(yo) * nx + wrapx(xo);
-  double f[9], fh[9];
-  pull_local(Ac, nx, ny, wrapx(xo), clampy(yo), uw6, f);
-  const double Pc = Ac[lslot(9, m)];
+  double f[kSafNPT][9], fh[9], Pc[kSafNPT];
+  unsigned m[kSafNPT];
+#pragma unroll
+  for (int s = 0; s < kSafNPT; ++s) {
+    const int yc = clampy(tl.y0 + jo + s * kSafRows);
+    m[s] = (unsigned)yc * nx + xw;
+    pull_local(Ac, nx, ny, xw, yc, uw6, f[s]);
+    Pc[s] = Ac[lslot(9, m[s])];
+  }
   if (ring) pull_local(Ac, nx, ny, wrapx(tl.x0 - 2 + hi), clampy(hy), uw6, fh);
-  double sd, mx, my;
-  moments<double>(f, sd, mx, my);
-  const double inv = recip<double>(sd);  // shared with the collision
-  if (yo < ny) {
-    const U2<double> u = u_tilde<double, false>(sd, mx, my, g, 0.0);
-    su[0][jo + 2][io + 2] = u.x;
-    su[1][jo + 2][io + 2] = u.y;
+  double sd[kSafNPT], mx[kSafNPT], my[kSafNPT], inv[kSafNPT];
+#pragma unroll
+  for (int s = 0; s < kSafNPT; ++s) {
+    moments<double>(f[s], sd[s], mx[s], my[s]);
+    inv[s] = recip<double>(sd[s]);  // shared with the collision
+    if (tl.y0 + jo + s * kSafRows < ny) {
+      const U2<double> u = u_tilde<double, false>(sd[s], mx[s], my[s], g, 0.0);
+      su[0][jo + s * kSafRows + 2][io + 2] = u.x;
+      su[1][jo + s * kSafRows + 2][io + 2] = u.y;
+    }
   }
   if (ring && hy >= 0 && hy < ny) {
     double hs, hx, hv;
@@ -2616,38 +2630,43 @@ __global__ void __launch_bounds__(kSafThreads) saf_fused_kernel(const double *__
     sT[2][j][ii] = syy - cf.lgt * 2.0 * kyy;
   }
   __syncthreads();
-  // collide and stream this thread's node
-  if (yo >= tl.y1 || xo >= nx) return;
-  const int js = jo + 1, is = io + 1;
-  double dn[3], up[3];
+  // collide and stream this thread's nodes
+  if (xo >= nx) return;
 #pragma unroll
-  for (int p = 0; p < 3; ++p) {
-    const double Tc = sT[p][js][is];
-    if (ny == 1) {
-      dn[p] = up[p] = Tc;
-    } else {
-      dn[p] = (yo > 0) ? sT[p][js - 1][is] : 2.0 * Tc - sT[p][js + 1][is];
-      up[p] = (yo < ny - 1) ? sT[p][js + 1][is] : 2.0 * Tc - sT[p][js - 1][is];
+  for (int s = 0; s < kSafNPT; ++s) {
+    const int yo = tl.y0 + jo + s * kSafRows;
+    if (yo >= tl.y1) continue;
+    const int js = jo + s * kSafRows + 1, is = io + 1;
+    double dn[3], up[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const double Tc = sT[p][js][is];
+      if (ny == 1) {
+        dn[p] = up[p] = Tc;
+      } else {
+        dn[p] = (yo > 0) ? sT[p][js - 1][is] : 2.0 * Tc - sT[p][js + 1][is];
+        up[p] = (yo < ny - 1) ? sT[p][js + 1][is] : 2.0 * Tc - sT[p][js - 1][is];
+      }
     }
-  }
-  const double fsx = 0.5 * (sT[0][js][is + 1] - sT[0][js][is - 1]) + 0.5 * (up[1] - dn[1]);
-  const double fsy = 0.5 * (sT[1][js][is + 1] - sT[1][js][is - 1]) + 0.5 * (up[2] - dn[2]);
-  const double fx = g + fsx, fy = fsy;
-  const double ux = (mx + 0.5 * fx) * inv, uy = (my + 0.5 * fy) * inv;
-  const double usq = ux * ux + uy * uy, uf = ux * fx + uy * fy;
-  const double om = c.omega, kf = c.kf;
+    const double fsx = 0.5 * (sT[0][js][is + 1] - sT[0][js][is - 1]) + 0.5 * (up[1] - dn[1]);
+    const double fsy = 0.5 * (sT[1][js][is + 1] - sT[1][js][is - 1]) + 0.5 * (up[2] - dn[2]);
+    const double fx = g + fsx, fy = fsy;
+    const double ux = (mx[s] + 0.5 * fx) * inv[s], uy = (my[s] + 0.5 * fy) * inv[s];
+    const double usq = ux * ux + uy * uy, uf = ux * fx + uy * fy;
+    const double om = c.omega, kf = c.kf;
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const double cu = cx[q] * ux + cy[q] * uy, cfo = cx[q] * fx + cy[q] * fy;
-    const double a = weight<double>(q);
-    const double neq = a * sd * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
-    const double F = a * kf * (3.0 * cfo + 9.0 * cu * cfo - 3.0 * uf);
-    const double v = f[q] - om * (f[q] - neq) + F;
-    if constexpr (NT) __builtin_nontemporal_store(v, &Bc[lslot(q, m)]);
-    else Bc[lslot(q, m)] = v;
+    for (int q = 0; q < 9; ++q) {
+      const double cu = cx[q] * ux + cy[q] * uy, cfo = cx[q] * fx + cy[q] * fy;
+      const double a = weight<double>(q);
+      const double neq = a * sd[s] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+      const double F = a * kf * (3.0 * cfo + 9.0 * cu * cfo - 3.0 * uf);
+      const double v = f[s][q] - om * (f[s][q] - neq) + F;
+      if constexpr (NT) __builtin_nontemporal_store(v, &Bc[lslot(q, m[s])]);
+      else Bc[lslot(q, m[s])] = v;
+    }
+    if constexpr (NT) __builtin_nontemporal_store(Pc[s], &Bc[lslot(9, m[s])]);
+    else Bc[lslot(9, m[s])] = Pc[s];
   }
-  if constexpr (NT) __builtin_nontemporal_store(Pc, &Bc[lslot(9, m)]);
-  else Bc[lslot(9, m)] = Pc;
 }
 
 // Observation of the stress-force path: one workgroup per row of every
