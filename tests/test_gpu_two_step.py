@@ -114,6 +114,24 @@ def test_two_step_mixed_handle(precision):
         assert e < TOL[precision][0] and ep < TOL[precision][1]
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_two_step_many_narrow_channels(precision):
+    """More narrow channels than the GPU holds two-step workgroups at once
+    (1,600 channels of every narrow width, 1 to 7 rows, a few with a moving
+    wall), so that every channel is one strip and the strips run in several
+    rounds: each channel equals its one-step run."""
+    widths = [1, 2, 4, 8, 16, 32, 64]
+    chans = [spec(widths[i % 7], 1 + (i * 5) % 7, **({"wall_velocity": 1e-3} if i % 97 == 0 else {}))
+             for i in range(1600)]
+    pairs, st = run_pair(chans, [8, 4], obs_every=4, seed=11, precision=precision)
+    worst = (0.0, 0.0)
+    for i, (a, b) in enumerate(pairs):
+        e, ep = state_diff(a, b, st[i][0])
+        worst = (max(worst[0], e), max(worst[1], ep))
+        assert e < TOL[precision][0] and ep < TOL[precision][1], (i, chans[i].nx, chans[i].ny, e, ep)
+    print(f"{precision} 1600 narrow channels: worst state {worst[0]:.2e} P {worst[1]:.2e}", flush=True)
+
+
 @pytest.mark.parametrize("precision,nx", [("fp32", 512), ("fp64", 320), ("fp32", 16), ("fp64", 8), ("fp32", 64)])
 def test_two_step_matches_oracle(orc, precision, nx):
     """Against the FP64 oracle node by node after 3 single steps and 3
