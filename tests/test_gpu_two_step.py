@@ -114,6 +114,32 @@ def test_two_step_mixed_handle(precision):
         assert e < TOL[precision][0] and ep < TOL[precision][1]
 
 
+@pytest.mark.parametrize("precision,big", [("fp32", (1024, 6600)), ("fp64", (1024, 3300))])
+def test_two_step_streamed_walls(orc, precision, big):
+    """A channel large enough to make the state streamed (above 256 MB per
+    buffer: FP32 then runs four nodes per lane) beside channels with a
+    moving half-way top wall and a Zou-He top, switched off at t = 19
+    (inside a two-step launch): every channel equals its one-step run, and
+    the wall channels equal the FP64 oracle node by node."""
+    kw = dict(wall_velocity=1e-3, t_startup=19, nn_pressure=False)
+    chans = [spec(*big), spec(512, 15, **kw), spec(512, 15, top_wall="zou_he", **kw)]
+    pairs, st = run_pair(chans, [24, 3], obs_every=8, seed=21, precision=precision)
+    for i, (a, b) in enumerate(pairs):
+        e, ep = state_diff(a, b, st[i][0])
+        print(f"{precision} channel {i} ({chans[i].nx}x{chans[i].ny}): state {e:.2e} P {ep:.2e}", flush=True)
+        assert e < TOL[precision][0] and ep < TOL[precision][1]
+    for i in (1, 2):
+        c = chans[i]
+        o = orc.Channel(c.nx, c.ny, c.force, tau_lb=c.tau_lb, G=c.G, tau0=c.tau0, gamma_c=c.gamma_c, eps=c.eps,
+                        visc_split=c.visc_split, t_startup=c.t_startup, nn_pressure=False,
+                        wall_velocity=c.wall_velocity, top_wall=c.top_wall)
+        o.set_state(*st[i], t=0)
+        o.run(27)
+        eo = np.abs(pairs[i][0][0] - o.n).max() / np.abs(o.n - workloads.REST_WEIGHTS[:, None, None]).max()
+        print(f"{precision} {c.top_wall} wall beside a streamed state: vs oracle {eo:.2e}", flush=True)
+        assert eo < ORACLE_TOL[precision][0]
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_two_step_many_narrow_channels(precision):
     """More narrow channels than the GPU holds two-step workgroups at once
