@@ -703,10 +703,10 @@ __global__ void __launch_bounds__(64 * LB_WG_WAVES) sweep_kernel(SweepArgs a) {
 //  * wavefront 1 (stage B, step t+1) marches the groups of [y0, y1), pulling
 //    from the ring (any row of the last few groups, by index), and stores.
 // A row of the channel is whole in one group, so no column beyond it is
-// needed. Stage B starts its march L - 1 iterations after stage A (L = 3,
-// or 4 and 5 when a group holds 2 and 1 rows) so that every group it reads
-// is in the ring; one barrier per iteration orders the ring's writes and
-// reads. Per node the arithmetic is the narrow sweep's.
+// needed. Stage B runs L iterations behind stage A (L = 3, or 4 and 5 when
+// a group holds 2 and 1 rows), or sooner at the end of the strip, so that
+// every group it reads is in the ring; one barrier per iteration orders the
+// ring's writes and reads. Per node the arithmetic is the narrow sweep's.
 constexpr int kN2Ring = 8;  // groups in the ring
 template <typename T, bool SHIFT, int TXW>
 __global__ void __launch_bounds__(128) sweep_narrow2_kernel(SweepArgs a) {
@@ -868,17 +868,26 @@ __global__ void __launch_bounds__(128) sweep_narrow2_kernel(SweepArgs a) {
     uCur = uNext;
   };
 
-  // Iteration j: stage A runs group j (after starting at j = 0); stage B
-  // starts at j = L - 1 and runs group j - L; one barrier per iteration.
-  const int niter = (nA > nB + L) ? nA : nB + L;
+  // Iteration j: stage A runs group j (after starting at j = 0). Stage B
+  // runs group b once stage A has written every group it reads, the groups
+  // up to b + L - 1 or stage A's last, nA - 1: at iteration
+  // jB(b) = max(min(b + L, nA), jB(0) + b), having started (groups -1 and
+  // 0) at min(L - 1, nA). One barrier per iteration.
+  const int jS = (L - 1 < nA) ? L - 1 : nA, jB0 = (L < nA) ? L : nA;
+  auto jB = [&](int b) {
+    const int r = (b + L < nA) ? b + L : nA;
+    return (r > jB0 + b) ? r : jB0 + b;
+  };
+  const int niter = (nA > jB(nB - 1) + 1) ? nA : jB(nB - 1) + 1;
   if (isA) start();
+  int bnext = 0;
 #pragma unroll 1
   for (int j = 0; j < niter; ++j) {
     if (isA) {
       if (j < nA) group(j);
     } else {
-      if (j == L - 1) start();
-      if (j >= L && j - L < nB) group(j - L);
+      if (j == jS) start();
+      if (bnext < nB && j == jB(bnext)) group(bnext++);
     }
     __syncthreads();
   }

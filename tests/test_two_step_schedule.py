@@ -1,13 +1,14 @@
 """CPU check of the narrow two-step sweep's schedule (sweep_narrow2_kernel):
 stage A (step t) writes row groups of 64 / nx rows into a ring of eight
-groups in LDS, one group per iteration; stage B (step t + 1) starts L - 1
-iterations later and reads, for its group b, rows of stage A's groups up to
-two rows past its next group. With one barrier per iteration, every ring
+groups in LDS, one group per iteration; stage B (step t + 1) starts at
+iteration min(L - 1, nA) and runs its group b at
+jB(b) = max(min(b + L, nA), jB(0) + b), reading rows of stage A's groups up
+to two rows past its next group. With one barrier per iteration, every ring
 read must find the group it wants written in an earlier iteration and not
 yet overwritten (the slot stage A writes in the same iteration must hold no
-group stage B still reads), and every row stage B stores must depend only
-on rows stage A computed exactly (y - 2 .. y + 2 inside the channel). The
-same index arithmetic as the kernel: row groups counted from
+group stage B still reads), and every row stage B stores must depend only on
+rows stage A computed exactly (y - 2 .. y + 2 inside the channel). The same
+index arithmetic as the kernel: row groups counted from
 yA0 = max(y0 - 2, 0), rows clamped to [yA0, yA1 - 1] before the ring
 lookup, L = 3 + 2 // (64 // nx)."""
 import pytest
@@ -37,14 +38,22 @@ def check_strip(ny, nx, y0, y1, lag=None):
                 # stage A's write of this iteration goes to slot j % RING
                 assert j >= na or g % RING != j % RING, (ny, nx, y0, y1, j, g)
 
-    for j in range(max(na, nb + lag)):
-        if j == lag - 1:  # stage B starts: the group below its first, and its first
+    js = min(lag - 1, na)
+    jb0 = min(lag, na)
+
+    def jb(b):
+        return max(min(b + lag, na), jb0 + b)
+
+    bnext = 0
+    for j in range(max(na, jb(nb - 1) + 1)):
+        if j == js:  # stage B starts: the group below its first, and its first
             reads([y0 - tyw + ly for ly in range(tyw)] + [y0 + ly for ly in range(tyw)], j)
-        if lag <= j < nb + lag:  # stage B's group b assembles group b + 1
-            b = j - lag
-            reads([y0 + (b + 1) * tyw + ly for ly in range(tyw)], j)
+        if bnext < nb and j == jb(bnext):  # stage B's group b assembles group b + 1
+            reads([y0 + (bnext + 1) * tyw + ly for ly in range(tyw)], j)
+            bnext += 1
         if j < na:
             slot[j % RING] = (j, j)
+    assert bnext == nb
     for y in range(y0, y1):
         for r in range(y - 2, y + 3):
             if 0 <= r < ny:
@@ -55,7 +64,7 @@ def check_strip(ny, nx, y0, y1, lag=None):
 def test_narrow_two_step_schedule(nx):
     tyw = 64 // nx
     for ny in list(range(1, 40)) + [64, 130, 200, 511]:
-        for h in sorted({tyw, 2 * tyw, 3 * tyw, 8 * tyw, max(tyw, 64)}):
+        for h in sorted({tyw * k for k in range(1, 9)} | {max(tyw, 64), 16 * tyw}):
             for y0 in range(0, ny, h):
                 check_strip(ny, nx, y0, min(y0 + h, ny))
 
